@@ -1,0 +1,73 @@
+"""The pins catch plausible slips in the oracle.
+
+Each case plants one mistake in a private copy of the oracle's C source (on
+the CPU, in a temporary directory), builds it, swaps it in for the real
+oracle, and checks that at least one pin of test_oracle_pins.py fails.  The
+real oracle is restored afterwards.
+"""
+import ctypes
+import os
+import subprocess
+
+import pytest
+
+import oracle
+import tests.test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "rsm_oracle.c")
+
+MUTATIONS = {
+    "truncated_mod": ("    if (q < 0) q += m;\n", ""),
+    "dropped_origin": ("int64_t v = t->origin[d];", "int64_t v = 0;"),
+    "transposed_paving": ("t->paving[d * rep_rank + k] * r[k]",
+                          "t->paving[k * t->arr_rank + d] * r[k]"),
+    "dropped_fitting": ("v += t->fitting[d * t->pat_rank + k] * i[k];", "(void)i;"),
+    "transposed_fitting": ("t->fitting[d * t->pat_rank + k] * i[k]",
+                           "t->fitting[k * t->arr_rank + d] * i[k]"),
+    "column_major_linearisation": ("lin = lin * t->shape[d] + floor_mod(v, t->shape[d]);",
+                                   "lin += floor_mod(v, t->shape[d]) * "
+                                   "(d ? t->shape[d - 1] : 1);"),
+    "reversed_weights": ("if (kind == OR_WSUM) term *= coeffs[pf];",
+                         "if (kind == OR_WSUM) term *= coeffs[np - 1 - pf];"),
+    "dot_same_operand": ("* x[1][element_offset(&in[1], rep_rank, r, i2)];",
+                         "* x[0][element_offset(&in[0], rep_rank, r, i)];"),
+    "adjoint_sign": ("gx[a] += c * g;", "gx[a] -= c * g;"),
+    "adjoint_weight_grad_uses_weight": ("gc[pf] += g * x[a];", "gc[pf] += c * x[a];"),
+    "adjoint_drops_weight": ("gx[a] += c * g;", "gx[a] += g;"),
+}
+
+PINS = [
+    pins.test_indices_hand_example_negative_origin,
+    pins.test_indices_hand_example_2d_transposed_roles,
+    pins.test_indices_match_numpy_wrap_ravel_random_tilers,
+    pins.test_small_sum_equals_block_reshape_sum,
+    pins.test_two_stage_equals_einsum,
+    pins.test_matmul_tilers_equal_naive_triple_loop,
+    pins.test_adjoint_identity_random_tilers,
+    pins.test_finite_differences_match_chain_adjoint,
+]
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    old, new = MUTATIONS[name]
+    src = open(SRC).read()
+    assert old in src, "mutation anchor vanished: " + name
+    mutant_src = tmp_path / "mutant.c"
+    mutant_src.write_text(src.replace(old, new, 1))
+    so = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", str(so),
+                           str(mutant_src), "-lm"])
+    real = oracle._load()
+    oracle._lib = oracle._bind(ctypes.CDLL(str(so)))
+    caught = []
+    try:
+        for pin in PINS:
+            try:
+                pin()
+            except (AssertionError, ValueError):
+                caught.append(pin.__name__)
+                break
+    finally:
+        oracle._lib = real
+    assert caught, "no pin caught mutation " + name

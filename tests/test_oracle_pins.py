@@ -1,0 +1,444 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+Each test below checks the oracle against something independent of its code:
+a brute-force index walk that never uses a modulo, library routines
+(NumPy's wrapping ravel, reshape/einsum sums, FFT circular correlation,
+matrix products), invariants of exact-paving tilers, the adjoint identity and
+central finite differences (exact for the quadratic loss used).  A plausible
+slip in the oracle -- truncated instead of floored modulo, a transposed
+paving or fitting matrix, a dropped origin/paving/fitting term, a swapped
+weight, a wrong sign in the adjoint -- fails at least one of them (see
+test_oracle_mutations.py, which plants such slips and checks they are caught).
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import rsm_workloads as W
+
+
+# ---------------------------------------------------------------------------
+# helpers that never use the oracle
+# ---------------------------------------------------------------------------
+
+def walk_indices(rep_shape, t):
+    """Index table by incremental stepping: start at the origin, add paving /
+    fitting columns while walking r and i in row-major order, and bring each
+    coordinate back into [0, s) by repeated addition / subtraction of s."""
+    s = np.array(t.array_shape, dtype=np.int64)
+    da = len(s)
+
+    def wrap(c):
+        c = c.copy()
+        for d in range(da):
+            while c[d] < 0:
+                c[d] += s[d]
+            while c[d] >= s[d]:
+                c[d] -= s[d]
+        return c
+
+    rows = []
+    for r in itertools.product(*[range(n) for n in rep_shape]):
+        base = np.array(t.origin, dtype=np.int64).copy()
+        for k, rk in enumerate(r):
+            for _ in range(rk):
+                base = base + t.paving[:, k]
+        row = []
+        for i in itertools.product(*[range(n) for n in t.pattern_shape]):
+            c = base.copy()
+            for k, ik in enumerate(i):
+                for _ in range(ik):
+                    c = c + t.fitting[:, k]
+            c = wrap(c)
+            lin = 0
+            for d in range(da):
+                lin = lin * int(s[d]) + int(c[d])
+            row.append(lin)
+        rows.append(row)
+    return np.array(rows, dtype=np.int64).reshape(
+        int(np.prod(rep_shape)) if rep_shape else 1,
+        int(np.prod(t.pattern_shape)) if t.pattern_shape else 1)
+
+
+def numpy_indices(rep_shape, t):
+    """Index table via NumPy's ravel_multi_index(mode='wrap')."""
+    rg = np.stack(np.meshgrid(*[np.arange(n) for n in rep_shape], indexing="ij"), 0) \
+        .reshape(len(rep_shape), -1) if rep_shape else np.zeros((0, 1), np.int64)
+    pg = np.stack(np.meshgrid(*[np.arange(n) for n in t.pattern_shape], indexing="ij"), 0) \
+        .reshape(len(t.pattern_shape), -1) if t.pattern_shape else np.zeros((0, 1), np.int64)
+    base = t.origin[:, None] + (t.paving @ rg if rep_shape else 0)          # [da, nr]
+    off = t.fitting @ pg if t.pattern_shape else np.zeros((len(t.array_shape), 1), np.int64)
+    coords = base[:, :, None] + off[:, None, :]                              # [da, nr, np]
+    return np.ravel_multi_index(tuple(coords.reshape(len(t.array_shape), -1)),
+                                t.array_shape, mode="wrap").reshape(coords.shape[1], coords.shape[2])
+
+
+# ---------------------------------------------------------------------------
+# P1: brute force on tiny arrays
+# ---------------------------------------------------------------------------
+
+def test_indices_match_incremental_walk_random_tilers():
+    rng = W.rng_for(1234)
+    for trial in range(300):
+        dr = int(rng.integers(0, 3))
+        rep = tuple(int(v) for v in rng.integers(1, 5, dr))
+        t = W.random_tiler(rng, dr)
+        want = walk_indices(rep, t)
+        got = oracle.indices(rep, t)
+        assert np.array_equal(got, want), (trial, rep, t)
+
+
+def test_indices_match_numpy_wrap_ravel_random_tilers():
+    rng = W.rng_for(99)
+    for trial in range(300):
+        dr = int(rng.integers(1, 4))
+        rep = tuple(int(v) for v in rng.integers(1, 6, dr))
+        t = W.random_tiler(rng, dr, max_side=7, max_origin=50)
+        assert np.array_equal(oracle.indices(rep, t), numpy_indices(rep, t)), (trial, t)
+
+
+def test_indices_hand_example_negative_origin():
+    # 1-D array of 5, origin -7, paving 3, fitting 2, pattern 3, 2 repetitions:
+    # r=0: -7,-5,-3 -> 3,0,2 ; r=1: -4,-2,0 -> 1,3,0   (floored modulo 5)
+    t = W.Tiler((5,), [-7], [[3]], [[2]], (3,))
+    assert oracle.indices((2,), t).tolist() == [[3, 0, 2], [1, 3, 0]]
+
+
+def test_indices_hand_example_2d_transposed_roles():
+    # array [2,3]; rep [3]; paving (0,1) walks columns; fitting (1,0) walks rows
+    t = W.Tiler((2, 3), [0, 0], [[0], [1]], [[1], [0]], (2,))
+    # r = column c: elements (0,c), (1,c) -> offsets c, 3 + c
+    assert oracle.indices((3,), t).tolist() == [[0, 3], [1, 4], [2, 5]]
+
+
+# ---------------------------------------------------------------------------
+# P2: exact cover of exact paving tilers; k^2 cover of stride-1 windows
+# ---------------------------------------------------------------------------
+
+def _hit_counts(rep, t):
+    idx = oracle.indices(rep, t).reshape(-1)
+    return np.bincount(idx, minlength=int(np.prod(t.array_shape)))
+
+
+def test_exact_cover_small_sum_tiler():
+    _, p = W.small_sum()
+    t = p.inputs[0]
+    assert np.prod(p.rep_shape) * np.prod(t.pattern_shape) == np.prod(t.array_shape)
+    assert np.all(_hit_counts(p.rep_shape, t) == 1)
+
+
+def test_exact_cover_two_stage_tilers_reduced():
+    ts = W.two_stage_filter(frames=2, rows=16, cols=32)
+    for p in (ts.h, ts.v):
+        t = p.inputs[0]
+        assert np.prod(p.rep_shape) * np.prod(t.pattern_shape) == np.prod(t.array_shape)
+        assert np.all(_hit_counts(p.rep_shape, t) == 1)
+
+
+@pytest.mark.parametrize("k", [3, 5, 7])
+def test_stride1_window_covers_each_element_k2_times(k):
+    p = W.filter2d_problem(11, 13, k, 1)
+    assert np.all(_hit_counts(p.rep_shape, p.inputs[0]) == k * k)
+
+
+def test_identity_output_tilers_single_assignment():
+    for rep in [(16, 16), (3, 5, 7)]:
+        t = W.identity_output(rep)
+        assert np.all(_hit_counts(rep, t) == 1)
+
+
+# ---------------------------------------------------------------------------
+# P3: identity-tiler copy; transposing copy
+# ---------------------------------------------------------------------------
+
+def test_identity_copy_is_bit_exact():
+    rng = W.rng_for(7)
+    x = W.random_array(rng, (5, 6, 7))
+    rep = x.shape
+    tin = W.identity_output(rep)
+    p = W.Problem(rep, [tin], W.identity_output(rep), W.COPY)
+    r = oracle.run(p, [x])
+    assert np.array_equal(r.out.astype(np.float32), x)
+    assert np.all(r.hits == 1)
+
+
+def test_copy_through_transposing_tiler():
+    rng = W.rng_for(8)
+    x = W.random_array(rng, (6, 9))
+    # rep [9,6]: r=(c,r0) reads x[r0,c]; writes B[c,r0]  -> B = x.T
+    tin = W.Tiler((6, 9), [0, 0], [[0, 1], [1, 0]], np.zeros((2, 0)), ())
+    p = W.Problem((9, 6), [tin], W.identity_output((9, 6)), W.COPY)
+    assert np.array_equal(oracle.run(p, [x]).out, x.T.astype(np.float64))
+
+
+def test_copy_pattern_block_scatter():
+    # each repetition copies a 2x3 block of x into a 2x3 block of B, blocks
+    # transposed in position: B block (j, i) <- x block (i, j)
+    rng = W.rng_for(9)
+    x = W.random_array(rng, (4, 9))          # 2 x 3 blocks of 2x3
+    tin = W.Tiler((4, 9), [0, 0], np.diag([2, 3]), np.eye(2, dtype=np.int64), (2, 3))
+    tout = W.Tiler((6, 6), [0, 0], [[0, 2], [3, 0]], np.eye(2, dtype=np.int64), (2, 3))
+    p = W.Problem((2, 3), [tin], tout, W.COPY)
+    r = oracle.run(p, [x])
+    want = np.zeros((6, 6))
+    for i in range(2):
+        for j in range(3):
+            want[2 * j:2 * j + 2, 3 * i:3 * i + 3] = x[2 * i:2 * i + 2, 3 * j:3 * j + 3]
+    assert np.array_equal(r.out, want)
+    assert np.all(r.hits == 1)
+
+
+def test_uncovered_output_keeps_prior():
+    x = np.arange(4, dtype=np.float32)
+    tin = W.Tiler((4,), [0], [[1]], np.zeros((1, 0)), ())
+    tout = W.Tiler((8,), [1], [[2]], np.zeros((1, 0)), ())     # writes 1,3,5,7
+    p = W.Problem((4,), [tin], tout, W.COPY)
+    prior = np.full(8, -5.0)
+    r = oracle.run(p, [x], prior=prior)
+    assert r.out.tolist() == [-5, 0, -5, 1, -5, 2, -5, 3]
+    assert r.hits.tolist() == [0, 1, 0, 1, 0, 1, 0, 1]
+
+
+def test_overlapping_output_counts_hits():
+    x = np.arange(6, dtype=np.float32)
+    tin = W.Tiler((6,), [0], [[1]], np.zeros((1, 0)), ())
+    tout = W.Tiler((3,), [0], [[1]], np.zeros((1, 0)), ())     # r and r+3 collide
+    p = W.Problem((6,), [tin], tout, W.COPY)
+    assert oracle.run(p, [x]).hits.tolist() == [2, 2, 2]
+
+
+# ---------------------------------------------------------------------------
+# P4: closed forms
+# ---------------------------------------------------------------------------
+
+def test_small_sum_equals_block_reshape_sum():
+    x, p = W.small_sum()
+    want = x.astype(np.float64).reshape(16, 4, 16, 4).sum(axis=(1, 3))
+    r = oracle.run(p, [x])
+    assert np.allclose(r.out, want, rtol=0, atol=1e-13)
+    assert np.allclose(r.abs_sum, np.abs(x.astype(np.float64)).reshape(16, 4, 16, 4).sum((1, 3)))
+
+
+def test_two_stage_equals_einsum():
+    ts = W.two_stage_filter(frames=2, rows=24, cols=48)
+    x = ts.x.astype(np.float64)
+    mid = np.einsum("fhwk,k->fhw", x.reshape(2, 24, 6, 8), ts.c_h.astype(np.float64))
+    out = np.einsum("fhkw,k->fhw", mid.reshape(2, 3, 8, 6), ts.c_v.astype(np.float64))
+    fw = oracle.chain_forward([ts.h, ts.v], ts.x)
+    assert np.allclose(fw[0].out, mid, rtol=0, atol=1e-14)
+    assert np.allclose(fw[1].out, out, rtol=0, atol=1e-14)
+
+
+def test_wrapped_fir_equals_roll():
+    # centred 13-tap horizontal filter with paving 8 (overlapping, wraps at both
+    # borders): y[f,h,w] = sum_k c[k] x[f,h,(8w - 6 + k) mod W]
+    taps, pave, o = 13, 8, -6
+    ts = W.two_stage_filter(frames=1, rows=3, cols=40, taps=taps, pave=pave, h_origin=o)
+    x = ts.x.astype(np.float64)
+    c = ts.c_h.astype(np.float64)
+    want = np.zeros((1, 3, 5))
+    for k in range(taps):
+        want += c[k] * np.roll(x, -(o + k), axis=2)[:, :, ::pave]
+    got = oracle.run(ts.h, [ts.x]).out
+    assert np.allclose(got, want, rtol=0, atol=1e-14)
+
+
+def _circular_filter_fft(x, c, o, s):
+    H, W_ = x.shape
+    k = c.shape[0]
+    cp = np.zeros((H, W_))
+    cp[:k, :k] = c
+    corr = np.real(np.fft.ifft2(np.fft.fft2(x) * np.conj(np.fft.fft2(cp))))
+    rows = (o + s * np.arange(-(-H // s))) % H
+    cols = (o + s * np.arange(-(-W_ // s))) % W_
+    return corr[np.ix_(rows, cols)]
+
+
+@pytest.mark.parametrize("H,W_,k,s", [(17, 23, 3, 1), (32, 20, 5, 2), (19, 33, 7, 4),
+                                      (40, 40, 9, 1), (9, 14, 9, 2)])
+def test_filter2d_equals_fft_circular_correlation(H, W_, k, s):
+    rng = W.rng_for(H * 1000 + W_)
+    x = rng.standard_normal((H, W_)).astype(np.float32)
+    c = (rng.uniform(-1, 1, (k, k)) / (k * k)).astype(np.float32)
+    p = W.filter2d_problem(H, W_, k, s, c)
+    want = _circular_filter_fft(x.astype(np.float64), c.astype(np.float64), -(k // 2), s)
+    got = oracle.run(p, [x]).out
+    assert np.allclose(got, want, rtol=0, atol=1e-12)
+
+
+def _naive_matmul(a, b):
+    M, K = a.shape
+    N = b.shape[1]
+    c = np.zeros((M, N))
+    for m in range(M):
+        for n in range(N):
+            acc = 0.0
+            for k in range(K):
+                acc += float(a[m, k]) * float(b[k, n])
+            c[m, n] = acc
+    return c
+
+
+def test_matmul_tilers_equal_naive_triple_loop():
+    a, b, _, _ = W.matmul_inputs(12, 10, 16, seed=5)
+    p = W.matmul_tilers(12, 10, 16)
+    got = oracle.run(p, [a, b]).out
+    assert np.allclose(got, _naive_matmul(a, b), rtol=0, atol=1e-12)
+
+
+def test_matmul_tilers_equal_blas_and_transposed_layout():
+    a, b, ab, bb = W.matmul_inputs(40, 24, 64, seed=6)
+    p = W.matmul_tilers(40, 24, 64)
+    assert np.allclose(oracle.run(p, [a, b]).out,
+                       a.astype(np.float64) @ b.astype(np.float64), rtol=0, atol=1e-11)
+    # BF16 bit patterns are widened exactly
+    got = oracle.run(p, [ab, bb]).out
+    want = W.bf16_bits_to_f32(ab).astype(np.float64) @ W.bf16_bits_to_f32(bb).astype(np.float64)
+    assert np.allclose(got, want, rtol=0, atol=1e-11)
+    # A stored transposed ([K, M]) : paving along columns, fitting along rows
+    at = np.ascontiguousarray(a.T)
+    ta = W.Tiler((64, 40), [0, 0], [[0, 0], [1, 0]], [[1], [0]], (64,))
+    pt = W.Problem((40, 24), [ta, p.inputs[1]], p.output, W.DOT)
+    assert np.allclose(oracle.run(pt, [at, b]).out,
+                       a.astype(np.float64) @ b.astype(np.float64), rtol=0, atol=1e-11)
+
+
+def test_run_sample_matches_run():
+    a, b, _, _ = W.matmul_inputs(20, 30, 40, seed=11)
+    p = W.matmul_tilers(20, 30, 40)
+    full = oracle.run(p, [a, b])
+    sel = np.array([0, 7, 599, 333, 42])
+    y, ya = oracle.run_sample(p, [a, b], sel)
+    assert np.array_equal(y[:, 0], full.out.reshape(-1)[sel])
+    assert np.array_equal(ya[:, 0], full.abs_sum.reshape(-1)[sel])
+
+
+# ---------------------------------------------------------------------------
+# P5: adjoint identity <T x, g> = <x, T^T g>, and the weight gradient by
+# linearity in the weights (forward with unit weights)
+# ---------------------------------------------------------------------------
+
+def test_adjoint_identity_random_tilers():
+    rng = W.rng_for(2024)
+    checked = 0
+    while checked < 60:
+        dr = int(rng.integers(1, 4))
+        rep = tuple(int(v) for v in rng.integers(1, 5, dr))
+        t = W.random_tiler(rng, dr, pattern_rank=int(rng.integers(0, 3)))
+        c = rng.uniform(-1, 1, t.pattern_shape).astype(np.float32)
+        p = W.Problem(rep, [t], W.identity_output(rep), W.WSUM, c)
+        x = W.random_array(rng, t.array_shape)
+        g = rng.uniform(-1, 1, rep)
+        tx = oracle.run(p, [x]).out
+        a = oracle.adjoint(p, x, g)
+        lhs = float(np.sum(tx * g))
+        rhs = float(np.sum(x.astype(np.float64) * a.gx))
+        assert abs(lhs - rhs) <= 1e-12 * (1 + np.sum(np.abs(tx * g))), (lhs, rhs)
+        # dL/dc_i of L = <T_c x, g> equals <T_{e_i} x, g>
+        npat = c.size
+        for i in range(npat):
+            e = np.zeros(npat, np.float32)
+            e[i] = 1.0
+            pe = W.Problem(rep, [t], W.identity_output(rep), W.WSUM, e.reshape(c.shape))
+            want = float(np.sum(oracle.run(pe, [x]).out * g))
+            assert abs(a.gc.reshape(-1)[i] - want) <= 1e-12 * (1 + abs(want))
+        checked += 1
+
+
+def test_adjoint_of_sum_is_broadcast():
+    x, p = W.small_sum()
+    g = W.rng_for(3).uniform(-1, 1, (16, 16))
+    a = oracle.adjoint(p, x, g)
+    want = np.repeat(np.repeat(g, 4, axis=0), 4, axis=1)
+    assert np.array_equal(a.gx, want)
+    assert a.gc is None
+
+
+# ---------------------------------------------------------------------------
+# P6: finite differences are exact for L = sum(w * out^2)
+# ---------------------------------------------------------------------------
+
+def _crop_problem():
+    """32x32 crop of the two-stage filter, treated as its own [1,32,32] array."""
+    ts = W.two_stage_filter(frames=1, rows=32, cols=32)
+    w = W.loss_weights((1, 4, 4))
+    return ts, w
+
+
+def _loss(stages, x):
+    fw = oracle.chain_forward(stages, x)
+    return fw
+
+
+def test_finite_differences_match_chain_adjoint():
+    ts, w = _crop_problem()
+    stages = [ts.h, ts.v]
+    x64 = ts.x.astype(np.float64)
+    adj = oracle.chain_adjoint(stages, x64, w)
+    h = 2.0 ** -4
+
+    def L(xv, ch, cv):
+        sh = W.Problem(ts.h.rep_shape, ts.h.inputs, ts.h.output, W.WSUM, ch)
+        sv = W.Problem(ts.v.rep_shape, ts.v.inputs, ts.v.output, W.WSUM, cv)
+        out = oracle.chain_forward([sh, sv], xv)[-1].out
+        return float(np.sum(w.astype(np.float64) * out * out))
+
+    ch = ts.c_h.astype(np.float64)
+    cv = ts.c_v.astype(np.float64)
+    base = L(x64, ch, cv)
+    assert abs(base - adj.loss) <= 1e-15 * abs(base)
+    flat = x64.reshape(-1)
+    gx_fd = np.zeros_like(flat)
+    for j in range(flat.size):
+        xp = flat.copy(); xp[j] += h
+        xm = flat.copy(); xm[j] -= h
+        gx_fd[j] = (L(xp.reshape(x64.shape), ch, cv) - L(xm.reshape(x64.shape), ch, cv)) / (2 * h)
+    assert np.allclose(adj.gx.reshape(-1), gx_fd, rtol=0, atol=1e-13)
+    for which, cvec in (("h", ch), ("v", cv)):
+        for k in range(8):
+            cp, cm = cvec.copy(), cvec.copy()
+            cp[k] += h
+            cm[k] -= h
+            if which == "h":
+                fd = (L(x64, cp, cv) - L(x64, cm, cv)) / (2 * h)
+                got = adj.gc[0][k]
+            else:
+                fd = (L(x64, ch, cp) - L(x64, ch, cm)) / (2 * h)
+                got = adj.gc[1][k]
+            assert abs(got - fd) <= 1e-12 * (1 + abs(fd)), (which, k, got, fd)
+
+
+def test_fused_closed_form_of_chain_gradient():
+    # gx[f,h,w] = c_h[w mod 8] c_v[h mod 8] gy[f, h//8, w//8], gy = 2 w out
+    ts = W.two_stage_filter(frames=2, rows=16, cols=24)
+    w = W.loss_weights((2, 2, 3))
+    adj = oracle.chain_adjoint([ts.h, ts.v], ts.x, w)
+    out = adj.forward[-1].out
+    gy = 2.0 * w.astype(np.float64) * out
+    ch = ts.c_h.astype(np.float64)
+    cv = ts.c_v.astype(np.float64)
+    want = np.einsum("fhw,a,b->fhawb", gy, cv, ch).reshape(2, 16, 24)
+    assert np.allclose(adj.gx, want, rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# inputs recipe sanity (shapes and seeds are deterministic)
+# ---------------------------------------------------------------------------
+
+def test_filter_batch_recipe_is_deterministic_and_in_range():
+    a = W.filter_batch(64, with_data=False)
+    b = W.filter_batch(64, with_data=True)
+    assert [(i.H, i.W, i.k, i.s) for i in a] == [(i.H, i.W, i.k, i.s) for i in b]
+    for i in b:
+        assert 32 <= i.H <= 2048 and 32 <= i.W <= 2048
+        assert i.k in (3, 5, 7, 9) and i.s in (1, 2, 4)
+        assert i.x.shape == (i.H, i.W) and i.coeffs.shape == (i.k, i.k)
+
+
+def test_bf16_rounding_is_rne():
+    v = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 1.0 + 2 ** -9, -2.5], np.float32)
+    r = W.bf16_bits_to_f32(W.f32_to_bf16_bits(v))
+    # 1+2^-8 is a tie -> even (1.0); 1+3*2^-8 tie -> even (1+2^-6)
+    assert r.tolist() == [1.0, 1.0, 1.0 + 2 ** -6, 1.0, -2.5]
