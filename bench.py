@@ -1,0 +1,279 @@
+#!/usr/bin/env python3
+"""Benchmark of the RSM repetitive-task hot path on one MI355X.
+
+Workload (the one the headline metric is quoted on): the two-stage
+downscaler-style filter on 30 frames of 1080x1920 FP32 -- an 8-tap
+horizontal weighted sum with paving 8, then an 8-tap vertical one -- run
+forward and through its adjoint (loss sum(w * out^2)), inputs resident in
+HBM.  One step = fused forward (input -> output, intermediate kept on chip)
++ dL/dout = 2 w out + fused adjoint (input gradient and both stages'
+weight gradients).
+
+  value      tiled elems/s: pattern elements gathered by every tiler of the
+             step (forward 69.98 M + adjoint 69.98 M per step) / step time
+  roofline   the adjoint kernel (the step's largest): algorithmic bytes per
+             launch (read x + dL/dout, write dL/dx) / its average duration,
+             measured with HIP events around each launch in the timed loop
+  cpu_baseline  the CPU oracle on a bounded sample of frames (single thread)
+
+Two copies of the input and of the input gradient alternate between steps so
+that the 256 MiB Infinity Cache does not serve repeated reads.
+
+Other measurements (matrix product on the matrix cores, batched vs plain
+2-D filters, unfused variants, the small 64x64 task) go under "extra".
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2516.6
+FP32_PEAK_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build runs every kernel on a single MI355X "
+              "and has no multi-GPU path (requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import rsm_workloads as W
+    from paper_1105_4424_amd import _abi, rsm
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+
+    F, H, Wd, T = 30, 1080, 1920, 8
+    log("generating inputs (30 x 1080 x 1920 FP32)")
+    ts = W.two_stage_filter(frames=F, rows=H, cols=Wd, taps=T)
+    w = W.loss_weights(ts.v.rep_shape)
+    stages = [ts.h, ts.v]
+    xs = [torch.from_numpy(ts.x).to(dev)]
+    xs.append(xs[0].clone())
+    ch = torch.from_numpy(ts.c_h).to(dev)
+    cv = torch.from_numpy(ts.c_v).to(dev)
+    w2 = (2.0 * torch.from_numpy(w)).to(dev)
+    out = torch.empty(ts.v.rep_shape, device=dev)
+    gy = torch.empty_like(out)
+    gxs = [torch.empty_like(xs[0]) for _ in range(2)]
+    gch = torch.empty(T, device=dev)
+    gcv = torch.empty(T, device=dev)
+    chain = rsm.Chain(stages, [ch, cv])
+
+    n_h = int(np.prod(ts.h.rep_shape)) * T
+    n_v = int(np.prod(ts.v.rep_shape)) * T
+    tiled_per_step = 2 * (n_h + n_v)
+    x_bytes = xs[0].numel() * 4
+    out_bytes = out.numel() * 4
+    fwd_bytes = x_bytes + out_bytes                  # read x, write out
+    adj_bytes = x_bytes + out_bytes + x_bytes        # read x, read dL/dout, write dL/dx
+
+    def step(k, ev=None):
+        x = xs[k & 1]
+        if ev is not None:
+            ev[0].record()
+        chain.forward(x, out)
+        if ev is not None:
+            ev[1].record()
+        torch.mul(w2, out, out=gy)
+        if ev is not None:
+            ev[2].record()
+        chain.adjoint(x, gy, gxs[k & 1], [gch, gcv])
+        if ev is not None:
+            ev[3].record()
+
+    log("warmup %d steps" % args.warmup)
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    log("timing %d steps" % args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(k, evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    fwd_us = float(np.mean([e[0].elapsed_time(e[1]) for e in evs])) * 1e3
+    adj_us = float(np.mean([e[2].elapsed_time(e[3]) for e in evs])) * 1e3
+    value = tiled_per_step / (ms_per_step * 1e-3)
+    adj_gbs = adj_bytes / (adj_us * 1e-6) / 1e9
+    fwd_gbs = fwd_bytes / (fwd_us * 1e-6) / 1e9
+    log("step %.3f ms | fused fwd %.1f us %.0f GB/s | fused adjoint %.1f us %.0f GB/s"
+        % (ms_per_step, fwd_us, fwd_gbs, adj_us, adj_gbs))
+
+    result = {
+        "metric": "tiled elems/s + HBM GB/s (fwd, adjoint); batched vs plain on 1 MI355X",
+        "value": value,
+        "unit": "tiled elems/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "two-stage 8-tap downscaler filter, fused forward + adjoint, "
+                               "30 frames 1080x1920 FP32", "frames": F, "rows": H, "cols": Wd,
+                   "taps": T, "paving": T, "tiled_elems_per_step": tiled_per_step,
+                   "hbm_bytes_per_step": fwd_bytes + adj_bytes},
+        "roofline": {"bound": "hbm", "achieved": adj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": adj_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "fir_chain_adjoint_kernel", "bytes_per_launch": adj_bytes,
+                     "avg_us": adj_us},
+        "extra": {"forward_fused": {"kernel": "fir_chain_kernel", "avg_us": fwd_us,
+                                    "bytes": fwd_bytes, "gbs": fwd_gbs,
+                                    "frac": fwd_gbs / HBM_PEAK_GBS},
+                  "adjoint_fused": {"avg_us": adj_us, "bytes": adj_bytes, "gbs": adj_gbs,
+                                    "frac": adj_gbs / HBM_PEAK_GBS}},
+    }
+
+    if not args.no_extra:
+        result["extra"].update(extras(args, ts, xs, stages, ch, cv, w2, chain))
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(args, W)
+
+    print(json.dumps(result), flush=True)
+
+
+def time_fn(fn, reps=20, warm=3):
+    import numpy as np
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev])) * 1e3
+
+
+def extras(args, ts, xs, stages, ch, cv, w2, chain):
+    import numpy as np
+    import torch
+
+    import rsm_workloads as W
+    from paper_1105_4424_amd import _abi, rsm
+
+    dev = xs[0].device
+    ex = {}
+    # unfused forward (two tap kernels, the intermediate written and re-read)
+    mid = torch.empty(ts.h.rep_shape, device=dev)
+    out = torch.empty(ts.v.rep_shape, device=dev)
+    gy = torch.empty_like(out)
+    state = {"k": 0}
+
+    def unfused_fwd():
+        k = state["k"] = state["k"] + 1
+        chain.forward(xs[k & 1], out, mids=[mid], flags=_abi.NO_FUSE)
+
+    us = time_fn(unfused_fwd)
+    b = xs[0].numel() * 4 + 2 * mid.numel() * 4 + out.numel() * 4
+    ex["forward_unfused"] = {"avg_us": us, "bytes": b, "gbs": b / us / 1e3, "frac": b / us / 1e3 / HBM_PEAK_GBS}
+    torch.mul(w2, out, out=gy)
+    gx = torch.empty_like(xs[0])
+    gch = torch.empty(8, device=dev)
+    gcv = torch.empty(8, device=dev)
+
+    def unfused_adj():
+        k = state["k"] = state["k"] + 1
+        chain.adjoint(xs[k & 1], gy, gx, [gch, gcv], mids=[mid], flags=_abi.NO_FUSE)
+
+    us = time_fn(unfused_adj)
+    b = (out.numel() + 2 * mid.numel() + 2 * xs[0].numel() + mid.numel() * 0) * 4 + mid.numel() * 4
+    ex["adjoint_unfused"] = {"avg_us": us, "bytes": b, "gbs": b / us / 1e3, "frac": b / us / 1e3 / HBM_PEAK_GBS}
+    log("unfused fwd %.1f us, unfused adjoint %.1f us" % (ex["forward_unfused"]["avg_us"], us))
+
+    # small plain task: 64x64 -> 16x16 sums
+    x0, p0 = W.small_sum()
+    xd = torch.from_numpy(x0).to(dev)
+    o0 = torch.empty((16, 16), device=dev)
+    ex["small_sum_64x64"] = {"avg_us": time_fn(lambda: rsm.run(p0, [xd], o0)), "kernel": rsm.plan(p0)}
+
+    # matrix product on the matrix cores
+    M = N = K = 4096
+    log("matrix product 4096^3")
+    a, bm, ab, bb = W.matmul_inputs(M, N, K)
+    pm = W.matmul_tilers(M, N, K)
+    da = torch.from_numpy(ab.view(np.int16)).view(torch.bfloat16).to(dev)
+    db = torch.from_numpy(bb.view(np.int16)).view(torch.bfloat16).to(dev)
+    cm = torch.empty((M, N), device=dev)
+    pm.compute = "bf16"
+    us = time_fn(lambda: rsm.run(pm, [da, db], cm))
+    tf = 2.0 * M * N * K / us / 1e6
+    ex["matmul_bf16_4096"] = {"avg_us": us, "tflops": tf, "frac": tf / BF16_PEAK_TFLOPS,
+                              "kernel": rsm.plan(pm, dtypes=(torch.bfloat16,))}
+    pm.compute = "f32"
+    fa = torch.from_numpy(a).to(dev)
+    fb = torch.from_numpy(bm).to(dev)
+    us = time_fn(lambda: rsm.run(pm, [fa, fb], cm), reps=10)
+    tf = 2.0 * M * N * K / us / 1e6
+    ex["matmul_f32_4096"] = {"avg_us": us, "tflops": tf, "frac": tf / FP32_PEAK_TFLOPS,
+                             "kernel": rsm.plan(pm)}
+    log("matmul bf16 %.1f TF/s, f32 %.1f TF/s" % (ex["matmul_bf16_4096"]["tflops"], tf))
+    del da, db, fa, fb, cm
+    return ex
+
+
+def cpu_baseline(args, W):
+    """The oracle (plain C, FP64, one thread) on a bounded sample of frames of
+    the same workload: forward of both stages and their adjoint."""
+    import numpy as np
+
+    import oracle
+
+    def run_frames(n):
+        ts = W.two_stage_filter(frames=n)
+        w = W.loss_weights(ts.v.rep_shape)
+        t0 = time.perf_counter()
+        oracle.chain_adjoint([ts.h, ts.v], ts.x, w)
+        return time.perf_counter() - t0
+
+    log("cpu baseline: oracle on 1 frame")
+    t1 = run_frames(1)
+    n = int(max(1, min(30, args.cpu_seconds / max(t1, 1e-3))))
+    log("cpu baseline: oracle on %d frames" % n)
+    tn = run_frames(n) if n > 1 else t1
+    per_frame_tiled = 2 * (1080 * 240 * 8 + 135 * 240 * 8)
+    return {"value": n * per_frame_tiled / tn, "unit": "tiled elems/s", "cores": 1,
+            "kind": "oracle", "seconds": tn,
+            "sample": "%d of 30 frames (1080x1920), forward of both stages + adjoint, FP64 C oracle, "
+                      "single thread; host has %d hardware threads" % (n, os.cpu_count() or 0)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,247 @@
+/*
+ * rsm.h -- C-ABI of librsm: RSM repetitive tasks on one MI355X (gfx950).
+ *
+ * A repetitive task (MARTE Repetitive Structure Modeling; the paper relies on
+ * it for its repetitive operations, Sec. 3 and Sec. 7, and on its Shaped
+ * multiplicity for the repetition space, Sec. 6.1) is
+ *
+ *   for every r in the repetition space (shape s_r, row-major):
+ *     pat_t(r)[i] = A_t[ (o_t + P_t r + F_t i) mod s_t ]      gather, per input tiler t
+ *     y(r)        = task(pat_1(r), pat_2(r))                  elementary task
+ *     B[ (o_b + P_b r + F_b j) mod s_b ] = y(r)[j]            scatter, output tiler
+ *
+ * The modulo is componentwise and floored (results in [0, s_d) also for
+ * negative operands).  Arrays are dense and row-major (dimension 0 slowest).
+ * P has one column per repetition dimension and F one column per pattern
+ * dimension; both are stored row-major with leading dimension RSM_MAX_RANK:
+ * entry (d, k) is at [d][k].
+ *
+ * The buffer descriptor follows the paper's DataAllocate class (Sec. 5):
+ * baseAddress -> device pointer, dimAllocation -> array_shape,
+ * typeAllocation -> dtype, spaceAddress -> always device global memory (HBM).
+ * Port direction (Sec. 6.3) maps to const pointers for inputs.
+ *
+ * Conventions for every call below:
+ *  - Ownership: the caller owns every buffer passed in.  The library owns only
+ *    opaque handles (rsm_batch) and an internal device workspace that it
+ *    grows on demand (used by the adjoint's weight-gradient reduction and by
+ *    unfused chains); descriptor structs are copied at call time.
+ *  - Streams: compute calls are asynchronous on the given hipStream_t (NULL =
+ *    the null stream).  Errors detectable on the host are returned before any
+ *    launch, with nothing written.  A failed HIP call returns RSM_E_HIP; the
+ *    detail is in rsm_last_error().
+ *  - Output elements that the output tiler does not reach are left untouched.
+ *    Calls whose output tiler writes an element twice race on it; request
+ *    RSM_CHECK_SINGLE_ASSIGN to have the host reject such tilers.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef RSM_H
+#define RSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RSM_MAX_RANK 8
+#define RSM_ABI_VERSION 1
+
+typedef enum {
+  RSM_OK = 0,
+  RSM_E_INVALID = 1,     /* null pointer, bad enum, inconsistent arguments     */
+  RSM_E_RANK = 2,        /* a rank outside [0, RSM_MAX_RANK]                    */
+  RSM_E_SHAPE = 3,       /* non-positive extent, shapes that do not agree       */
+  RSM_E_OVERFLOW = 4,    /* index arithmetic would not fit in 62 bits           */
+  RSM_E_OVERLAP = 5,     /* output tiler writes an element twice (when checked) */
+  RSM_E_UNSUPPORTED = 6, /* valid request that no kernel of this build handles  */
+  RSM_E_HIP = 7,         /* a HIP runtime call failed                           */
+  RSM_E_NOMEM = 8        /* device or host allocation failed                    */
+} rsm_status;
+
+typedef enum { RSM_F32 = 0, RSM_BF16 = 1, RSM_F64 = 2, RSM_I64 = 3 } rsm_dtype;
+
+typedef enum {
+  RSM_TASK_COPY = 0, /* y(r)[j] = pat(r)[j]; |in pattern| == |out pattern|, same dtype */
+  RSM_TASK_SUM = 1,  /* y(r) = sum_i pat(r)[i]                                         */
+  RSM_TASK_WSUM = 2, /* y(r) = sum_i c[i] pat(r)[i]; c pattern-shaped                  */
+  RSM_TASK_DOT = 3   /* y(r) = sum_i pat_1(r)[i] pat_2(r)[i]; two input tilers         */
+} rsm_task_kind;
+
+/* Flags. */
+#define RSM_CHECK_SINGLE_ASSIGN 0x1u /* host check: no output element written twice   */
+#define RSM_ACCUMULATE 0x2u          /* adjoint: add into gx / gc instead of overwrite */
+#define RSM_NO_FUSE 0x4u             /* chains: run stages one by one                  */
+#define RSM_FORCE_GENERIC 0x8u       /* use the generic gather kernel (any tiler)      */
+
+/* Repetition space: the Shaped multiplicity of the repeated task. rank 0 = one repetition. */
+typedef struct {
+  int32_t rank;
+  int32_t reserved;
+  int64_t shape[RSM_MAX_RANK];
+} rsm_space;
+
+/* One array and the tiler that reads or writes it. */
+typedef struct {
+  int32_t array_rank;                              /* d_a                              */
+  int32_t dtype;                                   /* rsm_dtype of the array elements  */
+  int64_t array_shape[RSM_MAX_RANK];               /* s (all > 0)                      */
+  int32_t pattern_rank;                            /* d_p; 0 = scalar pattern          */
+  int32_t reserved;
+  int64_t pattern_shape[RSM_MAX_RANK];             /* s_p (all > 0)                    */
+  int64_t origin[RSM_MAX_RANK];                    /* o, any sign                      */
+  int64_t paving[RSM_MAX_RANK][RSM_MAX_RANK];      /* P: [d][k], d < d_a, k < d_r      */
+  int64_t fitting[RSM_MAX_RANK][RSM_MAX_RANK];     /* F: [d][k], d < d_a, k < d_p      */
+} rsm_tiler;
+
+/* Elementary task. */
+typedef struct {
+  int32_t kind;        /* rsm_task_kind                                                 */
+  int32_t compute;     /* RSM_F32: FP32 arithmetic (F32 arrays, or BF16 arrays widened);
+                          RSM_BF16: BF16 products with FP32 accumulation (DOT on BF16
+                          arrays: the matrix-core path); RSM_F64: FP64 arrays             */
+  const void* coeffs;  /* WSUM: device pointer, pattern-shaped, FP32 (FP64 if compute
+                          is RSM_F64); ignored otherwise                                */
+} rsm_task;
+
+/* One stage of a chain: stage k reads array k and writes array k+1. */
+typedef struct {
+  rsm_space rep;
+  rsm_tiler in;
+  rsm_tiler out;
+  rsm_task task;
+} rsm_stage;
+
+/*
+ * rsm_validate -- host-only check of a task description (no device access).
+ * Checks ranks, extents, dtypes, task/pattern agreement, 62-bit index range,
+ * and with RSM_CHECK_SINGLE_ASSIGN that the output tiler writes each element
+ * at most once (costs O(|s_r| |s_p|) host time and |s_out| bytes of memory).
+ */
+rsm_status rsm_validate(const rsm_space* rep, const rsm_tiler* in, int32_t n_in,
+                        const rsm_tiler* out, const rsm_task* task, uint32_t flags);
+
+/*
+ * rsm_plan -- name of the kernel family the planner picks for a task
+ * (e.g. "fir_h_vec4", "pattern_reduce", "gemm_mfma_bf16", "generic").
+ * Host only.  Writes a NUL-terminated string of at most len bytes.
+ */
+rsm_status rsm_plan(const rsm_space* rep, const rsm_tiler* in, int32_t n_in,
+                    const rsm_tiler* out, const rsm_task* task, uint32_t flags,
+                    char* name, int32_t len);
+
+/*
+ * rsm_indices -- the index table of one tiler (the index step of the
+ * definition above): d_idx[r * |s_p| + i] = linear offset of e(r, i) in the
+ * tiler's array, int64, r and i flat row-major.  d_idx is a device buffer of
+ * |s_r| * |s_p| int64 elements.
+ */
+rsm_status rsm_indices(const rsm_space* rep, const rsm_tiler* t, int64_t* d_idx,
+                       void* hip_stream);
+
+/*
+ * rsm_run -- one repetitive task.  d_in is a HOST array of n_in DEVICE
+ * pointers (one per input tiler, in order); d_out is the output array.
+ * Task/dtype combinations: COPY any dtype (bit-exact, output dtype = input
+ * dtype); SUM/WSUM on F32 or BF16 arrays computed in FP32 (F64 in FP64) with
+ * an F32 (F64) output; DOT on two F32 arrays (FP32), two BF16 arrays (compute
+ * BF16: FP32 accumulation, F32 output) or two F64 arrays.
+ */
+rsm_status rsm_run(const rsm_space* rep, const rsm_tiler* in, const void* const* d_in,
+                   int32_t n_in, const rsm_tiler* out, void* d_out, const rsm_task* task,
+                   uint32_t flags, void* hip_stream);
+
+/*
+ * rsm_run_chain -- n_stages single-input tasks where stage k's output array
+ * is stage k+1's input array (stage k's out tiler and stage k+1's in tiler
+ * describe the same array).  d_mid is a HOST array of n_stages-1 DEVICE
+ * pointers for the intermediate arrays.  When the planner can fuse two
+ * consecutive weighted-sum stages (1-D patterns along different axes, identity
+ * output tilers) and d_mid is NULL or d_mid[k] is NULL, the intermediate is
+ * never written to memory; otherwise every d_mid[k] must be given and is
+ * written.  RSM_NO_FUSE forces stage-by-stage execution.
+ */
+rsm_status rsm_run_chain(const rsm_stage* stages, int32_t n_stages, const void* d_in,
+                         void* const* d_mid, void* d_out, uint32_t flags, void* hip_stream);
+
+/*
+ * rsm_run_adjoint -- adjoint of a SUM or WSUM task with a scalar output
+ * pattern (the task is linear in its input and in its weights):
+ *   gx[e_in(r,i)] = sum over (r,i) hitting it of c[i] * gy[e_out(r)]
+ *   gc[i]         = sum_r gy[e_out(r)] * x[e_in(r,i)]
+ * d_x: the task's input array (needed for gc only; may be NULL if d_gc is
+ * NULL).  d_gy: gradient w.r.t. the output array.  d_gx (input-array shaped)
+ * and d_gc (pattern-shaped, WSUM only) are FP32 device buffers, each NULL to
+ * skip it.  Without RSM_ACCUMULATE they are overwritten (gx elements no
+ * repetition reads become 0); with it the result is added.  The weight
+ * gradient is reduced deterministically (fixed-order tree); gx is
+ * deterministic except on the generic path for tilers whose reads overlap,
+ * which adds with atomics.
+ */
+rsm_status rsm_run_adjoint(const rsm_space* rep, const rsm_tiler* in, const void* d_x,
+                           const rsm_tiler* out, const void* d_gy, const rsm_task* task,
+                           void* d_gx, void* d_gc, uint32_t flags, void* hip_stream);
+
+/*
+ * rsm_run_chain_adjoint -- adjoint of a chain of SUM/WSUM stages.
+ * d_in: the chain's input array; d_mid: forward intermediates (HOST array of
+ * DEVICE pointers; may be NULL when the pair is fused: the intermediate is
+ * recomputed on chip); d_gy: gradient w.r.t. the last output; d_gx: gradient
+ * w.r.t. d_in (nullable); d_gc: HOST array of n_stages DEVICE pointers to
+ * per-stage weight gradients (array nullable, entries nullable).
+ */
+rsm_status rsm_run_chain_adjoint(const rsm_stage* stages, int32_t n_stages, const void* d_in,
+                                 const void* const* d_mid, const void* d_gy, void* d_gx,
+                                 void* const* d_gc, uint32_t flags, void* hip_stream);
+
+/*
+ * Batched execution of many independent single-input tasks in one launch.
+ * rsm_batch_create copies the descriptions, chooses a tile shape per problem
+ * (timing candidates on the given stream unless the tuning cache at
+ * tune_cache_path, NULL = none, already holds the choice; the cache is
+ * rewritten with new choices), uploads a device descriptor table, and
+ * returns an opaque handle.  Problems that the persistent kernel does not
+ * handle run through rsm_run inside the same rsm_batch_run call.
+ * rsm_batch_run captures one HIP graph holding the persistent launch on its
+ * first call and replays it afterwards (the device pointers given at create
+ * time are used every time).  rsm_batch_destroy frees the handle.
+ */
+typedef struct {
+  rsm_space rep;
+  rsm_tiler in;
+  rsm_tiler out;
+  rsm_task task;
+  const void* d_in;
+  void* d_out;
+} rsm_problem;
+
+typedef struct rsm_batch_s* rsm_batch;
+
+typedef struct {
+  int64_t n_problems;      /* problems in the batch                              */
+  int64_t n_persistent;    /* of which handled by the persistent kernel          */
+  int64_t n_tiles;         /* tiles in the persistent kernel's queue             */
+  int64_t grid;            /* persistent workgroups launched                     */
+  int64_t tuned_classes;   /* problem classes timed during create (cache misses) */
+  int64_t cached_classes;  /* problem classes taken from the cache               */
+} rsm_batch_info;
+
+rsm_status rsm_batch_create(const rsm_problem* problems, int32_t n, const char* tune_cache_path,
+                            uint32_t flags, void* hip_stream, rsm_batch* out);
+rsm_status rsm_batch_run(rsm_batch b, void* hip_stream);
+rsm_status rsm_batch_query(rsm_batch b, rsm_batch_info* info);
+rsm_status rsm_batch_destroy(rsm_batch b);
+
+/* Tile shape chosen for problem k of a batch (rows, cols of outputs per tile). */
+rsm_status rsm_batch_tile(rsm_batch b, int32_t k, int32_t* tile_rows, int32_t* tile_cols);
+
+const char* rsm_status_string(rsm_status s);
+const char* rsm_last_error(void); /* thread-local detail of the last failing call */
+int32_t rsm_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSM_H */

@@ -1,0 +1,116 @@
+"""ctypes mirror of include/rsm.h and the loader of librsm.so.
+
+Argument marshalling only: every computation runs in librsm's HIP kernels.
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+MAX_RANK = 8
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "librsm.so")
+
+# rsm_status
+OK, E_INVALID, E_RANK, E_SHAPE, E_OVERFLOW, E_OVERLAP, E_UNSUPPORTED, E_HIP, E_NOMEM = range(9)
+# rsm_dtype
+F32, BF16, F64, I64 = 0, 1, 2, 3
+# rsm_task_kind
+TASK_COPY, TASK_SUM, TASK_WSUM, TASK_DOT = 0, 1, 2, 3
+# flags
+CHECK_SINGLE_ASSIGN = 0x1
+ACCUMULATE = 0x2
+NO_FUSE = 0x4
+FORCE_GENERIC = 0x8
+
+I64x8 = ctypes.c_int64 * MAX_RANK
+I64x8x8 = (ctypes.c_int64 * MAX_RANK) * MAX_RANK
+
+
+class Space(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int32), ("reserved", ctypes.c_int32), ("shape", I64x8)]
+
+
+class Tiler(ctypes.Structure):
+    _fields_ = [
+        ("array_rank", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("array_shape", I64x8),
+        ("pattern_rank", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("pattern_shape", I64x8),
+        ("origin", I64x8),
+        ("paving", I64x8x8),
+        ("fitting", I64x8x8),
+    ]
+
+
+class Task(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("compute", ctypes.c_int32), ("coeffs", ctypes.c_void_p)]
+
+
+class Stage(ctypes.Structure):
+    _fields_ = [("rep", Space), ("in_", Tiler), ("out", Tiler), ("task", Task)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("rep", Space), ("in_", Tiler), ("out", Tiler), ("task", Task),
+                ("d_in", ctypes.c_void_p), ("d_out", ctypes.c_void_p)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("n_problems", ctypes.c_int64), ("n_persistent", ctypes.c_int64),
+                ("n_tiles", ctypes.c_int64), ("grid", ctypes.c_int64),
+                ("tuned_classes", ctypes.c_int64), ("cached_classes", ctypes.c_int64)]
+
+
+EXPORTS = [
+    "rsm_validate", "rsm_plan", "rsm_indices", "rsm_run", "rsm_run_chain", "rsm_run_adjoint",
+    "rsm_run_chain_adjoint", "rsm_batch_create", "rsm_batch_run", "rsm_batch_query",
+    "rsm_batch_tile", "rsm_batch_destroy", "rsm_status_string", "rsm_last_error",
+    "rsm_abi_version",
+]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load librsm.so and declare its signatures (raises if it is not built)."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("librsm.so is not built (%s); run __graft_entry__.build() or "
+                           "python -m paper_1105_4424_amd.build" % path)
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    st = ctypes.c_int
+    u32 = ctypes.c_uint32
+    i32 = ctypes.c_int32
+    lib.rsm_validate.argtypes = [P(Space), P(Tiler), i32, P(Tiler), P(Task), u32]
+    lib.rsm_plan.argtypes = [P(Space), P(Tiler), i32, P(Tiler), P(Task), u32, ctypes.c_char_p, i32]
+    lib.rsm_indices.argtypes = [P(Space), P(Tiler), vp, vp]
+    lib.rsm_run.argtypes = [P(Space), P(Tiler), P(vp), i32, P(Tiler), vp, P(Task), u32, vp]
+    lib.rsm_run_chain.argtypes = [P(Stage), i32, vp, P(vp), vp, u32, vp]
+    lib.rsm_run_adjoint.argtypes = [P(Space), P(Tiler), vp, P(Tiler), vp, P(Task), vp, vp, u32, vp]
+    lib.rsm_run_chain_adjoint.argtypes = [P(Stage), i32, vp, P(vp), vp, vp, P(vp), u32, vp]
+    lib.rsm_batch_create.argtypes = [P(Problem), i32, ctypes.c_char_p, u32, vp, P(vp)]
+    lib.rsm_batch_run.argtypes = [vp, vp]
+    lib.rsm_batch_query.argtypes = [vp, P(BatchInfo)]
+    lib.rsm_batch_tile.argtypes = [vp, i32, P(i32), P(i32)]
+    lib.rsm_batch_destroy.argtypes = [vp]
+    for name in ("rsm_validate", "rsm_plan", "rsm_indices", "rsm_run", "rsm_run_chain",
+                 "rsm_run_adjoint", "rsm_run_chain_adjoint", "rsm_batch_create", "rsm_batch_run",
+                 "rsm_batch_query", "rsm_batch_tile", "rsm_batch_destroy"):
+        getattr(lib, name).restype = st
+    lib.rsm_status_string.argtypes = [st]
+    lib.rsm_status_string.restype = ctypes.c_char_p
+    lib.rsm_last_error.argtypes = []
+    lib.rsm_last_error.restype = ctypes.c_char_p
+    lib.rsm_abi_version.argtypes = []
+    lib.rsm_abi_version.restype = i32
+    if path == LIB_PATH:
+        _lib = lib
+    return lib

@@ -1,0 +1,1018 @@
+// api.cpp -- C-ABI entry points, validation and the kernel planner.
+//
+// Every entry point validates its descriptors on the host, reduces each
+// tiler to a canonical descriptor, picks a kernel family and launches it on
+// the caller's stream.  No exception leaves this file.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rsm_internal.h"
+
+namespace rsm {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+rsm_status fail(rsm_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+rsm_status hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  return RSM_E_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// workspace: one grow-only device buffer per device
+// ---------------------------------------------------------------------------
+namespace {
+struct Workspace {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+std::mutex g_ws_mutex;
+Workspace g_ws[64];
+}  // namespace
+
+// Layout: [256 bytes: completion counter, kept at zero between kernels][data]
+void* workspace(size_t bytes, hipStream_t /*st*/, rsm_status* err, uint32_t** counter) {
+  *err = RSM_OK;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    *err = hip_fail(e, "hipGetDevice");
+    return nullptr;
+  }
+  if (dev < 0 || dev >= 64) {
+    *err = fail(RSM_E_UNSUPPORTED, "device index beyond 63");
+    return nullptr;
+  }
+  constexpr size_t kHead = 256;
+  std::lock_guard<std::mutex> lock(g_ws_mutex);
+  Workspace& w = g_ws[dev];
+  if (!(w.ptr && w.bytes >= bytes)) {
+    size_t want = bytes < (size_t(1) << 20) ? (size_t(1) << 20) : bytes;
+    if (w.ptr) {
+      // earlier launches on any stream may still use the old buffer
+      e = hipDeviceSynchronize();
+      if (e != hipSuccess) {
+        *err = hip_fail(e, "hipDeviceSynchronize (workspace growth)");
+        return nullptr;
+      }
+      (void)hipFree(w.ptr);
+      w.ptr = nullptr;
+      w.bytes = 0;
+    }
+    e = hipMalloc(&w.ptr, want + kHead);
+    if (e != hipSuccess) {
+      w.ptr = nullptr;
+      *err = fail(RSM_E_NOMEM, std::string("workspace hipMalloc failed: ") + hipGetErrorString(e));
+      return nullptr;
+    }
+    e = hipMemset(w.ptr, 0, kHead);
+    if (e != hipSuccess) {
+      *err = hip_fail(e, "hipMemset (workspace counter)");
+      return nullptr;
+    }
+    w.bytes = want;
+  }
+  if (counter) *counter = static_cast<uint32_t*>(w.ptr);
+  return static_cast<char*>(w.ptr) + kHead;
+}
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t kLimit62 = int64_t(1) << 62;
+
+bool mul_ok(int64_t a, int64_t b, int64_t* out) {
+  int64_t r;
+  if (__builtin_mul_overflow(a, b, &r) || r >= kLimit62 || r <= -kLimit62) return false;
+  *out = r;
+  return true;
+}
+
+int64_t floor_mod(int64_t a, int64_t m) {
+  int64_t q = a % m;
+  return q < 0 ? q + m : q;
+}
+
+bool dtype_ok(int32_t d) { return d == RSM_F32 || d == RSM_BF16 || d == RSM_F64 || d == RSM_I64; }
+
+int elem_size(int32_t d) {
+  switch (d) {
+    case RSM_F32: return 4;
+    case RSM_BF16: return 2;
+    case RSM_F64: return 8;
+    case RSM_I64: return 8;
+  }
+  return 0;
+}
+
+int64_t prod(const int64_t* v, int n) {
+  int64_t p = 1;
+  for (int k = 0; k < n; ++k) p *= v[k];
+  return p;
+}
+
+rsm_status check_space(const rsm_space* rep, int64_t* n_rep) {
+  if (!rep) return fail(RSM_E_INVALID, "repetition space is NULL");
+  if (rep->rank < 0 || rep->rank > RSM_MAX_RANK)
+    return fail(RSM_E_RANK, "repetition rank " + std::to_string(rep->rank) + " outside [0, 8]");
+  int64_t n = 1;
+  for (int k = 0; k < rep->rank; ++k) {
+    if (rep->shape[k] < 0)
+      return fail(RSM_E_SHAPE, "negative repetition extent in dimension " + std::to_string(k));
+    if (!mul_ok(n, rep->shape[k], &n))
+      return fail(RSM_E_OVERFLOW, "repetition space has more than 2^62 points");
+  }
+  *n_rep = n;
+  return RSM_OK;
+}
+
+rsm_status check_tiler(const rsm_tiler* t, const rsm_space* rep, const char* name,
+                       int64_t* n_pat) {
+  const std::string who(name);
+  if (!t) return fail(RSM_E_INVALID, who + " tiler is NULL");
+  if (t->array_rank < 0 || t->array_rank > RSM_MAX_RANK)
+    return fail(RSM_E_RANK, who + ": array rank " + std::to_string(t->array_rank) + " outside [0, 8]");
+  if (t->pattern_rank < 0 || t->pattern_rank > RSM_MAX_RANK)
+    return fail(RSM_E_RANK, who + ": pattern rank " + std::to_string(t->pattern_rank) + " outside [0, 8]");
+  if (!dtype_ok(t->dtype)) return fail(RSM_E_INVALID, who + ": unknown dtype");
+  int64_t n_arr = 1;
+  for (int d = 0; d < t->array_rank; ++d) {
+    if (t->array_shape[d] <= 0)
+      return fail(RSM_E_SHAPE, who + ": array extent " + std::to_string(d) + " is not positive");
+    if (!mul_ok(n_arr, t->array_shape[d], &n_arr))
+      return fail(RSM_E_OVERFLOW, who + ": array has more than 2^62 elements");
+  }
+  int64_t np = 1;
+  for (int k = 0; k < t->pattern_rank; ++k) {
+    if (t->pattern_shape[k] <= 0)
+      return fail(RSM_E_SHAPE, who + ": pattern extent " + std::to_string(k) + " is not positive");
+    if (!mul_ok(np, t->pattern_shape[k], &np))
+      return fail(RSM_E_OVERFLOW, who + ": pattern has more than 2^62 elements");
+  }
+  // Reduced steps are < s_d; the walk multiplies them by indices below the
+  // repetition / pattern extents and adds up to 16 such terms.
+  for (int d = 0; d < t->array_rank; ++d) {
+    const int64_t s = t->array_shape[d];
+    int64_t tmp;
+    for (int k = 0; k < rep->rank; ++k)
+      if (!mul_ok(s, rep->shape[k] + 1, &tmp) || !mul_ok(tmp, 16, &tmp))
+        return fail(RSM_E_OVERFLOW, who + ": paving arithmetic would exceed 62 bits");
+    for (int k = 0; k < t->pattern_rank; ++k)
+      if (!mul_ok(s, t->pattern_shape[k] + 1, &tmp) || !mul_ok(tmp, 16 * 64, &tmp))
+        return fail(RSM_E_OVERFLOW, who + ": fitting arithmetic would exceed 62 bits");
+  }
+  *n_pat = np;
+  return RSM_OK;
+}
+
+// e(r, i) on the host (used by the single-assignment check only)
+int64_t host_offset(const rsm_tiler& t, int rep_rank, const int64_t* r, const int64_t* i) {
+  int64_t lin = 0;
+  for (int d = 0; d < t.array_rank; ++d) {
+    const int64_t s = t.array_shape[d];
+    int64_t v = floor_mod(t.origin[d], s);
+    for (int k = 0; k < rep_rank; ++k) v = (v + floor_mod(t.paving[d][k], s) * r[k] % s) % s;
+    for (int k = 0; k < t.pattern_rank; ++k) v = (v + floor_mod(t.fitting[d][k], s) * i[k] % s) % s;
+    lin = lin * s + v;
+  }
+  return lin;
+}
+
+rsm_status check_single_assign(const rsm_space& rep, const rsm_tiler& out, int64_t n_rep,
+                               int64_t n_pat) {
+  const int64_t n_out = prod(out.array_shape, out.array_rank);
+  if (n_out > (int64_t(1) << 33))
+    return fail(RSM_E_UNSUPPORTED, "single-assignment check limited to 2^33 output elements");
+  std::vector<uint8_t> hit(size_t(n_out), 0);
+  int64_t r[RSM_MAX_RANK] = {0}, i[RSM_MAX_RANK] = {0};
+  for (int64_t rf = 0; rf < n_rep; ++rf) {
+    int64_t f = rf;
+    for (int k = rep.rank - 1; k >= 0; --k) { r[k] = f % rep.shape[k]; f /= rep.shape[k]; }
+    for (int64_t pf = 0; pf < n_pat; ++pf) {
+      int64_t g = pf;
+      for (int k = out.pattern_rank - 1; k >= 0; --k) { i[k] = g % out.pattern_shape[k]; g /= out.pattern_shape[k]; }
+      const int64_t e = host_offset(out, rep.rank, r, i);
+      if (hit[size_t(e)]) return fail(RSM_E_OVERLAP, "output tiler writes element " + std::to_string(e) + " twice");
+      hit[size_t(e)] = 1;
+    }
+  }
+  return RSM_OK;
+}
+
+struct Checked {
+  int64_t n_rep = 0;
+  int64_t n_pat_in[2] = {0, 0};
+  int64_t n_pat_out = 0;
+};
+
+rsm_status check_task(const rsm_space* rep, const rsm_tiler* in, int32_t n_in, const rsm_tiler* out,
+                      const rsm_task* task, uint32_t flags, Checked* c) {
+  rsm_status s = check_space(rep, &c->n_rep);
+  if (s) return s;
+  if (!task) return fail(RSM_E_INVALID, "task is NULL");
+  if (task->kind < RSM_TASK_COPY || task->kind > RSM_TASK_DOT)
+    return fail(RSM_E_INVALID, "unknown task kind " + std::to_string(task->kind));
+  if (!in) return fail(RSM_E_INVALID, "input tilers are NULL");
+  const int need = task->kind == RSM_TASK_DOT ? 2 : 1;
+  if (n_in != need)
+    return fail(RSM_E_INVALID, "task needs " + std::to_string(need) + " input tiler(s), got " + std::to_string(n_in));
+  for (int t = 0; t < n_in; ++t) {
+    s = check_tiler(&in[t], rep, t ? "input 1" : "input 0", &c->n_pat_in[t]);
+    if (s) return s;
+  }
+  s = check_tiler(out, rep, "output", &c->n_pat_out);
+  if (s) return s;
+  const int32_t dt = in[0].dtype;
+  if (task->kind == RSM_TASK_COPY) {
+    if (c->n_pat_in[0] != c->n_pat_out)
+      return fail(RSM_E_SHAPE, "COPY: input and output patterns differ in size");
+    if (out->dtype != dt) return fail(RSM_E_INVALID, "COPY: output dtype differs from input dtype");
+  } else {
+    if (c->n_pat_out != 1) return fail(RSM_E_SHAPE, "reducing task needs a single-element output pattern");
+    if (dt == RSM_I64) return fail(RSM_E_UNSUPPORTED, "arithmetic on int64 arrays is not supported");
+    if (task->kind == RSM_TASK_DOT) {
+      if (in[1].dtype != dt) return fail(RSM_E_INVALID, "DOT: the two inputs differ in dtype");
+      if (c->n_pat_in[0] != c->n_pat_in[1]) return fail(RSM_E_SHAPE, "DOT: patterns differ in size");
+    }
+    const int32_t want_out = dt == RSM_F64 ? RSM_F64 : RSM_F32;
+    if (out->dtype != want_out)
+      return fail(RSM_E_INVALID, dt == RSM_F64 ? "FP64 task needs an F64 output" : "task needs an F32 output");
+    if (task->compute == RSM_F64 && dt != RSM_F64)
+      return fail(RSM_E_INVALID, "compute F64 needs F64 arrays");
+    if (dt == RSM_F64 && task->compute != RSM_F64)
+      return fail(RSM_E_INVALID, "F64 arrays need compute F64");
+    if (task->compute == RSM_BF16 && (task->kind != RSM_TASK_DOT || dt != RSM_BF16))
+      return fail(RSM_E_INVALID, "compute BF16 is the DOT task on BF16 arrays");
+    if (task->compute != RSM_F32 && task->compute != RSM_BF16 && task->compute != RSM_F64)
+      return fail(RSM_E_INVALID, "unknown compute dtype");
+    if (task->kind == RSM_TASK_WSUM && !task->coeffs && c->n_rep > 0)
+      return fail(RSM_E_INVALID, "WSUM needs coefficients");
+  }
+  if ((flags & RSM_CHECK_SINGLE_ASSIGN) && c->n_rep > 0) {
+    s = check_single_assign(*rep, *out, c->n_rep, c->n_pat_out);
+    if (s) return s;
+  }
+  return RSM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// canonical descriptors
+// ---------------------------------------------------------------------------
+GTiler to_gtiler(const rsm_tiler& t, int rep_rank) {
+  GTiler g;
+  std::memset(&g, 0, sizeof(g));
+  g.arr_rank = t.array_rank;
+  g.pat_rank = t.pattern_rank;
+  for (int d = 0; d < kMaxRank; ++d) {
+    g.shape[d] = d < t.array_rank ? t.array_shape[d] : 1;
+    g.pat_shape[d] = d < t.pattern_rank ? t.pattern_shape[d] : 1;
+  }
+  for (int d = 0; d < t.array_rank; ++d) {
+    const int64_t s = t.array_shape[d];
+    g.origin[d] = floor_mod(t.origin[d], s);
+    for (int k = 0; k < rep_rank; ++k) g.pav[d][k] = floor_mod(t.paving[d][k], s);
+    for (int k = 0; k < t.pattern_rank; ++k) g.fit[d][k] = floor_mod(t.fitting[d][k], s);
+  }
+  return g;
+}
+
+bool is_identity_out(const rsm_space& rep, const rsm_tiler& t) {
+  if (t.array_rank != rep.rank) return false;
+  for (int d = 0; d < rep.rank; ++d) {
+    if (t.array_shape[d] != rep.shape[d] || t.origin[d] != 0) return false;
+    for (int k = 0; k < rep.rank; ++k)
+      if (t.paving[d][k] != (d == k ? 1 : 0)) return false;
+  }
+  for (int k = 0; k < t.pattern_rank; ++k)
+    if (t.pattern_shape[k] != 1) return false;
+  return true;
+}
+
+constexpr int64_t kI30 = int64_t(1) << 30;
+
+// Axis-aligned view [B, R, C]; see Win3.
+bool canon_win3(const rsm_space& rep, const rsm_tiler& t, Win3* w) {
+  const int da = t.array_rank;
+  if (da < 1 || da > 3 || rep.rank != da) return false;
+  const int sh = 3 - da;
+  for (int d = 0; d < 3; ++d) { w->A[d] = 1; w->rep[d] = 1; w->o[d] = 0; w->p[d] = 0; }
+  int64_t total = 1;
+  for (int d = 0; d < da; ++d) {
+    for (int k = 0; k < da; ++k)
+      if (d != k && t.paving[d][k] != 0) return false;
+    if (t.paving[d][d] < 0) return false;
+    if (t.array_shape[d] >= kI30 || rep.shape[d] >= kI30) return false;
+    const int64_t reach = std::abs(t.origin[d]) + t.paving[d][d] * (rep.shape[d] > 0 ? rep.shape[d] : 1);
+    if (reach >= kI30) return false;
+    total *= t.array_shape[d];
+    w->A[d + sh] = int32_t(t.array_shape[d]);
+    w->rep[d + sh] = int32_t(rep.shape[d]);
+    w->o[d + sh] = int32_t(t.origin[d]);
+    w->p[d + sh] = int32_t(t.paving[d][d]);
+  }
+  if (total >= (int64_t(1) << 31)) return false;
+  int64_t rtotal = int64_t(w->rep[0]) * w->rep[1] * w->rep[2];
+  if (rtotal >= (int64_t(1) << 31)) return false;
+  if (t.pattern_rank == 1) {
+    int axis = -1;
+    for (int d = 0; d < da; ++d) {
+      if (t.fitting[d][0] == 0) continue;
+      if (t.fitting[d][0] != 1 || axis >= 0) return false;
+      axis = d + sh;
+    }
+    if (axis < 1) return false;
+    if (t.pattern_shape[0] >= kI30) return false;
+    w->ax = axis;
+    w->taps = int32_t(t.pattern_shape[0]);
+    w->taps2 = 1;
+    return true;
+  }
+  if (t.pattern_rank == 2) {
+    if (da < 2) return false;
+    for (int d = 0; d < da; ++d)
+      for (int k = 0; k < 2; ++k) {
+        const int64_t want = (d + sh == 1 + k) ? 1 : 0;
+        if (t.fitting[d][k] != want) return false;
+      }
+    if (t.pattern_shape[0] >= 4096 || t.pattern_shape[1] >= 4096) return false;
+    w->ax = 0;
+    w->taps = int32_t(t.pattern_shape[0]);
+    w->taps2 = int32_t(t.pattern_shape[1]);
+    return true;
+  }
+  return false;
+}
+
+// Non-tap axes must not wrap: o >= 0 and o + p (rep - 1) < A.
+bool outer_axes_inside(const Win3& w, int skip_axis) {
+  for (int d = 0; d < 3; ++d) {
+    if (d == skip_axis) continue;
+    if (w.o[d] < 0) return false;
+    if (int64_t(w.o[d]) + int64_t(w.p[d]) * (w.rep[d] - 1) >= w.A[d]) return false;
+  }
+  return true;
+}
+
+// Each array element read by at most one repetition (1-D pattern).
+bool fir_injective(const Win3& w) {
+  for (int d = 0; d < 3; ++d) {
+    if (d == w.ax) continue;
+    if (w.rep[d] > 1 && w.p[d] < 1) return false;
+  }
+  return w.p[w.ax] >= w.taps && int64_t(w.p[w.ax]) * w.rep[w.ax] <= w.A[w.ax];
+}
+
+// Every array element read exactly once.
+bool fir_exact_cover(const Win3& w) {
+  for (int d = 0; d < 3; ++d) {
+    if (d == w.ax) continue;
+    if (w.rep[d] != w.A[d] || (w.A[d] > 1 && w.p[d] != 1)) return false;
+  }
+  return w.p[w.ax] == w.taps && int64_t(w.p[w.ax]) * w.rep[w.ax] == w.A[w.ax];
+}
+
+bool fir_vec4(const Win3& w, const void* x) {
+  if (w.ax != 2) return false;
+  if (w.taps % 4 || w.p[2] % 4 || floor_mod(w.o[2], 4) || w.A[2] % 4) return false;
+  return x == nullptr || (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+}
+
+enum class Fam { Empty, Generic, PatternReduce, Fir, Gemm };
+
+struct Plan {
+  Fam fam = Fam::Generic;
+  std::string name = "generic";
+  Win3 win{};
+  bool vec4 = false;
+  GemmArgs gemm{};
+  int max_rank = 1;
+};
+
+int max_rank_of(const rsm_space& rep, const rsm_tiler* in, int n_in, const rsm_tiler& out) {
+  int m = rep.rank;
+  for (int t = 0; t < n_in; ++t) {
+    m = std::max(m, in[t].array_rank);
+    m = std::max(m, in[t].pattern_rank);
+  }
+  m = std::max(m, out.array_rank);
+  m = std::max(m, out.pattern_rank);
+  return std::max(m, 1);
+}
+
+// A DOT task whose tilers form C[m,n] = sum_k A(m,k) B(k,n).
+bool match_gemm(const rsm_space& rep, const rsm_tiler* in, const rsm_tiler& out, GemmArgs* g) {
+  if (rep.rank != 2 || !is_identity_out(rep, out)) return false;
+  const rsm_tiler& A = in[0];
+  const rsm_tiler& B = in[1];
+  if (A.array_rank != 2 || B.array_rank != 2 || A.pattern_rank != 1 || B.pattern_rank != 1) return false;
+  const int64_t M = rep.shape[0], N = rep.shape[1], K = A.pattern_shape[0];
+  if (B.pattern_shape[0] != K) return false;
+  for (int d = 0; d < 2; ++d)
+    if (A.origin[d] != 0 || B.origin[d] != 0) return false;
+  if (M >= kI30 || N >= kI30 || K >= kI30) return false;
+  // A: rep dim 0 walks one array axis with step 1, the pattern walks the other with step 1.
+  if (A.paving[0][0] == 1 && A.paving[0][1] == 0 && A.paving[1][0] == 0 && A.paving[1][1] == 0 &&
+      A.fitting[0][0] == 0 && A.fitting[1][0] == 1 && A.array_shape[0] == M && A.array_shape[1] == K) {
+    g->a_sm = K; g->a_sk = 1;
+  } else if (A.paving[1][0] == 1 && A.paving[1][1] == 0 && A.paving[0][0] == 0 && A.paving[0][1] == 0 &&
+             A.fitting[1][0] == 0 && A.fitting[0][0] == 1 && A.array_shape[0] == K && A.array_shape[1] == M) {
+    g->a_sm = 1; g->a_sk = M;
+  } else {
+    return false;
+  }
+  if (B.paving[1][1] == 1 && B.paving[1][0] == 0 && B.paving[0][0] == 0 && B.paving[0][1] == 0 &&
+      B.fitting[0][0] == 1 && B.fitting[1][0] == 0 && B.array_shape[0] == K && B.array_shape[1] == N) {
+    g->b_sk = N; g->b_sn = 1;
+  } else if (B.paving[0][1] == 1 && B.paving[0][0] == 0 && B.paving[1][0] == 0 && B.paving[1][1] == 0 &&
+             B.fitting[1][0] == 1 && B.fitting[0][0] == 0 && B.array_shape[0] == N && B.array_shape[1] == K) {
+    g->b_sk = 1; g->b_sn = K;
+  } else {
+    return false;
+  }
+  g->M = int32_t(M); g->N = int32_t(N); g->K = int32_t(K);
+  g->c_sm = N;
+  return true;
+}
+
+Plan make_plan(const rsm_space& rep, const rsm_tiler* in, int n_in, const rsm_tiler& out,
+               const rsm_task& task, uint32_t flags, const void* const* d_in, int64_t n_rep,
+               int64_t n_pat) {
+  Plan p;
+  p.max_rank = max_rank_of(rep, in, n_in, out);
+  if (n_rep == 0) {
+    p.fam = Fam::Empty;
+    p.name = "empty";
+    return p;
+  }
+  if (flags & RSM_FORCE_GENERIC) return p;
+  const bool f32 = in[0].dtype == RSM_F32 && task.compute == RSM_F32;
+  if (task.kind == RSM_TASK_DOT) {
+    GemmArgs g{};
+    const bool bf = in[0].dtype == RSM_BF16 && (task.compute == RSM_BF16 || task.compute == RSM_F32);
+    if ((bf || f32) && match_gemm(rep, in, out, &g)) {
+      const int compute = bf ? RSM_BF16 : RSM_F32;
+      // operands read in place (k-contiguous) must start on a 16-byte boundary
+      bool aligned = true;
+      if (d_in) {
+        if (g.a_sk == 1 && (reinterpret_cast<uintptr_t>(d_in[0]) & 15)) aligned = false;
+        if (g.b_sk == 1 && (reinterpret_cast<uintptr_t>(d_in[1]) & 15)) aligned = false;
+      }
+      if (aligned && gemm_supported(g, compute)) {
+        p.fam = Fam::Gemm;
+        p.gemm = g;
+        p.gemm.a = d_in ? d_in[0] : nullptr;
+        p.gemm.b = d_in ? d_in[1] : nullptr;
+        p.name = gemm_variant_name(g, compute);
+        return p;
+      }
+    }
+    return p;
+  }
+  if (task.kind == RSM_TASK_COPY) return p;
+  // SUM / WSUM on FP32
+  if (!f32) return p;
+  Win3 w{};
+  const bool id_out = is_identity_out(rep, out);
+  if (task.kind == RSM_TASK_WSUM && id_out && canon_win3(rep, in[0], &w) && w.ax >= 1 &&
+      outer_axes_inside(w, w.ax)) {
+    p.fam = Fam::Fir;
+    p.win = w;
+    p.vec4 = fir_vec4(w, d_in ? d_in[0] : nullptr);
+    p.name = w.ax == 2 ? (p.vec4 ? "fir_cols_vec4" : "fir_cols") : "fir_rows";
+    return p;
+  }
+  if (n_pat <= 64) {
+    p.fam = Fam::PatternReduce;
+    p.name = "pattern_reduce";
+    return p;
+  }
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// execution of one planned task
+// ---------------------------------------------------------------------------
+rsm_status exec_run(const rsm_space& rep, const rsm_tiler* in, const void* const* d_in, int n_in,
+                    const rsm_tiler& out, void* d_out, const rsm_task& task, uint32_t flags,
+                    const Checked& c, hipStream_t st) {
+  Plan p = make_plan(rep, in, n_in, out, task, flags, d_in, c.n_rep, c.n_pat_in[0]);
+  hipError_t e = hipSuccess;
+  switch (p.fam) {
+    case Fam::Empty:
+      return RSM_OK;
+    case Fam::Gemm: {
+      p.gemm.c = static_cast<float*>(d_out);
+      const int compute = in[0].dtype == RSM_BF16 ? RSM_BF16 : RSM_F32;
+      e = launch_gemm(p.gemm, compute, st);
+      if (e != hipSuccess) return hip_fail(e, "gemm launch");
+      return RSM_OK;
+    }
+    case Fam::Fir: {
+      FirArgs a{};
+      a.w = p.win;
+      a.div_rc = make_fastdiv(uint32_t(p.win.rep[2]));
+      a.div_rr = make_fastdiv(uint32_t(p.win.rep[1]));
+      a.n_out = uint32_t(c.n_rep);
+      a.x = static_cast<const float*>(d_in[0]);
+      a.y = static_cast<float*>(d_out);
+      a.c = static_cast<const float*>(task.coeffs);
+      e = launch_fir(a, p.vec4, st);
+      if (e != hipSuccess) return hip_fail(e, "fir launch");
+      return RSM_OK;
+    }
+    case Fam::PatternReduce: {
+      PatternReduceArgs a{};
+      a.rep_rank = rep.rank;
+      for (int k = 0; k < kMaxRank; ++k) a.rep_shape[k] = k < rep.rank ? rep.shape[k] : 1;
+      a.n_rep = c.n_rep;
+      a.n_pat = c.n_pat_in[0];
+      int g = 0;
+      while ((int64_t(1) << g) < a.n_pat) ++g;
+      a.group_log2 = g;
+      a.in = to_gtiler(in[0], rep.rank);
+      a.out = to_gtiler(out, rep.rank);
+      a.x = static_cast<const float*>(d_in[0]);
+      a.y = static_cast<float*>(d_out);
+      a.c = task.kind == RSM_TASK_WSUM ? static_cast<const float*>(task.coeffs) : nullptr;
+      e = launch_pattern_reduce(a, p.max_rank, st);
+      if (e != hipSuccess) return hip_fail(e, "pattern_reduce launch");
+      return RSM_OK;
+    }
+    case Fam::Generic: {
+      GenericArgs a;
+      std::memset(&a, 0, sizeof(a));
+      a.rep_rank = rep.rank;
+      a.n_in = n_in;
+      for (int k = 0; k < kMaxRank; ++k) a.rep_shape[k] = k < rep.rank ? rep.shape[k] : 1;
+      a.n_rep = c.n_rep;
+      a.n_pat = c.n_pat_in[0];
+      for (int t = 0; t < n_in; ++t) {
+        a.in[t] = to_gtiler(in[t], rep.rank);
+        a.x[t] = d_in[t];
+      }
+      a.out = to_gtiler(out, rep.rank);
+      a.y = d_out;
+      a.coeffs = task.coeffs;
+      e = launch_generic(a, p.max_rank, in[0].dtype, out.dtype, task.kind, elem_size(in[0].dtype), st);
+      if (e != hipSuccess) return hip_fail(e, "generic launch");
+      return RSM_OK;
+    }
+  }
+  return fail(RSM_E_UNSUPPORTED, "no kernel family");
+}
+
+bool ptrs_ok(const void* const* d, int n) {
+  if (!d) return false;
+  for (int k = 0; k < n; ++k)
+    if (!d[k]) return false;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint
+// ---------------------------------------------------------------------------
+rsm_status check_adjoint(const rsm_space* rep, const rsm_tiler* in, const rsm_tiler* out,
+                         const rsm_task* task, Checked* c) {
+  rsm_status s = check_task(rep, in, 1, out, task, 0, c);
+  if (s) return s;
+  if (task->kind != RSM_TASK_SUM && task->kind != RSM_TASK_WSUM)
+    return fail(RSM_E_UNSUPPORTED, "adjoint is defined here for SUM and WSUM tasks");
+  if (in->dtype != RSM_F32 || task->compute != RSM_F32)
+    return fail(RSM_E_UNSUPPORTED, "adjoint supports FP32 arrays and FP32 compute");
+  return RSM_OK;
+}
+
+struct AdjPlan {
+  bool fir = false;
+  bool vec4 = false;
+  bool exact = false;
+  Win3 w{};
+};
+
+AdjPlan plan_adjoint(const rsm_space& rep, const rsm_tiler& in, const rsm_tiler& out,
+                     const rsm_task& task, uint32_t flags, const void* x, const void* gx) {
+  AdjPlan a;
+  if (flags & RSM_FORCE_GENERIC) return a;
+  Win3 w{};
+  if (task.kind == RSM_TASK_WSUM && is_identity_out(rep, out) && canon_win3(rep, in, &w) &&
+      w.ax >= 1 && w.taps <= 16 && outer_axes_inside(w, w.ax) && fir_injective(w)) {
+    a.fir = true;
+    a.w = w;
+    a.exact = fir_exact_cover(w);
+    a.vec4 = fir_vec4(w, x) && fir_vec4(w, gx);
+  }
+  return a;
+}
+
+// Workspace bytes the adjoint of one stage needs.
+size_t adjoint_ws_bytes(const AdjPlan& ap, int64_t n_rep, int64_t n_pat, bool want_gc) {
+  if (!want_gc) return 0;
+  if (ap.fir) {
+    FirAdjArgs tmp{};
+    tmp.n_rep = uint32_t(n_rep);
+    return size_t(fir_adjoint_grid(tmp)) * size_t(ap.w.taps) * sizeof(float);
+  }
+  const int64_t nblk = std::min<int64_t>(std::max<int64_t>((n_rep + 4095) / 4096, 1), 1024);
+  return size_t(nblk) * size_t(n_pat) * sizeof(float);
+}
+
+rsm_status exec_adjoint(const rsm_space& rep, const rsm_tiler& in, const void* d_x,
+                        const rsm_tiler& out, const void* d_gy, const rsm_task& task, void* d_gx,
+                        void* d_gc, uint32_t flags, const Checked& c, void* ws, uint32_t* counter,
+                        hipStream_t st) {
+  const int accumulate = (flags & RSM_ACCUMULATE) ? 1 : 0;
+  hipError_t e;
+  const AdjPlan ap = plan_adjoint(rep, in, out, task, flags, d_x, d_gx);
+  if (c.n_rep == 0) {
+    // nothing reads the input: the gradients are zero
+    if (!accumulate) {
+      if (d_gx && (e = launch_zero(d_gx, prod(in.array_shape, in.array_rank) * 4, st)) != hipSuccess)
+        return hip_fail(e, "zero gx");
+      if (d_gc && (e = launch_zero(d_gc, c.n_pat_in[0] * 4, st)) != hipSuccess)
+        return hip_fail(e, "zero gc");
+    }
+    return RSM_OK;
+  }
+  const int64_t n_arr = prod(in.array_shape, in.array_rank);
+  if (ap.fir) {
+    if (d_gx && !accumulate && !ap.exact) {
+      if ((e = launch_zero(d_gx, n_arr * 4, st)) != hipSuccess) return hip_fail(e, "zero gx");
+    }
+    FirAdjArgs a{};
+    a.w = ap.w;
+    a.div_rc = make_fastdiv(uint32_t(ap.w.rep[2]));
+    a.div_rr = make_fastdiv(uint32_t(ap.w.rep[1]));
+    a.n_rep = uint32_t(c.n_rep);
+    a.x = d_gc ? static_cast<const float*>(d_x) : nullptr;
+    a.gy = static_cast<const float*>(d_gy);
+    a.gx = static_cast<float*>(d_gx);
+    a.c = static_cast<const float*>(task.coeffs);
+    a.partial = d_gc ? static_cast<float*>(ws) : nullptr;
+    a.gc = static_cast<float*>(d_gc);
+    a.counter = counter;
+    a.accumulate = accumulate;
+    int grid = 0;
+    if ((e = launch_fir_adjoint(a, ap.vec4, &grid, st)) != hipSuccess) return hip_fail(e, "fir adjoint");
+    return RSM_OK;
+  }
+  // generic path
+  const int mr = max_rank_of(rep, &in, 1, out);
+  if (d_gx) {
+    if (!accumulate && (e = launch_zero(d_gx, n_arr * 4, st)) != hipSuccess) return hip_fail(e, "zero gx");
+    GenericAdjArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.rep_rank = rep.rank;
+    for (int k = 0; k < kMaxRank; ++k) a.rep_shape[k] = k < rep.rank ? rep.shape[k] : 1;
+    a.n_rep = c.n_rep;
+    a.n_pat = c.n_pat_in[0];
+    a.in = to_gtiler(in, rep.rank);
+    a.out = to_gtiler(out, rep.rank);
+    a.gy = static_cast<const float*>(d_gy);
+    a.gx = static_cast<float*>(d_gx);
+    a.c = task.kind == RSM_TASK_WSUM ? static_cast<const float*>(task.coeffs) : nullptr;
+    if ((e = launch_generic_adjoint(a, mr, st)) != hipSuccess) return hip_fail(e, "generic adjoint");
+  }
+  if (d_gc) {
+    GenericCoefGradArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.rep_rank = rep.rank;
+    for (int k = 0; k < kMaxRank; ++k) a.rep_shape[k] = k < rep.rank ? rep.shape[k] : 1;
+    a.n_rep = c.n_rep;
+    a.n_pat = c.n_pat_in[0];
+    a.in = to_gtiler(in, rep.rank);
+    a.out = to_gtiler(out, rep.rank);
+    a.x = static_cast<const float*>(d_x);
+    a.gy = static_cast<const float*>(d_gy);
+    a.partial = static_cast<float*>(ws);
+    const int64_t nblk = std::min<int64_t>(std::max<int64_t>((c.n_rep + 4095) / 4096, 1), 1024);
+    a.chunk = (c.n_rep + nblk - 1) / nblk;
+    if ((e = launch_generic_coef_grad(a, mr, int(nblk), st)) != hipSuccess)
+      return hip_fail(e, "generic weight gradient");
+    if ((e = launch_reduce_rows(a.partial, a.n_pat, nblk, static_cast<float*>(d_gc), accumulate, st)) !=
+        hipSuccess)
+      return hip_fail(e, "weight-gradient reduction");
+  }
+  return RSM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// chains
+// ---------------------------------------------------------------------------
+rsm_status check_chain(const rsm_stage* stages, int32_t n, std::vector<Checked>* cs) {
+  if (!stages || n < 1) return fail(RSM_E_INVALID, "chain needs at least one stage");
+  cs->resize(size_t(n));
+  for (int k = 0; k < n; ++k) {
+    const rsm_stage& s = stages[k];
+    if (s.task.kind == RSM_TASK_DOT) return fail(RSM_E_INVALID, "chain stages take one input");
+    rsm_status r = check_task(&s.rep, &s.in, 1, &s.out, &s.task, 0, &(*cs)[size_t(k)]);
+    if (r) return fail(r, "stage " + std::to_string(k) + ": " + g_last_error);
+    if (k > 0) {
+      const rsm_tiler& a = stages[k - 1].out;
+      const rsm_tiler& b = s.in;
+      bool same = a.array_rank == b.array_rank && a.dtype == b.dtype;
+      for (int d = 0; same && d < a.array_rank; ++d) same = a.array_shape[d] == b.array_shape[d];
+      if (!same)
+        return fail(RSM_E_SHAPE, "stage " + std::to_string(k) + " input array differs from stage " +
+                                     std::to_string(k - 1) + " output array");
+    }
+  }
+  return RSM_OK;
+}
+
+// Two FP32 weighted-sum stages, columns then rows, identity outputs.
+bool chain_fusable(const rsm_stage* st, int n, const void* x, Win3* h, Win3* v, bool* vec4) {
+  if (n != 2) return false;
+  for (int k = 0; k < 2; ++k) {
+    if (st[k].task.kind != RSM_TASK_WSUM || st[k].task.compute != RSM_F32 || st[k].in.dtype != RSM_F32)
+      return false;
+    if (!is_identity_out(st[k].rep, st[k].out)) return false;
+  }
+  if (!canon_win3(st[0].rep, st[0].in, h) || !canon_win3(st[1].rep, st[1].in, v)) return false;
+  if (h->ax != 2 || v->ax != 1) return false;
+  if (!outer_axes_inside(*h, 2) || !outer_axes_inside(*v, 1)) return false;
+  // stage 1 reads the stage-0 output array [h.rep]
+  for (int d = 0; d < 3; ++d)
+    if (v->A[d] != h->rep[d]) return false;
+  *vec4 = fir_vec4(*h, x);
+  return true;
+}
+
+}  // namespace
+}  // namespace rsm
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+using namespace rsm;
+
+#define RSM_GUARD_BEGIN try {
+#define RSM_GUARD_END                                                   \
+  }                                                                     \
+  catch (const std::bad_alloc&) {                                       \
+    return fail(RSM_E_NOMEM, "host allocation failed");                 \
+  }                                                                     \
+  catch (...) {                                                         \
+    return fail(RSM_E_INVALID, "internal error (exception)");           \
+  }
+
+extern "C" {
+
+int32_t rsm_abi_version(void) { return RSM_ABI_VERSION; }
+
+const char* rsm_status_string(rsm_status s) {
+  switch (s) {
+    case RSM_OK: return "RSM_OK";
+    case RSM_E_INVALID: return "RSM_E_INVALID";
+    case RSM_E_RANK: return "RSM_E_RANK";
+    case RSM_E_SHAPE: return "RSM_E_SHAPE";
+    case RSM_E_OVERFLOW: return "RSM_E_OVERFLOW";
+    case RSM_E_OVERLAP: return "RSM_E_OVERLAP";
+    case RSM_E_UNSUPPORTED: return "RSM_E_UNSUPPORTED";
+    case RSM_E_HIP: return "RSM_E_HIP";
+    case RSM_E_NOMEM: return "RSM_E_NOMEM";
+  }
+  return "RSM_E_UNKNOWN";
+}
+
+const char* rsm_last_error(void) { return g_last_error.c_str(); }
+
+rsm_status rsm_validate(const rsm_space* rep, const rsm_tiler* in, int32_t n_in,
+                        const rsm_tiler* out, const rsm_task* task, uint32_t flags) {
+  RSM_GUARD_BEGIN
+  Checked c;
+  return check_task(rep, in, n_in, out, task, flags, &c);
+  RSM_GUARD_END
+}
+
+rsm_status rsm_plan(const rsm_space* rep, const rsm_tiler* in, int32_t n_in, const rsm_tiler* out,
+                    const rsm_task* task, uint32_t flags, char* name, int32_t len) {
+  RSM_GUARD_BEGIN
+  Checked c;
+  rsm_status s = check_task(rep, in, n_in, out, task, flags & ~RSM_CHECK_SINGLE_ASSIGN, &c);
+  if (s) return s;
+  if (!name || len <= 0) return fail(RSM_E_INVALID, "name buffer is NULL");
+  const Plan p = make_plan(*rep, in, n_in, *out, *task, flags, nullptr, c.n_rep, c.n_pat_in[0]);
+  std::snprintf(name, size_t(len), "%s", p.name.c_str());
+  return RSM_OK;
+  RSM_GUARD_END
+}
+
+rsm_status rsm_indices(const rsm_space* rep, const rsm_tiler* t, int64_t* d_idx, void* hip_stream) {
+  RSM_GUARD_BEGIN
+  int64_t n_rep = 0, n_pat = 0;
+  rsm_status s = check_space(rep, &n_rep);
+  if (s) return s;
+  s = check_tiler(t, rep, "tiler", &n_pat);
+  if (s) return s;
+  if (n_rep == 0) return RSM_OK;
+  if (!d_idx) return fail(RSM_E_INVALID, "index buffer is NULL");
+  int64_t total;
+  if (!mul_ok(n_rep, n_pat, &total)) return fail(RSM_E_OVERFLOW, "index table has more than 2^62 entries");
+  const GTiler g = to_gtiler(*t, rep->rank);
+  hipError_t e = launch_indices(g, rep->rank, rep->shape, n_rep, n_pat, d_idx,
+                                static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "index launch");
+  return RSM_OK;
+  RSM_GUARD_END
+}
+
+rsm_status rsm_run(const rsm_space* rep, const rsm_tiler* in, const void* const* d_in, int32_t n_in,
+                   const rsm_tiler* out, void* d_out, const rsm_task* task, uint32_t flags,
+                   void* hip_stream) {
+  RSM_GUARD_BEGIN
+  Checked c;
+  rsm_status s = check_task(rep, in, n_in, out, task, flags, &c);
+  if (s) return s;
+  if (c.n_rep == 0) return RSM_OK;
+  if (!ptrs_ok(d_in, n_in) || !d_out) return fail(RSM_E_INVALID, "NULL device pointer");
+  return exec_run(*rep, in, d_in, n_in, *out, d_out, *task, flags, c,
+                  static_cast<hipStream_t>(hip_stream));
+  RSM_GUARD_END
+}
+
+rsm_status rsm_run_chain(const rsm_stage* stages, int32_t n_stages, const void* d_in,
+                         void* const* d_mid, void* d_out, uint32_t flags, void* hip_stream) {
+  RSM_GUARD_BEGIN
+  std::vector<Checked> cs;
+  rsm_status s = check_chain(stages, n_stages, &cs);
+  if (s) return s;
+  if (!d_in || !d_out) return fail(RSM_E_INVALID, "NULL device pointer");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const bool no_mid = !d_mid || !d_mid[0];
+  Win3 h{}, v{};
+  bool vec4 = false;
+  if (!(flags & RSM_NO_FUSE) && !(flags & RSM_FORCE_GENERIC) && no_mid &&
+      chain_fusable(stages, n_stages, d_in, &h, &v, &vec4)) {
+    if (cs[1].n_rep == 0) return RSM_OK;
+    FirChainArgs a{};
+    a.h = h;
+    a.v = v;
+    a.div_rc = make_fastdiv(uint32_t(v.rep[2]));
+    a.div_rr = make_fastdiv(uint32_t(v.rep[1]));
+    a.n_out = uint32_t(cs[1].n_rep);
+    a.x = static_cast<const float*>(d_in);
+    a.y = static_cast<float*>(d_out);
+    a.ch = static_cast<const float*>(stages[0].task.coeffs);
+    a.cv = static_cast<const float*>(stages[1].task.coeffs);
+    hipError_t e = launch_fir_chain(a, vec4, st);
+    if (e != hipSuccess) return hip_fail(e, "fused chain launch");
+    return RSM_OK;
+  }
+  if (n_stages > 1 && (!d_mid || !ptrs_ok(const_cast<const void* const*>(d_mid), n_stages - 1)))
+    return fail(RSM_E_INVALID, "unfused chain needs every intermediate buffer");
+  for (int k = 0; k < n_stages; ++k) {
+    const void* src = k == 0 ? d_in : d_mid[k - 1];
+    void* dst = k == n_stages - 1 ? d_out : d_mid[k];
+    const rsm_stage& sg = stages[k];
+    s = exec_run(sg.rep, &sg.in, &src, 1, sg.out, dst, sg.task, flags, cs[size_t(k)], st);
+    if (s) return s;
+  }
+  return RSM_OK;
+  RSM_GUARD_END
+}
+
+rsm_status rsm_run_adjoint(const rsm_space* rep, const rsm_tiler* in, const void* d_x,
+                           const rsm_tiler* out, const void* d_gy, const rsm_task* task, void* d_gx,
+                           void* d_gc, uint32_t flags, void* hip_stream) {
+  RSM_GUARD_BEGIN
+  Checked c;
+  rsm_status s = check_adjoint(rep, in, out, task, &c);
+  if (s) return s;
+  if (!d_gx && !d_gc) return RSM_OK;
+  if (d_gc && task->kind != RSM_TASK_WSUM) return fail(RSM_E_INVALID, "weight gradient needs a WSUM task");
+  if (c.n_rep > 0 && (!d_gy || (d_gc && !d_x))) return fail(RSM_E_INVALID, "NULL device pointer");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const AdjPlan ap = plan_adjoint(*rep, *in, *out, *task, flags, d_x, d_gx);
+  const size_t wsb = adjoint_ws_bytes(ap, c.n_rep, c.n_pat_in[0], d_gc != nullptr);
+  void* ws = nullptr;
+  uint32_t* counter = nullptr;
+  if (wsb) {
+    ws = workspace(wsb, st, &s, &counter);
+    if (s) return s;
+  }
+  return exec_adjoint(*rep, *in, d_x, *out, d_gy, *task, d_gx, d_gc, flags, c, ws, counter, st);
+  RSM_GUARD_END
+}
+
+rsm_status rsm_run_chain_adjoint(const rsm_stage* stages, int32_t n_stages, const void* d_in,
+                                 const void* const* d_mid, const void* d_gy, void* d_gx,
+                                 void* const* d_gc, uint32_t flags, void* hip_stream) {
+  RSM_GUARD_BEGIN
+  std::vector<Checked> cs;
+  rsm_status s = check_chain(stages, n_stages, &cs);
+  if (s) return s;
+  for (int k = 0; k < n_stages; ++k) {
+    Checked tmp;
+    s = check_adjoint(&stages[k].rep, &stages[k].in, &stages[k].out, &stages[k].task, &tmp);
+    if (s) return fail(s, "stage " + std::to_string(k) + ": " + g_last_error);
+    if (d_gc && d_gc[k] && stages[k].task.kind != RSM_TASK_WSUM)
+      return fail(RSM_E_INVALID, "weight gradient needs a WSUM stage");
+  }
+  if (!d_in || !d_gy) return fail(RSM_E_INVALID, "NULL device pointer");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int accumulate = (flags & RSM_ACCUMULATE) ? 1 : 0;
+  const bool no_mid = !d_mid || !d_mid[0];
+  Win3 h{}, v{};
+  bool vec4 = false;
+  hipError_t e;
+  if (!(flags & RSM_NO_FUSE) && !(flags & RSM_FORCE_GENERIC) && no_mid &&
+      chain_fusable(stages, n_stages, d_in, &h, &v, &vec4) && h.taps <= 16 && v.taps <= 16 &&
+      fir_injective(h) && fir_injective(v) && cs[1].n_rep > 0) {
+    vec4 = vec4 && fir_vec4(h, d_gx);
+    float* gch = d_gc ? static_cast<float*>(d_gc[0]) : nullptr;
+    float* gcv = d_gc ? static_cast<float*>(d_gc[1]) : nullptr;
+    if (d_gx && !accumulate && !(fir_exact_cover(h) && fir_exact_cover(v))) {
+      if ((e = launch_zero(d_gx, int64_t(h.A[0]) * h.A[1] * h.A[2] * 4, st)) != hipSuccess)
+        return hip_fail(e, "zero gx");
+    }
+    FirChainAdjArgs a{};
+    a.h = h;
+    a.v = v;
+    a.div_rc = make_fastdiv(uint32_t(v.rep[2]));
+    a.div_rr = make_fastdiv(uint32_t(v.rep[1]));
+    a.n_out = uint32_t(cs[1].n_rep);
+    a.x = static_cast<const float*>(d_in);
+    a.gy = static_cast<const float*>(d_gy);
+    a.gx = static_cast<float*>(d_gx);
+    a.ch = static_cast<const float*>(stages[0].task.coeffs);
+    a.cv = static_cast<const float*>(stages[1].task.coeffs);
+    a.accumulate = accumulate;
+    a.gch = gch;
+    a.gcv = gcv;
+    const int grid = fir_chain_adjoint_grid(a);
+    const int nc = h.taps + v.taps;
+    if (gch || gcv) {
+      a.partial = static_cast<float*>(workspace(size_t(grid) * nc * sizeof(float), st, &s, &a.counter));
+      if (s) return s;
+    }
+    if ((e = launch_fir_chain_adjoint(a, vec4, st)) != hipSuccess) return hip_fail(e, "fused chain adjoint");
+    return RSM_OK;
+  }
+  // stage by stage, in reverse; intermediate gradients live in the workspace
+  if (n_stages > 1 && (!d_mid || !ptrs_ok(d_mid, n_stages - 1)))
+    return fail(RSM_E_INVALID, "unfused chain adjoint needs every forward intermediate");
+  size_t max_mid = 0, max_part = 0;
+  std::vector<AdjPlan> aps(static_cast<size_t>(n_stages));
+  for (int k = 0; k < n_stages; ++k) {
+    const rsm_stage& sg = stages[k];
+    const void* xk = k == 0 ? d_in : d_mid[k - 1];
+    aps[size_t(k)] = plan_adjoint(sg.rep, sg.in, sg.out, sg.task, flags, xk, nullptr);
+    max_part = std::max(max_part, adjoint_ws_bytes(aps[size_t(k)], cs[size_t(k)].n_rep,
+                                                   cs[size_t(k)].n_pat_in[0], d_gc && d_gc[k]));
+    if (k > 0) max_mid = std::max(max_mid, size_t(prod(sg.in.array_shape, sg.in.array_rank)) * 4);
+  }
+  max_mid = (max_mid + 255) & ~size_t(255);
+  max_part = (max_part + 255) & ~size_t(255);
+  uint32_t* counter = nullptr;
+  char* ws = static_cast<char*>(workspace(2 * max_mid + max_part + 256, st, &s, &counter));
+  if (s) return s;
+  char* gbuf[2] = {ws, ws + max_mid};
+  void* part = ws + 2 * max_mid;
+  const void* g = d_gy;
+  for (int k = n_stages - 1; k >= 0; --k) {
+    const rsm_stage& sg = stages[k];
+    const void* xk = k == 0 ? d_in : d_mid[k - 1];
+    void* gxk = k == 0 ? d_gx : gbuf[k & 1];
+    void* gck = d_gc ? d_gc[k] : nullptr;
+    // intermediate gradients are overwritten; the caller's buffers follow the flags
+    uint32_t fk = flags & RSM_FORCE_GENERIC;
+    if (accumulate) fk |= RSM_ACCUMULATE;
+    if (k > 0 && accumulate) {
+      // accumulate applies to the caller's gc, not to the intermediate gradient
+      if (gck) {
+        s = exec_adjoint(sg.rep, sg.in, xk, sg.out, g, sg.task, nullptr, gck, fk, cs[size_t(k)], part,
+                         counter, st);
+        if (s) return s;
+      }
+      s = exec_adjoint(sg.rep, sg.in, xk, sg.out, g, sg.task, gxk, nullptr, fk & ~RSM_ACCUMULATE,
+                       cs[size_t(k)], part, counter, st);
+    } else {
+      s = exec_adjoint(sg.rep, sg.in, xk, sg.out, g, sg.task, gxk, gck, fk, cs[size_t(k)], part,
+                       counter, st);
+    }
+    if (s) return s;
+    g = gxk;
+    if (!g && k > 0) return fail(RSM_E_INVALID, "internal: missing intermediate gradient");
+  }
+  return RSM_OK;
+  RSM_GUARD_END
+}
+
+}  // extern "C"

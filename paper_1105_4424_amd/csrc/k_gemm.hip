@@ -1,0 +1,284 @@
+// k_gemm.hip -- the DOT task whose tilers form a dense matrix product.
+//
+// C[m, n] = sum_k A(m, k) B(k, n), FP32 accumulation on the matrix cores:
+//   * BF16 operands: v_mfma_f32_32x32x16_bf16 (products exact in FP32)
+//   * FP32 operands: v_mfma_f32_32x32x2_f32
+// The kernel wants both operands with k contiguous ("A[m][k]", "Bt[n][k]").
+// An operand whose tiler walks k along a strided axis is first transposed
+// into the library workspace by an LDS-tiled transpose kernel.
+//
+// Tiling: 128 x 128 outputs per workgroup of 4 waves (2 x 2), 64 x 64 per
+// wave as 2 x 2 MFMA tiles of 32 x 32; the k-loop stages 128-byte rows of
+// both operands in LDS (row pitch 144 B: the 16-lane phases of ds_read_b128
+// touch distinct banks), double-buffered, with the next tile prefetched into
+// registers while the current one feeds the MFMAs.  Workgroup ids are
+// remapped so that each XCD (ids are dealt round-robin to the 8 XCDs) works
+// on a contiguous, grouped band of output tiles and shares A / B panels in
+// its own L2.
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "rsm_internal.h"
+
+namespace rsm {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int kBM = 128;
+constexpr int kBN = 128;
+constexpr int kRowBytes = 128;        // one LDS row = 128 bytes of k
+constexpr int kPitch = 144;           // padded LDS row pitch in bytes
+constexpr int kThreads = 256;
+constexpr int kXcds = 8;
+constexpr int kGroupM = 8;            // tile rows per raster group
+
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<uint16_t> {
+  static constexpr int kPerChunk = 8;  // elements per 16-byte chunk
+  __device__ static __forceinline__ floatx16 step(uint4 a, uint4 b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Mfma<float> {
+  static constexpr int kPerChunk = 4;
+  // k-slot h of instruction s holds physical k = 8g + 4h + s: the same
+  // mapping on both operands, so the four products cover the 8 k values.
+  __device__ static __forceinline__ floatx16 step(uint4 a, uint4 b, floatx16 c) {
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
+    return c;
+  }
+};
+
+struct TnArgs {
+  int32_t M, N, K;
+  int64_t lda;   // elements between rows of A[m][k]
+  int64_t ldb;   // elements between rows of Bt[n][k]
+  int64_t ldc;
+  const void* a;
+  const void* b;
+  float* c;
+  int32_t tiles_m, tiles_n;
+};
+
+// Maps a hardware workgroup id to an output tile: XCD-contiguous bands,
+// grouped raster inside each band.
+__device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n, int* tm, int* tn) {
+  const int total = tiles_m * tiles_n;
+  int logical = bid;
+  if (total % kXcds == 0) logical = (bid % kXcds) * (total / kXcds) + bid / kXcds;
+  const int per_group = kGroupM * tiles_n;
+  const int group = logical / per_group;
+  const int first_m = group * kGroupM;
+  const int gm = (tiles_m - first_m) < kGroupM ? (tiles_m - first_m) : kGroupM;
+  const int in_group = logical - group * per_group;
+  *tm = first_m + in_group % gm;
+  *tn = in_group / gm;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads, 2) gemm_tn_kernel(TnArgs p) {
+  constexpr int E = Mfma<T>::kPerChunk;      // elements per 16-byte chunk
+  constexpr int BK = kRowBytes / sizeof(T);  // k elements per LDS row
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2][2][kBM * kPitch];
+
+  int tm, tn;
+  tile_of(blockIdx.x, p.tiles_m, p.tiles_n, &tm, &tn);
+  const int m0 = tm * kBM, n0 = tn * kBN;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int li = lane & 31, lh = lane >> 5;
+
+  const T* A = static_cast<const T*>(p.a);
+  const T* B = static_cast<const T*>(p.b);
+
+  // global -> register staging: 4 chunks of A and 4 of B per thread
+  uint4 ra[4], rb[4];
+  auto load_tile = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = t + kThreads * j;
+      const int row = q >> 3, ch = q & 7;
+      const int kk = k0 + ch * E;
+      const int am = m0 + row, bn = n0 + row;
+      uint4 z = make_uint4(0, 0, 0, 0);
+      ra[j] = (am < p.M && kk < p.K) ? *reinterpret_cast<const uint4*>(A + am * p.lda + kk) : z;
+      rb[j] = (bn < p.N && kk < p.K) ? *reinterpret_cast<const uint4*>(B + bn * p.ldb + kk) : z;
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = t + kThreads * j;
+      const int row = q >> 3, ch = q & 7;
+      *reinterpret_cast<uint4*>(&lds[buf][0][row * kPitch + ch * 16]) = ra[j];
+      *reinterpret_cast<uint4*>(&lds[buf][1][row * kPitch + ch * 16]) = rb[j];
+    }
+  };
+
+  floatx16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+
+  const int n_k = (p.K + BK - 1) / BK;
+  load_tile(0);
+  store_tile(0);
+  __syncthreads();
+  for (int kt = 0; kt < n_k; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < n_k) load_tile((kt + 1) * BK);
+    const unsigned char* la = lds[buf][0];
+    const unsigned char* lb = lds[buf][1];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int off = (2 * g + lh) * 16;
+      uint4 fa[2], fb[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        fa[i] = *reinterpret_cast<const uint4*>(la + (wm + 32 * i + li) * kPitch + off);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        fb[j] = *reinterpret_cast<const uint4*>(lb + (wn + 32 * j + li) * kPitch + off);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = Mfma<T>::step(fa[i], fb[j], acc[i][j]);
+    }
+    if (kt + 1 < n_k) store_tile(buf ^ 1);
+    __syncthreads();
+  }
+
+  // 32x32 accumulator layout: element v of lane l is row 8(v/4) + 4(l/32) + v%4, column l%32
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn + 32 * j + li;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = m0 + wm + 32 * i + 8 * (v >> 2) + 4 * lh + (v & 3);
+        if (row < p.M && col < p.N) p.c[int64_t(row) * p.ldc + col] = acc[i][j][v];
+      }
+    }
+}
+
+// dst[c][r] = src[r][c] for a rows x cols matrix (element type E)
+template <typename E>
+__global__ void __launch_bounds__(256) transpose_kernel(const E* __restrict__ src, E* __restrict__ dst,
+                                                        int rows, int cols, int64_t lds_src,
+                                                        int64_t lds_dst) {
+  __shared__ E tile[64][65];
+  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int gr = r0 + r, gc = c0 + tx;
+    if (gr < rows && gc < cols) tile[r][tx] = src[int64_t(gr) * lds_src + gc];
+  }
+  __syncthreads();
+  for (int c = ty; c < 64; c += 4) {
+    const int gc = c0 + c, gr = r0 + tx;
+    if (gr < rows && gc < cols) dst[int64_t(gc) * lds_dst + gr] = tile[tx][c];
+  }
+}
+
+template <typename E>
+hipError_t transpose(const void* src, void* dst, int rows, int cols, hipStream_t st) {
+  dim3 grid((cols + 63) / 64, (rows + 63) / 64);
+  transpose_kernel<E><<<grid, 256, 0, st>>>(static_cast<const E*>(src), static_cast<E*>(dst), rows,
+                                            cols, cols, rows);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool gemm_supported(const GemmArgs& a, int compute) {
+  const int per = compute == RSM_BF16 ? 8 : 4;   // elements per 16-byte chunk
+  if (a.M < 1 || a.N < 1 || a.K < 1) return false;
+  if (a.K % per) return false;
+  // the k-contiguous copies have row length K; both M and N strides must keep
+  // 16-byte alignment of every row
+  return true;
+}
+
+const char* gemm_variant_name(const GemmArgs& a, int compute) {
+  const bool ta = a.a_sk != 1, tb = a.b_sk != 1;
+  if (compute == RSM_BF16) {
+    if (ta && tb) return "gemm_mfma_bf16_tt";
+    if (ta) return "gemm_mfma_bf16_tn_at";
+    if (tb) return "gemm_mfma_bf16_nn";
+    return "gemm_mfma_bf16_nt";
+  }
+  if (ta && tb) return "gemm_mfma_f32_tt";
+  if (ta) return "gemm_mfma_f32_tn_at";
+  if (tb) return "gemm_mfma_f32_nn";
+  return "gemm_mfma_f32_nt";
+}
+
+hipError_t launch_gemm(const GemmArgs& g, int compute, hipStream_t st) {
+  const size_t es = compute == RSM_BF16 ? 2 : 4;
+  const bool ta = g.a_sk != 1, tb = g.b_sk != 1;
+  size_t bytes = 0;
+  const size_t a_bytes = ta ? ((size_t(g.M) * g.K * es + 255) & ~size_t(255)) : 0;
+  const size_t b_bytes = tb ? ((size_t(g.N) * g.K * es + 255) & ~size_t(255)) : 0;
+  bytes = a_bytes + b_bytes;
+  char* ws = nullptr;
+  if (bytes) {
+    rsm_status s;
+    ws = static_cast<char*>(workspace(bytes, st, &s));
+    if (s != RSM_OK) return hipErrorOutOfMemory;
+  }
+  TnArgs p;
+  p.M = g.M;
+  p.N = g.N;
+  p.K = g.K;
+  p.ldc = g.c_sm;
+  p.c = g.c;
+  p.a = g.a;
+  p.lda = g.a_sm;
+  p.b = g.b;
+  p.ldb = g.b_sn;
+  hipError_t e;
+  if (ta) {  // A stored [K][M]: make A[m][k]
+    e = es == 2 ? transpose<uint16_t>(g.a, ws, g.K, g.M, st) : transpose<float>(g.a, ws, g.K, g.M, st);
+    if (e != hipSuccess) return e;
+    p.a = ws;
+    p.lda = g.K;
+  }
+  if (tb) {  // B stored [K][N]: make Bt[n][k]
+    e = es == 2 ? transpose<uint16_t>(g.b, ws + a_bytes, g.K, g.N, st)
+                : transpose<float>(g.b, ws + a_bytes, g.K, g.N, st);
+    if (e != hipSuccess) return e;
+    p.b = ws + a_bytes;
+    p.ldb = g.K;
+  }
+  // 16-byte alignment of every row start of both operands
+  if (((reinterpret_cast<uintptr_t>(p.a) | reinterpret_cast<uintptr_t>(p.b)) & 15) ||
+      ((p.lda * es) & 15) || ((p.ldb * es) & 15))
+    return hipErrorInvalidValue;
+  p.tiles_m = (g.M + kBM - 1) / kBM;
+  p.tiles_n = (g.N + kBN - 1) / kBN;
+  const int grid = p.tiles_m * p.tiles_n;
+  if (compute == RSM_BF16)
+    gemm_tn_kernel<uint16_t><<<grid, kThreads, 0, st>>>(p);
+  else
+    gemm_tn_kernel<float><<<grid, kThreads, 0, st>>>(p);
+  return hipGetLastError();
+}
+
+}  // namespace rsm

@@ -1,0 +1,608 @@
+// k_window.hip -- kernels for axis-aligned tilers (weighted / plain sums).
+//
+//  * pattern_reduce: small patterns (<= 64 elements) on any affine tiler.  One
+//    lane per pattern element, a group of 2^k lanes per repetition, and a
+//    butterfly reduction across the group with wavefront shuffles.
+//  * fir:            1-D taps along one axis of a [B, R, C] view.  One output
+//    per thread per loop trip; taps along the contiguous axis are read as
+//    16-byte vectors, taps along rows are coalesced across the wavefront.
+//    Windows that cross a border take a modular path.
+//  * fir_chain:      two FIR stages (columns, then rows) fused: the
+//    intermediate array is never written; each thread reads the block of
+//    input the output depends on, exactly once.
+//  * fir_adjoint / fir_chain_adjoint: transposed tilers written as gathers
+//    (each input element is read by at most one repetition, so the
+//    scatter-add is a plain store) plus per-block weight-gradient partials.
+#include <hip/hip_runtime.h>
+
+#include "rsm_internal.h"
+
+namespace rsm {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxTaps = 16;   // taps held in registers by the adjoint kernels
+
+__device__ __forceinline__ int wrap_mod(int64_t v, int n) {
+  int64_t q = v % n;
+  return int(q < 0 ? q + n : q);
+}
+
+// ---------------------------------------------------------------------------
+// pattern_reduce
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ void __launch_bounds__(kBlock) pattern_reduce_kernel(PatternReduceArgs a) {
+  const int G = 1 << a.group_log2;
+  const int lane = threadIdx.x & (G - 1);
+  const int64_t groups_total = (int64_t(gridDim.x) * kBlock) >> a.group_log2;
+  const int64_t group0 = (int64_t(blockIdx.x) * kBlock + threadIdx.x) >> a.group_log2;
+
+  // pattern offset of this lane: (F i) mod s, i = lane's pattern multi-index
+  int64_t off[R];
+  {
+    int64_t i[R];
+    int64_t f = lane;
+#pragma unroll
+    for (int k = R - 1; k >= 0; --k) {
+      if (k < a.in.pat_rank) {
+        i[k] = f % a.in.pat_shape[k];
+        f /= a.in.pat_shape[k];
+      } else {
+        i[k] = 0;
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < R; ++d) {
+      off[d] = 0;
+      if (d < a.in.arr_rank) {
+        int64_t v = 0;
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+          if (k < a.in.pat_rank) v += a.in.fit[d][k] * i[k];
+        off[d] = v % a.in.shape[d];
+      }
+    }
+  }
+  const bool active = lane < a.n_pat;
+  const float coef = (active && a.c) ? a.c[lane] : 1.0f;
+
+  for (int64_t rf = group0; rf < a.n_rep; rf += groups_total) {
+    int64_t r[R];
+    {
+      int64_t f = rf;
+#pragma unroll
+      for (int k = R - 1; k >= 0; --k) {
+        if (k < a.rep_rank) {
+          r[k] = f % a.rep_shape[k];
+          f /= a.rep_shape[k];
+        } else {
+          r[k] = 0;
+        }
+      }
+    }
+    float v = 0.0f;
+    if (active) {
+      int64_t lin = 0;
+#pragma unroll
+      for (int d = 0; d < R; ++d) {
+        if (d < a.in.arr_rank) {
+          const int64_t s = a.in.shape[d];
+          int64_t c = a.in.origin[d];
+#pragma unroll
+          for (int k = 0; k < R; ++k) {
+            if (k < a.rep_rank) {
+              c += (a.in.pav[d][k] * r[k]) % s;
+              if (c >= s) c -= s;
+            }
+          }
+          c += off[d];
+          if (c >= s) c -= s;
+          lin = lin * s + c;
+        }
+      }
+      v = a.x[lin] * coef;
+    }
+    // butterfly across the group (G divides 64, groups never straddle a wave)
+    for (int m = G >> 1; m > 0; m >>= 1) v += __shfl_xor(v, m);
+    if (lane == 0) {
+      int64_t lin = 0;
+#pragma unroll
+      for (int d = 0; d < R; ++d) {
+        if (d < a.out.arr_rank) {
+          const int64_t s = a.out.shape[d];
+          int64_t c = a.out.origin[d];
+#pragma unroll
+          for (int k = 0; k < R; ++k) {
+            if (k < a.rep_rank) {
+              c += (a.out.pav[d][k] * r[k]) % s;
+              if (c >= s) c -= s;
+            }
+          }
+          lin = lin * s + c;
+        }
+      }
+      a.y[lin] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FIR helpers
+// ---------------------------------------------------------------------------
+struct OutPos {
+  int b, r, c;  // repetition coordinates
+};
+
+__device__ __forceinline__ OutPos decode(uint32_t o, const Win3& w, const FastDiv& drc,
+                                         const FastDiv& drr) {
+  const uint32_t row = fdiv(o, drc);
+  OutPos p;
+  p.c = int(o - row * uint32_t(w.rep[2]));
+  const uint32_t b = fdiv(row, drr);
+  p.r = int(row - b * uint32_t(w.rep[1]));
+  p.b = int(b);
+  return p;
+}
+
+// Sum_k c[k] * x[row_base + (start + k) mod n] along the contiguous axis
+// (element step 1).  `row_base` is the offset of the row's first element.
+template <bool VEC, int TT>
+__device__ __forceinline__ float taps_contig(const float* __restrict__ x, int row_base, int start,
+                                             int n, int taps, const float* __restrict__ c) {
+  float acc = 0.0f;
+  if (start >= 0 && start + taps <= n) {
+    const float* p = x + row_base + start;
+    if (VEC) {
+      const int nv = (TT ? TT : taps) / 4;
+#pragma unroll
+      for (int q = 0; q < nv; ++q) {
+        const float4 v = *reinterpret_cast<const float4*>(p + 4 * q);
+        acc = fmaf(c[4 * q + 0], v.x, acc);
+        acc = fmaf(c[4 * q + 1], v.y, acc);
+        acc = fmaf(c[4 * q + 2], v.z, acc);
+        acc = fmaf(c[4 * q + 3], v.w, acc);
+      }
+    } else {
+      const int nt = TT ? TT : taps;
+#pragma unroll 8
+      for (int k = 0; k < nt; ++k) acc = fmaf(c[k], p[k], acc);
+    }
+  } else {
+    int col = wrap_mod(start, n);
+    const int nt = TT ? TT : taps;
+    for (int k = 0; k < nt; ++k) {
+      acc = fmaf(c[k], x[row_base + col], acc);
+      if (++col == n) col = 0;
+    }
+  }
+  return acc;
+}
+
+// Sum_k c[k] * x[plane + ((start + k) mod n) * row_stride + col] along rows.
+template <int TT>
+__device__ __forceinline__ float taps_rows(const float* __restrict__ x, int plane, int start,
+                                           int n, int row_stride, int col, int taps,
+                                           const float* __restrict__ c) {
+  float acc = 0.0f;
+  const int nt = TT ? TT : taps;
+  if (start >= 0 && start + nt <= n) {
+    const float* p = x + plane + start * row_stride + col;
+#pragma unroll 8
+    for (int k = 0; k < nt; ++k) acc = fmaf(c[k], p[k * row_stride], acc);
+  } else {
+    int row = wrap_mod(start, n);
+    for (int k = 0; k < nt; ++k) {
+      acc = fmaf(c[k], x[plane + row * row_stride + col], acc);
+      if (++row == n) row = 0;
+    }
+  }
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// FIR forward
+// ---------------------------------------------------------------------------
+template <int AX, bool VEC, int TT>
+__global__ void __launch_bounds__(kBlock) fir_kernel(FirArgs a) {
+  const Win3& w = a.w;
+  const uint32_t stride = gridDim.x * kBlock;
+  for (uint32_t o = blockIdx.x * kBlock + threadIdx.x; o < a.n_out; o += stride) {
+    const OutPos q = decode(o, w, a.div_rc, a.div_rr);
+    const int ib = w.o[0] + w.p[0] * q.b;
+    float acc;
+    if (AX == 2) {
+      const int ir = w.o[1] + w.p[1] * q.r;
+      const int row_base = (ib * w.A[1] + ir) * w.A[2];
+      acc = taps_contig<VEC, TT>(a.x, row_base, w.o[2] + w.p[2] * q.c, w.A[2], w.taps, a.c);
+    } else {
+      const int ic = w.o[2] + w.p[2] * q.c;
+      acc = taps_rows<TT>(a.x, ib * w.A[1] * w.A[2], w.o[1] + w.p[1] * q.r, w.A[1], w.A[2], ic,
+                          w.taps, a.c);
+    }
+    a.y[o] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fused chain: out = V(H(x))
+// ---------------------------------------------------------------------------
+template <bool VEC, int T0, int T1>
+__global__ void __launch_bounds__(kBlock) fir_chain_kernel(FirChainArgs a) {
+  const Win3& h = a.h;
+  const Win3& v = a.v;
+  const uint32_t stride = gridDim.x * kBlock;
+  const int t1 = T1 ? T1 : v.taps;
+  for (uint32_t o = blockIdx.x * kBlock + threadIdx.x; o < a.n_out; o += stride) {
+    const OutPos q = decode(o, v, a.div_rc, a.div_rr);
+    const int mb = v.o[0] + v.p[0] * q.b;          // intermediate frame
+    const int mc = v.o[2] + v.p[2] * q.c;          // intermediate column
+    const int xb = h.o[0] + h.p[0] * mb;           // input frame
+    const int xstart = h.o[2] + h.p[2] * mc;       // first input column of the window
+    int mr = wrap_mod(int64_t(v.o[1]) + int64_t(v.p[1]) * q.r, v.A[1]);
+    float acc = 0.0f;
+#pragma unroll
+    for (int j = 0; j < (T1 ? T1 : 1 << 30); ++j) {
+      if (j >= t1) break;
+      const int xr = h.o[1] + h.p[1] * mr;
+      const int row_base = (xb * h.A[1] + xr) * h.A[2];
+      const float mid = taps_contig<VEC, T0>(a.x, row_base, xstart, h.A[2], h.taps, a.ch);
+      acc = fmaf(a.cv[j], mid, acc);
+      if (++mr == v.A[1]) mr = 0;
+    }
+    a.y[o] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// weight-gradient reduction inside the adjoint kernels
+//
+// Each workgroup reduces its per-thread partial vectors (wavefront butterfly,
+// then across the 4 waves in LDS) and stores one row of partials.  The
+// workgroup that arrives last at the completion counter sums the rows in a
+// fixed order and writes the gradient, so the result does not depend on
+// scheduling.  Rows are written and read with agent-scope atomic accesses and
+// the counter is updated with acquire-release ordering, which keeps the
+// exchange coherent across the XCDs' separate L2 caches.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void store_agent(float* p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float load_agent(const float* p) {
+  return __hip_atomic_load(const_cast<float*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int N>
+__device__ __forceinline__ void block_reduce_store(float (&v)[N], int n, float* out_row) {
+  __shared__ float sm[kBlock / 64][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    float t = v[i];
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) t += __shfl_xor(t, m);
+    v[i] = t;
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) sm[wave][i] = v[i];
+  }
+  __syncthreads();
+  if (int(threadIdx.x) < n) {
+    float t = 0.0f;
+#pragma unroll
+    for (int wv = 0; wv < kBlock / 64; ++wv) t += sm[wv][threadIdx.x];
+    store_agent(out_row + threadIdx.x, t);
+  }
+}
+
+// True in the last workgroup to arrive (all rows of partials are then visible).
+__device__ __forceinline__ bool arrive_last(uint32_t* counter) {
+  __shared__ int last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t prev =
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = prev == gridDim.x - 1;
+  }
+  __syncthreads();
+  return last != 0;
+}
+
+// out[j] (=|+=) sum over rows b < n_rows of partial[b * row + col0 + j], j < count
+__device__ __forceinline__ void reduce_rows_fixed(const float* partial, int n_rows, int row,
+                                                  int col0, int count, float* out, int accumulate) {
+  __shared__ float red[kBlock];
+  for (int j = 0; j < count; ++j) {
+    float acc = 0.0f;
+    for (int b = threadIdx.x; b < n_rows; b += kBlock) acc += load_agent(partial + int64_t(b) * row + col0 + j);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+      if (int(threadIdx.x) < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = accumulate ? out[j] + red[0] : red[0];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint of one injective FIR stage
+// ---------------------------------------------------------------------------
+template <int AX, bool VEC, int TT>
+__global__ void __launch_bounds__(kBlock) fir_adjoint_kernel(FirAdjArgs a) {
+  const Win3& w = a.w;
+  const int taps = TT ? TT : w.taps;
+  float gc[kMaxTaps];
+#pragma unroll
+  for (int k = 0; k < kMaxTaps; ++k) gc[k] = 0.0f;
+  float cr[kMaxTaps];
+#pragma unroll
+  for (int k = 0; k < kMaxTaps; ++k) cr[k] = k < taps ? a.c[k] : 0.0f;
+
+  const uint32_t stride = gridDim.x * kBlock;
+  for (uint32_t o = blockIdx.x * kBlock + threadIdx.x; o < a.n_rep; o += stride) {
+    const OutPos q = decode(o, w, a.div_rc, a.div_rr);
+    const float g = a.gy[o];
+    const int ib = w.o[0] + w.p[0] * q.b;
+    int base, step, pos, n;
+    if (AX == 2) {
+      base = (ib * w.A[1] + w.o[1] + w.p[1] * q.r) * w.A[2];
+      pos = w.o[2] + w.p[2] * q.c;
+      step = 1;
+      n = w.A[2];
+    } else {
+      base = ib * w.A[1] * w.A[2] + w.o[2] + w.p[2] * q.c;
+      pos = w.o[1] + w.p[1] * q.r;
+      step = w.A[2];
+      n = w.A[1];
+    }
+    const bool inside = pos >= 0 && pos + taps <= n;
+    if (AX == 2 && VEC && inside) {
+      float* gxp = a.gx ? a.gx + base + pos : nullptr;
+      const float* xp = a.x ? a.x + base + pos : nullptr;
+#pragma unroll
+      for (int q4 = 0; q4 < (TT ? TT : kMaxTaps) / 4; ++q4) {
+        if (4 * q4 >= taps) break;
+        if (xp) {
+          const float4 xv = *reinterpret_cast<const float4*>(xp + 4 * q4);
+          gc[4 * q4 + 0] = fmaf(g, xv.x, gc[4 * q4 + 0]);
+          gc[4 * q4 + 1] = fmaf(g, xv.y, gc[4 * q4 + 1]);
+          gc[4 * q4 + 2] = fmaf(g, xv.z, gc[4 * q4 + 2]);
+          gc[4 * q4 + 3] = fmaf(g, xv.w, gc[4 * q4 + 3]);
+        }
+        if (gxp) {
+          float4 gv = make_float4(cr[4 * q4 + 0] * g, cr[4 * q4 + 1] * g, cr[4 * q4 + 2] * g,
+                                  cr[4 * q4 + 3] * g);
+          float4* dst = reinterpret_cast<float4*>(gxp + 4 * q4);
+          if (a.accumulate) {
+            const float4 old = *dst;
+            gv.x += old.x; gv.y += old.y; gv.z += old.z; gv.w += old.w;
+          }
+          *dst = gv;
+        }
+      }
+    } else {
+      int e = inside ? pos : wrap_mod(pos, n);
+#pragma unroll
+      for (int k = 0; k < (TT ? TT : kMaxTaps); ++k) {
+        if (k >= taps) break;
+        const int off = base + e * step;
+        if (a.x) gc[k] = fmaf(g, a.x[off], gc[k]);
+        if (a.gx) {
+          const float gv = cr[k] * g;
+          a.gx[off] = a.accumulate ? a.gx[off] + gv : gv;
+        }
+        if (++e == n) e = 0;
+      }
+    }
+  }
+  if (a.partial) {
+    block_reduce_store<kMaxTaps>(gc, taps, a.partial + int64_t(blockIdx.x) * taps);
+    if (arrive_last(a.counter)) {
+      reduce_rows_fixed(a.partial, gridDim.x, taps, 0, taps, a.gc, a.accumulate);
+      if (threadIdx.x == 0) __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint of the fused chain (both stages injective)
+// ---------------------------------------------------------------------------
+template <bool VEC, int T0, int T1>
+__global__ void __launch_bounds__(kBlock) fir_chain_adjoint_kernel(FirChainAdjArgs a) {
+  const Win3& h = a.h;
+  const Win3& v = a.v;
+  const int t0 = T0 ? T0 : h.taps;
+  const int t1 = T1 ? T1 : v.taps;
+  float ch[kMaxTaps], cv[kMaxTaps], gp[2 * kMaxTaps];
+#pragma unroll
+  for (int k = 0; k < kMaxTaps; ++k) {
+    ch[k] = k < t0 ? a.ch[k] : 0.0f;
+    cv[k] = k < t1 ? a.cv[k] : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < 2 * kMaxTaps; ++k) gp[k] = 0.0f;
+
+  const uint32_t stride = gridDim.x * kBlock;
+  for (uint32_t o = blockIdx.x * kBlock + threadIdx.x; o < a.n_out; o += stride) {
+    const OutPos q = decode(o, v, a.div_rc, a.div_rr);
+    const float g = a.gy[o];
+    const int mb = v.o[0] + v.p[0] * q.b;
+    const int mc = v.o[2] + v.p[2] * q.c;
+    const int xb = h.o[0] + h.p[0] * mb;
+    const int xstart = h.o[2] + h.p[2] * mc;
+    const bool inside = xstart >= 0 && xstart + t0 <= h.A[2];
+    int mr = wrap_mod(int64_t(v.o[1]) + int64_t(v.p[1]) * q.r, v.A[1]);
+#pragma unroll
+    for (int j = 0; j < (T1 ? T1 : kMaxTaps); ++j) {
+      if (j >= t1) break;
+      const int row_base = (xb * h.A[1] + h.o[1] + h.p[1] * mr) * h.A[2];
+      const float gm = cv[j] * g;          // gradient of this intermediate element
+      float xs[kMaxTaps];
+      if (VEC && inside) {
+        const float* xp = a.x + row_base + xstart;
+#pragma unroll
+        for (int q4 = 0; q4 < (T0 ? T0 : kMaxTaps) / 4; ++q4) {
+          if (4 * q4 >= t0) break;
+          const float4 xv = *reinterpret_cast<const float4*>(xp + 4 * q4);
+          xs[4 * q4 + 0] = xv.x; xs[4 * q4 + 1] = xv.y;
+          xs[4 * q4 + 2] = xv.z; xs[4 * q4 + 3] = xv.w;
+        }
+      } else {
+        int e = inside ? xstart : wrap_mod(xstart, h.A[2]);
+#pragma unroll
+        for (int k = 0; k < (T0 ? T0 : kMaxTaps); ++k) {
+          if (k >= t0) break;
+          xs[k] = a.x[row_base + e];
+          if (++e == h.A[2]) e = 0;
+        }
+      }
+      float mid = 0.0f;
+#pragma unroll
+      for (int k = 0; k < (T0 ? T0 : kMaxTaps); ++k) {
+        if (k >= t0) break;
+        mid = fmaf(ch[k], xs[k], mid);
+        gp[k] = fmaf(gm, xs[k], gp[k]);                 // d/dch[k]
+      }
+      gp[kMaxTaps + j] = fmaf(g, mid, gp[kMaxTaps + j]);  // d/dcv[j]
+      if (a.gx) {
+        if (VEC && inside) {
+          float* dst = a.gx + row_base + xstart;
+#pragma unroll
+          for (int q4 = 0; q4 < (T0 ? T0 : kMaxTaps) / 4; ++q4) {
+            if (4 * q4 >= t0) break;
+            float4 gv = make_float4(ch[4 * q4 + 0] * gm, ch[4 * q4 + 1] * gm,
+                                    ch[4 * q4 + 2] * gm, ch[4 * q4 + 3] * gm);
+            float4* d4 = reinterpret_cast<float4*>(dst + 4 * q4);
+            if (a.accumulate) {
+              const float4 old = *d4;
+              gv.x += old.x; gv.y += old.y; gv.z += old.z; gv.w += old.w;
+            }
+            *d4 = gv;
+          }
+        } else {
+          int e = inside ? xstart : wrap_mod(xstart, h.A[2]);
+#pragma unroll
+          for (int k = 0; k < (T0 ? T0 : kMaxTaps); ++k) {
+            if (k >= t0) break;
+            const float gv = ch[k] * gm;
+            float* d = a.gx + row_base + e;
+            *d = a.accumulate ? *d + gv : gv;
+            if (++e == h.A[2]) e = 0;
+          }
+        }
+      }
+      if (++mr == v.A[1]) mr = 0;
+    }
+  }
+  if (a.partial) {
+    // pack [ch grads (t0) | cv grads (t1)] contiguously
+    float packed[2 * kMaxTaps];
+#pragma unroll
+    for (int k = 0; k < 2 * kMaxTaps; ++k) packed[k] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kMaxTaps; ++k) {
+      if (k < t0) packed[k] = gp[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxTaps; ++k) {
+      if (k < t1) packed[t0 + k] = gp[kMaxTaps + k];
+    }
+    block_reduce_store<2 * kMaxTaps>(packed, t0 + t1, a.partial + int64_t(blockIdx.x) * (t0 + t1));
+    if (arrive_last(a.counter)) {
+      if (a.gch) reduce_rows_fixed(a.partial, gridDim.x, t0 + t1, 0, t0, a.gch, a.accumulate);
+      if (a.gcv) reduce_rows_fixed(a.partial, gridDim.x, t0 + t1, t0, t1, a.gcv, a.accumulate);
+      if (threadIdx.x == 0) __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+int stream_grid(uint32_t work, int waves_per_cu = 8) {
+  // enough resident blocks to cover the chip several times, grid-stride beyond
+  const int cap = 256 * waves_per_cu;
+  const uint32_t need = (work + kBlock - 1) / kBlock;
+  return int(need < uint32_t(cap) ? (need ? need : 1) : cap);
+}
+
+}  // namespace
+
+hipError_t launch_pattern_reduce(const PatternReduceArgs& a, int max_rank, hipStream_t st) {
+  const int64_t lanes = a.n_rep << a.group_log2;
+  int64_t grid = (lanes + kBlock - 1) / kBlock;
+  if (grid < 1) grid = 1;
+  if (grid > 16384) grid = 16384;
+  if (max_rank <= 4)
+    pattern_reduce_kernel<4><<<unsigned(grid), kBlock, 0, st>>>(a);
+  else
+    pattern_reduce_kernel<kMaxRank><<<unsigned(grid), kBlock, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fir(const FirArgs& a, bool vec4, hipStream_t st) {
+  const int grid = stream_grid(a.n_out, 16);
+  if (a.w.ax == 2) {
+    if (vec4 && a.w.taps == 8)
+      fir_kernel<2, true, 8><<<grid, kBlock, 0, st>>>(a);
+    else if (vec4)
+      fir_kernel<2, true, 0><<<grid, kBlock, 0, st>>>(a);
+    else if (a.w.taps == 8)
+      fir_kernel<2, false, 8><<<grid, kBlock, 0, st>>>(a);
+    else
+      fir_kernel<2, false, 0><<<grid, kBlock, 0, st>>>(a);
+  } else {
+    if (a.w.taps == 8)
+      fir_kernel<1, false, 8><<<grid, kBlock, 0, st>>>(a);
+    else
+      fir_kernel<1, false, 0><<<grid, kBlock, 0, st>>>(a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fir_chain(const FirChainArgs& a, bool vec4, hipStream_t st) {
+  const int grid = stream_grid(a.n_out, 16);
+  if (vec4 && a.h.taps == 8 && a.v.taps == 8)
+    fir_chain_kernel<true, 8, 8><<<grid, kBlock, 0, st>>>(a);
+  else if (vec4)
+    fir_chain_kernel<true, 0, 0><<<grid, kBlock, 0, st>>>(a);
+  else
+    fir_chain_kernel<false, 0, 0><<<grid, kBlock, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+int fir_adjoint_grid(const FirAdjArgs& a) { return stream_grid(a.n_rep, 8); }
+
+hipError_t launch_fir_adjoint(const FirAdjArgs& a, bool vec4, int* grid_out, hipStream_t st) {
+  const int grid = fir_adjoint_grid(a);
+  if (grid_out) *grid_out = grid;
+  if (a.w.ax == 2) {
+    if (vec4 && a.w.taps == 8)
+      fir_adjoint_kernel<2, true, 8><<<grid, kBlock, 0, st>>>(a);
+    else if (vec4)
+      fir_adjoint_kernel<2, true, 0><<<grid, kBlock, 0, st>>>(a);
+    else
+      fir_adjoint_kernel<2, false, 0><<<grid, kBlock, 0, st>>>(a);
+  } else {
+    if (a.w.taps == 8)
+      fir_adjoint_kernel<1, false, 8><<<grid, kBlock, 0, st>>>(a);
+    else
+      fir_adjoint_kernel<1, false, 0><<<grid, kBlock, 0, st>>>(a);
+  }
+  return hipGetLastError();
+}
+
+int fir_chain_adjoint_grid(const FirChainAdjArgs& a) { return stream_grid(a.n_out, 8); }
+
+hipError_t launch_fir_chain_adjoint(const FirChainAdjArgs& a, bool vec4, hipStream_t st) {
+  const int grid = fir_chain_adjoint_grid(a);
+  if (vec4 && a.h.taps == 8 && a.v.taps == 8)
+    fir_chain_adjoint_kernel<true, 8, 8><<<grid, kBlock, 0, st>>>(a);
+  else if (vec4)
+    fir_chain_adjoint_kernel<true, 0, 0><<<grid, kBlock, 0, st>>>(a);
+  else
+    fir_chain_adjoint_kernel<false, 0, 0><<<grid, kBlock, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace rsm

@@ -1,0 +1,256 @@
+// rsm_internal.h -- descriptors shared by the host planner and the gfx950 kernels.
+//
+// The planner (api.cpp) validates a task, reduces every tiler to a
+// canonical device descriptor and picks a kernel family; the launchers
+// (k_*.hip) only launch.  Nothing here is part of the public C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "rsm.h"
+
+namespace rsm {
+
+constexpr int kMaxRank = RSM_MAX_RANK;
+
+// ---------------------------------------------------------------------------
+// Generic tiler descriptor (any affine tiler, int64 arithmetic).
+// origin/paving/fitting are stored reduced into [0, s_d) so that every step
+// of an incremental walk is an add plus at most one conditional subtract.
+// ---------------------------------------------------------------------------
+struct GTiler {
+  int32_t arr_rank;
+  int32_t pat_rank;
+  int64_t shape[kMaxRank];
+  int64_t origin[kMaxRank];              // o mod s
+  int64_t pav[kMaxRank][kMaxRank];       // P mod s  [d][k]
+  int64_t fit[kMaxRank][kMaxRank];       // F mod s  [d][k]
+  int64_t pat_shape[kMaxRank];
+};
+
+enum TaskKind : int32_t { kCopy = 0, kSum = 1, kWsum = 2, kDot = 3 };
+
+struct GenericArgs {
+  int32_t rep_rank;
+  int32_t n_in;
+  int64_t rep_shape[kMaxRank];
+  int64_t n_rep;   // |s_r|
+  int64_t n_pat;   // |s_p| (flat pattern length walked by every tiler)
+  GTiler in[2];
+  GTiler out;
+  const void* x[2];
+  void* y;
+  const void* coeffs;
+};
+
+// Canonical 3-D view [B, R, C] of an axis-aligned tiler: diagonal paving
+// (repetition dim d steps array dim d by p[d]), origin o, and a 1-D pattern
+// of `taps` elements along axis `ax` with unit fitting, or a 2-D pattern
+// along axes (1, 2) with unit fitting.  All values fit in int32.
+struct Win3 {
+  int32_t A[3];     // array shape
+  int32_t rep[3];   // repetition shape
+  int32_t o[3];     // origin as given (may be negative)
+  int32_t p[3];     // paving diagonal (>= 0)
+  int32_t ax;       // tap axis for 1-D patterns (1 or 2); 0 for 2-D patterns
+  int32_t taps;     // 1-D: pattern length; 2-D: rows of the pattern
+  int32_t taps2;    // 2-D: columns of the pattern; 1 otherwise
+};
+
+// Unsigned 32-bit division by a run-time constant via multiply-high
+// (round-up method of Granlund & Montgomery, 1994): q = (hi(n*m) + n) >> s,
+// exact for every n < 2^32 when d >= 1.
+struct FastDiv {
+  uint32_t d, m, s;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  uint32_t s = 0;
+  while ((uint64_t(1) << s) < d) ++s;
+  f.s = s;
+  f.m = uint32_t(((uint64_t(1) << 32) * ((uint64_t(1) << s) - d)) / d + 1);
+  return f;
+}
+
+__host__ __device__ inline uint32_t fdiv(uint32_t n, const FastDiv& f) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  uint32_t hi = __umulhi(n, f.m);
+#else
+  uint32_t hi = uint32_t((uint64_t(n) * f.m) >> 32);
+#endif
+  return uint32_t((uint64_t(hi) + n) >> f.s);
+}
+
+// 1-D tap filter (FIR) over a Win3 view, identity output tiler.
+struct FirArgs {
+  Win3 w;
+  FastDiv div_rc;     // divide by rep[2]
+  FastDiv div_rr;     // divide by rep[1]
+  uint32_t n_out;     // rep[0]*rep[1]*rep[2]
+  const float* x;
+  float* y;
+  const float* c;
+};
+
+// Two chained FIR stages, the first along axis 2 and the second along axis 1.
+struct FirChainArgs {
+  Win3 h;             // stage 0 (taps along columns), on x
+  Win3 v;             // stage 1 (taps along rows), on the stage-0 output
+  FastDiv div_rc;     // divide by v.rep[2]
+  FastDiv div_rr;     // divide by v.rep[1]
+  uint32_t n_out;
+  const float* x;
+  float* y;
+  const float* ch;
+  const float* cv;
+};
+
+// Adjoint of an injective FIR stage (no input element read twice).
+struct FirAdjArgs {
+  Win3 w;
+  FastDiv div_rc, div_rr;
+  uint32_t n_rep;
+  const float* x;      // nullable when gc is not requested
+  const float* gy;
+  float* gx;           // nullable
+  const float* c;
+  float* partial;      // [gridDim.x][taps] per-block weight-gradient partials, nullable
+  float* gc;           // weight gradient (written by the last workgroup), nullable
+  uint32_t* counter;   // zero on entry; workgroups count in, the last one resets it
+  int32_t accumulate;
+};
+
+struct FirChainAdjArgs {
+  Win3 h, v;
+  FastDiv div_rc, div_rr;
+  uint32_t n_out;
+  const float* x;
+  const float* gy;
+  float* gx;           // nullable
+  const float* ch;
+  const float* cv;
+  float* partial;      // [gridDim.x][h.taps + v.taps], nullable
+  float* gch;          // weight gradients (written by the last workgroup), nullable
+  float* gcv;
+  uint32_t* counter;   // zero on entry; the last workgroup resets it
+  int32_t accumulate;
+};
+
+// Small-pattern reduction: a group of G lanes (G = 2^k >= |pattern|, G <= 64)
+// per repetition, one lane per pattern element, butterfly reduction.
+struct PatternReduceArgs {
+  int32_t rep_rank;
+  int32_t group_log2;
+  int64_t rep_shape[kMaxRank];
+  int64_t n_rep;
+  int64_t n_pat;
+  GTiler in;
+  GTiler out;
+  const float* x;
+  float* y;
+  const float* c;      // nullable (SUM)
+};
+
+// Generic adjoint: gx by atomic scatter-add, weight gradient by partials.
+struct GenericAdjArgs {
+  int32_t rep_rank;
+  int64_t rep_shape[kMaxRank];
+  int64_t n_rep;
+  int64_t n_pat;
+  GTiler in;
+  GTiler out;
+  const float* x;
+  const float* gy;
+  float* gx;
+  const float* c;      // nullable (SUM)
+};
+
+struct GenericCoefGradArgs {
+  int32_t rep_rank;
+  int64_t rep_shape[kMaxRank];
+  int64_t n_rep;
+  int64_t n_pat;
+  GTiler in;
+  GTiler out;
+  const float* x;
+  const float* gy;
+  float* partial;      // [n_pat][gridDim.x]
+  int64_t chunk;       // repetitions per block
+};
+
+// Dense matrix product recognised from DOT tilers: C[M,N] = A . B with
+// A element (m,k) at a + m*lda_m + k*lda_k and B element (k,n) at
+// b + k*ldb_k + n*ldb_n (one stride of each pair is 1).
+struct GemmArgs {
+  int32_t M, N, K;
+  int64_t a_sm, a_sk;   // strides of A along m and k
+  int64_t b_sk, b_sn;   // strides of B along k and n
+  int64_t c_sm;         // row stride of C (column stride 1)
+  const void* a;
+  const void* b;
+  float* c;
+};
+
+// 2-D k x k window, stride s, on one [H, W] array (batched over B frames),
+// identity output [ceil-ish rep rows, rep cols].
+struct Filter2DProblem {
+  int32_t H, W;         // input array
+  int32_t RH, RW;       // output (repetition) shape
+  int32_t oh, ow;       // origin mod H, mod W
+  int32_t k, s;         // pattern side, paving stride
+  int32_t tile_h, tile_w;
+  int32_t tiles_w;      // tiles along W
+  int32_t n_tiles;      // tiles of this problem
+  int64_t tile_base;    // first tile id of this problem in a batch queue
+  const float* x;
+  float* y;
+  const float* c;       // k*k coefficients
+};
+
+// ---------------------------------------------------------------------------
+// launchers (return hipError_t of the launch)
+// ---------------------------------------------------------------------------
+hipError_t launch_indices(const GTiler& t, int rep_rank, const int64_t* rep_shape,
+                          int64_t n_rep, int64_t n_pat, int64_t* d_idx, hipStream_t st);
+hipError_t launch_generic(const GenericArgs& a, int max_rank, int in_dtype, int out_dtype,
+                          int kind, int elem_bytes, hipStream_t st);
+hipError_t launch_pattern_reduce(const PatternReduceArgs& a, int max_rank, hipStream_t st);
+hipError_t launch_fir(const FirArgs& a, bool vec4, hipStream_t st);
+hipError_t launch_fir_chain(const FirChainArgs& a, bool vec4, hipStream_t st);
+hipError_t launch_fir_adjoint(const FirAdjArgs& a, bool vec4, int* grid_out, hipStream_t st);
+int fir_adjoint_grid(const FirAdjArgs& a);
+hipError_t launch_fir_chain_adjoint(const FirChainAdjArgs& a, bool vec4, hipStream_t st);
+int fir_chain_adjoint_grid(const FirChainAdjArgs& a);
+hipError_t launch_reduce_partials(const float* partial, int n_blocks, int n_coef, int row_stride,
+                                  float* out, int accumulate, hipStream_t st);
+hipError_t launch_generic_adjoint(const GenericAdjArgs& a, int max_rank, hipStream_t st);
+hipError_t launch_generic_coef_grad(const GenericCoefGradArgs& a, int max_rank, int n_blocks,
+                                    hipStream_t st);
+hipError_t launch_reduce_rows(const float* partial, int64_t n_rows, int64_t n_cols,
+                              float* out, int accumulate, hipStream_t st);
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
+hipError_t launch_gemm(const GemmArgs& a, int compute, hipStream_t st);
+const char* gemm_variant_name(const GemmArgs& a, int compute);
+bool gemm_supported(const GemmArgs& a, int compute);
+hipError_t launch_filter2d(const Filter2DProblem& p, hipStream_t st);
+hipError_t launch_filter2d_persistent(const Filter2DProblem* d_probs, int n_probs,
+                                      const int64_t* d_tile_prefix, int64_t n_tiles,
+                                      int grid, hipStream_t st);
+int filter2d_persistent_grid();
+bool filter2d_supported(int k, int s, int tile_h, int tile_w);
+
+// Device workspace owned by the library (per device, grown on demand).
+// *counter (if given) receives a 32-bit completion counter that is zero
+// between kernels (kernels that use it leave it at zero).
+void* workspace(size_t bytes, hipStream_t st, rsm_status* err, uint32_t** counter = nullptr);
+
+// Error reporting: sets the thread-local detail string and returns s.
+rsm_status fail(rsm_status s, const std::string& msg);
+rsm_status hip_fail(hipError_t e, const char* what);
+
+}  // namespace rsm

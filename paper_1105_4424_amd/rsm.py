@@ -1,0 +1,364 @@
+"""torch-facing wrappers over the C-ABI (marshalling only).
+
+Tiler descriptions are duck-typed: any object with ``array_shape``,
+``origin``, ``paving`` (d_a x d_r), ``fitting`` (d_a x d_p) and
+``pattern_shape`` works (``rsm_workloads.Tiler`` is one).  A problem has
+``rep_shape``, ``inputs`` (list of tilers), ``output`` (tiler) and ``task``
+(0 copy, 1 sum, 2 weighted sum, 3 dot).  Arrays are contiguous torch
+tensors on the GPU; weights are passed as device tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _abi
+
+_DTYPES = {torch.float32: _abi.F32, torch.bfloat16: _abi.BF16, torch.float64: _abi.F64,
+           torch.int64: _abi.I64}
+_COMPUTE = {"f32": _abi.F32, "bf16": _abi.BF16, "f64": _abi.F64}
+
+
+class RsmError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        lib = _abi.load()
+        name = lib.rsm_status_string(status).decode()
+        super().__init__("%s: %s" % (name, detail))
+        self.status = status
+        self.name = name
+
+
+def _check(status: int):
+    if status != _abi.OK:
+        raise RsmError(status, _abi.load().rsm_last_error().decode())
+
+
+def _space(rep_shape: Sequence[int]) -> _abi.Space:
+    s = _abi.Space()
+    s.rank = len(rep_shape)
+    for k, v in enumerate(list(rep_shape)[:_abi.MAX_RANK]):
+        s.shape[k] = int(v)
+    return s
+
+
+def _tiler(t, dtype: int) -> _abi.Tiler:
+    s = _abi.Tiler()
+    shape = tuple(int(v) for v in t.array_shape)
+    pshape = tuple(int(v) for v in t.pattern_shape)
+    da, dp = len(shape), len(pshape)
+    P = np.asarray(t.paving, dtype=np.int64).reshape(da, -1) if da else np.zeros((0, 0), np.int64)
+    F = np.asarray(t.fitting, dtype=np.int64).reshape(da, dp)
+    o = np.asarray(t.origin, dtype=np.int64).reshape(da)
+    # ranks are passed as given (the library rejects ranks above 8); only the
+    # entries that fit in the fixed-size arrays are copied
+    s.array_rank, s.pattern_rank, s.dtype = da, dp, dtype
+    M = _abi.MAX_RANK
+    for d in range(min(da, M)):
+        s.array_shape[d] = shape[d]
+        s.origin[d] = int(o[d])
+        for k in range(min(P.shape[1], M)):
+            s.paving[d][k] = int(P[d, k])
+        for k in range(min(dp, M)):
+            s.fitting[d][k] = int(F[d, k])
+    for k in range(min(dp, M)):
+        s.pattern_shape[k] = pshape[k]
+    return s
+
+
+def _dcode(t: torch.Tensor) -> int:
+    try:
+        return _DTYPES[t.dtype]
+    except KeyError:
+        raise TypeError("unsupported dtype %s" % t.dtype)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if t.device.type != "cuda":
+        raise ValueError("arrays must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("arrays must be contiguous (row-major)")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _task(kind: int, compute: int, coeffs: Optional[torch.Tensor]) -> _abi.Task:
+    t = _abi.Task()
+    t.kind, t.compute = int(kind), int(compute)
+    t.coeffs = _ptr(coeffs).value if coeffs is not None else None
+    return t
+
+
+def _compute_for(problem, x: torch.Tensor) -> int:
+    c = getattr(problem, "compute", "f32")
+    if x.dtype == torch.float64:
+        return _abi.F64
+    return _COMPUTE.get(c, _abi.F32)
+
+
+def _out_dtype_code(problem, x: torch.Tensor) -> int:
+    if problem.task == _abi.TASK_COPY:
+        return _dcode(x)
+    return _abi.F64 if x.dtype == torch.float64 else _abi.F32
+
+
+# ---------------------------------------------------------------------------
+# plain calls
+# ---------------------------------------------------------------------------
+
+def validate(problem, dtypes: Sequence[torch.dtype] = (torch.float32,),
+             check_single_assign: bool = False, compute: str = None):
+    lib = _abi.load()
+    codes = [_DTYPES[d] for d in dtypes]
+    tin = (_abi.Tiler * len(problem.inputs))(*[_tiler(t, codes[min(i, len(codes) - 1)])
+                                               for i, t in enumerate(problem.inputs)])
+    c0 = codes[0]
+    out_code = c0 if problem.task == _abi.TASK_COPY else (_abi.F64 if c0 == _abi.F64 else _abi.F32)
+    comp = _COMPUTE[compute] if compute else (_abi.F64 if c0 == _abi.F64 else
+                                              _COMPUTE.get(getattr(problem, "compute", "f32")))
+    task = _abi.Task(problem.task, comp, ctypes.c_void_p(1).value)
+    _check(lib.rsm_validate(ctypes.byref(_space(problem.rep_shape)), tin, len(problem.inputs),
+                            ctypes.byref(_tiler(problem.output, out_code)), ctypes.byref(task),
+                            _abi.CHECK_SINGLE_ASSIGN if check_single_assign else 0))
+
+
+def plan(problem, dtypes: Sequence[torch.dtype] = (torch.float32,), flags: int = 0,
+         compute: str = None) -> str:
+    """Kernel family the planner picks (host only)."""
+    lib = _abi.load()
+    codes = [_DTYPES[d] for d in dtypes]
+    tin = (_abi.Tiler * len(problem.inputs))(*[_tiler(t, codes[min(i, len(codes) - 1)])
+                                               for i, t in enumerate(problem.inputs)])
+    c0 = codes[0]
+    out_code = c0 if problem.task == _abi.TASK_COPY else (_abi.F64 if c0 == _abi.F64 else _abi.F32)
+    comp = _COMPUTE[compute] if compute else (_abi.F64 if c0 == _abi.F64 else
+                                              _COMPUTE.get(getattr(problem, "compute", "f32")))
+    task = _abi.Task(problem.task, comp, ctypes.c_void_p(1).value)
+    buf = ctypes.create_string_buffer(64)
+    _check(lib.rsm_plan(ctypes.byref(_space(problem.rep_shape)), tin, len(problem.inputs),
+                        ctypes.byref(_tiler(problem.output, out_code)), ctypes.byref(task), flags,
+                        buf, 64))
+    return buf.value.decode()
+
+
+def indices(rep_shape: Sequence[int], tiler, device="cuda", stream=None) -> torch.Tensor:
+    """Index table e(r, i) (linear offsets), int64 [|s_r|, |s_p|], on the GPU."""
+    lib = _abi.load()
+    nr = int(np.prod(rep_shape)) if len(rep_shape) else 1
+    np_ = int(np.prod(tiler.pattern_shape)) if len(tiler.pattern_shape) else 1
+    out = torch.empty((nr, np_), dtype=torch.int64, device=device)
+    _check(lib.rsm_indices(ctypes.byref(_space(rep_shape)), ctypes.byref(_tiler(tiler, _abi.F32)),
+                           _ptr(out), _stream(stream)))
+    return out
+
+
+def run(problem, inputs: List[torch.Tensor], out: torch.Tensor, coeffs: torch.Tensor = None,
+        flags: int = 0, stream=None, compute: str = None) -> torch.Tensor:
+    lib = _abi.load()
+    n = len(inputs)
+    tin = (_abi.Tiler * n)(*[_tiler(t, _dcode(x)) for t, x in zip(problem.inputs, inputs)])
+    ptrs = (ctypes.c_void_p * n)(*[_ptr(x).value for x in inputs])
+    comp = _COMPUTE[compute] if compute else _compute_for(problem, inputs[0])
+    task = _task(problem.task, comp, coeffs)
+    _check(lib.rsm_run(ctypes.byref(_space(problem.rep_shape)), tin, ptrs, n,
+                       ctypes.byref(_tiler(problem.output, _dcode(out))), _ptr(out),
+                       ctypes.byref(task), flags, _stream(stream)))
+    return out
+
+
+def _stages(stages, coeffs, x_dtype=torch.float32):
+    n = len(stages)
+    arr = (_abi.Stage * n)()
+    for k, st in enumerate(stages):
+        arr[k].rep = _space(st.rep_shape)
+        arr[k].in_ = _tiler(st.inputs[0], _DTYPES[x_dtype])
+        arr[k].out = _tiler(st.output, _abi.F64 if x_dtype == torch.float64 else _abi.F32)
+        c = coeffs[k] if coeffs is not None else None
+        arr[k].task = _task(st.task, _abi.F64 if x_dtype == torch.float64 else _abi.F32, c)
+    return arr
+
+
+def run_chain(stages, x: torch.Tensor, out: torch.Tensor, coeffs: Sequence[torch.Tensor],
+              mids: Optional[Sequence[torch.Tensor]] = None, flags: int = 0, stream=None):
+    lib = _abi.load()
+    arr = _stages(stages, coeffs, x.dtype)
+    mp = None
+    if mids is not None:
+        mp = (ctypes.c_void_p * len(mids))(*[_ptr(m).value for m in mids])
+    _check(lib.rsm_run_chain(arr, len(stages), _ptr(x), mp, _ptr(out), flags, _stream(stream)))
+    return out
+
+
+def run_adjoint(problem, x: Optional[torch.Tensor], gy: torch.Tensor,
+                gx: Optional[torch.Tensor] = None, gc: Optional[torch.Tensor] = None,
+                coeffs: Optional[torch.Tensor] = None, flags: int = 0, stream=None):
+    lib = _abi.load()
+    task = _task(problem.task, _abi.F32, coeffs)
+    _check(lib.rsm_run_adjoint(ctypes.byref(_space(problem.rep_shape)),
+                               ctypes.byref(_tiler(problem.inputs[0], _abi.F32)), _ptr(x),
+                               ctypes.byref(_tiler(problem.output, _abi.F32)), _ptr(gy),
+                               ctypes.byref(task), _ptr(gx), _ptr(gc), flags, _stream(stream)))
+
+
+def run_chain_adjoint(stages, x: torch.Tensor, gy: torch.Tensor, gx: Optional[torch.Tensor],
+                      gcs: Optional[Sequence[Optional[torch.Tensor]]], coeffs: Sequence[torch.Tensor],
+                      mids: Optional[Sequence[torch.Tensor]] = None, flags: int = 0, stream=None):
+    lib = _abi.load()
+    arr = _stages(stages, coeffs)
+    mp = None
+    if mids is not None:
+        mp = (ctypes.c_void_p * len(mids))(*[_ptr(m).value for m in mids])
+    gp = None
+    if gcs is not None:
+        gp = (ctypes.c_void_p * len(stages))(*[(_ptr(g).value if g is not None else None) for g in gcs])
+    _check(lib.rsm_run_chain_adjoint(arr, len(stages), _ptr(x), mp, _ptr(gy), _ptr(gx), gp, flags,
+                                     _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# autograd
+# ---------------------------------------------------------------------------
+
+class TiledTask(torch.autograd.Function):
+    """y = T_c(x) for a single-input SUM / WSUM task; backward runs the
+    adjoint kernels (transposed-tiler scatter-add for x, pattern reduction
+    for the weights)."""
+
+    @staticmethod
+    def forward(ctx, x, coeffs, problem, flags=0):
+        out = torch.zeros(tuple(problem.output.array_shape), device=x.device, dtype=torch.float32)
+        run(problem, [x], out, coeffs=coeffs, flags=flags)
+        ctx.save_for_backward(x, coeffs)
+        ctx.problem, ctx.flags = problem, flags
+        return out
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, coeffs = ctx.saved_tensors
+        gy = gy.contiguous()
+        gx = torch.empty_like(x) if ctx.needs_input_grad[0] else None
+        gc = torch.empty_like(coeffs) if (coeffs is not None and ctx.needs_input_grad[1]) else None
+        if gx is not None or gc is not None:
+            run_adjoint(ctx.problem, x, gy, gx, gc, coeffs, ctx.flags & _abi.FORCE_GENERIC)
+        return gx, gc, None, None
+
+
+class TiledChain(torch.autograd.Function):
+    """out = V(H(x)) for two chained weighted-sum stages.  fuse=True keeps the
+    intermediate on chip (forward) and recomputes it in the fused adjoint."""
+
+    @staticmethod
+    def forward(ctx, x, ch, cv, stages, fuse=True):
+        out = torch.empty(tuple(stages[1].output.array_shape), device=x.device, dtype=torch.float32)
+        if fuse:
+            run_chain(stages, x, out, [ch, cv])
+            mid = None
+        else:
+            mid = torch.empty(tuple(stages[0].output.array_shape), device=x.device, dtype=torch.float32)
+            run_chain(stages, x, out, [ch, cv], mids=[mid], flags=_abi.NO_FUSE)
+        ctx.save_for_backward(x, ch, cv)
+        ctx.stages, ctx.mid, ctx.fuse = stages, mid, fuse
+        return out
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, ch, cv = ctx.saved_tensors
+        gy = gy.contiguous()
+        gx = torch.empty_like(x) if ctx.needs_input_grad[0] else None
+        gch = torch.empty_like(ch) if ctx.needs_input_grad[1] else None
+        gcv = torch.empty_like(cv) if ctx.needs_input_grad[2] else None
+        run_chain_adjoint(ctx.stages, x, gy, gx, [gch, gcv], [ch, cv],
+                          mids=None if ctx.fuse else [ctx.mid],
+                          flags=0 if ctx.fuse else _abi.NO_FUSE)
+        return gx, gch, gcv, None, None
+
+
+# ---------------------------------------------------------------------------
+# batches
+# ---------------------------------------------------------------------------
+
+class Batch:
+    """Many independent single-input tasks run by one persistent launch
+    (captured once into a HIP graph, replayed by later calls)."""
+
+    def __init__(self, problems, inputs: Sequence[torch.Tensor], outputs: Sequence[torch.Tensor],
+                 coeffs: Sequence[Optional[torch.Tensor]], tune_cache: Optional[str] = None,
+                 flags: int = 0, stream=None):
+        lib = _abi.load()
+        n = len(problems)
+        arr = (_abi.Problem * n)()
+        for k, p in enumerate(problems):
+            arr[k].rep = _space(p.rep_shape)
+            arr[k].in_ = _tiler(p.inputs[0], _dcode(inputs[k]))
+            arr[k].out = _tiler(p.output, _dcode(outputs[k]))
+            arr[k].task = _task(p.task, _compute_for(p, inputs[k]), coeffs[k])
+            arr[k].d_in = _ptr(inputs[k]).value
+            arr[k].d_out = _ptr(outputs[k]).value
+        # the handle uses these buffers on every run: keep them alive
+        self._keep = (list(inputs), list(outputs), list(coeffs))
+        self._h = ctypes.c_void_p()
+        _check(lib.rsm_batch_create(arr, n, tune_cache.encode() if tune_cache else None, flags,
+                                    _stream(stream), ctypes.byref(self._h)))
+        self.n = n
+
+    def run(self, stream=None):
+        _check(_abi.load().rsm_batch_run(self._h, _stream(stream)))
+
+    def info(self) -> dict:
+        i = _abi.BatchInfo()
+        _check(_abi.load().rsm_batch_query(self._h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in _abi.BatchInfo._fields_}
+
+    def tile(self, k: int):
+        r, c = ctypes.c_int32(), ctypes.c_int32()
+        _check(_abi.load().rsm_batch_tile(self._h, k, ctypes.byref(r), ctypes.byref(c)))
+        return r.value, c.value
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _abi.load().rsm_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Chain:
+    """A chain whose descriptors are marshalled once; forward() and adjoint()
+    then cost one C call each (for tight loops)."""
+
+    def __init__(self, stages, coeffs: Sequence[torch.Tensor]):
+        self.stages = stages
+        self._coeffs = list(coeffs)
+        self._arr = _stages(stages, coeffs)
+        self._n = len(stages)
+        self._lib = _abi.load()
+
+    def forward(self, x, out, mids=None, flags: int = 0, stream=None):
+        mp = None
+        if mids is not None:
+            mp = (ctypes.c_void_p * len(mids))(*[_ptr(m).value for m in mids])
+        _check(self._lib.rsm_run_chain(self._arr, self._n, _ptr(x), mp, _ptr(out), flags,
+                                       _stream(stream)))
+        return out
+
+    def adjoint(self, x, gy, gx, gcs, mids=None, flags: int = 0, stream=None):
+        mp = None
+        if mids is not None:
+            mp = (ctypes.c_void_p * len(mids))(*[_ptr(m).value for m in mids])
+        gp = None
+        if gcs is not None:
+            gp = (ctypes.c_void_p * self._n)(*[(_ptr(g).value if g is not None else None) for g in gcs])
+        _check(self._lib.rsm_run_chain_adjoint(self._arr, self._n, _ptr(x), mp, _ptr(gy), _ptr(gx),
+                                               gp, flags, _stream(stream)))

@@ -1,0 +1,140 @@
+"""C-ABI checks that need no GPU: exports, struct layout, validation, planning."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import rsm_workloads as W
+from paper_1105_4424_amd import _abi, rsm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rsm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rsm_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = _abi.load()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(_abi.EXPORTS) == names
+    out = subprocess.run(["nm", "-D", "--defined-only", _abi.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    for n in names:
+        assert re.search(r" T %s$" % n, out, re.M), n
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "rsm.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(rsm_space), sizeof(rsm_tiler), sizeof(rsm_task),
+         sizeof(rsm_stage), sizeof(rsm_problem), sizeof(rsm_batch_info));
+  printf("%zu %zu %zu %zu %zu %zu\n", offsetof(rsm_tiler, pattern_rank), offsetof(rsm_tiler, origin),
+         offsetof(rsm_tiler, paving), offsetof(rsm_tiler, fitting), offsetof(rsm_problem, d_in),
+         offsetof(rsm_task, coeffs));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    sizes, offs = [list(map(int, l.split())) for l in
+                   subprocess.check_output([str(exe)]).decode().strip().splitlines()]
+    assert sizes == [ctypes.sizeof(c) for c in (_abi.Space, _abi.Tiler, _abi.Task, _abi.Stage,
+                                                _abi.Problem, _abi.BatchInfo)]
+    assert offs == [_abi.Tiler.pattern_rank.offset, _abi.Tiler.origin.offset,
+                    _abi.Tiler.paving.offset, _abi.Tiler.fitting.offset, _abi.Problem.d_in.offset,
+                    _abi.Task.coeffs.offset]
+
+
+def test_status_strings():
+    lib = _abi.load()
+    for s in range(9):
+        assert lib.rsm_status_string(s).decode().startswith("RSM_")
+    assert lib.rsm_abi_version() == 1
+
+
+def _expect(status_name, fn):
+    with pytest.raises(rsm.RsmError) as e:
+        fn()
+    assert e.value.name == status_name, str(e.value)
+
+
+def test_validation_errors():
+    ok_t = W.Tiler((8,), [0], [[1]], [[1]], (2,))
+    out = W.identity_output((4,))
+    # non-positive array extent
+    _expect("RSM_E_SHAPE", lambda: rsm.validate(
+        W.Problem((4,), [W.Tiler((0,), [0], [[1]], [[1]], (2,))], out, W.SUM)))
+    # non-positive pattern extent
+    _expect("RSM_E_SHAPE", lambda: rsm.validate(
+        W.Problem((4,), [W.Tiler((8,), [0], [[1]], [[1]], (0,))], out, W.SUM)))
+    # rank too large
+    big = W.Tiler((2,) * 9, [0] * 9, np.zeros((9, 1)), np.zeros((9, 0)), ())
+    _expect("RSM_E_RANK", lambda: rsm.validate(W.Problem((4,), [big], out, W.SUM)))
+    # SUM with a multi-element output pattern
+    out2 = W.Tiler((4, 2), [0, 0], [[1], [0]], [[0], [1]], (2,))
+    _expect("RSM_E_SHAPE", lambda: rsm.validate(W.Problem((4,), [ok_t], out2, W.SUM)))
+    # COPY with mismatched pattern sizes
+    _expect("RSM_E_SHAPE", lambda: rsm.validate(W.Problem((4,), [ok_t], out, W.COPY)))
+    # DOT with one input
+    _expect("RSM_E_INVALID", lambda: rsm.validate(W.Problem((4,), [ok_t], out, W.DOT)))
+    # 62-bit overflow of the index arithmetic
+    huge = W.Tiler((1 << 40,), [0], [[1]], [[1]], (1 << 23,))
+    _expect("RSM_E_OVERFLOW", lambda: rsm.validate(W.Problem((1 << 21,), [huge], W.identity_output((1 << 21,)), W.SUM)))
+    # the valid one passes
+    rsm.validate(W.Problem((4,), [ok_t], out, W.SUM))
+
+
+def test_single_assignment_check():
+    t = W.Tiler((6,), [0], [[1]], np.zeros((1, 0)), ())
+    collide = W.Tiler((3,), [0], [[1]], np.zeros((1, 0)), ())
+    p = W.Problem((6,), [t], collide, W.COPY)
+    rsm.validate(p)                       # not checked by default
+    _expect("RSM_E_OVERLAP", lambda: rsm.validate(p, check_single_assign=True))
+    rsm.validate(W.Problem((6,), [t], W.identity_output((6,)), W.COPY), check_single_assign=True)
+
+
+def test_planner_routes_workloads_to_their_kernels():
+    x, p0 = W.small_sum()
+    assert rsm.plan(p0) == "pattern_reduce"
+    ts = W.two_stage_filter(frames=2, rows=16, cols=32)
+    assert rsm.plan(ts.h) == "fir_cols_vec4"
+    assert rsm.plan(ts.v) == "fir_rows"
+    assert rsm.plan(ts.h, flags=_abi.FORCE_GENERIC) == "generic"
+    tw = W.two_stage_filter(frames=1, rows=8, cols=40, taps=13, pave=8, h_origin=-6)
+    assert rsm.plan(tw.h) == "fir_cols"
+    import torch
+    mm = W.matmul_tilers(256, 256, 256)
+    mm.compute = "bf16"
+    assert rsm.plan(mm, dtypes=(torch.bfloat16,)).startswith("gemm_mfma_bf16")
+    mm.compute = "f32"
+    assert rsm.plan(mm).startswith("gemm_mfma_f32")
+    # random tilers fall back to the generic kernel (or the small-pattern one)
+    rng = W.rng_for(5)
+    t = W.random_tiler(rng, 2, pattern_rank=2, max_pattern_side=9)
+    name = rsm.plan(W.Problem((3, 3), [t], W.identity_output((3, 3)), W.SUM))
+    assert name in ("generic", "pattern_reduce")
+
+
+def test_empty_repetition_space_is_a_no_op_plan():
+    t = W.Tiler((8,), [0], [[1]], [[1]], (2,))
+    assert rsm.plan(W.Problem((0,), [t], W.identity_output((0,)) if False else
+                              W.Tiler((1,), [0], [[1]], np.zeros((1, 0)), ()), W.SUM)) == "empty"
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    with pytest.raises(RuntimeError, match="not built"):
+        _abi.load(str(tmp_path / "nope.so"))

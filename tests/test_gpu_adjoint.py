@@ -1,0 +1,189 @@
+"""GPU parity of the adjoint kernels and the autograd wrappers.
+
+* single stages (tap kernels and generic atomic path) against the oracle's
+  adjoint on a seeded output gradient;
+* the two-stage chain, fused and unfused, at full size (30 x 1080 x 1920);
+* the loss sum(w * out^2) through torch autograd on the 32x32 crop against
+  FP64 central differences (exact for this quadratic loss) and the oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import rsm_workloads as W
+from paper_1105_4424_amd import _abi, rsm
+
+from .helpers import check_close, dev, host, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _abs_problem(p):
+    return W.Problem(p.rep_shape, p.inputs, p.output, p.task,
+                     None if p.coeffs is None else np.abs(p.coeffs))
+
+
+def _adjoint_check(p, x, gy, flags=0, what=""):
+    a = oracle.adjoint(p, x, gy)
+    gx = torch.full(p.inputs[0].array_shape, float("nan"), device="cuda")
+    gc = torch.full(p.inputs[0].pattern_shape, float("nan"), device="cuda") if p.task == W.WSUM else None
+    rsm.run_adjoint(p, dev(x), dev(gy), gx, gc, dev(p.coeffs) if p.coeffs is not None else None,
+                    flags=flags)
+    check_close(host(gx), a.gx, a.gx_abs, what=what + " gx")
+    if gc is not None:
+        check_close(host(gc), a.gc, a.gc_abs, what=what + " gc")
+    # accumulate: adds onto the previous contents
+    if gc is not None:
+        gx2 = gx.clone()
+        gc2 = gc.clone()
+        rsm.run_adjoint(p, dev(x), dev(gy), gx2, gc2, dev(p.coeffs), flags=flags | _abi.ACCUMULATE)
+        check_close(host(gx2), 2 * a.gx, 2 * a.gx_abs, what=what + " gx accumulate")
+        check_close(host(gc2), 2 * a.gc, 2 * a.gc_abs, what=what + " gc accumulate")
+
+
+@pytest.mark.parametrize("force_generic", [False, True])
+def test_stage_adjoints_two_frames(force_generic):
+    ts = W.two_stage_filter(frames=2)
+    rng = W.rng_for(77)
+    for st, name in ((ts.h, "h"), (ts.v, "v")):
+        x = ts.x if name == "h" else oracle.run(ts.h, [ts.x]).out.astype(np.float32)
+        gy = rng.uniform(-1, 1, st.rep_shape).astype(np.float32)
+        say("adjoint", name, "generic" if force_generic else "fir")
+        _adjoint_check(st, x, gy, _abi.FORCE_GENERIC if force_generic else 0, "stage " + name)
+
+
+@pytest.mark.parametrize("taps,pave,ho,vo,rows,cols", [
+    (8, 8, -3, -3, 64, 96),      # injective, wrapping: tap kernels
+    (13, 8, -6, 0, 48, 80),      # overlapping reads: generic atomic scatter-add
+    (5, 7, 0, -2, 31, 47),       # gaps between windows (elements never read get 0)
+])
+def test_stage_adjoint_variants(taps, pave, ho, vo, rows, cols):
+    ts = W.two_stage_filter(frames=2, rows=rows, cols=cols, taps=taps, pave=pave, h_origin=ho,
+                            v_origin=vo, seed=taps + rows)
+    rng = W.rng_for(taps)
+    for st, name in ((ts.h, "h"), (ts.v, "v")):
+        x = ts.x if name == "h" else oracle.run(ts.h, [ts.x]).out.astype(np.float32)
+        gy = rng.uniform(-1, 1, st.rep_shape).astype(np.float32)
+        _adjoint_check(st, x, gy, 0, "variant %s %s" % (name, (taps, pave, ho, vo)))
+
+
+def test_adjoint_random_tilers_generic():
+    rng = W.rng_for(91)
+    for trial in range(25):
+        dr = int(rng.integers(1, 3))
+        rep = tuple(int(v) for v in rng.integers(1, 6, dr))
+        t = W.random_tiler(rng, dr, max_side=9, max_pattern_side=4)
+        c = rng.uniform(-1, 1, t.pattern_shape).astype(np.float32)
+        p = W.Problem(rep, [t], W.identity_output(rep), W.WSUM, c)
+        x = W.random_array(rng, t.array_shape)
+        gy = rng.uniform(-1, 1, rep).astype(np.float32)
+        _adjoint_check(p, x, gy, 0, "random %d" % trial)
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_chain_adjoint_full_size(fused):
+    ts = W.two_stage_filter()
+    stages = [ts.h, ts.v]
+    gy = W.rng_for(12).uniform(-1, 1, ts.v.rep_shape).astype(np.float32)
+    say("oracle chain adjoint, 30 frames")
+    fw = oracle.chain_forward(stages, ts.x)
+    av = oracle.adjoint(ts.v, fw[0].out, gy)
+    ah = oracle.adjoint(ts.h, ts.x, av.gx)
+    # |term| bounds through both stages: the oracle on absolute values
+    abs_v = oracle.adjoint(_abs_problem(ts.v), np.abs(fw[0].out), np.abs(gy))
+    abs_h = oracle.adjoint(_abs_problem(ts.h), np.abs(ts.x), abs_v.gx)
+    x = dev(ts.x)
+    gx = torch.full(ts.x.shape, float("nan"), device="cuda")
+    gch = torch.full((8,), float("nan"), device="cuda")
+    gcv = torch.full((8,), float("nan"), device="cuda")
+    mids = None
+    if not fused:
+        mid = torch.empty(ts.h.rep_shape, device="cuda")
+        rsm.run(ts.h, [x], mid, coeffs=dev(ts.c_h))
+        mids = [mid]
+    rsm.run_chain_adjoint(stages, x, dev(gy), gx, [gch, gcv], [dev(ts.c_h), dev(ts.c_v)], mids=mids,
+                          flags=0 if fused else _abi.NO_FUSE)
+    check_close(host(gx), ah.gx, abs_h.gx, what="chain gx fused=%s" % fused)
+    check_close(host(gch), ah.gc, abs_h.gc, what="chain gc_h fused=%s" % fused)
+    check_close(host(gcv), av.gc, abs_v.gc, what="chain gc_v fused=%s" % fused)
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_crop_loss_autograd_vs_finite_differences(fused):
+    """32x32 crop of frame 0 as its own [1,32,32] array; loss sum(w out^2)."""
+    ts = W.two_stage_filter(frames=1, rows=32, cols=32)
+    w = W.loss_weights((1, 4, 4))
+    stages = [ts.h, ts.v]
+    x = dev(ts.x).requires_grad_(True)
+    ch = dev(ts.c_h).requires_grad_(True)
+    cv = dev(ts.c_v).requires_grad_(True)
+    out = rsm.TiledChain.apply(x, ch, cv, stages, fused)
+    loss = (dev(w) * out * out).sum()
+    loss.backward()
+    # FP64 central differences of the oracle forward (exact: L is quadratic in
+    # every coordinate), step 2^-4
+    h = 2.0 ** -4
+    x64 = ts.x.astype(np.float64)
+    w64 = w.astype(np.float64)
+
+    def L(xv, chv, cvv):
+        sh = W.Problem(ts.h.rep_shape, ts.h.inputs, ts.h.output, W.WSUM, chv)
+        sv = W.Problem(ts.v.rep_shape, ts.v.inputs, ts.v.output, W.WSUM, cvv)
+        o = oracle.chain_forward([sh, sv], xv)[-1].out
+        return float(np.sum(w64 * o * o))
+
+    ch64, cv64 = ts.c_h.astype(np.float64), ts.c_v.astype(np.float64)
+    flat = x64.reshape(-1)
+    fd = np.zeros_like(flat)
+    for j in range(flat.size):
+        xp, xm = flat.copy(), flat.copy()
+        xp[j] += h
+        xm[j] -= h
+        fd[j] = (L(xp.reshape(x64.shape), ch64, cv64) - L(xm.reshape(x64.shape), ch64, cv64)) / (2 * h)
+    fdc = []
+    for which in range(2):
+        g = np.zeros(8)
+        for k in range(8):
+            cp = [ch64.copy(), cv64.copy()]
+            cm = [ch64.copy(), cv64.copy()]
+            cp[which][k] += h
+            cm[which][k] -= h
+            g[k] = (L(x64, *cp) - L(x64, *cm)) / (2 * h)
+        fdc.append(g)
+    ref = oracle.chain_adjoint(stages, ts.x, w)
+    # |term| bound: the oracle adjoint on absolute values of everything
+    absd = oracle.chain_adjoint([_abs_problem(s) for s in stages], np.abs(ts.x), np.abs(w))
+    gx_bound = absd.gx
+    check_close(host(x.grad).reshape(-1), fd, gx_bound.reshape(-1), what="gx vs FD")
+    check_close(host(x.grad), ref.gx, gx_bound, what="gx vs oracle")
+    for k, g in enumerate((ch.grad, cv.grad)):
+        check_close(host(g), fdc[k], absd.gc[k], what="gc[%d] vs FD" % k)
+        check_close(host(g), ref.gc[k], absd.gc[k], what="gc[%d] vs oracle" % k)
+
+
+def test_tiled_task_autograd_single_stage():
+    ts = W.two_stage_filter(frames=2, rows=64, cols=128)
+    gy = W.rng_for(5).uniform(-1, 1, ts.h.rep_shape).astype(np.float32)
+    x = dev(ts.x).requires_grad_(True)
+    c = dev(ts.c_h).requires_grad_(True)
+    y = rsm.TiledTask.apply(x, c, ts.h)
+    y.backward(dev(gy))
+    a = oracle.adjoint(ts.h, ts.x, gy)
+    check_close(host(x.grad), a.gx, a.gx_abs, what="TiledTask gx")
+    check_close(host(c.grad), a.gc, a.gc_abs, what="TiledTask gc")
+
+
+def test_deterministic_weight_gradient():
+    ts = W.two_stage_filter(frames=4)
+    gy = dev(W.rng_for(6).uniform(-1, 1, ts.v.rep_shape).astype(np.float32))
+    x = dev(ts.x)
+    res = []
+    for _ in range(2):
+        gch = torch.empty(8, device="cuda")
+        gcv = torch.empty(8, device="cuda")
+        gx = torch.empty_like(x)
+        rsm.run_chain_adjoint([ts.h, ts.v], x, gy, gx, [gch, gcv], [dev(ts.c_h), dev(ts.c_v)])
+        res.append((host(gx), host(gch), host(gcv)))
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(a, b)

@@ -1,0 +1,81 @@
+"""GPU parity of the matrix product expressed through tilers (DOT task).
+
+BF16 operands: products are exact in FP32 and accumulation is FP32, so the
+result is held to the FP32 bound against the FP64 oracle on the BF16-rounded
+inputs; the error against FP64 of the original FP32 inputs (input
+quantisation) is reported, with a sanity gate of 1e-2 normwise.
+FP32 operands: FP32 bound against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import rsm_workloads as W
+from paper_1105_4424_amd import rsm
+
+from .helpers import bf16_dev, check_close, dev, host, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _layouts(M, N, K):
+    """(name, A tiler, B tiler, A transform, B transform) for the four storage orders."""
+    base = W.matmul_tilers(M, N, K)
+    ta_n, tb_n = base.inputs
+    ta_t = W.Tiler((K, M), [0, 0], [[0, 0], [1, 0]], [[1], [0]], (K,))
+    tb_t = W.Tiler((N, K), [0, 0], [[0, 1], [0, 0]], [[0], [1]], (K,))
+    ident = lambda a: a
+    trans = lambda a: np.ascontiguousarray(a.T)
+    return [("nn", ta_n, tb_n, ident, ident), ("tn", ta_t, tb_n, trans, ident),
+            ("nt", ta_n, tb_t, ident, trans), ("tt", ta_t, tb_t, trans, trans)]
+
+
+@pytest.mark.parametrize("M,N,K", [(256, 256, 256), (200, 136, 264), (130, 300, 72), (1, 33, 8)])
+@pytest.mark.parametrize("dtype", ["bf16", "f32"])
+def test_gemm_ragged_all_layouts(M, N, K, dtype):
+    a, b, ab, bb = W.matmul_inputs(M, N, K, seed=M + N + K)
+    for name, ta, tb, fa, fb in _layouts(M, N, K):
+        p = W.Problem((M, N), [ta, tb], W.identity_output((M, N)), W.DOT, compute=dtype)
+        assert rsm.plan(p, dtypes=(torch.bfloat16 if dtype == "bf16" else torch.float32,)) \
+            .startswith("gemm_mfma_" + dtype), name
+        if dtype == "bf16":
+            xa, xb = fa(ab), fb(bb)
+            da, db = bf16_dev(xa), bf16_dev(xb)
+        else:
+            xa, xb = fa(a), fb(b)
+            da, db = dev(xa), dev(xb)
+        r = oracle.run(p, [xa, xb])
+        out = torch.full((M, N), float("nan"), device="cuda")
+        rsm.run(p, [da, db], out)
+        check_close(host(out), r.out, r.abs_sum, what="%s %s %dx%dx%d" % (dtype, name, M, N, K))
+
+
+def test_gemm_full_size_sampled_and_error_report():
+    M = N = K = 4096
+    say("generating 4096^3 inputs")
+    a, b, ab, bb = W.matmul_inputs(M, N, K)
+    p = W.matmul_tilers(M, N, K)
+    rng = W.rng_for(123)
+    sel = rng.choice(M * N, 512, replace=False)
+    sel = np.concatenate([sel, [0, N - 1, (M - 1) * N, M * N - 1]])
+    # BF16 on the matrix cores
+    p.compute = "bf16"
+    out = torch.full((M, N), float("nan"), device="cuda")
+    rsm.run(p, [bf16_dev(ab), bf16_dev(bb)], out)
+    got = host(out).reshape(-1)[sel]
+    y_q, ya_q = oracle.run_sample(p, [ab, bb], sel)            # FP64 on BF16-rounded inputs
+    y_f, _ = oracle.run_sample(p, [a, b], sel)                 # FP64 on the FP32 inputs
+    check_close(got, y_q[:, 0], ya_q[:, 0], what="bf16 4096^3 vs FP64(bf16 inputs)")
+    err_q = float(np.linalg.norm(got - y_f[:, 0]) / np.linalg.norm(y_f[:, 0]))
+    say("bf16 normwise relative error vs FP64 of FP32 inputs: %.3e" % err_q)
+    assert err_q < 1e-2
+    # FP32
+    p.compute = "f32"
+    out32 = torch.full((M, N), float("nan"), device="cuda")
+    rsm.run(p, [dev(a), dev(b)], out32)
+    got32 = host(out32).reshape(-1)[sel]
+    y32, ya32 = oracle.run_sample(p, [a, b], sel)
+    check_close(got32, y32[:, 0], ya32[:, 0], what="f32 4096^3")
+    assert np.all(np.isfinite(host(out32)))
+    assert np.all(np.isfinite(host(out)))
