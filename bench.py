@@ -33,7 +33,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2516.6
-FP32_PEAK_TFLOPS = 157.3
+FP32_PEAK_TFLOPS = 157.3       # FP32 vector/matrix peak with packed math
+FP32_NOPK_TFLOPS = 78.6        # FP32 FMA peak without packed math (what the filters compile to)
 
 
 def log(*a):
@@ -246,6 +247,29 @@ def extras(args, ts, xs, stages, ch, cv, w2, chain):
                              "kernel": rsm.plan(pm)}
     log("matmul bf16 %.1f TF/s, f32 %.1f TF/s" % (ex["matmul_bf16_4096"]["tflops"], tf))
     del da, db, fa, fb, cm
+
+    # 512 uneven 2-D filters: one persistent graph launch vs 512 plain launches
+    log("batched 2-D filters: 512 instances")
+    insts = W.filter_batch(512)
+    bx = [torch.from_numpy(i.x).to(dev) for i in insts]
+    bc = [torch.from_numpy(i.coeffs).to(dev) for i in insts]
+    bo = [torch.empty(i.out_shape, device=dev) for i in insts]
+    batch = rsm.Batch([i.problem() for i in insts], bx, bo, bc)
+    info = batch.info()
+    us_b = time_fn(batch.run, reps=20)
+    us_p = time_fn(batch.run_plain, reps=10)
+    nbytes = sum(4 * (i.H * i.W + i.out_shape[0] * i.out_shape[1]) for i in insts)
+    flops = sum(2 * i.out_shape[0] * i.out_shape[1] * i.k * i.k for i in insts)
+    ideal_us = sum(max(4e-6 * (i.H * i.W + i.out_shape[0] * i.out_shape[1]) / HBM_PEAK_GBS * 1e3,
+                       2e-6 * i.out_shape[0] * i.out_shape[1] * i.k * i.k / FP32_NOPK_TFLOPS)
+                   for i in insts)
+    ex["batched_2d_filters_512"] = {
+        "batched_us": us_b, "plain_us": us_p, "speedup": us_p / us_b, "bytes": nbytes,
+        "flops": flops, "gbs": nbytes / us_b / 1e3, "roofline_ideal_us": ideal_us,
+        "frac": ideal_us / us_b, "tiles": info["n_tiles"], "grid": info["grid"],
+        "tuned_classes": info["tuned_classes"]}
+    log("batched %.1f us, plain %.1f us, ideal %.1f us" % (us_b, us_p, ideal_us))
+    batch.close()
     return ex
 
 

@@ -124,7 +124,8 @@ rsm_status rsm_validate(const rsm_space* rep, const rsm_tiler* in, int32_t n_in,
 
 /*
  * rsm_plan -- name of the kernel family the planner picks for a task
- * (e.g. "fir_h_vec4", "pattern_reduce", "gemm_mfma_bf16", "generic").
+ * (e.g. "fir_cols_vec4", "filter2d_k5_s2", "pattern_reduce", "gemm_mfma_bf16_nn",
+ * "generic").
  * Host only.  Writes a NUL-terminated string of at most len bytes.
  */
 rsm_status rsm_plan(const rsm_space* rep, const rsm_tiler* in, int32_t n_in,
@@ -204,8 +205,13 @@ rsm_status rsm_run_chain_adjoint(const rsm_stage* stages, int32_t n_stages, cons
  * returns an opaque handle.  Problems that the persistent kernel does not
  * handle run through rsm_run inside the same rsm_batch_run call.
  * rsm_batch_run captures one HIP graph holding the persistent launch on its
- * first call and replays it afterwards (the device pointers given at create
- * time are used every time).  rsm_batch_destroy frees the handle.
+ * first call (on a private stream) and replays it on the given stream
+ * afterwards; the device pointers given at create time are used every time.
+ * Persistent problems: FP32 weighted-sum (WSUM) k x k windows (k in 3,5,7,9)
+ * with equal row/column stride s in 1,2,4, unit fitting and an identity
+ * output tiler.  Batches on one device must not run concurrently with each
+ * other (each owns a private queue, but the caller's streams order replays).
+ * rsm_batch_destroy frees the handle.
  */
 typedef struct {
   rsm_space rep;
@@ -230,8 +236,12 @@ typedef struct {
 rsm_status rsm_batch_create(const rsm_problem* problems, int32_t n, const char* tune_cache_path,
                             uint32_t flags, void* hip_stream, rsm_batch* out);
 rsm_status rsm_batch_run(rsm_batch b, void* hip_stream);
+/* The same problems with the same tile shapes, one kernel launch per problem
+ * in list order on the stream (no persistent kernel, no graph): the baseline
+ * the batched launch is compared against. */
+rsm_status rsm_batch_run_plain(rsm_batch b, void* hip_stream);
 rsm_status rsm_batch_query(rsm_batch b, rsm_batch_info* info);
-rsm_status rsm_batch_destroy(rsm_batch b);
+rsm_status rsm_batch_destroy(rsm_batch b); /* waits for the device, then frees */
 
 /* Tile shape chosen for problem k of a batch (rows, cols of outputs per tile). */
 rsm_status rsm_batch_tile(rsm_batch b, int32_t k, int32_t* tile_rows, int32_t* tile_cols);

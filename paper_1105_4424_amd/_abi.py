@@ -67,7 +67,8 @@ class BatchInfo(ctypes.Structure):
 
 EXPORTS = [
     "rsm_validate", "rsm_plan", "rsm_indices", "rsm_run", "rsm_run_chain", "rsm_run_adjoint",
-    "rsm_run_chain_adjoint", "rsm_batch_create", "rsm_batch_run", "rsm_batch_query",
+    "rsm_run_chain_adjoint", "rsm_batch_create", "rsm_batch_run", "rsm_batch_run_plain",
+    "rsm_batch_query",
     "rsm_batch_tile", "rsm_batch_destroy", "rsm_status_string", "rsm_last_error",
     "rsm_abi_version",
 ]
@@ -98,12 +99,13 @@ def load(path: str = LIB_PATH):
     lib.rsm_run_chain_adjoint.argtypes = [P(Stage), i32, vp, P(vp), vp, vp, P(vp), u32, vp]
     lib.rsm_batch_create.argtypes = [P(Problem), i32, ctypes.c_char_p, u32, vp, P(vp)]
     lib.rsm_batch_run.argtypes = [vp, vp]
+    lib.rsm_batch_run_plain.argtypes = [vp, vp]
     lib.rsm_batch_query.argtypes = [vp, P(BatchInfo)]
     lib.rsm_batch_tile.argtypes = [vp, i32, P(i32), P(i32)]
     lib.rsm_batch_destroy.argtypes = [vp]
     for name in ("rsm_validate", "rsm_plan", "rsm_indices", "rsm_run", "rsm_run_chain",
                  "rsm_run_adjoint", "rsm_run_chain_adjoint", "rsm_batch_create", "rsm_batch_run",
-                 "rsm_batch_query", "rsm_batch_tile", "rsm_batch_destroy"):
+                 "rsm_batch_run_plain", "rsm_batch_query", "rsm_batch_tile", "rsm_batch_destroy"):
         getattr(lib, name).restype = st
     lib.rsm_status_string.argtypes = [st]
     lib.rsm_status_string.restype = ctypes.c_char_p

@@ -394,7 +394,7 @@ bool fir_vec4(const Win3& w, const void* x) {
   return x == nullptr || (reinterpret_cast<uintptr_t>(x) & 15) == 0;
 }
 
-enum class Fam { Empty, Generic, PatternReduce, Fir, Gemm };
+enum class Fam { Empty, Generic, PatternReduce, Fir, Filter2D, Gemm };
 
 struct Plan {
   Fam fam = Fam::Generic;
@@ -402,6 +402,7 @@ struct Plan {
   Win3 win{};
   bool vec4 = false;
   GemmArgs gemm{};
+  Filter2DProblem f2d{};
   int max_rank = 1;
 };
 
@@ -498,6 +499,13 @@ Plan make_plan(const rsm_space& rep, const rsm_tiler* in, int n_in, const rsm_ti
     p.name = w.ax == 2 ? (p.vec4 ? "fir_cols_vec4" : "fir_cols") : "fir_rows";
     return p;
   }
+  Filter2DProblem fp{};
+  if (plan_filter2d(rep, in[0], out, task, &fp)) {
+    p.fam = Fam::Filter2D;
+    p.f2d = fp;
+    p.name = "filter2d_k" + std::to_string(fp.k) + "_s" + std::to_string(fp.s);
+    return p;
+  }
   if (n_pat <= 64) {
     p.fam = Fam::PatternReduce;
     p.name = "pattern_reduce";
@@ -521,7 +529,7 @@ rsm_status exec_run(const rsm_space& rep, const rsm_tiler* in, const void* const
       p.gemm.c = static_cast<float*>(d_out);
       const int compute = in[0].dtype == RSM_BF16 ? RSM_BF16 : RSM_F32;
       e = launch_gemm(p.gemm, compute, st);
-      if (e != hipSuccess) return hip_fail(e, "gemm launch");
+      if (e != hipSuccess) return fail(RSM_E_HIP, g_last_error);  // detail set by launch_gemm
       return RSM_OK;
     }
     case Fam::Fir: {
@@ -535,6 +543,16 @@ rsm_status exec_run(const rsm_space& rep, const rsm_tiler* in, const void* const
       a.c = static_cast<const float*>(task.coeffs);
       e = launch_fir(a, p.vec4, st);
       if (e != hipSuccess) return hip_fail(e, "fir launch");
+      return RSM_OK;
+    }
+    case Fam::Filter2D: {
+      Filter2DProblem fp = p.f2d;
+      fp.x = static_cast<const float*>(d_in[0]);
+      fp.y = static_cast<float*>(d_out);
+      fp.c = static_cast<const float*>(task.coeffs);
+      filter2d_set_tiles(&fp, 1);
+      e = launch_filter2d(fp, st);
+      if (e != hipSuccess) return hip_fail(e, "filter2d launch");
       return RSM_OK;
     }
     case Fam::PatternReduce: {
@@ -755,6 +773,29 @@ bool chain_fusable(const rsm_stage* st, int n, const void* x, Win3* h, Win3* v, 
 }
 
 }  // namespace
+
+bool plan_filter2d(const rsm_space& rep, const rsm_tiler& in, const rsm_tiler& out,
+                   const rsm_task& task, Filter2DProblem* fp) {
+  if (task.kind != RSM_TASK_WSUM || in.dtype != RSM_F32 || task.compute != RSM_F32) return false;
+  if (!is_identity_out(rep, out)) return false;
+  Win3 w{};
+  if (!canon_win3(rep, in, &w) || w.ax != 0) return false;
+  if (w.taps != w.taps2 || w.p[1] != w.p[2] || !filter2d_supported(w.taps, w.p[1])) return false;
+  // identity along frames
+  if (w.o[0] != 0 || w.rep[0] != w.A[0] || (w.A[0] > 1 && w.p[0] != 1)) return false;
+  *fp = Filter2DProblem{};
+  fp->H = w.A[1];
+  fp->W = w.A[2];
+  fp->RH = w.rep[1];
+  fp->RW = w.rep[2];
+  fp->oh = int32_t(floor_mod(w.o[1], w.A[1]));
+  fp->ow = int32_t(floor_mod(w.o[2], w.A[2]));
+  fp->k = w.taps;
+  fp->s = w.p[1];
+  fp->frames = w.A[0];
+  return true;
+}
+
 }  // namespace rsm
 
 // ===========================================================================

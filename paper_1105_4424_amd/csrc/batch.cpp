@@ -1,53 +1,359 @@
 // batch.cpp -- many independent repetitive tasks behind one handle.
+//
+// Problems that are k x k weighted windows (the 2-D filter family) go to one
+// persistent kernel: the host orders them by decreasing estimated cost
+// (max of HBM time and FP32 ALU time), lays their tiles out in that order,
+// and uploads the descriptor table, the tile prefix sums and a two-word queue
+// once.  The first rsm_batch_run captures the persistent launch into a HIP
+// graph on a private stream; every call replays the graph on the caller's
+// stream.  Remaining problems run through rsm_run in the same call.
+//
+// Tile shapes come from an autotuner: problems are grouped into classes
+// (window side, stride, output-size bucket); for each class missing from the
+// tuning cache every tile class is timed with HIP events over that class's
+// own problems (plain launches, best of 3), and the fastest is kept.  The
+// cache is a small JSON object keyed by class, stamped with the device
+// architecture and the kernel revision; a file that does not parse or carries
+// another stamp is ignored and rewritten.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
 #include "rsm_internal.h"
 
+namespace {
+
+constexpr const char* kKernelRevision = "filter2d-r1";
+constexpr double kHbmBytesPerS = 8.0e12;
+constexpr double kFp32FmaPerS = 39.3e12;   // unpacked FP32 FMA issue rate of the chip
+
+std::string arch_name() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t colon = a.find(':');
+  return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+std::string class_key(const rsm::Filter2DProblem& p) {
+  const int64_t outs = int64_t(p.RH) * p.RW * p.frames;
+  const int bucket = outs < (int64_t(1) << 12) ? 0 : outs < (int64_t(1) << 16) ? 1 : 2;
+  return "k" + std::to_string(p.k) + "_s" + std::to_string(p.s) + "_b" + std::to_string(bucket);
+}
+
+double est_cost(const rsm::Filter2DProblem& p) {
+  const double outs = double(p.RH) * p.RW * p.frames;
+  const double bytes = 4.0 * (double(p.H) * p.W * p.frames + outs);
+  const double fmas = outs * p.k * p.k;
+  return std::max(bytes / kHbmBytesPerS, fmas / kFp32FmaPerS);
+}
+
+// {"revision": "...", "arch": "...", "choices": {"k3_s1_b2": 1, ...}}
+bool load_cache(const std::string& path, const std::string& arch, std::map<std::string, int>* out) {
+  std::ifstream f(path);
+  if (!f) return false;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string t = ss.str();
+  auto field = [&](const std::string& name) -> std::string {
+    const std::string key = "\"" + name + "\"";
+    size_t i = t.find(key);
+    if (i == std::string::npos) return "";
+    i = t.find('"', t.find(':', i + key.size()) + 1);
+    if (i == std::string::npos) return "";
+    const size_t j = t.find('"', i + 1);
+    return j == std::string::npos ? "" : t.substr(i + 1, j - i - 1);
+  };
+  if (field("revision") != kKernelRevision || field("arch") != arch) return false;
+  size_t i = t.find("\"choices\"");
+  if (i == std::string::npos) return false;
+  i = t.find('{', i);
+  const size_t end = t.find('}', i);
+  if (i == std::string::npos || end == std::string::npos) return false;
+  std::map<std::string, int> m;
+  size_t pos = i + 1;
+  while (true) {
+    const size_t a = t.find('"', pos);
+    if (a == std::string::npos || a > end) break;
+    const size_t b = t.find('"', a + 1);
+    const size_t c = t.find(':', b);
+    if (b == std::string::npos || c == std::string::npos || c > end) return false;
+    char* e = nullptr;
+    const long v = std::strtol(t.c_str() + c + 1, &e, 10);
+    if (e == t.c_str() + c + 1 || v < 0 || v > 2) return false;
+    m[t.substr(a + 1, b - a - 1)] = int(v);
+    pos = size_t(e - t.c_str());
+  }
+  *out = m;
+  return true;
+}
+
+void save_cache(const std::string& path, const std::string& arch, const std::map<std::string, int>& m) {
+  const std::string tmp = path + ".tmp";
+  {
+    std::ofstream f(tmp);
+    if (!f) return;
+    f << "{\"revision\": \"" << kKernelRevision << "\", \"arch\": \"" << arch << "\", \"choices\": {";
+    bool first = true;
+    for (const auto& kv : m) {
+      f << (first ? "" : ", ") << "\"" << kv.first << "\": " << kv.second;
+      first = false;
+    }
+    f << "}}\n";
+  }
+  std::rename(tmp.c_str(), path.c_str());
+}
+
+}  // namespace
+
 struct rsm_batch_s {
   std::vector<rsm_problem> problems;
-  std::vector<int32_t> tile_rows, tile_cols;
+  std::vector<int> persistent;                 // problem indices, in queue order
+  std::vector<int> others;                     // problem indices run through rsm_run
+  std::vector<rsm::Filter2DProblem> fp;        // per problem (valid for persistent ones)
+  rsm::Filter2DProblem* d_probs = nullptr;
+  int64_t* d_prefix = nullptr;
+  uint32_t* d_queue = nullptr;
+  int64_t n_tiles = 0;
+  int grid = 0;
+  int device = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
   rsm_batch_info info{};
+
+  ~rsm_batch_s() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (d_probs) (void)hipFree(d_probs);
+    if (d_prefix) (void)hipFree(d_prefix);
+    if (d_queue) (void)hipFree(d_queue);
+  }
 };
 
 using namespace rsm;
 
+namespace {
+
+// Times tile class tc over the given problems (plain launches), best of 3, in ms.
+rsm_status time_class(rsm_batch_s* b, const std::vector<int>& idx, int tc, hipStream_t st, float* ms) {
+  hipEvent_t e0, e1;
+  hipError_t e;
+  if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+  if ((e = hipEventCreate(&e1)) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(e, "hipEventCreate");
+  }
+  float best = 1e30f;
+  rsm_status s = RSM_OK;
+  for (int rep = 0; rep < 4 && s == RSM_OK; ++rep) {  // first pass warms up
+    (void)hipEventRecord(e0, st);
+    for (int k : idx) {
+      Filter2DProblem p = b->fp[size_t(k)];
+      filter2d_set_tiles(&p, tc);
+      if ((e = launch_filter2d(p, st)) != hipSuccess) {
+        s = hip_fail(e, "autotuner launch");
+        break;
+      }
+    }
+    (void)hipEventRecord(e1, st);
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+      s = hip_fail(e, "autotuner timing");
+      break;
+    }
+    float t = 0.0f;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    if (rep > 0) best = std::min(best, t);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = best;
+  return s;
+}
+
+rsm_status build_queue(rsm_batch_s* b) {
+  std::stable_sort(b->persistent.begin(), b->persistent.end(), [&](int x, int y) {
+    return est_cost(b->fp[size_t(x)]) > est_cost(b->fp[size_t(y)]);
+  });
+  const size_t n = b->persistent.size();
+  std::vector<Filter2DProblem> table(n);
+  std::vector<int64_t> prefix(n + 1, 0);
+  for (size_t i = 0; i < n; ++i) {
+    table[i] = b->fp[size_t(b->persistent[i])];
+    prefix[i + 1] = prefix[i] + table[i].n_tiles;
+  }
+  b->n_tiles = prefix[n];
+  if (b->n_tiles >= (int64_t(1) << 31)) return fail(RSM_E_UNSUPPORTED, "batch has more than 2^31 tiles");
+  hipError_t e;
+  if ((e = hipMalloc(&b->d_probs, sizeof(Filter2DProblem) * std::max<size_t>(n, 1))) != hipSuccess ||
+      (e = hipMalloc(&b->d_prefix, sizeof(int64_t) * (n + 1))) != hipSuccess ||
+      (e = hipMalloc(&b->d_queue, 256)) != hipSuccess)
+    return fail(RSM_E_NOMEM, std::string("batch tables: ") + hipGetErrorString(e));
+  if ((e = hipMemcpy(b->d_probs, table.data(), sizeof(Filter2DProblem) * n, hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(b->d_prefix, prefix.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemset(b->d_queue, 0, 256)) != hipSuccess)
+    return hip_fail(e, "batch table upload");
+  const int g = filter2d_persistent_grid();
+  b->grid = int(std::max<int64_t>(1, std::min<int64_t>(g, b->n_tiles)));
+  if ((e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+    return hip_fail(e, "hipStreamCreateWithFlags");
+  return RSM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
-rsm_status rsm_batch_create(const rsm_problem* problems, int32_t n, const char* /*tune_cache_path*/,
-                            uint32_t flags, void* /*hip_stream*/, rsm_batch* out) {
+rsm_status rsm_batch_create(const rsm_problem* problems, int32_t n, const char* tune_cache_path,
+                            uint32_t flags, void* hip_stream, rsm_batch* out) {
+  rsm_batch_s* b = nullptr;
   try {
     if (!out) return fail(RSM_E_INVALID, "output handle pointer is NULL");
     *out = nullptr;
     if (n < 0 || (n > 0 && !problems)) return fail(RSM_E_INVALID, "bad problem list");
     for (int k = 0; k < n; ++k) {
       const rsm_problem& p = problems[k];
+      if (p.task.kind == RSM_TASK_DOT) return fail(RSM_E_INVALID, "batched problems take one input");
       rsm_status s = rsm_validate(&p.rep, &p.in, 1, &p.out, &p.task, flags & RSM_CHECK_SINGLE_ASSIGN);
       if (s) return fail(s, "problem " + std::to_string(k) + ": " + rsm_last_error());
-      if (p.task.kind == RSM_TASK_DOT) return fail(RSM_E_INVALID, "batched problems take one input");
+      if (!p.d_in || !p.d_out) return fail(RSM_E_INVALID, "problem " + std::to_string(k) + ": NULL buffer");
     }
-    rsm_batch_s* b = new rsm_batch_s;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    b = new rsm_batch_s;
+    (void)hipGetDevice(&b->device);
     b->problems.assign(problems, problems + n);
-    b->tile_rows.assign(size_t(n), 0);
-    b->tile_cols.assign(size_t(n), 0);
+    b->fp.resize(size_t(n));
+    for (int k = 0; k < n; ++k) {
+      const rsm_problem& p = problems[k];
+      Filter2DProblem f{};
+      int64_t n_rep = 1;
+      for (int d = 0; d < p.rep.rank; ++d) n_rep *= p.rep.shape[d];
+      if (n_rep > 0 && !(flags & RSM_FORCE_GENERIC) && plan_filter2d(p.rep, p.in, p.out, p.task, &f)) {
+        f.x = static_cast<const float*>(p.d_in);
+        f.y = static_cast<float*>(p.d_out);
+        f.c = static_cast<const float*>(p.task.coeffs);
+        filter2d_set_tiles(&f, 1);
+        b->fp[size_t(k)] = f;
+        b->persistent.push_back(k);
+      } else {
+        b->others.push_back(k);
+      }
+    }
+    // ---- autotune tile classes ----
+    const std::string arch = arch_name();
+    std::map<std::string, int> cache;
+    const std::string path = tune_cache_path ? tune_cache_path : "";
+    if (!path.empty()) load_cache(path, arch, &cache);
+    std::map<std::string, std::vector<int>> classes;
+    for (int k : b->persistent) classes[class_key(b->fp[size_t(k)])].push_back(k);
+    bool changed = false;
+    for (const auto& kv : classes) {
+      auto it = cache.find(kv.first);
+      int choice;
+      if (it != cache.end()) {
+        choice = it->second;
+        b->info.cached_classes += 1;
+      } else {
+        float best = 1e30f;
+        choice = 1;
+        for (int tc = 0; tc < 3; ++tc) {
+          float ms = 0.0f;
+          rsm_status s = time_class(b, kv.second, tc, st, &ms);
+          if (s) {
+            delete b;
+            return s;
+          }
+          if (ms < best) {
+            best = ms;
+            choice = tc;
+          }
+        }
+        cache[kv.first] = choice;
+        changed = true;
+        b->info.tuned_classes += 1;
+      }
+      for (int k : kv.second) filter2d_set_tiles(&b->fp[size_t(k)], choice);
+    }
+    if (changed && !path.empty()) save_cache(path, arch, cache);
+    if (!b->persistent.empty()) {
+      rsm_status s = build_queue(b);
+      if (s) {
+        delete b;
+        return s;
+      }
+    }
     b->info.n_problems = n;
+    b->info.n_persistent = int64_t(b->persistent.size());
+    b->info.n_tiles = b->n_tiles;
+    b->info.grid = b->grid;
     *out = b;
     return RSM_OK;
   } catch (const std::bad_alloc&) {
+    delete b;
     return fail(RSM_E_NOMEM, "host allocation failed");
   } catch (...) {
+    delete b;
     return fail(RSM_E_INVALID, "internal error (exception)");
   }
 }
 
 rsm_status rsm_batch_run(rsm_batch b, void* hip_stream) {
   if (!b) return fail(RSM_E_INVALID, "batch handle is NULL");
-  for (size_t k = 0; k < b->problems.size(); ++k) {
-    const rsm_problem& p = b->problems[k];
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  hipError_t e;
+  if (!b->persistent.empty()) {
+    if (!b->exec) {
+      if ((e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return hip_fail(e, "hipStreamBeginCapture");
+      e = launch_filter2d_persistent(b->d_probs, int(b->persistent.size()), b->d_prefix, b->n_tiles,
+                                     b->d_queue, b->grid, b->cap_stream);
+      hipGraph_t g = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
+      if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(e, "persistent launch during capture");
+      }
+      if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+      b->graph = g;
+      if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) {
+        b->exec = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+      }
+    }
+    if ((e = hipGraphLaunch(b->exec, st)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  }
+  for (int k : b->others) {
+    const rsm_problem& p = b->problems[size_t(k)];
+    const void* src = p.d_in;
+    rsm_status s = rsm_run(&p.rep, &p.in, &src, 1, &p.out, p.d_out, &p.task, 0, hip_stream);
+    if (s) return s;
+  }
+  return RSM_OK;
+}
+
+rsm_status rsm_batch_run_plain(rsm_batch b, void* hip_stream) {
+  if (!b) return fail(RSM_E_INVALID, "batch handle is NULL");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (int k : b->persistent) {
+    hipError_t e = launch_filter2d(b->fp[size_t(k)], st);
+    if (e != hipSuccess) return hip_fail(e, "filter2d launch");
+  }
+  for (int k : b->others) {
+    const rsm_problem& p = b->problems[size_t(k)];
     const void* src = p.d_in;
     rsm_status s = rsm_run(&p.rep, &p.in, &src, 1, &p.out, p.d_out, &p.task, 0, hip_stream);
     if (s) return s;
@@ -64,12 +370,16 @@ rsm_status rsm_batch_query(rsm_batch b, rsm_batch_info* info) {
 rsm_status rsm_batch_tile(rsm_batch b, int32_t k, int32_t* tile_rows, int32_t* tile_cols) {
   if (!b || !tile_rows || !tile_cols) return fail(RSM_E_INVALID, "NULL argument");
   if (k < 0 || size_t(k) >= b->problems.size()) return fail(RSM_E_INVALID, "problem index out of range");
-  *tile_rows = b->tile_rows[size_t(k)];
-  *tile_cols = b->tile_cols[size_t(k)];
+  const bool pers = std::find(b->persistent.begin(), b->persistent.end(), k) != b->persistent.end();
+  *tile_rows = pers ? b->fp[size_t(k)].tile_h : 0;
+  *tile_cols = pers ? b->fp[size_t(k)].tile_w : 0;
   return RSM_OK;
 }
 
 rsm_status rsm_batch_destroy(rsm_batch b) {
+  if (!b) return RSM_OK;
+  // a replay may still be running on some stream: wait before freeing its tables
+  (void)hipDeviceSynchronize();
   delete b;
   return RSM_OK;
 }

@@ -1,0 +1,290 @@
+// k_filter2d.hip -- k x k weighted windows with stride s on 2-D arrays.
+//
+// A workgroup of 256 threads (16 x 16) computes one tile of TH x TW outputs
+// (TH = 16 RY, TW = 16 RX with RX S = 4).  The input region the tile's
+// windows overlap, ((TH-1) S + K) x ((TW-1) S + K) elements, is staged in LDS
+// once, with the modular wrap applied while loading (centred origins wrap on
+// every border).  Each thread then computes an RY x RX block of outputs:
+// every LDS row segment it needs (RX S + K - S floats, 16-byte aligned
+// because RX S = 4) is read once with ds_read_b128 and reused across its RX
+// outputs, so LDS traffic per output falls with RX and RY.  Weights are
+// uniform across the workgroup and live in scalar registers.
+//
+// Two launch forms share the tile body:
+//  * filter2d_kernel: one problem, one workgroup per tile (plain launches);
+//  * filter2d_persistent: a grid sized to the chip pops tile ids from a
+//    device counter across many problems (ordered by decreasing cost on the
+//    host), finds each tile's problem by binary search over the tile prefix
+//    sums, and runs the body instantiated for that problem's (K, S, tile).
+//    The last workgroup to finish resets the counters, so the launch can be
+//    replayed from a graph without any memset node.
+#include <hip/hip_runtime.h>
+
+#include "rsm_internal.h"
+
+namespace rsm {
+namespace {
+
+constexpr int kThreads = 256;
+
+__host__ __device__ constexpr int rx_of(int S) { return 4 / S; }
+__host__ __device__ constexpr int seg_of(int K, int S) { return (rx_of(S) - 1) * S + K; }
+// floats read per row segment, rounded up to whole 16-byte vectors
+__host__ __device__ constexpr int seg4_of(int K, int S) { return (seg_of(K, S) + 3) / 4; }
+__host__ __device__ constexpr int lds_rows(int K, int S, int RY) { return (16 * RY - 1) * S + K; }
+__host__ __device__ constexpr int lds_pitch(int K, int S) {
+  // widest read: last thread's segment start (15 * RX * S = 60) + 4 * seg4
+  return 60 + 4 * seg4_of(K, S) + 4;
+}
+__host__ __device__ constexpr int lds_cols(int K, int S) { return (16 * rx_of(S) - 1) * S + K; }
+
+__device__ __forceinline__ int mod_pos(int v, int n) {
+  // v >= 0 here; reduce into [0, n)
+  return v < n ? v : v % n;
+}
+
+template <int K, int S, int RY>
+__device__ __forceinline__ void filter_tile(const Filter2DProblem& p, int64_t local, float* lds) {
+  constexpr int RX = rx_of(S);
+  constexpr int TH = 16 * RY, TW = 16 * RX;
+  constexpr int LR = lds_rows(K, S, RY), LC = lds_cols(K, S), LP = lds_pitch(K, S);
+  constexpr int SEG4 = seg4_of(K, S);
+
+  const int tiles_pf = p.tiles_per_frame;
+  const int frame = int(local / tiles_pf);
+  const int rem = int(local - int64_t(frame) * tiles_pf);
+  const int ty = rem / p.tiles_w;
+  const int tx = rem - ty * p.tiles_w;
+  const float* __restrict__ x = p.x + int64_t(frame) * p.H * p.W;
+  float* __restrict__ y = p.y + int64_t(frame) * p.RH * p.RW;
+
+  // ---- stage the tile's input region, wrapping modulo the array shape ----
+  const int iy0 = p.oh + ty * TH * S;   // >= 0 (origin stored reduced)
+  const int ix0 = p.ow + tx * TW * S;
+  const int t = threadIdx.x;
+  const int lane = t & 63, rq = t >> 6;
+  __syncthreads();  // the previous tile's readers are done with LDS
+  if (iy0 + LR <= p.H && ix0 + LC <= p.W) {
+    for (int r = rq; r < LR; r += 4) {
+      const float* src = x + int64_t(iy0 + r) * p.W + ix0;
+      for (int c = lane; c < LC; c += 64) lds[r * LP + c] = src[c];
+    }
+  } else {
+    int gxs[(LC + 63) / 64];
+#pragma unroll
+    for (int u = 0; u < (LC + 63) / 64; ++u) gxs[u] = mod_pos(ix0 + lane + 64 * u, p.W);
+    for (int r = rq; r < LR; r += 4) {
+      const float* src = x + int64_t(mod_pos(iy0 + r, p.H)) * p.W;
+#pragma unroll
+      for (int u = 0; u < (LC + 63) / 64; ++u) {
+        const int c = lane + 64 * u;
+        if (c < LC) lds[r * LP + c] = src[gxs[u]];
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- RY x RX outputs per thread ----
+  const int tr = t >> 4, tc = t & 15;
+  float acc[RY][RX];
+#pragma unroll
+  for (int i = 0; i < RY; ++i)
+#pragma unroll
+    for (int j = 0; j < RX; ++j) acc[i][j] = 0.0f;
+  const float* __restrict__ cw = p.c;
+  for (int dy = 0; dy < K; ++dy) {
+    float w[K];
+#pragma unroll
+    for (int dx = 0; dx < K; ++dx) w[dx] = cw[dy * K + dx];
+#pragma unroll
+    for (int i = 0; i < RY; ++i) {
+      const float* row = lds + ((tr * RY + i) * S + dy) * LP + tc * RX * S;
+      float seg[4 * SEG4];
+#pragma unroll
+      for (int v = 0; v < SEG4; ++v) {
+        const float4 q = *reinterpret_cast<const float4*>(row + 4 * v);
+        seg[4 * v + 0] = q.x; seg[4 * v + 1] = q.y; seg[4 * v + 2] = q.z; seg[4 * v + 3] = q.w;
+      }
+#pragma unroll
+      for (int j = 0; j < RX; ++j)
+#pragma unroll
+        for (int dx = 0; dx < K; ++dx) acc[i][j] = fmaf(w[dx], seg[j * S + dx], acc[i][j]);
+    }
+  }
+  const int oy0 = ty * TH + tr * RY, ox0 = tx * TW + tc * RX;
+#pragma unroll
+  for (int i = 0; i < RY; ++i) {
+    const int oy = oy0 + i;
+    if (oy >= p.RH) break;
+#pragma unroll
+    for (int j = 0; j < RX; ++j) {
+      const int ox = ox0 + j;
+      if (ox < p.RW) y[int64_t(oy) * p.RW + ox] = acc[i][j];
+    }
+  }
+}
+
+// RY for tile class tc of stride S
+__host__ __device__ constexpr int ry_of(int S, int tc) {
+  return S == 4 ? (tc == 0 ? 1 : tc == 1 ? 2 : 3) : (tc == 0 ? 1 : tc == 1 ? 2 : 4);
+}
+
+template <int K, int S>
+__device__ __forceinline__ void dispatch_tc(const Filter2DProblem& p, int64_t local, float* lds) {
+  switch (p.tc) {
+    case 0: filter_tile<K, S, ry_of(S, 0)>(p, local, lds); break;
+    case 1: filter_tile<K, S, ry_of(S, 1)>(p, local, lds); break;
+    default: filter_tile<K, S, ry_of(S, 2)>(p, local, lds); break;
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void dispatch_s(const Filter2DProblem& p, int64_t local, float* lds) {
+  switch (p.s) {
+    case 1: dispatch_tc<K, 1>(p, local, lds); break;
+    case 2: dispatch_tc<K, 2>(p, local, lds); break;
+    default: dispatch_tc<K, 4>(p, local, lds); break;
+  }
+}
+
+__device__ __forceinline__ void dispatch_all(const Filter2DProblem& p, int64_t local, float* lds) {
+  switch (p.k) {
+    case 3: dispatch_s<3>(p, local, lds); break;
+    case 5: dispatch_s<5>(p, local, lds); break;
+    case 7: dispatch_s<7>(p, local, lds); break;
+    default: dispatch_s<9>(p, local, lds); break;
+  }
+}
+
+template <int K, int S, int RY>
+__global__ void __launch_bounds__(kThreads) filter2d_kernel(Filter2DProblem p) {
+  extern __shared__ float lds[];
+  filter_tile<K, S, RY>(p, blockIdx.x, lds);
+}
+
+__global__ void __launch_bounds__(kThreads) filter2d_persistent(const Filter2DProblem* __restrict__ probs,
+                                                                int n_probs,
+                                                                const int64_t* __restrict__ prefix,
+                                                                int64_t n_tiles, uint32_t* queue) {
+  extern __shared__ float lds[];
+  __shared__ int64_t s_tile;
+  while (true) {
+    if (threadIdx.x == 0)
+      s_tile = __hip_atomic_fetch_add(&queue[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    __syncthreads();  // every thread holds the id before thread 0 may fetch again
+    if (tile >= n_tiles) break;
+    // problem owning this tile: last k with prefix[k] <= tile
+    int lo = 0, hi = n_probs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (prefix[mid] <= tile) lo = mid; else hi = mid - 1;
+    }
+    const Filter2DProblem p = probs[lo];
+    dispatch_all(p, tile - prefix[lo], lds);
+  }
+  // the last workgroup out resets the queue for the next launch
+  if (threadIdx.x == 0) {
+    const uint32_t done =
+        __hip_atomic_fetch_add(&queue[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (done == gridDim.x - 1) {
+      __hip_atomic_store(&queue[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&queue[1], 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+template <int K, int S>
+hipError_t launch_ks(const Filter2DProblem& p, int64_t n_tiles, hipStream_t st) {
+  switch (p.tc) {
+    case 0: {
+      constexpr int RY = ry_of(S, 0);
+      filter2d_kernel<K, S, RY><<<unsigned(n_tiles), kThreads, lds_rows(K, S, RY) * lds_pitch(K, S) * 4, st>>>(p);
+      break;
+    }
+    case 1: {
+      constexpr int RY = ry_of(S, 1);
+      filter2d_kernel<K, S, RY><<<unsigned(n_tiles), kThreads, lds_rows(K, S, RY) * lds_pitch(K, S) * 4, st>>>(p);
+      break;
+    }
+    default: {
+      constexpr int RY = ry_of(S, 2);
+      filter2d_kernel<K, S, RY><<<unsigned(n_tiles), kThreads, lds_rows(K, S, RY) * lds_pitch(K, S) * 4, st>>>(p);
+      break;
+    }
+  }
+  return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_k(const Filter2DProblem& p, int64_t n_tiles, hipStream_t st) {
+  switch (p.s) {
+    case 1: return launch_ks<K, 1>(p, n_tiles, st);
+    case 2: return launch_ks<K, 2>(p, n_tiles, st);
+    default: return launch_ks<K, 4>(p, n_tiles, st);
+  }
+}
+
+}  // namespace
+
+bool filter2d_supported(int k, int s) {
+  return (k == 3 || k == 5 || k == 7 || k == 9) && (s == 1 || s == 2 || s == 4);
+}
+
+int filter2d_tile_rows(int s, int tc) { return 16 * ry_of(s, tc); }
+int filter2d_tile_cols(int s) { return 16 * rx_of(s); }
+
+size_t filter2d_lds_bytes(int k, int s, int tc) {
+  return size_t(lds_rows(k, s, ry_of(s, tc))) * lds_pitch(k, s) * 4;
+}
+
+size_t filter2d_max_lds_bytes() {
+  size_t m = 0;
+  for (int k = 3; k <= 9; k += 2)
+    for (int s = 1; s <= 4; s *= 2)
+      for (int tc = 0; tc < 3; ++tc) m = filter2d_lds_bytes(k, s, tc) > m ? filter2d_lds_bytes(k, s, tc) : m;
+  return m;
+}
+
+// Fills the tiling fields of p for tile class tc (0..2).
+void filter2d_set_tiles(Filter2DProblem* p, int tc) {
+  p->tc = tc;
+  p->tile_h = filter2d_tile_rows(p->s, tc);
+  p->tile_w = filter2d_tile_cols(p->s);
+  p->tiles_w = (p->RW + p->tile_w - 1) / p->tile_w;
+  const int tiles_h = (p->RH + p->tile_h - 1) / p->tile_h;
+  p->tiles_per_frame = tiles_h * p->tiles_w;
+  p->n_tiles = int64_t(p->tiles_per_frame) * p->frames;
+}
+
+hipError_t launch_filter2d(const Filter2DProblem& p, hipStream_t st) {
+  if (p.n_tiles <= 0) return hipSuccess;
+  switch (p.k) {
+    case 3: return launch_k<3>(p, p.n_tiles, st);
+    case 5: return launch_k<5>(p, p.n_tiles, st);
+    case 7: return launch_k<7>(p, p.n_tiles, st);
+    default: return launch_k<9>(p, p.n_tiles, st);
+  }
+}
+
+int filter2d_persistent_grid() {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+  }
+  // 64 KiB of LDS per workgroup at most: two resident workgroups per CU
+  return 2 * cus;
+}
+
+hipError_t launch_filter2d_persistent(const Filter2DProblem* d_probs, int n_probs,
+                                      const int64_t* d_tile_prefix, int64_t n_tiles, uint32_t* d_queue,
+                                      int grid, hipStream_t st) {
+  filter2d_persistent<<<grid, kThreads, filter2d_max_lds_bytes(), st>>>(d_probs, n_probs, d_tile_prefix,
+                                                                       n_tiles, d_queue);
+  return hipGetLastError();
+}
+
+}  // namespace rsm

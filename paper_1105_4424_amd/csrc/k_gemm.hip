@@ -106,27 +106,23 @@ __global__ void __launch_bounds__(kThreads, 2) gemm_tn_kernel(TnArgs p) {
 
   // global -> register staging: 4 chunks of A and 4 of B per thread
   uint4 ra[4], rb[4];
-  auto load_tile = [&](int k0) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int q = t + kThreads * j;
-      const int row = q >> 3, ch = q & 7;
-      const int kk = k0 + ch * E;
-      const int am = m0 + row, bn = n0 + row;
-      uint4 z = make_uint4(0, 0, 0, 0);
-      ra[j] = (am < p.M && kk < p.K) ? *reinterpret_cast<const uint4*>(A + am * p.lda + kk) : z;
-      rb[j] = (bn < p.N && kk < p.K) ? *reinterpret_cast<const uint4*>(B + bn * p.ldb + kk) : z;
-    }
-  };
-  auto store_tile = [&](int buf) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int q = t + kThreads * j;
-      const int row = q >> 3, ch = q & 7;
-      *reinterpret_cast<uint4*>(&lds[buf][0][row * kPitch + ch * 16]) = ra[j];
-      *reinterpret_cast<uint4*>(&lds[buf][1][row * kPitch + ch * 16]) = rb[j];
-    }
-  };
+#define RSM_GEMM_LOAD(K0)                                                                  \
+  _Pragma("unroll") for (int j = 0; j < 4; ++j) {                                          \
+    const int q = t + kThreads * j;                                                        \
+    const int row = q >> 3, kk = (K0) + (q & 7) * E;                                       \
+    const int am = m0 + row, bn = n0 + row;                                                \
+    ra[j] = (am < p.M && kk < p.K) ? *reinterpret_cast<const uint4*>(A + am * p.lda + kk)  \
+                                   : make_uint4(0, 0, 0, 0);                               \
+    rb[j] = (bn < p.N && kk < p.K) ? *reinterpret_cast<const uint4*>(B + bn * p.ldb + kk)  \
+                                   : make_uint4(0, 0, 0, 0);                               \
+  }
+#define RSM_GEMM_STORE(BUF)                                                                \
+  _Pragma("unroll") for (int j = 0; j < 4; ++j) {                                          \
+    const int q = t + kThreads * j;                                                        \
+    const int row = q >> 3, ch = q & 7;                                                    \
+    *reinterpret_cast<uint4*>(&lds[BUF][0][row * kPitch + ch * 16]) = ra[j];               \
+    *reinterpret_cast<uint4*>(&lds[BUF][1][row * kPitch + ch * 16]) = rb[j];               \
+  }
 
   floatx16 acc[2][2];
 #pragma unroll
@@ -137,12 +133,14 @@ __global__ void __launch_bounds__(kThreads, 2) gemm_tn_kernel(TnArgs p) {
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
   const int n_k = (p.K + BK - 1) / BK;
-  load_tile(0);
-  store_tile(0);
+  RSM_GEMM_LOAD(0);
+  RSM_GEMM_STORE(0);
   __syncthreads();
   for (int kt = 0; kt < n_k; ++kt) {
     const int buf = kt & 1;
-    if (kt + 1 < n_k) load_tile((kt + 1) * BK);
+    if (kt + 1 < n_k) {
+      RSM_GEMM_LOAD((kt + 1) * BK);
+    }
     const unsigned char* la = lds[buf][0];
     const unsigned char* lb = lds[buf][1];
 #pragma unroll
@@ -160,9 +158,13 @@ __global__ void __launch_bounds__(kThreads, 2) gemm_tn_kernel(TnArgs p) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = Mfma<T>::step(fa[i], fb[j], acc[i][j]);
     }
-    if (kt + 1 < n_k) store_tile(buf ^ 1);
+    if (kt + 1 < n_k) {
+      RSM_GEMM_STORE(buf ^ 1);
+    }
     __syncthreads();
   }
+#undef RSM_GEMM_LOAD
+#undef RSM_GEMM_STORE
 
   // 32x32 accumulator layout: element v of lane l is row 8(v/4) + 4(l/32) + v%4, column l%32
 #pragma unroll
@@ -231,16 +233,15 @@ const char* gemm_variant_name(const GemmArgs& a, int compute) {
 }
 
 hipError_t launch_gemm(const GemmArgs& g, int compute, hipStream_t st) {
+  (void)hipGetLastError();  // clear a stale error left by an unrelated earlier call
   const size_t es = compute == RSM_BF16 ? 2 : 4;
   const bool ta = g.a_sk != 1, tb = g.b_sk != 1;
-  size_t bytes = 0;
   const size_t a_bytes = ta ? ((size_t(g.M) * g.K * es + 255) & ~size_t(255)) : 0;
   const size_t b_bytes = tb ? ((size_t(g.N) * g.K * es + 255) & ~size_t(255)) : 0;
-  bytes = a_bytes + b_bytes;
   char* ws = nullptr;
-  if (bytes) {
+  if (a_bytes + b_bytes) {
     rsm_status s;
-    ws = static_cast<char*>(workspace(bytes, st, &s));
+    ws = static_cast<char*>(workspace(a_bytes + b_bytes, st, &s));
     if (s != RSM_OK) return hipErrorOutOfMemory;
   }
   TnArgs p;
@@ -256,21 +257,30 @@ hipError_t launch_gemm(const GemmArgs& g, int compute, hipStream_t st) {
   hipError_t e;
   if (ta) {  // A stored [K][M]: make A[m][k]
     e = es == 2 ? transpose<uint16_t>(g.a, ws, g.K, g.M, st) : transpose<float>(g.a, ws, g.K, g.M, st);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) {
+      fail(RSM_E_HIP, std::string("gemm: transpose of A failed: ") + hipGetErrorString(e));
+      return e;
+    }
     p.a = ws;
     p.lda = g.K;
   }
   if (tb) {  // B stored [K][N]: make Bt[n][k]
     e = es == 2 ? transpose<uint16_t>(g.b, ws + a_bytes, g.K, g.N, st)
                 : transpose<float>(g.b, ws + a_bytes, g.K, g.N, st);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) {
+      fail(RSM_E_HIP, std::string("gemm: transpose of B failed: ") + hipGetErrorString(e));
+      return e;
+    }
     p.b = ws + a_bytes;
     p.ldb = g.K;
   }
   // 16-byte alignment of every row start of both operands
   if (((reinterpret_cast<uintptr_t>(p.a) | reinterpret_cast<uintptr_t>(p.b)) & 15) ||
-      ((p.lda * es) & 15) || ((p.ldb * es) & 15))
+      ((p.lda * es) & 15) || ((p.ldb * es) & 15)) {
+    fail(RSM_E_HIP, "gemm: operand rows not 16-byte aligned (lda " + std::to_string(p.lda) +
+                        ", ldb " + std::to_string(p.ldb) + ")");
     return hipErrorInvalidValue;
+  }
   p.tiles_m = (g.M + kBM - 1) / kBM;
   p.tiles_n = (g.N + kBN - 1) / kBN;
   const int grid = p.tiles_m * p.tiles_n;
@@ -278,7 +288,11 @@ hipError_t launch_gemm(const GemmArgs& g, int compute, hipStream_t st) {
     gemm_tn_kernel<uint16_t><<<grid, kThreads, 0, st>>>(p);
   else
     gemm_tn_kernel<float><<<grid, kThreads, 0, st>>>(p);
-  return hipGetLastError();
+  e = hipGetLastError();
+  if (e != hipSuccess)
+    fail(RSM_E_HIP, "gemm: kernel launch (grid " + std::to_string(grid) + ") failed: " +
+                        hipGetErrorString(e));
+  return e;
 }
 
 }  // namespace rsm

@@ -227,6 +227,22 @@ __global__ void __launch_bounds__(kBlock) fir_kernel(FirArgs a) {
 // ---------------------------------------------------------------------------
 // fused chain: out = V(H(x))
 // ---------------------------------------------------------------------------
+// Offsets of the T1 input rows an output of the fused chain reads, when
+// neither stage's window wraps (the common, interior case); false otherwise.
+template <int T0, int T1>
+__device__ __forceinline__ bool chain_rows(const Win3& h, const Win3& v, const OutPos& q,
+                                           int (&off)[T1]) {
+  const int mb = v.o[0] + v.p[0] * q.b;          // intermediate frame
+  const int mc = v.o[2] + v.p[2] * q.c;          // intermediate column
+  const int xb = h.o[0] + h.p[0] * mb;           // input frame
+  const int xstart = h.o[2] + h.p[2] * mc;       // first input column of the window
+  const int mr0 = v.o[1] + v.p[1] * q.r;         // first intermediate row
+  const bool inside = xstart >= 0 && xstart + T0 <= h.A[2] && mr0 >= 0 && mr0 + T1 <= v.A[1];
+#pragma unroll
+  for (int j = 0; j < T1; ++j) off[j] = (xb * h.A[1] + h.o[1] + h.p[1] * (mr0 + j)) * h.A[2] + xstart;
+  return inside;
+}
+
 template <bool VEC, int T0, int T1>
 __global__ void __launch_bounds__(kBlock) fir_chain_kernel(FirChainArgs a) {
   const Win3& h = a.h;
@@ -235,15 +251,40 @@ __global__ void __launch_bounds__(kBlock) fir_chain_kernel(FirChainArgs a) {
   const int t1 = T1 ? T1 : v.taps;
   for (uint32_t o = blockIdx.x * kBlock + threadIdx.x; o < a.n_out; o += stride) {
     const OutPos q = decode(o, v, a.div_rc, a.div_rr);
-    const int mb = v.o[0] + v.p[0] * q.b;          // intermediate frame
-    const int mc = v.o[2] + v.p[2] * q.c;          // intermediate column
-    const int xb = h.o[0] + h.p[0] * mb;           // input frame
-    const int xstart = h.o[2] + h.p[2] * mc;       // first input column of the window
+    if constexpr (VEC && T0 > 0 && T1 > 0) {
+      // interior: issue every 16-byte load of the T1 x T0 input block first
+      int off[T1];
+      if (chain_rows<T0, T1>(h, v, q, off)) {
+        float4 blk[T1][T0 / 4];
+#pragma unroll
+        for (int j = 0; j < T1; ++j)
+#pragma unroll
+          for (int u = 0; u < T0 / 4; ++u) blk[j][u] = *reinterpret_cast<const float4*>(a.x + off[j] + 4 * u);
+        float acc = 0.0f;
+#pragma unroll
+        for (int j = 0; j < T1; ++j) {
+          float mid = 0.0f;
+#pragma unroll
+          for (int u = 0; u < T0 / 4; ++u) {
+            mid = fmaf(a.ch[4 * u + 0], blk[j][u].x, mid);
+            mid = fmaf(a.ch[4 * u + 1], blk[j][u].y, mid);
+            mid = fmaf(a.ch[4 * u + 2], blk[j][u].z, mid);
+            mid = fmaf(a.ch[4 * u + 3], blk[j][u].w, mid);
+          }
+          acc = fmaf(a.cv[j], mid, acc);
+        }
+        a.y[o] = acc;
+        continue;
+      }
+    }
+    // general case: any window position, modular wrap along both tap axes
+    const int mb = v.o[0] + v.p[0] * q.b;
+    const int mc = v.o[2] + v.p[2] * q.c;
+    const int xb = h.o[0] + h.p[0] * mb;
+    const int xstart = h.o[2] + h.p[2] * mc;
     int mr = wrap_mod(int64_t(v.o[1]) + int64_t(v.p[1]) * q.r, v.A[1]);
     float acc = 0.0f;
-#pragma unroll
-    for (int j = 0; j < (T1 ? T1 : 1 << 30); ++j) {
-      if (j >= t1) break;
+    for (int j = 0; j < t1; ++j) {
       const int xr = h.o[1] + h.p[1] * mr;
       const int row_base = (xb * h.A[1] + xr) * h.A[2];
       const float mid = taps_contig<VEC, T0>(a.x, row_base, xstart, h.A[2], h.taps, a.ch);
@@ -359,20 +400,29 @@ __global__ void __launch_bounds__(kBlock) fir_adjoint_kernel(FirAdjArgs a) {
       n = w.A[1];
     }
     const bool inside = pos >= 0 && pos + taps <= n;
+    // loads first (all taps), then the weight-gradient arithmetic, then stores
+    float xs[kMaxTaps];
     if (AX == 2 && VEC && inside) {
-      float* gxp = a.gx ? a.gx + base + pos : nullptr;
-      const float* xp = a.x ? a.x + base + pos : nullptr;
+      if (a.x) {
+        const float* xp = a.x + base + pos;
 #pragma unroll
-      for (int q4 = 0; q4 < (TT ? TT : kMaxTaps) / 4; ++q4) {
-        if (4 * q4 >= taps) break;
-        if (xp) {
+        for (int q4 = 0; q4 < (TT ? TT : kMaxTaps) / 4; ++q4) {
+          if (4 * q4 >= taps) break;
           const float4 xv = *reinterpret_cast<const float4*>(xp + 4 * q4);
-          gc[4 * q4 + 0] = fmaf(g, xv.x, gc[4 * q4 + 0]);
-          gc[4 * q4 + 1] = fmaf(g, xv.y, gc[4 * q4 + 1]);
-          gc[4 * q4 + 2] = fmaf(g, xv.z, gc[4 * q4 + 2]);
-          gc[4 * q4 + 3] = fmaf(g, xv.w, gc[4 * q4 + 3]);
+          xs[4 * q4 + 0] = xv.x; xs[4 * q4 + 1] = xv.y;
+          xs[4 * q4 + 2] = xv.z; xs[4 * q4 + 3] = xv.w;
         }
-        if (gxp) {
+#pragma unroll
+        for (int k = 0; k < (TT ? TT : kMaxTaps); ++k) {
+          if (k >= taps) break;
+          gc[k] = fmaf(g, xs[k], gc[k]);
+        }
+      }
+      if (a.gx) {
+        float* gxp = a.gx + base + pos;
+#pragma unroll
+        for (int q4 = 0; q4 < (TT ? TT : kMaxTaps) / 4; ++q4) {
+          if (4 * q4 >= taps) break;
           float4 gv = make_float4(cr[4 * q4 + 0] * g, cr[4 * q4 + 1] * g, cr[4 * q4 + 2] * g,
                                   cr[4 * q4 + 3] * g);
           float4* dst = reinterpret_cast<float4*>(gxp + 4 * q4);
@@ -384,17 +434,33 @@ __global__ void __launch_bounds__(kBlock) fir_adjoint_kernel(FirAdjArgs a) {
         }
       }
     } else {
+      int offs[kMaxTaps];
       int e = inside ? pos : wrap_mod(pos, n);
 #pragma unroll
       for (int k = 0; k < (TT ? TT : kMaxTaps); ++k) {
         if (k >= taps) break;
-        const int off = base + e * step;
-        if (a.x) gc[k] = fmaf(g, a.x[off], gc[k]);
-        if (a.gx) {
-          const float gv = cr[k] * g;
-          a.gx[off] = a.accumulate ? a.gx[off] + gv : gv;
-        }
+        offs[k] = base + e * step;
         if (++e == n) e = 0;
+      }
+      if (a.x) {
+#pragma unroll
+        for (int k = 0; k < (TT ? TT : kMaxTaps); ++k) {
+          if (k >= taps) break;
+          xs[k] = a.x[offs[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < (TT ? TT : kMaxTaps); ++k) {
+          if (k >= taps) break;
+          gc[k] = fmaf(g, xs[k], gc[k]);
+        }
+      }
+      if (a.gx) {
+#pragma unroll
+        for (int k = 0; k < (TT ? TT : kMaxTaps); ++k) {
+          if (k >= taps) break;
+          const float gv = cr[k] * g;
+          a.gx[offs[k]] = a.accumulate ? a.gx[offs[k]] + gv : gv;
+        }
       }
     }
   }
@@ -429,6 +495,50 @@ __global__ void __launch_bounds__(kBlock) fir_chain_adjoint_kernel(FirChainAdjAr
   for (uint32_t o = blockIdx.x * kBlock + threadIdx.x; o < a.n_out; o += stride) {
     const OutPos q = decode(o, v, a.div_rc, a.div_rr);
     const float g = a.gy[o];
+    if constexpr (VEC && T0 > 0 && T1 > 0) {
+      // interior: all loads of the T1 x T0 input block, then arithmetic, then stores
+      int off[T1];
+      if (chain_rows<T0, T1>(h, v, q, off)) {
+        float4 blk[T1][T0 / 4];
+#pragma unroll
+        for (int j = 0; j < T1; ++j)
+#pragma unroll
+          for (int u = 0; u < T0 / 4; ++u) blk[j][u] = *reinterpret_cast<const float4*>(a.x + off[j] + 4 * u);
+#pragma unroll
+        for (int j = 0; j < T1; ++j) {
+          const float gm = cv[j] * g;
+          float mid = 0.0f;
+#pragma unroll
+          for (int u = 0; u < T0 / 4; ++u) {
+            const float xv[4] = {blk[j][u].x, blk[j][u].y, blk[j][u].z, blk[j][u].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              mid = fmaf(ch[4 * u + e], xv[e], mid);
+              gp[4 * u + e] = fmaf(gm, xv[e], gp[4 * u + e]);
+            }
+          }
+          gp[kMaxTaps + j] = fmaf(g, mid, gp[kMaxTaps + j]);
+        }
+        if (a.gx) {
+#pragma unroll
+          for (int j = 0; j < T1; ++j) {
+            const float gm = cv[j] * g;
+#pragma unroll
+            for (int u = 0; u < T0 / 4; ++u) {
+              float4 gv = make_float4(ch[4 * u + 0] * gm, ch[4 * u + 1] * gm, ch[4 * u + 2] * gm,
+                                      ch[4 * u + 3] * gm);
+              float4* d4 = reinterpret_cast<float4*>(a.gx + off[j] + 4 * u);
+              if (a.accumulate) {
+                const float4 old = *d4;
+                gv.x += old.x; gv.y += old.y; gv.z += old.z; gv.w += old.w;
+              }
+              *d4 = gv;
+            }
+          }
+        }
+        continue;
+      }
+    }
     const int mb = v.o[0] + v.p[0] * q.b;
     const int mc = v.o[2] + v.p[2] * q.c;
     const int xb = h.o[0] + h.p[0] * mb;

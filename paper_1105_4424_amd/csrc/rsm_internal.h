@@ -196,20 +196,22 @@ struct GemmArgs {
   float* c;
 };
 
-// 2-D k x k window, stride s, on one [H, W] array (batched over B frames),
-// identity output [ceil-ish rep rows, rep cols].
+// 2-D k x k window with stride s along rows and columns of [frames, H, W]
+// (identity along frames), identity output [frames, RH, RW].
 struct Filter2DProblem {
-  int32_t H, W;         // input array
-  int32_t RH, RW;       // output (repetition) shape
-  int32_t oh, ow;       // origin mod H, mod W
-  int32_t k, s;         // pattern side, paving stride
-  int32_t tile_h, tile_w;
-  int32_t tiles_w;      // tiles along W
-  int32_t n_tiles;      // tiles of this problem
-  int64_t tile_base;    // first tile id of this problem in a batch queue
+  int32_t H, W;           // input array (per frame)
+  int32_t RH, RW;         // output (repetition) shape per frame
+  int32_t oh, ow;         // origin reduced into [0, H), [0, W)
+  int32_t k, s;           // pattern side (3, 5, 7, 9), paving stride (1, 2, 4)
+  int32_t tc;             // tile class (0..2)
+  int32_t tile_h, tile_w; // outputs per tile
+  int32_t tiles_w;        // tiles along a row of outputs
+  int32_t tiles_per_frame;
+  int32_t frames;
+  int64_t n_tiles;        // tiles of this problem
   const float* x;
   float* y;
-  const float* c;       // k*k coefficients
+  const float* c;         // k*k weights, row-major
 };
 
 // ---------------------------------------------------------------------------
@@ -239,10 +241,19 @@ const char* gemm_variant_name(const GemmArgs& a, int compute);
 bool gemm_supported(const GemmArgs& a, int compute);
 hipError_t launch_filter2d(const Filter2DProblem& p, hipStream_t st);
 hipError_t launch_filter2d_persistent(const Filter2DProblem* d_probs, int n_probs,
-                                      const int64_t* d_tile_prefix, int64_t n_tiles,
+                                      const int64_t* d_tile_prefix, int64_t n_tiles, uint32_t* d_queue,
                                       int grid, hipStream_t st);
 int filter2d_persistent_grid();
-bool filter2d_supported(int k, int s, int tile_h, int tile_w);
+bool filter2d_supported(int k, int s);
+void filter2d_set_tiles(Filter2DProblem* p, int tc);
+size_t filter2d_lds_bytes(int k, int s, int tc);
+size_t filter2d_max_lds_bytes();
+
+// Planner hook shared with the batch: true when (rep, in, out, task) is a
+// k x k weighted window the 2-D filter kernels handle; fills everything in
+// *fp except the tile class.
+bool plan_filter2d(const rsm_space& rep, const rsm_tiler& in, const rsm_tiler& out,
+                   const rsm_task& task, Filter2DProblem* fp);
 
 // Device workspace owned by the library (per device, grown on demand).
 // *counter (if given) receives a 32-bit completion counter that is zero

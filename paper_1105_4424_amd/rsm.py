@@ -312,6 +312,10 @@ class Batch:
     def run(self, stream=None):
         _check(_abi.load().rsm_batch_run(self._h, _stream(stream)))
 
+    def run_plain(self, stream=None):
+        """Same problems and tile shapes, one launch per problem (no graph)."""
+        _check(_abi.load().rsm_batch_run_plain(self._h, _stream(stream)))
+
     def info(self) -> dict:
         i = _abi.BatchInfo()
         _check(_abi.load().rsm_batch_query(self._h, ctypes.byref(i)))
