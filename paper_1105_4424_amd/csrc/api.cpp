@@ -28,6 +28,14 @@ rsm_status fail(rsm_status s, const std::string& msg) {
   return s;
 }
 
+bool reduce_in_kernel() {
+  static const bool v = [] {
+    const char* e = std::getenv("RSM_ADJOINT_REDUCE");
+    return e && std::string(e) == "inkernel";
+  }();
+  return v;
+}
+
 rsm_status hip_fail(hipError_t e, const char* what) {
   g_last_error = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
   return RSM_E_HIP;
@@ -447,6 +455,9 @@ bool match_gemm(const rsm_space& rep, const rsm_tiler* in, const rsm_tiler& out,
   } else {
     return false;
   }
+  // a single row (column) is k-contiguous whatever the storage order says
+  if (M == 1) { g->a_sk = 1; g->a_sm = K; }
+  if (N == 1) { g->b_sk = 1; g->b_sn = K; }
   g->M = int32_t(M); g->N = int32_t(N); g->K = int32_t(K);
   g->c_sm = N;
   return true;
@@ -684,10 +695,14 @@ rsm_status exec_adjoint(const rsm_space& rep, const rsm_tiler& in, const void* d
     a.c = static_cast<const float*>(task.coeffs);
     a.partial = d_gc ? static_cast<float*>(ws) : nullptr;
     a.gc = static_cast<float*>(d_gc);
-    a.counter = counter;
+    a.counter = reduce_in_kernel() ? counter : nullptr;
     a.accumulate = accumulate;
     int grid = 0;
     if ((e = launch_fir_adjoint(a, ap.vec4, &grid, st)) != hipSuccess) return hip_fail(e, "fir adjoint");
+    if (d_gc && !a.counter &&
+        (e = launch_reduce_partials(a.partial, grid, ap.w.taps, ap.w.taps, static_cast<float*>(d_gc),
+                                    accumulate, st)) != hipSuccess)
+      return hip_fail(e, "weight-gradient reduction");
     return RSM_OK;
   }
   // generic path
@@ -997,13 +1012,21 @@ rsm_status rsm_run_chain_adjoint(const rsm_stage* stages, int32_t n_stages, cons
     a.accumulate = accumulate;
     a.gch = gch;
     a.gcv = gcv;
-    const int grid = fir_chain_adjoint_grid(a);
+    const int grid = fir_chain_adjoint_grid(a, vec4);
     const int nc = h.taps + v.taps;
     if (gch || gcv) {
       a.partial = static_cast<float*>(workspace(size_t(grid) * nc * sizeof(float), st, &s, &a.counter));
       if (s) return s;
+      if (!reduce_in_kernel()) a.counter = nullptr;
     }
     if ((e = launch_fir_chain_adjoint(a, vec4, st)) != hipSuccess) return hip_fail(e, "fused chain adjoint");
+    if (a.partial && !a.counter) {
+      if (gch && (e = launch_reduce_partials(a.partial, grid, h.taps, nc, gch, accumulate, st)) != hipSuccess)
+        return hip_fail(e, "weight-gradient reduction");
+      if (gcv && (e = launch_reduce_partials(a.partial + h.taps, grid, v.taps, nc, gcv, accumulate, st)) !=
+                     hipSuccess)
+        return hip_fail(e, "weight-gradient reduction");
+    }
     return RSM_OK;
   }
   // stage by stage, in reverse; intermediate gradients live in the workspace

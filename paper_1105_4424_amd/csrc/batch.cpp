@@ -3,8 +3,8 @@
 // Problems that are k x k weighted windows (the 2-D filter family) go to one
 // persistent kernel: the host orders them by decreasing estimated cost
 // (max of HBM time and FP32 ALU time), lays their tiles out in that order,
-// and uploads the descriptor table, the tile prefix sums and a two-word queue
-// once.  The first rsm_batch_run captures the persistent launch into a HIP
+// and uploads the descriptor table and the (problem, tile) table once.  The persistent kernel walks the (problem, tile) table round-robin.
+// The first rsm_batch_run captures the persistent launch into a HIP
 // graph on a private stream; every call replays the graph on the caller's
 // stream.  Remaining problems run through rsm_run in the same call.
 //
@@ -33,7 +33,7 @@
 
 namespace {
 
-constexpr const char* kKernelRevision = "filter2d-r1";
+constexpr const char* kKernelRevision = "filter2d-r2";
 constexpr double kHbmBytesPerS = 8.0e12;
 constexpr double kFp32FmaPerS = 39.3e12;   // unpacked FP32 FMA issue rate of the chip
 
@@ -123,8 +123,7 @@ struct rsm_batch_s {
   std::vector<int> others;                     // problem indices run through rsm_run
   std::vector<rsm::Filter2DProblem> fp;        // per problem (valid for persistent ones)
   rsm::Filter2DProblem* d_probs = nullptr;
-  int64_t* d_prefix = nullptr;
-  uint32_t* d_queue = nullptr;
+  uint32_t* d_tiles = nullptr;                 // [n_tiles][2]: problem (table row), tile
   int64_t n_tiles = 0;
   int grid = 0;
   int device = 0;
@@ -138,8 +137,7 @@ struct rsm_batch_s {
     if (graph) (void)hipGraphDestroy(graph);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (d_probs) (void)hipFree(d_probs);
-    if (d_prefix) (void)hipFree(d_prefix);
-    if (d_queue) (void)hipFree(d_queue);
+    if (d_tiles) (void)hipFree(d_tiles);
   }
 };
 
@@ -189,23 +187,28 @@ rsm_status build_queue(rsm_batch_s* b) {
   });
   const size_t n = b->persistent.size();
   std::vector<Filter2DProblem> table(n);
-  std::vector<int64_t> prefix(n + 1, 0);
+  int64_t total = 0;
   for (size_t i = 0; i < n; ++i) {
     table[i] = b->fp[size_t(b->persistent[i])];
-    prefix[i + 1] = prefix[i] + table[i].n_tiles;
+    total += table[i].n_tiles;
   }
-  b->n_tiles = prefix[n];
+  b->n_tiles = total;
   if (b->n_tiles >= (int64_t(1) << 31)) return fail(RSM_E_UNSUPPORTED, "batch has more than 2^31 tiles");
+  std::vector<uint32_t> tiles(size_t(2 * std::max<int64_t>(total, 1)));
+  size_t pos = 0;
+  for (size_t i = 0; i < n; ++i)
+    for (int64_t k = 0; k < table[i].n_tiles; ++k) {
+      tiles[pos++] = uint32_t(i);
+      tiles[pos++] = uint32_t(k);
+    }
   hipError_t e;
   if ((e = hipMalloc(&b->d_probs, sizeof(Filter2DProblem) * std::max<size_t>(n, 1))) != hipSuccess ||
-      (e = hipMalloc(&b->d_prefix, sizeof(int64_t) * (n + 1))) != hipSuccess ||
-      (e = hipMalloc(&b->d_queue, 256)) != hipSuccess)
+      (e = hipMalloc(&b->d_tiles, sizeof(uint32_t) * tiles.size())) != hipSuccess)
     return fail(RSM_E_NOMEM, std::string("batch tables: ") + hipGetErrorString(e));
   if ((e = hipMemcpy(b->d_probs, table.data(), sizeof(Filter2DProblem) * n, hipMemcpyHostToDevice)) !=
           hipSuccess ||
-      (e = hipMemcpy(b->d_prefix, prefix.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice)) !=
-          hipSuccess ||
-      (e = hipMemset(b->d_queue, 0, 256)) != hipSuccess)
+      (e = hipMemcpy(b->d_tiles, tiles.data(), sizeof(uint32_t) * tiles.size(), hipMemcpyHostToDevice)) !=
+          hipSuccess)
     return hip_fail(e, "batch table upload");
   const int g = filter2d_persistent_grid();
   b->grid = int(std::max<int64_t>(1, std::min<int64_t>(g, b->n_tiles)));
@@ -319,8 +322,7 @@ rsm_status rsm_batch_run(rsm_batch b, void* hip_stream) {
     if (!b->exec) {
       if ((e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
         return hip_fail(e, "hipStreamBeginCapture");
-      e = launch_filter2d_persistent(b->d_probs, int(b->persistent.size()), b->d_prefix, b->n_tiles,
-                                     b->d_queue, b->grid, b->cap_stream);
+      e = launch_filter2d_persistent(b->d_probs, b->d_tiles, b->n_tiles, b->grid, b->cap_stream);
       hipGraph_t g = nullptr;
       const hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
       if (e != hipSuccess) {

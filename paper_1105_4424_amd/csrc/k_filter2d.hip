@@ -12,12 +12,13 @@
 //
 // Two launch forms share the tile body:
 //  * filter2d_kernel: one problem, one workgroup per tile (plain launches);
-//  * filter2d_persistent: a grid sized to the chip pops tile ids from a
-//    device counter across many problems (ordered by decreasing cost on the
-//    host), finds each tile's problem by binary search over the tile prefix
-//    sums, and runs the body instantiated for that problem's (K, S, tile).
-//    The last workgroup to finish resets the counters, so the launch can be
-//    replayed from a graph without any memset node.
+//  * filter2d_persistent: a grid sized to the chip (three workgroups per CU)
+//    walks a host-built table of (problem, tile) entries, ordered by
+//    decreasing problem cost, round-robin: workgroup b takes entries b,
+//    b + grid, ...  Each workgroup fetches the next entry and its problem
+//    descriptor before running the current tile, so no tile waits on a
+//    descriptor load; there is no atomic and nothing to reset between graph
+//    replays.
 #include <hip/hip_runtime.h>
 
 #include "rsm_internal.h"
@@ -124,9 +125,10 @@ __device__ __forceinline__ void filter_tile(const Filter2DProblem& p, int64_t lo
   }
 }
 
-// RY for tile class tc of stride S
+// RY for tile class tc of stride S (LDS per workgroup stays under 41 KB, so
+// three workgroups fit in a CU's 160 KB)
 __host__ __device__ constexpr int ry_of(int S, int tc) {
-  return S == 4 ? (tc == 0 ? 1 : tc == 1 ? 2 : 3) : (tc == 0 ? 1 : tc == 1 ? 2 : 4);
+  return S == 4 ? (tc == 0 ? 1 : 2) : (tc == 0 ? 1 : tc == 1 ? 2 : 4);
 }
 
 template <int K, int S>
@@ -162,36 +164,28 @@ __global__ void __launch_bounds__(kThreads) filter2d_kernel(Filter2DProblem p) {
   filter_tile<K, S, RY>(p, blockIdx.x, lds);
 }
 
-__global__ void __launch_bounds__(kThreads) filter2d_persistent(const Filter2DProblem* __restrict__ probs,
-                                                                int n_probs,
-                                                                const int64_t* __restrict__ prefix,
-                                                                int64_t n_tiles, uint32_t* queue) {
+__global__ void __launch_bounds__(kThreads, 3) filter2d_persistent(const Filter2DProblem* __restrict__ probs,
+                                                                   const uint2* __restrict__ tiles,
+                                                                   int64_t n_tiles) {
   extern __shared__ float lds[];
-  __shared__ int64_t s_tile;
+  int64_t t = blockIdx.x;
+  if (t >= n_tiles) return;
+  uint2 e = tiles[t];
+  Filter2DProblem p = probs[e.x];
   while (true) {
-    if (threadIdx.x == 0)
-      s_tile = __hip_atomic_fetch_add(&queue[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const int64_t tile = s_tile;
-    __syncthreads();  // every thread holds the id before thread 0 may fetch again
-    if (tile >= n_tiles) break;
-    // problem owning this tile: last k with prefix[k] <= tile
-    int lo = 0, hi = n_probs - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (prefix[mid] <= tile) lo = mid; else hi = mid - 1;
+    const int64_t tn = t + gridDim.x;
+    const bool more = tn < n_tiles;
+    uint2 en = e;
+    Filter2DProblem pn = p;
+    if (more) {
+      en = tiles[tn];
+      pn = probs[en.x];
     }
-    const Filter2DProblem p = probs[lo];
-    dispatch_all(p, tile - prefix[lo], lds);
-  }
-  // the last workgroup out resets the queue for the next launch
-  if (threadIdx.x == 0) {
-    const uint32_t done =
-        __hip_atomic_fetch_add(&queue[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (done == gridDim.x - 1) {
-      __hip_atomic_store(&queue[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&queue[1], 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    dispatch_all(p, e.y, lds);
+    if (!more) break;
+    t = tn;
+    e = en;
+    p = pn;
   }
 }
 
@@ -275,15 +269,13 @@ int filter2d_persistent_grid() {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
       cus = v;
   }
-  // 64 KiB of LDS per workgroup at most: two resident workgroups per CU
-  return 2 * cus;
+  return 3 * cus;
 }
 
-hipError_t launch_filter2d_persistent(const Filter2DProblem* d_probs, int n_probs,
-                                      const int64_t* d_tile_prefix, int64_t n_tiles, uint32_t* d_queue,
+hipError_t launch_filter2d_persistent(const Filter2DProblem* d_probs, const void* d_tiles, int64_t n_tiles,
                                       int grid, hipStream_t st) {
-  filter2d_persistent<<<grid, kThreads, filter2d_max_lds_bytes(), st>>>(d_probs, n_probs, d_tile_prefix,
-                                                                       n_tiles, d_queue);
+  filter2d_persistent<<<grid, kThreads, filter2d_max_lds_bytes(), st>>>(
+      d_probs, static_cast<const uint2*>(d_tiles), n_tiles);
   return hipGetLastError();
 }
 

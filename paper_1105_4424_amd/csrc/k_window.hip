@@ -296,6 +296,64 @@ __global__ void __launch_bounds__(kBlock) fir_chain_kernel(FirChainArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// fused chain, 8 column taps, lane pairs
+//
+// Lanes 2m and 2m+1 share one output: each loads one 16-byte half of the
+// 8-tap window of every row, so consecutive lanes read consecutive 16-byte
+// chunks and every load instruction covers 1 KiB of contiguous input.  The
+// two half sums of a row are combined with a lane shuffle.  A lane's half
+// (its parity) never changes inside the grid-stride loop (the stride is even).
+// ---------------------------------------------------------------------------
+template <int T1>
+__global__ void __launch_bounds__(kBlock) fir_chain_pair_kernel(FirChainArgs a) {
+  const Win3& h = a.h;
+  const Win3& v = a.v;
+  const uint32_t n_half = 2u * a.n_out;
+  const uint32_t stride = gridDim.x * kBlock;
+  const int hh = threadIdx.x & 1;
+  float c4[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) c4[e] = a.ch[4 * hh + e];
+  for (uint32_t g = blockIdx.x * kBlock + threadIdx.x; g < n_half; g += stride) {
+    const uint32_t o = g >> 1;
+    const OutPos q = decode(o, v, a.div_rc, a.div_rr);
+    int off[T1];
+    if (chain_rows<8, T1>(h, v, q, off)) {
+      float4 blk[T1];
+#pragma unroll
+      for (int j = 0; j < T1; ++j) blk[j] = *reinterpret_cast<const float4*>(a.x + off[j] + 4 * hh);
+      float acc = 0.0f;
+#pragma unroll
+      for (int j = 0; j < T1; ++j) {
+        float part = c4[0] * blk[j].x;
+        part = fmaf(c4[1], blk[j].y, part);
+        part = fmaf(c4[2], blk[j].z, part);
+        part = fmaf(c4[3], blk[j].w, part);
+        // lane 2m holds taps 0-3, lane 2m+1 taps 4-7: add them in that order
+        const float other = __shfl_xor(part, 1);
+        const float mid = hh ? other + part : part + other;
+        acc = fmaf(a.cv[j], mid, acc);
+      }
+      if (hh == 0) a.y[o] = acc;
+    } else if (hh == 0) {
+      // window wraps: the even lane evaluates the output on the modular path
+      const int mb = v.o[0] + v.p[0] * q.b;
+      const int mc = v.o[2] + v.p[2] * q.c;
+      const int xb = h.o[0] + h.p[0] * mb;
+      const int xstart = h.o[2] + h.p[2] * mc;
+      int mr = wrap_mod(int64_t(v.o[1]) + int64_t(v.p[1]) * q.r, v.A[1]);
+      float acc = 0.0f;
+      for (int j = 0; j < T1; ++j) {
+        const int row_base = (xb * h.A[1] + h.o[1] + h.p[1] * mr) * h.A[2];
+        acc = fmaf(a.cv[j], taps_contig<false, 8>(a.x, row_base, xstart, h.A[2], 8, a.ch), acc);
+        if (++mr == v.A[1]) mr = 0;
+      }
+      a.y[o] = acc;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // weight-gradient reduction inside the adjoint kernels
 //
 // Each workgroup reduces its per-thread partial vectors (wavefront butterfly,
@@ -314,7 +372,7 @@ __device__ __forceinline__ float load_agent(const float* p) {
 }
 
 template <int N>
-__device__ __forceinline__ void block_reduce_store(float (&v)[N], int n, float* out_row) {
+__device__ __forceinline__ void block_reduce_store(float (&v)[N], int n, float* out_row, bool coherent) {
   __shared__ float sm[kBlock / 64][N];
 #pragma unroll
   for (int i = 0; i < N; ++i) {
@@ -333,7 +391,10 @@ __device__ __forceinline__ void block_reduce_store(float (&v)[N], int n, float* 
     float t = 0.0f;
 #pragma unroll
     for (int wv = 0; wv < kBlock / 64; ++wv) t += sm[wv][threadIdx.x];
-    store_agent(out_row + threadIdx.x, t);
+    if (coherent)
+      store_agent(out_row + threadIdx.x, t);
+    else
+      out_row[threadIdx.x] = t;
   }
 }
 
@@ -465,8 +526,8 @@ __global__ void __launch_bounds__(kBlock) fir_adjoint_kernel(FirAdjArgs a) {
     }
   }
   if (a.partial) {
-    block_reduce_store<kMaxTaps>(gc, taps, a.partial + int64_t(blockIdx.x) * taps);
-    if (arrive_last(a.counter)) {
+    block_reduce_store<kMaxTaps>(gc, taps, a.partial + int64_t(blockIdx.x) * taps, a.counter != nullptr);
+    if (a.counter && arrive_last(a.counter)) {
       reduce_rows_fixed(a.partial, gridDim.x, taps, 0, taps, a.gc, a.accumulate);
       if (threadIdx.x == 0) __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -620,10 +681,154 @@ __global__ void __launch_bounds__(kBlock) fir_chain_adjoint_kernel(FirChainAdjAr
     for (int k = 0; k < kMaxTaps; ++k) {
       if (k < t1) packed[t0 + k] = gp[kMaxTaps + k];
     }
-    block_reduce_store<2 * kMaxTaps>(packed, t0 + t1, a.partial + int64_t(blockIdx.x) * (t0 + t1));
-    if (arrive_last(a.counter)) {
+    block_reduce_store<2 * kMaxTaps>(packed, t0 + t1, a.partial + int64_t(blockIdx.x) * (t0 + t1),
+                                     a.counter != nullptr);
+    if (a.counter && arrive_last(a.counter)) {
       if (a.gch) reduce_rows_fixed(a.partial, gridDim.x, t0 + t1, 0, t0, a.gch, a.accumulate);
       if (a.gcv) reduce_rows_fixed(a.partial, gridDim.x, t0 + t1, t0, t1, a.gcv, a.accumulate);
+      if (threadIdx.x == 0) __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint of the fused chain, 8 column taps, lane pairs, software-pipelined:
+// the loads of a thread's next output are issued before the stores of the
+// current one, so stores retire while the next block streams in.
+// ---------------------------------------------------------------------------
+template <int T1>
+struct PairBlock {
+  uint32_t o;
+  int off[T1];
+  float4 x[T1];
+  float g;
+  bool fast;
+};
+
+template <int T1>
+__device__ __forceinline__ void pair_fetch(const FirChainAdjArgs& a, uint32_t gidx, int hh,
+                                           PairBlock<T1>& b) {
+  b.o = gidx >> 1;
+  const OutPos q = decode(b.o, a.v, a.div_rc, a.div_rr);
+  b.fast = chain_rows<8, T1>(a.h, a.v, q, b.off);
+  b.g = a.gy[b.o];
+  if (b.fast) {
+#pragma unroll
+    for (int j = 0; j < T1; ++j) b.x[j] = *reinterpret_cast<const float4*>(a.x + b.off[j] + 4 * hh);
+  }
+}
+
+template <int T1>
+__global__ void __launch_bounds__(kBlock) fir_chain_adjoint_pair_kernel(FirChainAdjArgs a) {
+  const Win3& h = a.h;
+  const Win3& v = a.v;
+  const uint32_t n_half = 2u * a.n_out;
+  const uint32_t stride = gridDim.x * kBlock;
+  const int hh = threadIdx.x & 1;
+  float c4[4], cv[T1], g4[4], gv[T1];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    c4[e] = a.ch[4 * hh + e];
+    g4[e] = 0.0f;
+  }
+#pragma unroll
+  for (int j = 0; j < T1; ++j) {
+    cv[j] = a.cv[j];
+    gv[j] = 0.0f;
+  }
+  uint32_t gi = blockIdx.x * kBlock + threadIdx.x;
+  PairBlock<T1> cur;
+  if (gi < n_half) pair_fetch<T1>(a, gi, hh, cur);
+  while (gi < n_half) {
+    const uint32_t gn = gi + stride;
+    PairBlock<T1> nxt;
+    if (gn < n_half) pair_fetch<T1>(a, gn, hh, nxt);
+    const float g = cur.g;
+    if (cur.fast) {
+#pragma unroll
+      for (int j = 0; j < T1; ++j) {
+        const float gm = cv[j] * g;
+        float part = c4[0] * cur.x[j].x;
+        part = fmaf(c4[1], cur.x[j].y, part);
+        part = fmaf(c4[2], cur.x[j].z, part);
+        part = fmaf(c4[3], cur.x[j].w, part);
+        const float other = __shfl_xor(part, 1);
+        const float mid = hh ? other + part : part + other;
+        if (hh == 0) gv[j] = fmaf(g, mid, gv[j]);
+        g4[0] = fmaf(gm, cur.x[j].x, g4[0]);
+        g4[1] = fmaf(gm, cur.x[j].y, g4[1]);
+        g4[2] = fmaf(gm, cur.x[j].z, g4[2]);
+        g4[3] = fmaf(gm, cur.x[j].w, g4[3]);
+      }
+      if (a.gx) {
+#pragma unroll
+        for (int j = 0; j < T1; ++j) {
+          const float gm = cv[j] * g;
+          float4 w4 = make_float4(c4[0] * gm, c4[1] * gm, c4[2] * gm, c4[3] * gm);
+          float4* d4 = reinterpret_cast<float4*>(a.gx + cur.off[j] + 4 * hh);
+          if (a.accumulate) {
+            const float4 old = *d4;
+            w4.x += old.x; w4.y += old.y; w4.z += old.z; w4.w += old.w;
+          }
+          *d4 = w4;
+        }
+      }
+    } else {
+      // window wraps: each lane handles its own four taps on the modular path
+      const OutPos q = decode(cur.o, v, a.div_rc, a.div_rr);
+      const int mb = v.o[0] + v.p[0] * q.b;
+      const int mc = v.o[2] + v.p[2] * q.c;
+      const int xb = h.o[0] + h.p[0] * mb;
+      const int xstart = h.o[2] + h.p[2] * mc;
+      int mr = wrap_mod(int64_t(v.o[1]) + int64_t(v.p[1]) * q.r, v.A[1]);
+      for (int j = 0; j < T1; ++j) {
+        const int row_base = (xb * h.A[1] + h.o[1] + h.p[1] * mr) * h.A[2];
+        const float gm = cv[j] * g;
+        int col = wrap_mod(int64_t(xstart) + 4 * hh, h.A[2]);
+        float xs[4];
+        int cols[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          cols[e] = col;
+          xs[e] = a.x[row_base + col];
+          if (++col == h.A[2]) col = 0;
+        }
+        float part = c4[0] * xs[0];
+        part = fmaf(c4[1], xs[1], part);
+        part = fmaf(c4[2], xs[2], part);
+        part = fmaf(c4[3], xs[3], part);
+        const float other = __shfl_xor(part, 1);
+        const float mid = hh ? other + part : part + other;
+        if (hh == 0) gv[j] = fmaf(g, mid, gv[j]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          g4[e] = fmaf(gm, xs[e], g4[e]);
+          if (a.gx) {
+            float* d = a.gx + row_base + cols[e];
+            *d = a.accumulate ? *d + c4[e] * gm : c4[e] * gm;
+          }
+        }
+        if (++mr == v.A[1]) mr = 0;
+      }
+    }
+    cur = nxt;
+    gi = gn;
+  }
+  if (a.partial) {
+    // [d/dch (8) | d/dcv (T1)]: a lane owns half of the ch slots
+    float packed[8 + T1];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      packed[e] = hh ? 0.0f : g4[e];
+      packed[4 + e] = hh ? g4[e] : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < T1; ++j) packed[8 + j] = gv[j];
+    block_reduce_store<8 + T1>(packed, 8 + T1, a.partial + int64_t(blockIdx.x) * (8 + T1),
+                               a.counter != nullptr);
+    if (a.counter && arrive_last(a.counter)) {
+      if (a.gch) reduce_rows_fixed(a.partial, gridDim.x, 8 + T1, 0, 8, a.gch, a.accumulate);
+      if (a.gcv) reduce_rows_fixed(a.partial, gridDim.x, 8 + T1, 8, T1, a.gcv, a.accumulate);
       if (threadIdx.x == 0) __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
@@ -671,10 +876,12 @@ hipError_t launch_fir(const FirArgs& a, bool vec4, hipStream_t st) {
 }
 
 hipError_t launch_fir_chain(const FirChainArgs& a, bool vec4, hipStream_t st) {
+  if (vec4 && a.h.taps == 8 && a.v.taps == 8) {
+    fir_chain_pair_kernel<8><<<stream_grid(2u * a.n_out, 16), kBlock, 0, st>>>(a);
+    return hipGetLastError();
+  }
   const int grid = stream_grid(a.n_out, 16);
-  if (vec4 && a.h.taps == 8 && a.v.taps == 8)
-    fir_chain_kernel<true, 8, 8><<<grid, kBlock, 0, st>>>(a);
-  else if (vec4)
+  if (vec4)
     fir_chain_kernel<true, 0, 0><<<grid, kBlock, 0, st>>>(a);
   else
     fir_chain_kernel<false, 0, 0><<<grid, kBlock, 0, st>>>(a);
@@ -702,12 +909,22 @@ hipError_t launch_fir_adjoint(const FirAdjArgs& a, bool vec4, int* grid_out, hip
   return hipGetLastError();
 }
 
-int fir_chain_adjoint_grid(const FirChainAdjArgs& a) { return stream_grid(a.n_out, 8); }
+static bool chain_adjoint_uses_pairs(const FirChainAdjArgs& a, bool vec4) {
+  return vec4 && a.h.taps == 8 && a.v.taps == 8;
+}
+
+int fir_chain_adjoint_grid(const FirChainAdjArgs& a, bool vec4) {
+  return chain_adjoint_uses_pairs(a, vec4) ? stream_grid(2u * a.n_out, 8) : stream_grid(a.n_out, 8);
+}
+
+int fir_chain_adjoint_partial_width(const FirChainAdjArgs& a, bool vec4) {
+  return chain_adjoint_uses_pairs(a, vec4) ? 8 + a.v.taps : a.h.taps + a.v.taps;
+}
 
 hipError_t launch_fir_chain_adjoint(const FirChainAdjArgs& a, bool vec4, hipStream_t st) {
-  const int grid = fir_chain_adjoint_grid(a);
-  if (vec4 && a.h.taps == 8 && a.v.taps == 8)
-    fir_chain_adjoint_kernel<true, 8, 8><<<grid, kBlock, 0, st>>>(a);
+  const int grid = fir_chain_adjoint_grid(a, vec4);
+  if (chain_adjoint_uses_pairs(a, vec4))
+    fir_chain_adjoint_pair_kernel<8><<<grid, kBlock, 0, st>>>(a);
   else if (vec4)
     fir_chain_adjoint_kernel<true, 0, 0><<<grid, kBlock, 0, st>>>(a);
   else

@@ -121,7 +121,8 @@ struct FirAdjArgs {
   const float* c;
   float* partial;      // [gridDim.x][taps] per-block weight-gradient partials, nullable
   float* gc;           // weight gradient (written by the last workgroup), nullable
-  uint32_t* counter;   // zero on entry; workgroups count in, the last one resets it
+  uint32_t* counter;   // null: partials only (reduced by a second kernel); else zero on
+                       // entry, workgroups count in and the last one reduces and resets it
   int32_t accumulate;
 };
 
@@ -137,7 +138,7 @@ struct FirChainAdjArgs {
   float* partial;      // [gridDim.x][h.taps + v.taps], nullable
   float* gch;          // weight gradients (written by the last workgroup), nullable
   float* gcv;
-  uint32_t* counter;   // zero on entry; the last workgroup resets it
+  uint32_t* counter;   // as in FirAdjArgs
   int32_t accumulate;
 };
 
@@ -227,7 +228,7 @@ hipError_t launch_fir_chain(const FirChainArgs& a, bool vec4, hipStream_t st);
 hipError_t launch_fir_adjoint(const FirAdjArgs& a, bool vec4, int* grid_out, hipStream_t st);
 int fir_adjoint_grid(const FirAdjArgs& a);
 hipError_t launch_fir_chain_adjoint(const FirChainAdjArgs& a, bool vec4, hipStream_t st);
-int fir_chain_adjoint_grid(const FirChainAdjArgs& a);
+int fir_chain_adjoint_grid(const FirChainAdjArgs& a, bool vec4);
 hipError_t launch_reduce_partials(const float* partial, int n_blocks, int n_coef, int row_stride,
                                   float* out, int accumulate, hipStream_t st);
 hipError_t launch_generic_adjoint(const GenericAdjArgs& a, int max_rank, hipStream_t st);
@@ -240,8 +241,8 @@ hipError_t launch_gemm(const GemmArgs& a, int compute, hipStream_t st);
 const char* gemm_variant_name(const GemmArgs& a, int compute);
 bool gemm_supported(const GemmArgs& a, int compute);
 hipError_t launch_filter2d(const Filter2DProblem& p, hipStream_t st);
-hipError_t launch_filter2d_persistent(const Filter2DProblem* d_probs, int n_probs,
-                                      const int64_t* d_tile_prefix, int64_t n_tiles, uint32_t* d_queue,
+// d_tiles: n_tiles entries of two uint32 (problem index, tile within the problem)
+hipError_t launch_filter2d_persistent(const Filter2DProblem* d_probs, const void* d_tiles, int64_t n_tiles,
                                       int grid, hipStream_t st);
 int filter2d_persistent_grid();
 bool filter2d_supported(int k, int s);
@@ -259,6 +260,10 @@ bool plan_filter2d(const rsm_space& rep, const rsm_tiler& in, const rsm_tiler& o
 // *counter (if given) receives a 32-bit completion counter that is zero
 // between kernels (kernels that use it leave it at zero).
 void* workspace(size_t bytes, hipStream_t st, rsm_status* err, uint32_t** counter = nullptr);
+
+// Weight-gradient reduction of the adjoint kernels: true = the last workgroup
+// reduces in the same launch, false = a second small kernel reduces.
+bool reduce_in_kernel();
 
 // Error reporting: sets the thread-local detail string and returns s.
 rsm_status fail(rsm_status s, const std::string& msg);
