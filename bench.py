@@ -49,7 +49,36 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of the input (known bytes) for counter scaling")
     return ap.parse_args()
+
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fir_chain_adjoint_two_stage_30x1080x1920_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1105_4424_amd", "csrc", "k_window.hip")
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the adjoint kernel from the committed counter
+    summary, or None when the summary is missing or was taken on a different
+    revision of the kernel source."""
+    try:
+        fields = {}
+        for line in open(TRAFFIC_SUMMARY):
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+        if fields.get("kernel source sha256[:16]") != kernel_source_hash():
+            return None
+        return float(fields["traffic bytes per launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def main():
@@ -148,7 +177,7 @@ def main():
                    "taps": T, "paving": T, "tiled_elems_per_step": tiled_per_step,
                    "hbm_bytes_per_step": fwd_bytes + adj_bytes},
         "roofline": {"bound": "hbm", "achieved": adj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": adj_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "frac": adj_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "fir_chain_adjoint_kernel", "bytes_per_launch": adj_bytes,
                      "avg_us": adj_us},
         "extra": {"forward_fused": {"kernel": "fir_chain_kernel", "avg_us": fwd_us,
@@ -157,6 +186,12 @@ def main():
                   "adjoint_fused": {"avg_us": adj_us, "bytes": adj_bytes, "gbs": adj_gbs,
                                     "frac": adj_gbs / HBM_PEAK_GBS}},
     }
+
+    if args.copy_calibration:
+        # a plain copy of known size: 248.832 MB read + 248.832 MB written per launch
+        for _ in range(3):
+            gxs[0].copy_(xs[0])
+        torch.cuda.synchronize()
 
     if not args.no_extra:
         result["extra"].update(extras(args, ts, xs, stages, ch, cv, w2, chain))
@@ -270,6 +305,20 @@ def extras(args, ts, xs, stages, ch, cv, w2, chain):
         "tuned_classes": info["tuned_classes"]}
     log("batched %.1f us, plain %.1f us, ideal %.1f us" % (us_b, us_p, ideal_us))
     batch.close()
+    del bx, bo
+
+    # sparse matrix-vector product of the case study's size (indirect tilers), FP64
+    A = W.stencil27_csr(51)
+    rp = torch.from_numpy(A.row_ptr).to(dev)
+    ci = torch.from_numpy(A.col_idx).to(dev)
+    va = torch.from_numpy(A.vals).to(dev)
+    xv = torch.from_numpy(W.rng_for(6).uniform(-1, 1, A.n)).to(dev)
+    yv = torch.empty(A.n, dtype=torch.float64, device=dev)
+    us = time_fn(lambda: rsm.run_csr(rp, ci, va, xv, yv), reps=50)
+    b = A.nnz * 12 + (A.n + 1) * 4 + A.n * 8 * 2
+    ex["spmv_f64_stencil27_51cubed"] = {"avg_us": us, "bytes": b, "gbs": b / us / 1e3,
+                                        "frac": b / us / 1e3 / HBM_PEAK_GBS, "n": A.n, "nnz": A.nnz}
+    log("spmv %.1f us %.0f GB/s" % (us, b / us / 1e3))
     return ex
 
 

@@ -197,6 +197,26 @@ rsm_status rsm_run_chain_adjoint(const rsm_stage* stages, int32_t n_stages, cons
                                  void* const* d_gc, uint32_t flags, void* hip_stream);
 
 /*
+ * rsm_run_csr -- the repetitive task with data-dependent (indirect) tilers
+ * that the paper's conjugate-gradient case study runs on the GPU (Sec. 7,
+ * the sparse DGEMV): for every row r of a CSR matrix the pattern is the
+ * row's stored entries, read through a contiguous tiler on d_vals and an
+ * indirect tiler (fitting given by d_col_idx) on d_x; the task is DOT and the
+ * output tiler is the identity on d_y:
+ *     y[r] = sum over k in [row_ptr[r], row_ptr[r+1]) of vals[k] * x[col_idx[k]]
+ * d_row_ptr: n_rows + 1 int32, d_col_idx: nnz int32 (device buffers);
+ * d_vals (nnz), d_x (n_cols), d_y (n_rows): dtype RSM_F64 or RSM_F32.  Row
+ * bounds outside [0, nnz] are clamped and column indices outside [0, n_cols)
+ * contribute nothing, so malformed input cannot fault; with
+ * RSM_CHECK_INDICES the host copies the index arrays and rejects them
+ * (RSM_E_INVALID) instead.  Limits: n_rows, n_cols, nnz < 2^31.
+ */
+#define RSM_CHECK_INDICES 0x10u
+rsm_status rsm_run_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t* d_row_ptr,
+                       const int32_t* d_col_idx, const void* d_vals, const void* d_x, void* d_y,
+                       int32_t dtype, uint32_t flags, void* hip_stream);
+
+/*
  * Batched execution of many independent single-input tasks in one launch.
  * rsm_batch_create copies the descriptions, chooses a tile shape per problem
  * (timing candidates on the given stream unless the tuning cache at

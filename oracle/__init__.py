@@ -18,6 +18,7 @@ repetitive tasks of the paper's Sec. 3, Sec. 6.1 and Sec. 7):
   adjoint      transposed gather of the weighted sum, and its weight gradient
   chain_forward / chain_adjoint   two stages composed, loss sum(w * out^2)
   batch_run    independent tasks in list order
+  run_csr      indirect tilers: the sparse matrix-vector product (Sec. 7)
 """
 from __future__ import annotations
 
@@ -72,7 +73,10 @@ def _bind(lib):
                                       ctypes.c_int64, i64p, f64p, f64p]
     lib.oracle_adjoint.argtypes = [ctypes.c_int32, i64p, tp, f64p, tp, f64p, f64p,
                                    f64p, f64p, f64p, f64p]
-    for f in (lib.oracle_indices, lib.oracle_run, lib.oracle_run_sample, lib.oracle_adjoint):
+    i32p = P(ctypes.c_int32)
+    lib.oracle_run_csr.argtypes = [ctypes.c_int64, i32p, i32p, f64p, f64p, f64p, f64p]
+    for f in (lib.oracle_indices, lib.oracle_run, lib.oracle_run_sample, lib.oracle_adjoint,
+              lib.oracle_run_csr):
         f.restype = ctypes.c_int
     return lib
 
@@ -275,3 +279,19 @@ def chain_adjoint(stages, x: np.ndarray, w: np.ndarray) -> ChainResult:
 def batch_run(problems, inputs) -> List[RunResult]:
     """Independent tasks in the order listed."""
     return [run(p, [x]) for p, x in zip(problems, inputs)]
+
+
+def run_csr(csr, x: np.ndarray):
+    """y = A x for a CSR matrix (row_ptr, col_idx, vals), FP64; returns (y, |terms| sums)."""
+    lib = _load()
+    rp = np.ascontiguousarray(csr.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(csr.col_idx, dtype=np.int32)
+    va = widen(csr.vals).reshape(-1)
+    xw = widen(x).reshape(-1)
+    y = np.zeros(csr.n)
+    ya = np.zeros(csr.n)
+    rc = lib.oracle_run_csr(csr.n, _ptr(rp, ctypes.c_int32), _ptr(ci, ctypes.c_int32),
+                            _ptr(va, ctypes.c_double), _ptr(xw, ctypes.c_double),
+                            _ptr(y, ctypes.c_double), _ptr(ya, ctypes.c_double))
+    assert rc == 0
+    return y, ya

@@ -236,3 +236,26 @@ int oracle_adjoint(int32_t rep_rank, const int64_t* rep_shape,
     }
     return 0;
 }
+
+/*
+ * Repetitive task with data-dependent (indirect) tilers: the sparse
+ * matrix-vector product of the paper's conjugate-gradient case study (Sec. 7,
+ * "DGEMV(sparse)").  Repetition r reads the pattern vals[row_ptr[r] ..
+ * row_ptr[r+1]) through a contiguous tiler and x[col_idx[k]] through the
+ * indirect one, applies DOT and writes y[r].  yabs[r] = sum of |terms|.
+ */
+int oracle_run_csr(int64_t n_rows, const int32_t* row_ptr, const int32_t* col_idx,
+                   const double* vals, const double* x, double* y, double* yabs)
+{
+    for (int64_t r = 0; r < n_rows; ++r) {
+        double acc = 0.0, aabs = 0.0;
+        for (int64_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k) {
+            double term = vals[k] * x[col_idx[k]];
+            acc += term;
+            aabs += fabs(term);
+        }
+        y[r] = acc;
+        yabs[r] = aabs;
+    }
+    return 0;
+}

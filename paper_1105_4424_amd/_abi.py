@@ -23,6 +23,7 @@ CHECK_SINGLE_ASSIGN = 0x1
 ACCUMULATE = 0x2
 NO_FUSE = 0x4
 FORCE_GENERIC = 0x8
+CHECK_INDICES = 0x10
 
 I64x8 = ctypes.c_int64 * MAX_RANK
 I64x8x8 = (ctypes.c_int64 * MAX_RANK) * MAX_RANK
@@ -70,7 +71,7 @@ EXPORTS = [
     "rsm_run_chain_adjoint", "rsm_batch_create", "rsm_batch_run", "rsm_batch_run_plain",
     "rsm_batch_query",
     "rsm_batch_tile", "rsm_batch_destroy", "rsm_status_string", "rsm_last_error",
-    "rsm_abi_version",
+    "rsm_abi_version", "rsm_run_csr",
 ]
 
 _lib = None
@@ -97,6 +98,8 @@ def load(path: str = LIB_PATH):
     lib.rsm_run_chain.argtypes = [P(Stage), i32, vp, P(vp), vp, u32, vp]
     lib.rsm_run_adjoint.argtypes = [P(Space), P(Tiler), vp, P(Tiler), vp, P(Task), vp, vp, u32, vp]
     lib.rsm_run_chain_adjoint.argtypes = [P(Stage), i32, vp, P(vp), vp, vp, P(vp), u32, vp]
+    lib.rsm_run_csr.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp, vp,
+                                i32, u32, vp]
     lib.rsm_batch_create.argtypes = [P(Problem), i32, ctypes.c_char_p, u32, vp, P(vp)]
     lib.rsm_batch_run.argtypes = [vp, vp]
     lib.rsm_batch_run_plain.argtypes = [vp, vp]
@@ -105,7 +108,7 @@ def load(path: str = LIB_PATH):
     lib.rsm_batch_destroy.argtypes = [vp]
     for name in ("rsm_validate", "rsm_plan", "rsm_indices", "rsm_run", "rsm_run_chain",
                  "rsm_run_adjoint", "rsm_run_chain_adjoint", "rsm_batch_create", "rsm_batch_run",
-                 "rsm_batch_run_plain", "rsm_batch_query", "rsm_batch_tile", "rsm_batch_destroy"):
+                 "rsm_run_csr", "rsm_batch_run_plain", "rsm_batch_query", "rsm_batch_tile", "rsm_batch_destroy"):
         getattr(lib, name).restype = st
     lib.rsm_status_string.argtypes = [st]
     lib.rsm_status_string.restype = ctypes.c_char_p

@@ -29,7 +29,7 @@ COMMON = [
     "-Wno-pass-failed",
 ]
 
-SOURCES = ["api.cpp", "batch.cpp", "k_generic.hip", "k_window.hip", "k_gemm.hip", "k_filter2d.hip"]
+SOURCES = ["api.cpp", "batch.cpp", "k_generic.hip", "k_window.hip", "k_gemm.hip", "k_filter2d.hip", "k_sparse.hip"]
 
 
 def _compile(src: str) -> str:

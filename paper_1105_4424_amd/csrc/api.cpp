@@ -1079,4 +1079,36 @@ rsm_status rsm_run_chain_adjoint(const rsm_stage* stages, int32_t n_stages, cons
   RSM_GUARD_END
 }
 
+rsm_status rsm_run_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t* d_row_ptr,
+                       const int32_t* d_col_idx, const void* d_vals, const void* d_x, void* d_y,
+                       int32_t dtype, uint32_t flags, void* hip_stream) {
+  RSM_GUARD_BEGIN
+  if (n_rows < 0 || n_cols < 0 || nnz < 0) return fail(RSM_E_SHAPE, "negative CSR size");
+  const int64_t lim = int64_t(1) << 31;
+  if (n_rows >= lim || n_cols >= lim || nnz >= lim) return fail(RSM_E_UNSUPPORTED, "CSR sizes limited to 2^31");
+  if (dtype != RSM_F64 && dtype != RSM_F32) return fail(RSM_E_INVALID, "CSR dtype must be F64 or F32");
+  if (n_rows == 0) return RSM_OK;
+  if (!d_row_ptr || !d_y || (nnz > 0 && (!d_col_idx || !d_vals)) || (n_cols > 0 && !d_x))
+    return fail(RSM_E_INVALID, "NULL device pointer");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  hipError_t e;
+  if (flags & RSM_CHECK_INDICES) {
+    std::vector<int32_t> rp(static_cast<size_t>(n_rows + 1)), ci(static_cast<size_t>(nnz));
+    if ((e = hipMemcpyAsync(rp.data(), d_row_ptr, rp.size() * 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (nnz && (e = hipMemcpyAsync(ci.data(), d_col_idx, ci.size() * 4, hipMemcpyDeviceToHost, st)) != hipSuccess) ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+      return hip_fail(e, "index copy for checking");
+    if (rp[0] != 0 || rp[size_t(n_rows)] != nnz) return fail(RSM_E_INVALID, "row_ptr must start at 0 and end at nnz");
+    for (int64_t r = 0; r < n_rows; ++r)
+      if (rp[size_t(r + 1)] < rp[size_t(r)]) return fail(RSM_E_INVALID, "row_ptr decreases at row " + std::to_string(r));
+    for (int64_t k = 0; k < nnz; ++k)
+      if (ci[size_t(k)] < 0 || ci[size_t(k)] >= n_cols)
+        return fail(RSM_E_INVALID, "column index out of range at entry " + std::to_string(k));
+  }
+  CsrArgs a{n_rows, n_cols, nnz, d_row_ptr, d_col_idx, d_vals, d_x, d_y};
+  if ((e = launch_csr(a, dtype, st)) != hipSuccess) return hip_fail(e, "csr launch");
+  return RSM_OK;
+  RSM_GUARD_END
+}
+
 }  // extern "C"

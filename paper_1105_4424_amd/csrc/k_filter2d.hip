@@ -12,7 +12,7 @@
 //
 // Two launch forms share the tile body:
 //  * filter2d_kernel: one problem, one workgroup per tile (plain launches);
-//  * filter2d_persistent: a grid sized to the chip (three workgroups per CU)
+//  * filter2d_persistent: a grid sized to the chip (seven workgroups per CU)
 //    walks a host-built table of (problem, tile) entries, ordered by
 //    decreasing problem cost, round-robin: workgroup b takes entries b,
 //    b + grid, ...  Each workgroup fetches the next entry and its problem
@@ -45,41 +45,80 @@ __device__ __forceinline__ int mod_pos(int v, int n) {
 }
 
 template <int K, int S, int RY>
-__device__ __forceinline__ void filter_tile(const Filter2DProblem& p, int64_t local, float* lds) {
+__device__ __forceinline__ void filter_tile(const Filter2DProblem p, int64_t local, float* lds) {
   constexpr int RX = rx_of(S);
   constexpr int TH = 16 * RY, TW = 16 * RX;
   constexpr int LR = lds_rows(K, S, RY), LC = lds_cols(K, S), LP = lds_pitch(K, S);
   constexpr int SEG4 = seg4_of(K, S);
 
-  const int tiles_pf = p.tiles_per_frame;
-  const int frame = int(local / tiles_pf);
-  const int rem = int(local - int64_t(frame) * tiles_pf);
+  const uint32_t tiles_pf = uint32_t(p.tiles_per_frame);
+  const int frame = int(uint32_t(local) / tiles_pf);
+  const int rem = int(uint32_t(local) - uint32_t(frame) * tiles_pf);
   const int ty = rem / p.tiles_w;
   const int tx = rem - ty * p.tiles_w;
   const float* __restrict__ x = p.x + int64_t(frame) * p.H * p.W;
   float* __restrict__ y = p.y + int64_t(frame) * p.RH * p.RW;
 
   // ---- stage the tile's input region, wrapping modulo the array shape ----
+  // Thread (rq, lane) stages rows rq, rq + 4, ... at columns lane and
+  // lane + 64: successive elements are a constant stride apart, so addresses
+  // are plain adds.  Rows go out in chunks of CR, all loads of a chunk issued
+  // before any is consumed.
+  constexpr int NR = (LR + 3) / 4;          // rows per row group
+  constexpr int NC = (LC + 63) / 64;        // column passes (1 or 2)
+  constexpr int CR = NR < 8 ? NR : 8;       // rows per chunk
+  constexpr int NCH = (NR + CR - 1) / CR;
   const int iy0 = p.oh + ty * TH * S;   // >= 0 (origin stored reduced)
   const int ix0 = p.ow + tx * TW * S;
   const int t = threadIdx.x;
   const int lane = t & 63, rq = t >> 6;
-  __syncthreads();  // the previous tile's readers are done with LDS
-  if (iy0 + LR <= p.H && ix0 + LC <= p.W) {
-    for (int r = rq; r < LR; r += 4) {
-      const float* src = x + int64_t(iy0 + r) * p.W + ix0;
-      for (int c = lane; c < LC; c += 64) lds[r * LP + c] = src[c];
+  const bool interior = iy0 + LR <= p.H && ix0 + LC <= p.W;
+  float* ldst = lds + rq * LP + lane;
+  if (interior) {
+    const float* src = x + int64_t(iy0 + rq) * p.W + ix0 + lane;
+    const int64_t step = 4 * int64_t(p.W);
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      float v[CR][NC];
+#pragma unroll
+      for (int i = 0; i < CR; ++i) {
+        const int r = rq + 4 * (ch * CR + i);
+#pragma unroll
+        for (int u = 0; u < NC; ++u)
+          v[i][u] = (r < LR && lane + 64 * u < LC) ? src[64 * u] : 0.0f;
+        src += step;
+      }
+      if (ch == 0) __syncthreads();  // the previous tile's readers are done with LDS
+#pragma unroll
+      for (int i = 0; i < CR; ++i) {
+        const int r = rq + 4 * (ch * CR + i);
+#pragma unroll
+        for (int u = 0; u < NC; ++u)
+          if (r < LR && lane + 64 * u < LC) ldst[4 * (ch * CR + i) * LP + 64 * u] = v[i][u];
+      }
     }
   } else {
-    int gxs[(LC + 63) / 64];
+    int gcol[NC];
 #pragma unroll
-    for (int u = 0; u < (LC + 63) / 64; ++u) gxs[u] = mod_pos(ix0 + lane + 64 * u, p.W);
-    for (int r = rq; r < LR; r += 4) {
-      const float* src = x + int64_t(mod_pos(iy0 + r, p.H)) * p.W;
+    for (int u = 0; u < NC; ++u) gcol[u] = mod_pos(ix0 + lane + 64 * u, p.W);
 #pragma unroll
-      for (int u = 0; u < (LC + 63) / 64; ++u) {
-        const int c = lane + 64 * u;
-        if (c < LC) lds[r * LP + c] = src[gxs[u]];
+    for (int ch = 0; ch < NCH; ++ch) {
+      float v[CR][NC];
+#pragma unroll
+      for (int i = 0; i < CR; ++i) {
+        const int r = rq + 4 * (ch * CR + i);
+        const float* row = x + int64_t(mod_pos(iy0 + r, p.H)) * p.W;
+#pragma unroll
+        for (int u = 0; u < NC; ++u)
+          v[i][u] = (r < LR && lane + 64 * u < LC) ? row[gcol[u]] : 0.0f;
+      }
+      if (ch == 0) __syncthreads();  // the previous tile's readers are done with LDS
+#pragma unroll
+      for (int i = 0; i < CR; ++i) {
+        const int r = rq + 4 * (ch * CR + i);
+#pragma unroll
+        for (int u = 0; u < NC; ++u)
+          if (r < LR && lane + 64 * u < LC) ldst[4 * (ch * CR + i) * LP + 64 * u] = v[i][u];
       }
     }
   }
@@ -93,6 +132,9 @@ __device__ __forceinline__ void filter_tile(const Filter2DProblem& p, int64_t lo
 #pragma unroll
     for (int j = 0; j < RX; ++j) acc[i][j] = 0.0f;
   const float* __restrict__ cw = p.c;
+  // one window row per trip: keeps live registers to one row segment per
+  // output row (full unrolling hoists K x RY segments and spills)
+#pragma unroll 1
   for (int dy = 0; dy < K; ++dy) {
     float w[K];
 #pragma unroll
@@ -125,23 +167,33 @@ __device__ __forceinline__ void filter_tile(const Filter2DProblem& p, int64_t lo
   }
 }
 
-// RY for tile class tc of stride S (LDS per workgroup stays under 41 KB, so
-// three workgroups fit in a CU's 160 KB)
+// RY for tile class tc of stride S.  LDS per workgroup stays under 22 KB so
+// that seven workgroups fit in a CU's 160 KB.
 __host__ __device__ constexpr int ry_of(int S, int tc) {
-  return S == 4 ? (tc == 0 ? 1 : 2) : (tc == 0 ? 1 : tc == 1 ? 2 : 4);
+  return S == 4 ? 1 : S == 2 ? (tc == 0 ? 1 : 2) : (tc == 0 ? 1 : tc == 1 ? 2 : 4);
 }
 
 template <int K, int S>
-__device__ __forceinline__ void dispatch_tc(const Filter2DProblem& p, int64_t local, float* lds) {
-  switch (p.tc) {
-    case 0: filter_tile<K, S, ry_of(S, 0)>(p, local, lds); break;
-    case 1: filter_tile<K, S, ry_of(S, 1)>(p, local, lds); break;
-    default: filter_tile<K, S, ry_of(S, 2)>(p, local, lds); break;
+__device__ __forceinline__ void dispatch_tc(const Filter2DProblem p, int64_t local, float* lds) {
+  // one case per distinct tile shape (tile classes that share a shape share the code)
+  if constexpr (S == 4) {
+    filter_tile<K, S, 1>(p, local, lds);
+  } else if constexpr (S == 2) {
+    if (ry_of(S, p.tc) == 1)
+      filter_tile<K, S, 1>(p, local, lds);
+    else
+      filter_tile<K, S, 2>(p, local, lds);
+  } else {
+    switch (ry_of(S, p.tc)) {
+      case 1: filter_tile<K, S, 1>(p, local, lds); break;
+      case 2: filter_tile<K, S, 2>(p, local, lds); break;
+      default: filter_tile<K, S, 4>(p, local, lds); break;
+    }
   }
 }
 
 template <int K>
-__device__ __forceinline__ void dispatch_s(const Filter2DProblem& p, int64_t local, float* lds) {
+__device__ __forceinline__ void dispatch_s(const Filter2DProblem p, int64_t local, float* lds) {
   switch (p.s) {
     case 1: dispatch_tc<K, 1>(p, local, lds); break;
     case 2: dispatch_tc<K, 2>(p, local, lds); break;
@@ -149,7 +201,7 @@ __device__ __forceinline__ void dispatch_s(const Filter2DProblem& p, int64_t loc
   }
 }
 
-__device__ __forceinline__ void dispatch_all(const Filter2DProblem& p, int64_t local, float* lds) {
+__device__ __forceinline__ void dispatch_all(const Filter2DProblem p, int64_t local, float* lds) {
   switch (p.k) {
     case 3: dispatch_s<3>(p, local, lds); break;
     case 5: dispatch_s<5>(p, local, lds); break;
@@ -164,7 +216,7 @@ __global__ void __launch_bounds__(kThreads) filter2d_kernel(Filter2DProblem p) {
   filter_tile<K, S, RY>(p, blockIdx.x, lds);
 }
 
-__global__ void __launch_bounds__(kThreads, 3) filter2d_persistent(const Filter2DProblem* __restrict__ probs,
+__global__ void __launch_bounds__(kThreads, 7) filter2d_persistent(const Filter2DProblem* __restrict__ probs,
                                                                    const uint2* __restrict__ tiles,
                                                                    int64_t n_tiles) {
   extern __shared__ float lds[];
@@ -269,7 +321,7 @@ int filter2d_persistent_grid() {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
       cus = v;
   }
-  return 3 * cus;
+  return 7 * cus;
 }
 
 hipError_t launch_filter2d_persistent(const Filter2DProblem* d_probs, const void* d_tiles, int64_t n_tiles,

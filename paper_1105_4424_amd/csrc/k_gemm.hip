@@ -180,6 +180,103 @@ __global__ void __launch_bounds__(kThreads, 2) gemm_tn_kernel(TnArgs p) {
     }
 }
 
+// Large-tile variant: 256 x 256 outputs per workgroup of 4 waves, each wave
+// owning a 128 x 128 block (4 x 4 MFMA tiles of 32 x 32, 256 accumulators).
+// Both operand tiles (256 rows x 128 bytes of k) are double-buffered in LDS
+// (2 x 73.7 KB, one workgroup per CU) and the next k-tile is prefetched into
+// registers while the current one feeds the matrix cores.
+constexpr int kBig = 256;
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads, 1) gemm_tn_big_kernel(TnArgs p) {
+  constexpr int E = Mfma<T>::kPerChunk;
+  constexpr int BK = kRowBytes / sizeof(T);
+  extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
+  unsigned char* lds = dyn;  // [2 buffers][2 operands][256 rows][kPitch]
+  constexpr int kOp = kBig * kPitch;
+
+  int tm, tn;
+  tile_of(blockIdx.x, p.tiles_m, p.tiles_n, &tm, &tn);
+  const int m0 = tm * kBig, n0 = tn * kBig;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = (wave >> 1) * 128, wn = (wave & 1) * 128;
+  const int li = lane & 31, lh = lane >> 5;
+  const T* A = static_cast<const T*>(p.a);
+  const T* B = static_cast<const T*>(p.b);
+
+  uint4 ra[8], rb[8];
+#define RSM_BIG_LOAD(K0)                                                                   \
+  _Pragma("unroll") for (int j = 0; j < 8; ++j) {                                          \
+    const int row = (t >> 3) + 32 * j, kk = (K0) + (t & 7) * E;                            \
+    const int am = m0 + row, bn = n0 + row;                                                \
+    ra[j] = (am < p.M && kk < p.K) ? *reinterpret_cast<const uint4*>(A + am * p.lda + kk)  \
+                                   : make_uint4(0, 0, 0, 0);                               \
+    rb[j] = (bn < p.N && kk < p.K) ? *reinterpret_cast<const uint4*>(B + bn * p.ldb + kk)  \
+                                   : make_uint4(0, 0, 0, 0);                               \
+  }
+#define RSM_BIG_STORE(BUF)                                                                 \
+  _Pragma("unroll") for (int j = 0; j < 8; ++j) {                                          \
+    const int row = (t >> 3) + 32 * j, off = row * kPitch + (t & 7) * 16;                  \
+    *reinterpret_cast<uint4*>(lds + (BUF) * 2 * kOp + off) = ra[j];                        \
+    *reinterpret_cast<uint4*>(lds + (BUF) * 2 * kOp + kOp + off) = rb[j];                  \
+  }
+
+  floatx16 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+
+  const int n_k = (p.K + BK - 1) / BK;
+  RSM_BIG_LOAD(0);
+  RSM_BIG_STORE(0);
+  __syncthreads();
+  for (int kt = 0; kt < n_k; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < n_k) {
+      RSM_BIG_LOAD((kt + 1) * BK);
+    }
+    const unsigned char* la = lds + buf * 2 * kOp;
+    const unsigned char* lb = la + kOp;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int off = (2 * g + lh) * 16;
+      uint4 fa[4], fb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        fa[i] = *reinterpret_cast<const uint4*>(la + (wm + 32 * i + li) * kPitch + off);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        fb[j] = *reinterpret_cast<const uint4*>(lb + (wn + 32 * j + li) * kPitch + off);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<T>::step(fa[i], fb[j], acc[i][j]);
+    }
+    if (kt + 1 < n_k) {
+      RSM_BIG_STORE(buf ^ 1);
+    }
+    __syncthreads();
+  }
+#undef RSM_BIG_LOAD
+#undef RSM_BIG_STORE
+
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = n0 + wn + 32 * j + li;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = m0 + wm + 32 * i + 8 * (v >> 2) + 4 * lh + (v & 3);
+        if (row < p.M && col < p.N) p.c[int64_t(row) * p.ldc + col] = acc[i][j][v];
+      }
+    }
+}
+
 // dst[c][r] = src[r][c] for a rows x cols matrix (element type E)
 template <typename E>
 __global__ void __launch_bounds__(256) transpose_kernel(const E* __restrict__ src, E* __restrict__ dst,
@@ -281,13 +378,28 @@ hipError_t launch_gemm(const GemmArgs& g, int compute, hipStream_t st) {
                         ", ldb " + std::to_string(p.ldb) + ")");
     return hipErrorInvalidValue;
   }
-  p.tiles_m = (g.M + kBM - 1) / kBM;
-  p.tiles_n = (g.N + kBN - 1) / kBN;
+  // large tiles once the output has at least one 256 x 256 tile per CU
+  const bool big = int64_t(g.M) * g.N >= int64_t(256) * 256 * 200;
+  const int tile = big ? kBig : kBM;
+  p.tiles_m = (g.M + tile - 1) / tile;
+  p.tiles_n = (g.N + tile - 1) / tile;
   const int grid = p.tiles_m * p.tiles_n;
-  if (compute == RSM_BF16)
+  const size_t lds_big = size_t(2) * 2 * kBig * kPitch;
+  if (big) {
+    if (compute == RSM_BF16) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_tn_big_kernel<uint16_t>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_big));
+      gemm_tn_big_kernel<uint16_t><<<grid, kThreads, lds_big, st>>>(p);
+    } else {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_tn_big_kernel<float>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_big));
+      gemm_tn_big_kernel<float><<<grid, kThreads, lds_big, st>>>(p);
+    }
+  } else if (compute == RSM_BF16) {
     gemm_tn_kernel<uint16_t><<<grid, kThreads, 0, st>>>(p);
-  else
+  } else {
     gemm_tn_kernel<float><<<grid, kThreads, 0, st>>>(p);
+  }
   e = hipGetLastError();
   if (e != hipSuccess)
     fail(RSM_E_HIP, "gemm: kernel launch (grid " + std::to_string(grid) + ") failed: " +

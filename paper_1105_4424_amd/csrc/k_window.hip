@@ -305,38 +305,63 @@ __global__ void __launch_bounds__(kBlock) fir_chain_kernel(FirChainArgs a) {
 // (its parity) never changes inside the grid-stride loop (the stride is even).
 // ---------------------------------------------------------------------------
 template <int T1>
+struct FwdPairBlock {
+  uint32_t o;
+  int off[T1];
+  float4 x[T1];
+  bool fast;
+};
+
+template <int T1>
+__device__ __forceinline__ void fwd_pair_fetch(const FirChainArgs& a, uint32_t gidx, int hh,
+                                               FwdPairBlock<T1>& b) {
+  b.o = gidx >> 1;
+  const OutPos q = decode(b.o, a.v, a.div_rc, a.div_rr);
+  b.fast = chain_rows<8, T1>(a.h, a.v, q, b.off);
+  if (b.fast) {
+#pragma unroll
+    for (int j = 0; j < T1; ++j) b.x[j] = *reinterpret_cast<const float4*>(a.x + b.off[j] + 4 * hh);
+  }
+}
+
+// Software-pipelined: the next output's loads are issued before the current
+// output is reduced and stored.
+template <int T1>
 __global__ void __launch_bounds__(kBlock) fir_chain_pair_kernel(FirChainArgs a) {
   const Win3& h = a.h;
   const Win3& v = a.v;
   const uint32_t n_half = 2u * a.n_out;
   const uint32_t stride = gridDim.x * kBlock;
   const int hh = threadIdx.x & 1;
-  float c4[4];
+  float c4[4], cv[T1];
 #pragma unroll
   for (int e = 0; e < 4; ++e) c4[e] = a.ch[4 * hh + e];
-  for (uint32_t g = blockIdx.x * kBlock + threadIdx.x; g < n_half; g += stride) {
-    const uint32_t o = g >> 1;
-    const OutPos q = decode(o, v, a.div_rc, a.div_rr);
-    int off[T1];
-    if (chain_rows<8, T1>(h, v, q, off)) {
-      float4 blk[T1];
 #pragma unroll
-      for (int j = 0; j < T1; ++j) blk[j] = *reinterpret_cast<const float4*>(a.x + off[j] + 4 * hh);
+  for (int j = 0; j < T1; ++j) cv[j] = a.cv[j];
+  uint32_t gi = blockIdx.x * kBlock + threadIdx.x;
+  FwdPairBlock<T1> cur;
+  if (gi < n_half) fwd_pair_fetch<T1>(a, gi, hh, cur);
+  while (gi < n_half) {
+    const uint32_t gn = gi + stride;
+    FwdPairBlock<T1> nxt;
+    if (gn < n_half) fwd_pair_fetch<T1>(a, gn, hh, nxt);
+    if (cur.fast) {
       float acc = 0.0f;
 #pragma unroll
       for (int j = 0; j < T1; ++j) {
-        float part = c4[0] * blk[j].x;
-        part = fmaf(c4[1], blk[j].y, part);
-        part = fmaf(c4[2], blk[j].z, part);
-        part = fmaf(c4[3], blk[j].w, part);
+        float part = c4[0] * cur.x[j].x;
+        part = fmaf(c4[1], cur.x[j].y, part);
+        part = fmaf(c4[2], cur.x[j].z, part);
+        part = fmaf(c4[3], cur.x[j].w, part);
         // lane 2m holds taps 0-3, lane 2m+1 taps 4-7: add them in that order
         const float other = __shfl_xor(part, 1);
         const float mid = hh ? other + part : part + other;
-        acc = fmaf(a.cv[j], mid, acc);
+        acc = fmaf(cv[j], mid, acc);
       }
-      if (hh == 0) a.y[o] = acc;
+      if (hh == 0) a.y[cur.o] = acc;
     } else if (hh == 0) {
       // window wraps: the even lane evaluates the output on the modular path
+      const OutPos q = decode(cur.o, v, a.div_rc, a.div_rr);
       const int mb = v.o[0] + v.p[0] * q.b;
       const int mc = v.o[2] + v.p[2] * q.c;
       const int xb = h.o[0] + h.p[0] * mb;
@@ -345,11 +370,13 @@ __global__ void __launch_bounds__(kBlock) fir_chain_pair_kernel(FirChainArgs a) 
       float acc = 0.0f;
       for (int j = 0; j < T1; ++j) {
         const int row_base = (xb * h.A[1] + h.o[1] + h.p[1] * mr) * h.A[2];
-        acc = fmaf(a.cv[j], taps_contig<false, 8>(a.x, row_base, xstart, h.A[2], 8, a.ch), acc);
+        acc = fmaf(cv[j], taps_contig<false, 8>(a.x, row_base, xstart, h.A[2], 8, a.ch), acc);
         if (++mr == v.A[1]) mr = 0;
       }
-      a.y[o] = acc;
+      a.y[cur.o] = acc;
     }
+    cur = nxt;
+    gi = gn;
   }
 }
 
@@ -877,7 +904,7 @@ hipError_t launch_fir(const FirArgs& a, bool vec4, hipStream_t st) {
 
 hipError_t launch_fir_chain(const FirChainArgs& a, bool vec4, hipStream_t st) {
   if (vec4 && a.h.taps == 8 && a.v.taps == 8) {
-    fir_chain_pair_kernel<8><<<stream_grid(2u * a.n_out, 16), kBlock, 0, st>>>(a);
+    fir_chain_pair_kernel<8><<<stream_grid(2u * a.n_out, 8), kBlock, 0, st>>>(a);
     return hipGetLastError();
   }
   const int grid = stream_grid(a.n_out, 16);

@@ -215,6 +215,18 @@ struct Filter2DProblem {
   const float* c;         // k*k weights, row-major
 };
 
+// CSR sparse matrix-vector product (indirect tilers).
+struct CsrArgs {
+  int64_t n_rows;
+  int64_t n_cols;
+  int64_t nnz;
+  const int32_t* row_ptr;   // n_rows + 1
+  const int32_t* col_idx;   // nnz
+  const void* vals;         // nnz (FP32 or FP64)
+  const void* x;            // n_cols
+  void* y;                  // n_rows
+};
+
 // ---------------------------------------------------------------------------
 // launchers (return hipError_t of the launch)
 // ---------------------------------------------------------------------------
@@ -241,6 +253,8 @@ hipError_t launch_gemm(const GemmArgs& a, int compute, hipStream_t st);
 const char* gemm_variant_name(const GemmArgs& a, int compute);
 bool gemm_supported(const GemmArgs& a, int compute);
 hipError_t launch_filter2d(const Filter2DProblem& p, hipStream_t st);
+hipError_t launch_csr(const CsrArgs& a, int dtype, hipStream_t st);
+int csr_group_size(int64_t n_rows, int64_t nnz);
 // d_tiles: n_tiles entries of two uint32 (problem index, tile within the problem)
 hipError_t launch_filter2d_persistent(const Filter2DProblem* d_probs, const void* d_tiles, int64_t n_tiles,
                                       int grid, hipStream_t st);

@@ -223,6 +223,20 @@ def run_chain_adjoint(stages, x: torch.Tensor, gy: torch.Tensor, gx: Optional[to
                                      _stream(stream)))
 
 
+def run_csr(row_ptr: torch.Tensor, col_idx: torch.Tensor, vals: torch.Tensor, x: torch.Tensor,
+            y: torch.Tensor, check_indices: bool = False, stream=None) -> torch.Tensor:
+    """y = A x for a CSR matrix (indirect tilers; int32 indices on the GPU)."""
+    lib = _abi.load()
+    if row_ptr.dtype != torch.int32 or col_idx.dtype != torch.int32:
+        raise TypeError("row_ptr and col_idx must be int32")
+    if not (vals.dtype == x.dtype == y.dtype):
+        raise TypeError("vals, x and y must share a dtype")
+    _check(lib.rsm_run_csr(y.numel(), x.numel(), col_idx.numel(), _ptr(row_ptr), _ptr(col_idx),
+                           _ptr(vals), _ptr(x), _ptr(y), _dcode(vals),
+                           _abi.CHECK_INDICES if check_indices else 0, _stream(stream)))
+    return y
+
+
 # ---------------------------------------------------------------------------
 # autograd
 # ---------------------------------------------------------------------------

@@ -275,3 +275,78 @@ def random_tiler(rng: np.random.Generator, rep_rank: int, max_rank: int = 3,
 
 def random_array(rng: np.random.Generator, shape, dtype=np.float32) -> np.ndarray:
     return rng.uniform(-1.0, 1.0, size=tuple(shape)).astype(dtype)
+
+
+# ---------------------------------------------------------------------------
+# Sparse matrix of the conjugate-gradient case study (Sec. 7): N = 132651,
+# NNZ = 3442951.  These are exactly the counts of a 27-point stencil on a
+# 51^3 grid (N = 51^3, NNZ = (3*51 - 2)^3), so the stand-in is that stencil
+# with seeded symmetric weights and a dominant diagonal (symmetric positive
+# definite, as the method requires).
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Csr:
+    n: int
+    row_ptr: np.ndarray   # int32 [n + 1]
+    col_idx: np.ndarray   # int32 [nnz]
+    vals: np.ndarray      # float64 [nnz]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.size)
+
+
+def stencil27_csr(side: int = 51, seed: int = 5) -> Csr:
+    """27-point stencil on a side^3 grid, row-major grid numbering.
+    Off-diagonal weights -(1 + 0.5 u), u ~ U[0,1) per undirected edge (so the
+    matrix is symmetric); diagonal = sum of |off-diagonal| of the row + 0.25."""
+    rng = rng_for(seed)
+    n = side ** 3
+    g = np.arange(n, dtype=np.int64).reshape(side, side, side)
+    offs = [(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)]
+    # edge weights: one draw per (node, positive-direction offset), mirrored
+    pos = [o for o in offs if o > (0, 0, 0)]
+    wpos = {}
+    for o in pos:
+        wpos[o] = -(1.0 + 0.5 * rng.random((side, side, side)))
+    rows, cols, vals = [], [], []
+    for o in offs:
+        if o == (0, 0, 0):
+            continue
+        a, b, c = o
+        src = g[max(0, -a):side - max(0, a), max(0, -b):side - max(0, b), max(0, -c):side - max(0, c)]
+        dst = g[max(0, a):side - max(0, -a), max(0, b):side - max(0, -b), max(0, c):side - max(0, -c)]
+        if o in wpos:
+            w = wpos[o][max(0, -a):side - max(0, a), max(0, -b):side - max(0, b), max(0, -c):side - max(0, c)]
+        else:
+            m = (-a, -b, -c)
+            # weight of the mirrored edge, indexed at its source (= this dst)
+            w = wpos[m][max(0, a):side - max(0, -a), max(0, b):side - max(0, -b), max(0, c):side - max(0, -c)]
+        rows.append(src.reshape(-1))
+        cols.append(dst.reshape(-1))
+        vals.append(w.reshape(-1))
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    vals = np.concatenate(vals)
+    diag = np.zeros(n)
+    np.add.at(diag, rows, np.abs(vals))
+    rows = np.concatenate([rows, np.arange(n)])
+    cols = np.concatenate([cols, np.arange(n)])
+    vals = np.concatenate([vals, diag + 0.25])
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    row_ptr = np.zeros(n + 1, np.int64)
+    np.add.at(row_ptr, rows + 1, 1)
+    row_ptr = np.cumsum(row_ptr)
+    return Csr(n, row_ptr.astype(np.int32), cols.astype(np.int32), vals.astype(np.float64))
+
+
+def random_csr(rng: np.random.Generator, n_rows: int, n_cols: int, max_per_row: int = 9,
+               allow_empty: bool = True) -> Csr:
+    """Random sparsity (rows may be empty), values U[-1,1), unsorted columns allowed."""
+    counts = rng.integers(0 if allow_empty else 1, max_per_row + 1, n_rows)
+    row_ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    col_idx = rng.integers(0, n_cols, int(row_ptr[-1])).astype(np.int32)
+    vals = rng.uniform(-1.0, 1.0, int(row_ptr[-1]))
+    return Csr(n_rows, row_ptr, col_idx, vals)

@@ -442,3 +442,43 @@ def test_bf16_rounding_is_rne():
     r = W.bf16_bits_to_f32(W.f32_to_bf16_bits(v))
     # 1+2^-8 is a tie -> even (1.0); 1+3*2^-8 tie -> even (1+2^-6)
     assert r.tolist() == [1.0, 1.0, 1.0 + 2 ** -6, 1.0, -2.5]
+
+
+# ---------------------------------------------------------------------------
+# indirect tilers: sparse matrix-vector product
+# ---------------------------------------------------------------------------
+
+def test_csr_matches_scipy_and_dense():
+    import scipy.sparse as sp
+    rng = W.rng_for(404)
+    for trial in range(20):
+        nr, nc = int(rng.integers(1, 40)), int(rng.integers(1, 40))
+        A = W.random_csr(rng, nr, nc)
+        x = rng.uniform(-1, 1, nc)
+        y, ya = oracle.run_csr(A, x)
+        M = sp.csr_matrix((A.vals, A.col_idx, A.row_ptr), shape=(nr, nc))
+        assert np.allclose(y, M @ x, rtol=0, atol=1e-13)
+        assert np.allclose(y, M.toarray() @ x, rtol=0, atol=1e-13)
+        Mabs = sp.csr_matrix((np.abs(A.vals), A.col_idx, A.row_ptr), shape=(nr, nc))
+        assert np.allclose(ya, Mabs.toarray() @ np.abs(x), rtol=0, atol=1e-13)
+
+
+def test_csr_empty_rows_and_duplicate_columns():
+    A = W.Csr(3, np.array([0, 0, 3, 3], np.int32), np.array([1, 1, 0], np.int32),
+              np.array([2.0, 3.0, -1.0]))
+    y, _ = oracle.run_csr(A, np.array([10.0, 100.0]))
+    assert y.tolist() == [0.0, 490.0, 0.0]
+
+
+def test_stencil_matrix_structure_and_spd():
+    # the case study's counts: N = 51^3, NNZ = (3*51-2)^3
+    A = W.stencil27_csr(51)
+    assert A.n == 132651 and A.nnz == 3442951
+    import scipy.sparse as sp
+    small = W.stencil27_csr(6)
+    M = sp.csr_matrix((small.vals, small.col_idx, small.row_ptr), shape=(small.n, small.n)).toarray()
+    assert np.array_equal(M, M.T)
+    assert np.linalg.eigvalsh(M).min() > 0
+    # interior rows have 27 entries, corners 8
+    counts = np.diff(small.row_ptr)
+    assert counts.max() == 27 and counts.min() == 8
