@@ -19,6 +19,8 @@ repetitive tasks of the paper's Sec. 3, Sec. 6.1 and Sec. 7):
   chain_forward / chain_adjoint   two stages composed, loss sum(w * out^2)
   batch_run    independent tasks in list order
   run_csr      indirect tilers: the sparse matrix-vector product (Sec. 7)
+  cg           the conjugate-gradient loop built from those tasks (Sec. 7,
+               stopping rule of Table 1)
 """
 from __future__ import annotations
 
@@ -78,6 +80,9 @@ def _bind(lib):
     for f in (lib.oracle_indices, lib.oracle_run, lib.oracle_run_sample, lib.oracle_adjoint,
               lib.oracle_run_csr):
         f.restype = ctypes.c_int
+    lib.oracle_cg.argtypes = [ctypes.c_int64, i32p, i32p, f64p, f64p, f64p, ctypes.c_double,
+                              ctypes.c_int64, f64p, f64p, f64p]
+    lib.oracle_cg.restype = ctypes.c_int64
     return lib
 
 
@@ -295,3 +300,38 @@ def run_csr(csr, x: np.ndarray):
                             _ptr(y, ctypes.c_double), _ptr(ya, ctypes.c_double))
     assert rc == 0
     return y, ya
+
+
+class CgResult:
+    def __init__(self, x, iters, res, alpha, beta):
+        self.x = x            # last iterate
+        self.iters = iters    # iterations taken
+        self.res = res        # ||r_k||, k = 0..iters
+        self.alpha = alpha    # step lengths, k = 0..iters-1
+        self.beta = beta      # direction updates, k = 0..iters-1
+
+
+def cg(csr, b: np.ndarray, tol: float = 1e-10, max_iter: Optional[int] = None,
+       x0: Optional[np.ndarray] = None) -> CgResult:
+    """Conjugate gradient on a CSR matrix, FP64, from x0 (default zero) until
+    ||r|| <= tol ||b|| or max_iter iterations (default n)."""
+    lib = _load()
+    n = int(csr.n)
+    if max_iter is None:
+        max_iter = n
+    rp = np.ascontiguousarray(csr.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(csr.col_idx, dtype=np.int32)
+    va = widen(csr.vals).reshape(-1)
+    bw = np.ascontiguousarray(widen(b).reshape(-1))
+    x = np.zeros(n) if x0 is None else np.array(widen(x0).reshape(-1), dtype=np.float64)
+    res = np.zeros(max_iter + 1)
+    alpha = np.zeros(max(max_iter, 1))
+    beta = np.zeros(max(max_iter, 1))
+    k = lib.oracle_cg(n, _ptr(rp, ctypes.c_int32), _ptr(ci, ctypes.c_int32),
+                      _ptr(va, ctypes.c_double), _ptr(bw, ctypes.c_double),
+                      _ptr(x, ctypes.c_double), float(tol), int(max_iter),
+                      _ptr(res, ctypes.c_double), _ptr(alpha, ctypes.c_double),
+                      _ptr(beta, ctypes.c_double))
+    if k < 0:
+        raise ValueError("conjugate gradient broke down: matrix not positive definite")
+    return CgResult(x, int(k), res[:k + 1].copy(), alpha[:k].copy(), beta[:k].copy())

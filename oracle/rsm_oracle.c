@@ -259,3 +259,77 @@ int oracle_run_csr(int64_t n_rows, const int32_t* row_ptr, const int32_t* col_id
     }
     return 0;
 }
+
+/* Plain sequential FP64 inner product. */
+static double dot(int64_t n, const double* a, const double* b)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/*
+ * Conjugate gradient on the CSR matrix, the loop of the paper's case study
+ * (Sec. 7): every matrix-vector product is the indirect-tiler task above, the
+ * inner products and vector updates are element-wise repetitions, and the
+ * loop runs while the continue-condition holds.  The recurrences are the
+ * Hestenes-Stiefel ones in the textbook the paper cites (Golub & Van Loan):
+ *
+ *   r0 = b - A x0,  p0 = r0,  rho0 = <r0, r0>
+ *   while ||r_k|| > tol ||b|| and k < max_iter:
+ *     q = A p_k;  alpha = rho_k / <p_k, q>
+ *     x_{k+1} = x_k + alpha p_k;  r_{k+1} = r_k - alpha q
+ *     rho_{k+1} = <r_{k+1}, r_{k+1}>;  beta = rho_{k+1} / rho_k
+ *     p_{k+1} = r_{k+1} + beta p_k
+ *
+ * The relative residual test with tol follows the stopping rule of the
+ * paper's Table 1 (tol = 1e-10, Matlab pcg's criterion).  x holds x0 on entry
+ * and the last iterate on exit.  res (nullable, max_iter + 1 entries)
+ * receives ||r_k||, alpha / beta (nullable, max_iter entries) the step
+ * scalars.  Returns the number of iterations taken, or -1 on a breakdown
+ * (<p, A p> <= 0: the matrix is not positive definite).
+ */
+int64_t oracle_cg(int64_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                  const double* vals, const double* b, double* x, double tol,
+                  int64_t max_iter, double* res, double* alpha_out, double* beta_out)
+{
+    double* r = (double*)malloc(sizeof(double) * (size_t)(n ? n : 1));
+    double* p = (double*)malloc(sizeof(double) * (size_t)(n ? n : 1));
+    double* q = (double*)malloc(sizeof(double) * (size_t)(n ? n : 1));
+    double* scratch = (double*)malloc(sizeof(double) * (size_t)(n ? n : 1));
+    oracle_run_csr(n, row_ptr, col_idx, vals, x, q, scratch);
+    for (int64_t i = 0; i < n; ++i) {
+        r[i] = b[i] - q[i];
+        p[i] = r[i];
+    }
+    double rho = dot(n, r, r);
+    const double bnorm = sqrt(dot(n, b, b));
+    int64_t k = 0;
+    if (res) res[0] = sqrt(rho);
+    while (k < max_iter && sqrt(rho) > tol * bnorm) {
+        oracle_run_csr(n, row_ptr, col_idx, vals, p, q, scratch);
+        const double pq = dot(n, p, q);
+        if (!(pq > 0.0)) {
+            k = -1;
+            break;
+        }
+        const double alpha = rho / pq;
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] += alpha * p[i];
+            r[i] -= alpha * q[i];
+        }
+        const double rho_next = dot(n, r, r);
+        const double beta = rho_next / rho;
+        for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
+        if (alpha_out) alpha_out[k] = alpha;
+        if (beta_out) beta_out[k] = beta;
+        rho = rho_next;
+        ++k;
+        if (res) res[k] = sqrt(rho);
+    }
+    free(r);
+    free(p);
+    free(q);
+    free(scratch);
+    return k;
+}

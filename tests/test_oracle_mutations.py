@@ -34,6 +34,14 @@ MUTATIONS = {
     "adjoint_sign": ("gx[a] += c * g;", "gx[a] -= c * g;"),
     "adjoint_weight_grad_uses_weight": ("gc[pf] += g * x[a];", "gc[pf] += c * x[a];"),
     "adjoint_drops_weight": ("gx[a] += c * g;", "gx[a] += g;"),
+    "csr_first_column_only": ("double term = vals[k] * x[col_idx[k]];",
+                              "double term = vals[k] * x[col_idx[row_ptr[r]]];"),
+    "cg_initial_residual_sign": ("r[i] = b[i] - q[i];", "r[i] = b[i] + q[i];"),
+    "cg_residual_update_sign": ("r[i] -= alpha * q[i];", "r[i] += alpha * q[i];"),
+    "cg_beta_inverted": ("const double beta = rho_next / rho;",
+                         "const double beta = rho / rho_next;"),
+    "cg_direction_from_residual": ("p[i] = r[i] + beta * p[i];", "p[i] = r[i] + beta * r[i];"),
+    "cg_absolute_stop": ("sqrt(rho) > tol * bnorm", "sqrt(rho) > tol"),
 }
 
 PINS = [
@@ -45,6 +53,10 @@ PINS = [
     pins.test_matmul_tilers_equal_naive_triple_loop,
     pins.test_adjoint_identity_random_tilers,
     pins.test_finite_differences_match_chain_adjoint,
+    pins.test_csr_matches_scipy_and_dense,
+    pins.test_cg_solution_matches_dense_solve,
+    pins.test_cg_iterates_match_scipy,
+    pins.test_cg_stopping_rule_is_relative,
 ]
 
 

@@ -482,3 +482,111 @@ def test_stencil_matrix_structure_and_spd():
     # interior rows have 27 entries, corners 8
     counts = np.diff(small.row_ptr)
     assert counts.max() == 27 and counts.min() == 8
+
+
+# ---------------------------------------------------------------------------
+# conjugate gradient (the case study's loop)
+# ---------------------------------------------------------------------------
+
+def _dense_to_csr(M):
+    rows, cols = np.nonzero(M)
+    row_ptr = np.zeros(M.shape[0] + 1, np.int32)
+    np.add.at(row_ptr, rows + 1, 1)
+    return W.Csr(M.shape[0], np.cumsum(row_ptr).astype(np.int32), cols.astype(np.int32),
+                 M[rows, cols].astype(np.float64))
+
+
+def _spd(rng, n, cond=50.0):
+    """Dense SPD matrix with eigenvalues log-spaced in [1, cond]."""
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    return (Q * np.geomspace(1.0, cond, n)) @ Q.T
+
+
+def test_cg_identity_takes_one_step():
+    b = W.rng_for(500).uniform(-1, 1, 17)
+    r = oracle.cg(_dense_to_csr(np.eye(17)), b)
+    assert r.iters == 1
+    assert np.allclose(r.x, b, rtol=0, atol=1e-15)
+    assert r.alpha[0] == pytest.approx(1.0)
+
+
+def test_cg_terminates_after_distinct_eigenvalue_count():
+    # in exact arithmetic CG stops after as many steps as A has distinct
+    # eigenvalues (here 3) on a right-hand side that excites all of them
+    d = np.array([1.0, 1.0, 4.0, 4.0, 4.0, 9.0, 9.0])
+    b = W.rng_for(501).uniform(0.5, 1.0, d.size)
+    r = oracle.cg(_dense_to_csr(np.diag(d)), b, tol=1e-12)
+    assert r.iters == 3
+    assert np.allclose(r.x, b / d, rtol=1e-12, atol=0)
+
+
+def test_cg_solution_matches_dense_solve():
+    rng = W.rng_for(502)
+    for n, cond in ((5, 3.0), (30, 50.0), (64, 1e3)):
+        M = _spd(rng, n, cond)
+        b = rng.uniform(-1, 1, n)
+        r = oracle.cg(_dense_to_csr(M), b, tol=1e-12, max_iter=10 * n)
+        x = np.linalg.solve(M, b)
+        # forward error <= cond * relative residual (plus rounding)
+        assert np.linalg.norm(r.x - x) <= 2 * cond * 1e-12 * np.linalg.norm(x) + 1e-13
+        assert np.linalg.norm(b - M @ r.x) <= 1.01e-12 * np.linalg.norm(b) + 1e-14
+        # from a nonzero start the same solution is reached
+        r0 = oracle.cg(_dense_to_csr(M), b, tol=1e-12, max_iter=10 * n, x0=rng.uniform(-1, 1, n))
+        assert np.linalg.norm(r0.x - x) <= 2 * cond * 1e-12 * np.linalg.norm(x) + 1e-13
+
+
+def test_cg_iterates_match_scipy():
+    # SciPy's cg runs the same recurrences; after k steps from x0 = 0 both
+    # hold the same iterate up to rounding
+    import scipy.sparse as sp
+    from scipy.sparse.linalg import cg as scipy_cg
+    rng = W.rng_for(503)
+    M = _spd(rng, 40, 20.0)
+    b = rng.uniform(-1, 1, 40)
+    A = _dense_to_csr(M)
+    S = sp.csr_matrix((A.vals, A.col_idx, A.row_ptr), shape=(40, 40))
+    for k in (1, 2, 5, 9):
+        ours = oracle.cg(A, b, tol=0.0, max_iter=k)
+        ref, _ = scipy_cg(S, b, x0=np.zeros(40), rtol=0.0, atol=0.0, maxiter=k)
+        assert ours.iters == k
+        assert np.allclose(ours.x, ref, rtol=0, atol=1e-12 * np.linalg.norm(ref))
+
+
+def test_cg_residuals_orthogonal_and_directions_conjugate():
+    # Krylov properties: r_i . r_j = 0 and p_i . A p_j = 0 for i != j (checked
+    # on residuals recomputed as b - A x_k from separate runs)
+    rng = W.rng_for(504)
+    n = 24
+    M = _spd(rng, n, 10.0)
+    b = rng.uniform(-1, 1, n)
+    A = _dense_to_csr(M)
+    xs = [np.zeros(n)] + [oracle.cg(A, b, tol=0.0, max_iter=k).x for k in range(1, 7)]
+    rs = [b - M @ x for x in xs]
+    ps = [xs[k + 1] - xs[k] for k in range(6)]        # alpha_k p_k
+    for i in range(6):
+        for j in range(i):
+            assert abs(rs[i] @ rs[j]) <= 1e-10 * np.linalg.norm(rs[i]) * np.linalg.norm(rs[j])
+            assert abs(ps[i] @ M @ ps[j]) <= 1e-10 * np.sqrt((ps[i] @ M @ ps[i]) * (ps[j] @ M @ ps[j]))
+    # the recorded residual norms are those of b - A x_k
+    full = oracle.cg(A, b, tol=0.0, max_iter=6)
+    for k in range(7):
+        assert full.res[k] == pytest.approx(np.linalg.norm(rs[k]), rel=1e-9, abs=1e-14)
+
+
+def test_cg_stopping_rule_is_relative():
+    # scaling b by a power of two scales every iterate exactly and leaves the
+    # iteration count unchanged
+    rng = W.rng_for(505)
+    M = _spd(rng, 30, 100.0)
+    b = rng.uniform(-1, 1, 30)
+    A = _dense_to_csr(M)
+    r1 = oracle.cg(A, b, tol=1e-8, max_iter=300)
+    r2 = oracle.cg(A, 2.0 ** 20 * b, tol=1e-8, max_iter=300)
+    assert r1.iters == r2.iters < 300
+    assert np.array_equal(r2.x, 2.0 ** 20 * r1.x)
+    assert r1.res[-1] <= 1e-8 * np.linalg.norm(b) < r1.res[-2]
+
+
+def test_cg_rejects_indefinite():
+    with pytest.raises(ValueError):
+        oracle.cg(_dense_to_csr(np.diag([1.0, -2.0, 3.0])), np.ones(3))
