@@ -182,45 +182,155 @@ __global__ void __launch_bounds__(kThreads, 2) gemm_tn_kernel(TnArgs p) {
 
 // Large-tile variant: 256 x 256 outputs per workgroup of 4 waves, each wave
 // owning a 128 x 128 block (4 x 4 MFMA tiles of 32 x 32, 256 accumulators).
-// Both operand tiles (256 rows x 128 bytes of k) are double-buffered in LDS
-// (2 x 73.7 KB, one workgroup per CU) and the next k-tile is prefetched into
-// registers while the current one feeds the matrix cores.
+// Pipeline (one workgroup per CU):
+//  * LDS holds two k-tiles (2 x 73.7 KB): the matrix cores read one while the
+//    other is refilled;
+//  * one register staging set: during the first k-group of tile t it is
+//    written to LDS (as tile t + 1) and at once reloaded with tile t + 2, so
+//    each global load has a full tile of MFMAs to arrive;
+//  * MFMA fragments are double-buffered: the LDS reads of the next k-group
+//    are issued before the MFMAs of the current one;
+//  * operands are read with raw buffer loads: a per-thread byte offset in
+//    one VGPR plus a uniform offset (row block, k-tile) in an SGPR.  A read
+//    past the operand's last byte returns zero, which pads the M / N tails;
+//    k-chunks past K are sent out of range the same way.
+// Every uniform offset (row block of rows up to m0 + 255, plus K) must stay
+// below 2 GiB so that adding kOutOfRange cannot wrap (the launcher checks).
 constexpr int kBig = 256;
+constexpr uint32_t kBufferWord3 = 0x00020000;   // 32-bit data format, raw access
+constexpr uint32_t kOutOfRange = 0x80000000u;
+
+struct BigTile {
+  __amdgpu_buffer_rsrc_t ra, rb;
+  uint32_t va, vb;       // thread's byte offset within a 32-row block
+  uint32_t sa, sb;       // bytes between consecutive 32-row blocks
+  uint32_t a0, b0;       // byte offset of the tile's first row
+  uint32_t kbytes_thr;   // thread's k offset in bytes
+  uint32_t kbytes;       // K in bytes
+};
+
+// Loads staging registers j in [J0, J0 + NJ) of both operands (rows
+// (t >> 3) + 32 j of the tile) for the k-tile at byte offset k0_bytes.
+template <int J0, int NJ>
+__device__ __forceinline__ void big_load(const BigTile& b, uint32_t k0_bytes, uint4 (&r)[16]) {
+  const bool ok = k0_bytes + b.kbytes_thr < b.kbytes;
+  const uint32_t va = ok ? b.va : kOutOfRange;
+  const uint32_t vb = ok ? b.vb : kOutOfRange;
+#pragma unroll
+  for (int j = J0; j < J0 + NJ; ++j) {
+    r[j] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                         b.ra, va, b.a0 + j * b.sa + k0_bytes, 0));
+    r[8 + j] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                             b.rb, vb, b.b0 + j * b.sb + k0_bytes, 0));
+  }
+}
+
+template <int J0, int NJ>
+__device__ __forceinline__ void big_store(unsigned char* buf, int t, const uint4 (&r)[16]) {
+  constexpr int kOp = kBig * kPitch;
+#pragma unroll
+  for (int j = J0; j < J0 + NJ; ++j) {
+    const int off = ((t >> 3) + 32 * j) * kPitch + (t & 7) * 16;
+    *reinterpret_cast<uint4*>(buf + off) = r[j];
+    *reinterpret_cast<uint4*>(buf + kOp + off) = r[8 + j];
+  }
+}
+
+__device__ __forceinline__ void big_frags(const unsigned char* la, int wm, int wn, int li, int off,
+                                          uint4 (&fa)[4], uint4 (&fb)[4]) {
+  constexpr int kOp = kBig * kPitch;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) fa[i] = *reinterpret_cast<const uint4*>(la + (wm + 32 * i + li) * kPitch + off);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) fb[j] = *reinterpret_cast<const uint4*>(la + kOp + (wn + 32 * j + li) * kPitch + off);
+}
+
+// MFMAs of one LDS k-tile.  With `refill` set, the staged tile is written
+// there a quarter per k-group, each quarter right after that group's MFMAs
+// are issued; each quarter of the staging set is then reloaded from k byte
+// offset `k_next` (K bytes once no k-tile is left: all out of range).
+
+// One k-group G of a k-tile: the 16 MFMAs of group G, with the LDS reads of
+// group G + 1's fragments, a quarter of the refill (LDS writes of staged
+// data) and the reload of that quarter slotted between them, one memory
+// instruction after each MFMA.
+template <typename T, int G>
+__device__ __forceinline__ void big_group(const unsigned char* la, unsigned char* refill, uint32_t k_next,
+                                          const BigTile& bt, int t, uint4 (&stage)[16], int wm, int wn,
+                                          int li, int lh, uint4 (&fa)[2][4], uint4 (&fb)[2][4],
+                                          floatx16 (&acc)[4][4]) {
+  constexpr int c = G & 1;
+  if (G < 3) big_frags(la, wm, wn, li, (2 * (G + 1) + lh) * 16, fa[c ^ 1], fb[c ^ 1]);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<T>::step(fa[c][i], fb[c][j], acc[i][j]);
+  big_store<2 * G, 2>(refill, t, stage);
+  big_load<2 * G, 2>(bt, k_next, stage);
+  // instruction classes: 0x008 MFMA, 0x020 VMEM read, 0x100 DS read, 0x200 DS write
+  if (G < 3) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+  }
+  __builtin_amdgcn_sched_group_barrier(0x008, G < 3 ? 0 : 8, 0);
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// MFMAs of one LDS k-tile.  The staged next tile is written to `refill` a
+// quarter per k-group and each quarter of the staging set is reloaded from k
+// byte offset `k_next` (K bytes once no k-tile is left: all out of range,
+// and the writes then go to a buffer that is not read again).
+template <typename T>
+__device__ __forceinline__ void big_compute(const unsigned char* la, unsigned char* refill, uint32_t k_next,
+                                            const BigTile& bt, int t, uint4 (&stage)[16], int wm, int wn,
+                                            int li, int lh, floatx16 (&acc)[4][4]) {
+  uint4 fa[2][4], fb[2][4];
+  big_frags(la, wm, wn, li, lh * 16, fa[0], fb[0]);
+  big_group<T, 0>(la, refill, k_next, bt, t, stage, wm, wn, li, lh, fa, fb, acc);
+  big_group<T, 1>(la, refill, k_next, bt, t, stage, wm, wn, li, lh, fa, fb, acc);
+  big_group<T, 2>(la, refill, k_next, bt, t, stage, wm, wn, li, lh, fa, fb, acc);
+  big_group<T, 3>(la, refill, k_next, bt, t, stage, wm, wn, li, lh, fa, fb, acc);
+}
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads, 1) gemm_tn_big_kernel(TnArgs p) {
-  constexpr int E = Mfma<T>::kPerChunk;
-  constexpr int BK = kRowBytes / sizeof(T);
   extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
-  unsigned char* lds = dyn;  // [2 buffers][2 operands][256 rows][kPitch]
-  constexpr int kOp = kBig * kPitch;
+  constexpr int kBuf = 2 * kBig * kPitch;   // one k-tile: A rows then B rows
 
   int tm, tn;
   tile_of(blockIdx.x, p.tiles_m, p.tiles_n, &tm, &tn);
-  const int m0 = tm * kBig, n0 = tn * kBig;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wm = (wave >> 1) * 128, wn = (wave & 1) * 128;
   const int li = lane & 31, lh = lane >> 5;
-  const T* A = static_cast<const T*>(p.a);
-  const T* B = static_cast<const T*>(p.b);
-
-  uint4 ra[8], rb[8];
-#define RSM_BIG_LOAD(K0)                                                                   \
-  _Pragma("unroll") for (int j = 0; j < 8; ++j) {                                          \
-    const int row = (t >> 3) + 32 * j, kk = (K0) + (t & 7) * E;                            \
-    const int am = m0 + row, bn = n0 + row;                                                \
-    ra[j] = (am < p.M && kk < p.K) ? *reinterpret_cast<const uint4*>(A + am * p.lda + kk)  \
-                                   : make_uint4(0, 0, 0, 0);                               \
-    rb[j] = (bn < p.N && kk < p.K) ? *reinterpret_cast<const uint4*>(B + bn * p.ldb + kk)  \
-                                   : make_uint4(0, 0, 0, 0);                               \
-  }
-#define RSM_BIG_STORE(BUF)                                                                 \
-  _Pragma("unroll") for (int j = 0; j < 8; ++j) {                                          \
-    const int row = (t >> 3) + 32 * j, off = row * kPitch + (t & 7) * 16;                  \
-    *reinterpret_cast<uint4*>(lds + (BUF) * 2 * kOp + off) = ra[j];                        \
-    *reinterpret_cast<uint4*>(lds + (BUF) * 2 * kOp + kOp + off) = rb[j];                  \
-  }
+  const int m0 = tm * kBig, n0 = tn * kBig;
+  constexpr uint32_t S = sizeof(T);
+  const uint32_t a_span = uint32_t((int64_t(p.M - 1) * p.lda + p.K) * S);
+  const uint32_t b_span = uint32_t((int64_t(p.N - 1) * p.ldb + p.K) * S);
+  BigTile bt;
+  bt.ra = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p.a), short(0), int(a_span), int(kBufferWord3));
+  bt.rb = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p.b), short(0), int(b_span), int(kBufferWord3));
+  bt.kbytes_thr = uint32_t(t & 7) * 16u;
+  bt.va = uint32_t(t >> 3) * uint32_t(p.lda) * S + bt.kbytes_thr;
+  bt.vb = uint32_t(t >> 3) * uint32_t(p.ldb) * S + bt.kbytes_thr;
+  bt.sa = 32u * uint32_t(p.lda) * S;
+  bt.sb = 32u * uint32_t(p.ldb) * S;
+  bt.a0 = uint32_t(m0) * uint32_t(p.lda) * S;
+  bt.b0 = uint32_t(n0) * uint32_t(p.ldb) * S;
+  bt.kbytes = uint32_t(p.K) * S;
 
   floatx16 acc[4][4];
 #pragma unroll
@@ -230,39 +340,19 @@ __global__ void __launch_bounds__(kThreads, 1) gemm_tn_big_kernel(TnArgs p) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
-  const int n_k = (p.K + BK - 1) / BK;
-  RSM_BIG_LOAD(0);
-  RSM_BIG_STORE(0);
+  const int n_k = int((bt.kbytes + kRowBytes - 1) / kRowBytes);
+  uint4 stage[16];
+  big_load<0, 8>(bt, 0, stage);
+  big_store<0, 8>(dyn, t, stage);
+  if (n_k > 1) big_load<0, 8>(bt, kRowBytes, stage);
   __syncthreads();
   for (int kt = 0; kt < n_k; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < n_k) {
-      RSM_BIG_LOAD((kt + 1) * BK);
-    }
-    const unsigned char* la = lds + buf * 2 * kOp;
-    const unsigned char* lb = la + kOp;
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const int off = (2 * g + lh) * 16;
-      uint4 fa[4], fb[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        fa[i] = *reinterpret_cast<const uint4*>(la + (wm + 32 * i + li) * kPitch + off);
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        fb[j] = *reinterpret_cast<const uint4*>(lb + (wn + 32 * j + li) * kPitch + off);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<T>::step(fa[i], fb[j], acc[i][j]);
-    }
-    if (kt + 1 < n_k) {
-      RSM_BIG_STORE(buf ^ 1);
-    }
+    const unsigned char* la = dyn + (kt & 1) * kBuf;
+    unsigned char* refill = dyn + ((kt + 1) & 1) * kBuf;
+    big_compute<T>(la, refill, kt + 2 < n_k ? uint32_t(kt + 2) * kRowBytes : bt.kbytes, bt, t, stage, wm,
+                   wn, li, lh, acc);
     __syncthreads();
   }
-#undef RSM_BIG_LOAD
-#undef RSM_BIG_STORE
 
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -379,7 +469,12 @@ hipError_t launch_gemm(const GemmArgs& g, int compute, hipStream_t st) {
     return hipErrorInvalidValue;
   }
   // large tiles once the output has at least one 256 x 256 tile per CU
-  const bool big = int64_t(g.M) * g.N >= int64_t(256) * 256 * 200;
+  // (its buffer loads use 32-bit offsets, which must stay below 2 GiB up to
+  // the last row of the last, padded 256-row block plus K)
+  const int64_t a_span = (int64_t(g.M + kBig) * p.lda + g.K) * int64_t(es);
+  const int64_t b_span = (int64_t(g.N + kBig) * p.ldb + g.K) * int64_t(es);
+  const bool big = int64_t(g.M) * g.N >= int64_t(256) * 256 * 200 && a_span < (int64_t(1) << 31) &&
+                   b_span < (int64_t(1) << 31);
   const int tile = big ? kBig : kBM;
   p.tiles_m = (g.M + tile - 1) / tile;
   p.tiles_n = (g.N + tile - 1) / tile;
