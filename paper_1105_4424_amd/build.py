@@ -29,7 +29,8 @@ COMMON = [
     "-Wno-pass-failed",
 ]
 
-SOURCES = ["api.cpp", "batch.cpp", "k_generic.hip", "k_window.hip", "k_gemm.hip", "k_filter2d.hip", "k_sparse.hip"]
+SOURCES = ["api.cpp", "batch.cpp", "k_generic.hip", "k_window.hip", "k_gemm.hip", "k_filter2d.hip", "k_sparse.hip",
+           "k_cg.hip"]
 
 
 def _compile(src: str) -> str:

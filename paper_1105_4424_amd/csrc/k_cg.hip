@@ -1,0 +1,245 @@
+// k_cg.hip -- the conjugate-gradient loop of the paper's case study (Sec. 7)
+// on the device, FP64.
+//
+// Every step of the loop is a repetitive task: the sparse matrix-vector
+// product (indirect tilers, one repetition per row), the inner products
+// (a reduction over the element repetitions) and the vector updates
+// (element-wise repetitions).  The paper runs the scalar steps on the CPU
+// between launches; here they stay on the device so the loop never waits for
+// the host.  One iteration is three kernels:
+//
+//   cg_spmv  rho_k from the <r,r> partials; stop test; q = A p; <p,q> partials
+//   cg_xr    alpha = rho_k / <p,q>; x += alpha p; r -= alpha q; <r,r> partials
+//   cg_p     beta = rho_{k+1} / rho_k; p = r + beta p; k += 1
+//
+// Every workgroup rebuilds a scalar from the previous kernel's per-workgroup
+// partials in one fixed order, so all workgroups hold the same bits and the
+// loop is deterministic for a given launch shape.  Each field of the state
+// block is written by workgroup 0 of one kernel only and read by the other
+// kernels, never by the kernel that writes it: rho / done by cg_spmv,
+// breakdown by cg_xr, k by cg_p.  After the stop test has fired, every kernel
+// returns at once, so surplus launched iterations change nothing.
+#include <hip/hip_runtime.h>
+
+#include "rsm_internal.h"
+
+namespace rsm {
+namespace {
+
+constexpr int kBlock = 256;
+
+// Sum of v over the workgroup, fixed tree order; the result is returned to
+// every thread.
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+  lds[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double s = lds[0];
+  __syncthreads();
+  return s;
+}
+
+// Sum of part[0..n) in a fixed order (thread t adds t, t + 256, ..., then the
+// tree): identical bits in every workgroup.
+__device__ __forceinline__ double partial_sum(const double* part, int n, double* lds) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) s += part[i];
+  return block_sum(s, lds);
+}
+
+__device__ __forceinline__ bool lead() { return blockIdx.x == 0 && threadIdx.x == 0; }
+
+// y[r] = sum_k vals[k] x[col_idx[k]] for the rows of this group of G lanes,
+// two rows at a time; calls f(r, y_r) on lane 0 of the group.  Each lane
+// takes entries lane, lane + G, ..., lane + (E - 1) G of a row chunk and
+// issues all index and value loads of both rows before the gathers of x, so
+// a lane has 4 E loads in flight.  Row bounds are clamped into [0, nnz] and
+// columns outside [0, n) contribute nothing.
+constexpr int kEntries = 4;   // E
+
+template <int G, typename F>
+__device__ __forceinline__ void spmv_rows(const CgArgs& a, const double* __restrict__ x, F f) {
+  constexpr int E = kEntries;
+  const int lane = threadIdx.x & (G - 1);
+  const int64_t groups = int64_t(gridDim.x) * (kBlock / G);
+  for (int64_t r0 = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / G; r0 < a.n; r0 += 2 * groups) {
+    const int64_t r1 = r0 + groups;
+    const bool has1 = r1 < a.n;
+    int64_t b0 = a.row_ptr[r0], e0 = a.row_ptr[r0 + 1];
+    int64_t b1 = has1 ? a.row_ptr[r1] : 0, e1 = has1 ? a.row_ptr[r1 + 1] : 0;
+    b0 = b0 < 0 ? 0 : (b0 > a.nnz ? a.nnz : b0);
+    e0 = e0 < b0 ? b0 : (e0 > a.nnz ? a.nnz : e0);
+    b1 = b1 < 0 ? 0 : (b1 > a.nnz ? a.nnz : b1);
+    e1 = e1 < b1 ? b1 : (e1 > a.nnz ? a.nnz : e1);
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int64_t k0 = b0 + lane, k1 = b1 + lane; k0 < e0 || k1 < e1; k0 += G * E, k1 += G * E) {
+      int32_t c0[E], c1[E];
+      double v0[E], v1[E];
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int64_t q0 = k0 + j * G, q1 = k1 + j * G;
+        c0[j] = q0 < e0 ? a.col_idx[q0] : -1;
+        v0[j] = q0 < e0 ? a.vals[q0] : 0.0;
+        c1[j] = q1 < e1 ? a.col_idx[q1] : -1;
+        v1[j] = q1 < e1 ? a.vals[q1] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        if (uint32_t(c0[j]) < uint32_t(a.n)) acc0 += v0[j] * x[c0[j]];
+        if (uint32_t(c1[j]) < uint32_t(a.n)) acc1 += v1[j] * x[c1[j]];
+      }
+    }
+#pragma unroll
+    for (int m = G >> 1; m > 0; m >>= 1) {
+      acc0 += __shfl_xor(acc0, m);
+      acc1 += __shfl_xor(acc1, m);
+    }
+    if (lane == 0) {
+      f(r0, acc0);
+      if (has1) f(r1, acc1);
+    }
+  }
+}
+
+// r = b - A x0, p = r; partials of <r,r> and <b,b>.
+template <int G>
+__global__ void __launch_bounds__(kBlock) cg_init_kernel(CgArgs a) {
+  __shared__ double lds[kBlock];
+  double rr = 0.0, bb = 0.0;
+  spmv_rows<G>(a, a.x, [&](int64_t r, double ax) {
+    const double b = a.b[r];
+    const double res = b - ax;
+    a.r[r] = res;
+    a.p[r] = res;
+    rr += res * res;
+    bb += b * b;
+  });
+  rr = block_sum(rr, lds);
+  bb = block_sum(bb, lds);
+  if (threadIdx.x == 0) {
+    a.part_rr[blockIdx.x] = rr;
+    a.part_bb[blockIdx.x] = bb;
+  }
+}
+
+// One workgroup: ||b|| and a fresh state block.
+__global__ void __launch_bounds__(kBlock) cg_start_kernel(CgArgs a) {
+  __shared__ double lds[kBlock];
+  const double bb = partial_sum(a.part_bb, a.grid, lds);
+  if (threadIdx.x == 0) {
+    a.st->bnorm = sqrt(bb);
+    a.st->rho = 0.0;
+    a.st->k = 0;
+    a.st->done = 0;
+    a.st->breakdown = 0;
+  }
+}
+
+template <int G>
+__global__ void __launch_bounds__(kBlock) cg_spmv_kernel(CgArgs a) {
+  __shared__ double lds[kBlock];
+  const double rho = partial_sum(a.part_rr, a.grid, lds);
+  const int64_t k = a.st->k;
+  const bool stop = a.st->breakdown != 0 || k >= a.max_iter || !(sqrt(rho) > a.tol * a.st->bnorm);
+  if (lead()) {
+    a.st->rho = rho;
+    a.st->done = stop ? 1 : 0;
+    if (a.res) a.res[k] = sqrt(rho);
+  }
+  if (stop) return;
+  double pq = 0.0;
+  spmv_rows<G>(a, a.p, [&](int64_t r, double q) {
+    a.q[r] = q;
+    pq += a.p[r] * q;
+  });
+  pq = block_sum(pq, lds);
+  if (threadIdx.x == 0) a.part_pq[blockIdx.x] = pq;
+}
+
+__global__ void __launch_bounds__(kBlock) cg_xr_kernel(CgArgs a) {
+  __shared__ double lds[kBlock];
+  if (a.st->done) return;
+  const double pq = partial_sum(a.part_pq, a.grid, lds);
+  if (!(pq > 0.0)) {  // A is not positive definite along p
+    if (lead()) a.st->breakdown = 1;
+    return;
+  }
+  const double alpha = a.st->rho / pq;
+  if (lead() && a.alpha) a.alpha[a.st->k] = alpha;
+  double rr = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < a.n; i += int64_t(gridDim.x) * kBlock) {
+    const double p = a.p[i];
+    a.x[i] += alpha * p;
+    const double res = a.r[i] - alpha * a.q[i];
+    a.r[i] = res;
+    rr += res * res;
+  }
+  rr = block_sum(rr, lds);
+  if (threadIdx.x == 0) a.part_rr[blockIdx.x] = rr;
+}
+
+__global__ void __launch_bounds__(kBlock) cg_p_kernel(CgArgs a) {
+  __shared__ double lds[kBlock];
+  if (a.st->done || a.st->breakdown) return;
+  const double rho_next = partial_sum(a.part_rr, a.grid, lds);
+  const double beta = rho_next / a.st->rho;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < a.n; i += int64_t(gridDim.x) * kBlock)
+    a.p[i] = a.r[i] + beta * a.p[i];
+  if (lead()) {
+    const int64_t k = a.st->k;
+    if (a.beta) a.beta[k] = beta;
+    a.st->k = k + 1;
+  }
+}
+
+template <int G>
+hipError_t launch_g(const CgArgs& a, bool init, int iters, hipStream_t st) {
+  const unsigned grid = unsigned(a.grid);
+  if (init) {
+    cg_init_kernel<G><<<grid, kBlock, 0, st>>>(a);
+    cg_start_kernel<<<1, kBlock, 0, st>>>(a);
+  }
+  for (int i = 0; i < iters; ++i) {
+    cg_spmv_kernel<G><<<grid, kBlock, 0, st>>>(a);
+    cg_xr_kernel<<<grid, kBlock, 0, st>>>(a);
+    cg_p_kernel<<<grid, kBlock, 0, st>>>(a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// Lanes per row: the power of two (4..64) that covers the mean row length
+// with kEntries entries per lane.
+int cg_group_size(int64_t n, int64_t nnz) {
+  const double mean = n > 0 ? double(nnz) / double(n) : 0.0;
+  int g = 4;
+  while (g < 64 && g * kEntries < mean) g *= 2;
+  return g;
+}
+
+// Enough workgroups for one pass over the rows (two rows per lane group), at
+// most 2048: every loop kernel rebuilds its scalar from this many partials.
+int cg_grid(int64_t n, int64_t nnz) {
+  const int64_t lanes = ((n + 1) / 2) * cg_group_size(n, nnz);
+  int64_t g = (lanes + kBlock - 1) / kBlock;
+  if (g > 2048) g = 2048;
+  if (g < 1) g = 1;
+  return int(g);
+}
+
+hipError_t launch_cg(const CgArgs& a, bool init, int iters, hipStream_t st) {
+  switch (cg_group_size(a.n, a.nnz)) {
+    case 4: return launch_g<4>(a, init, iters, st);
+    case 8: return launch_g<8>(a, init, iters, st);
+    case 16: return launch_g<16>(a, init, iters, st);
+    case 32: return launch_g<32>(a, init, iters, st);
+    default: return launch_g<64>(a, init, iters, st);
+  }
+}
+
+}  // namespace rsm

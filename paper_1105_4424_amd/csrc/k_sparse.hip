@@ -2,12 +2,14 @@
 // sparse matrix-vector product in CSR form.
 //
 // A group of G lanes (G a power of two, chosen from the mean row length)
-// handles one row: lanes stride through the row's entries (consecutive
-// lanes read consecutive values and column indices, so those loads
-// coalesce), gather x through the column indices (x is small enough to stay
-// in L2), and reduce with a butterfly of wavefront shuffles.  Row bounds are
-// clamped into [0, nnz] and column indices outside [0, n_cols) contribute
-// nothing, so malformed input cannot read out of bounds.
+// handles two rows at a time: each lane takes entries lane, lane + G, ...,
+// lane + 3 G of a row chunk (consecutive lanes read consecutive values and
+// column indices, so those loads coalesce), issues every index and value
+// load of both rows before gathering x through the column indices (x is
+// small enough to stay in L2), and the group reduces with a butterfly of
+// wavefront shuffles.  Row bounds are clamped into [0, nnz] and column
+// indices outside [0, n_cols) contribute nothing, so malformed input cannot
+// read out of bounds.
 #include <hip/hip_runtime.h>
 
 #include "rsm_internal.h"
@@ -17,31 +19,58 @@ namespace {
 
 constexpr int kBlock = 256;
 
+constexpr int kEntries = 4;   // entries per lane per row chunk
+
 template <typename T, int G>
 __global__ void __launch_bounds__(kBlock) csr_kernel(CsrArgs a) {
+  constexpr int E = kEntries;
   const T* __restrict__ vals = static_cast<const T*>(a.vals);
   const T* __restrict__ x = static_cast<const T*>(a.x);
   T* __restrict__ y = static_cast<T*>(a.y);
   const int lane = threadIdx.x & (G - 1);
   const int64_t groups = int64_t(gridDim.x) * (kBlock / G);
-  for (int64_t r = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / G; r < a.n_rows; r += groups) {
-    int64_t b = a.row_ptr[r], e = a.row_ptr[r + 1];
-    b = b < 0 ? 0 : (b > a.nnz ? a.nnz : b);
-    e = e < b ? b : (e > a.nnz ? a.nnz : e);
-    T acc = T(0);
-    for (int64_t k = b + lane; k < e; k += G) {
-      const int32_t c = a.col_idx[k];
-      if (uint32_t(c) < uint32_t(a.n_cols)) acc += vals[k] * x[c];
+  for (int64_t r0 = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / G; r0 < a.n_rows; r0 += 2 * groups) {
+    const int64_t r1 = r0 + groups;
+    const bool has1 = r1 < a.n_rows;
+    int64_t b0 = a.row_ptr[r0], e0 = a.row_ptr[r0 + 1];
+    int64_t b1 = has1 ? a.row_ptr[r1] : 0, e1 = has1 ? a.row_ptr[r1 + 1] : 0;
+    b0 = b0 < 0 ? 0 : (b0 > a.nnz ? a.nnz : b0);
+    e0 = e0 < b0 ? b0 : (e0 > a.nnz ? a.nnz : e0);
+    b1 = b1 < 0 ? 0 : (b1 > a.nnz ? a.nnz : b1);
+    e1 = e1 < b1 ? b1 : (e1 > a.nnz ? a.nnz : e1);
+    T acc0 = T(0), acc1 = T(0);
+    for (int64_t k0 = b0 + lane, k1 = b1 + lane; k0 < e0 || k1 < e1; k0 += G * E, k1 += G * E) {
+      int32_t c0[E], c1[E];
+      T v0[E], v1[E];
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int64_t q0 = k0 + j * G, q1 = k1 + j * G;
+        c0[j] = q0 < e0 ? a.col_idx[q0] : -1;
+        v0[j] = q0 < e0 ? vals[q0] : T(0);
+        c1[j] = q1 < e1 ? a.col_idx[q1] : -1;
+        v1[j] = q1 < e1 ? vals[q1] : T(0);
+      }
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        if (uint32_t(c0[j]) < uint32_t(a.n_cols)) acc0 += v0[j] * x[c0[j]];
+        if (uint32_t(c1[j]) < uint32_t(a.n_cols)) acc1 += v1[j] * x[c1[j]];
+      }
     }
 #pragma unroll
-    for (int m = G >> 1; m > 0; m >>= 1) acc += __shfl_xor(acc, m);
-    if (lane == 0) y[r] = acc;
+    for (int m = G >> 1; m > 0; m >>= 1) {
+      acc0 += __shfl_xor(acc0, m);
+      acc1 += __shfl_xor(acc1, m);
+    }
+    if (lane == 0) {
+      y[r0] = acc0;
+      if (has1) y[r1] = acc1;
+    }
   }
 }
 
 template <typename T>
 hipError_t launch_t(const CsrArgs& a, int g, hipStream_t st) {
-  const int64_t lanes = a.n_rows * g;
+  const int64_t lanes = ((a.n_rows + 1) / 2) * g;
   int64_t grid = (lanes + kBlock - 1) / kBlock;
   if (grid > 8192) grid = 8192;
   if (grid < 1) grid = 1;
@@ -60,7 +89,7 @@ hipError_t launch_t(const CsrArgs& a, int g, hipStream_t st) {
 int csr_group_size(int64_t n_rows, int64_t nnz) {
   const double mean = n_rows > 0 ? double(nnz) / double(n_rows) : 0.0;
   int g = 4;
-  while (g < 64 && g < mean) g *= 2;
+  while (g < 64 && g * kEntries < mean) g *= 2;
   return g;
 }
 

@@ -227,6 +227,37 @@ struct CsrArgs {
   void* y;                  // n_rows
 };
 
+// Device-resident state of one conjugate-gradient solve (library workspace).
+struct CgState {
+  double rho;          // rho_k = <r_k, r_k>        (written by cg_spmv)
+  double bnorm;        // ||b||                     (written once at start)
+  int64_t k;           // iterations completed      (written by cg_p)
+  int32_t done;        // stop test fired           (written by cg_spmv)
+  int32_t breakdown;   // <p, A p> <= 0 was met     (written by cg_xr)
+};
+
+struct CgArgs {
+  int64_t n, nnz;
+  const int32_t* row_ptr;   // n + 1
+  const int32_t* col_idx;   // nnz
+  const double* vals;       // nnz
+  const double* b;          // n
+  double* x;                // n: x0 in, iterate out
+  double* r;                // n, workspace
+  double* p;                // n, workspace
+  double* q;                // n, workspace
+  double* part_pq;          // grid, workspace
+  double* part_rr;          // grid, workspace
+  double* part_bb;          // grid, workspace
+  CgState* st;              // workspace
+  double* res;              // nullable, max_iter + 1
+  double* alpha;            // nullable, max_iter
+  double* beta;             // nullable, max_iter
+  double tol;
+  int64_t max_iter;
+  int32_t grid;             // workgroups of every loop kernel
+};
+
 // ---------------------------------------------------------------------------
 // launchers (return hipError_t of the launch)
 // ---------------------------------------------------------------------------
@@ -255,6 +286,9 @@ bool gemm_supported(const GemmArgs& a, int compute);
 hipError_t launch_filter2d(const Filter2DProblem& p, hipStream_t st);
 hipError_t launch_csr(const CsrArgs& a, int dtype, hipStream_t st);
 int csr_group_size(int64_t n_rows, int64_t nnz);
+// init: r = b - A x, p = r, fresh state; then `iters` loop iterations
+hipError_t launch_cg(const CgArgs& a, bool init, int iters, hipStream_t st);
+int cg_grid(int64_t n, int64_t nnz);
 // d_tiles: n_tiles entries of two uint32 (problem index, tile within the problem)
 hipError_t launch_filter2d_persistent(const Filter2DProblem* d_probs, const void* d_tiles, int64_t n_tiles,
                                       int grid, hipStream_t st);

@@ -350,3 +350,30 @@ def random_csr(rng: np.random.Generator, n_rows: int, n_cols: int, max_per_row: 
     col_idx = rng.integers(0, n_cols, int(row_ptr[-1])).astype(np.int32)
     vals = rng.uniform(-1.0, 1.0, int(row_ptr[-1]))
     return Csr(n_rows, row_ptr, col_idx, vals)
+
+
+def dense_csr(M: np.ndarray) -> Csr:
+    """CSR form of a dense matrix (its nonzero entries, row-major order)."""
+    rows, cols = np.nonzero(M)
+    counts = np.bincount(rows, minlength=M.shape[0])
+    row_ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    return Csr(M.shape[0], row_ptr, cols.astype(np.int32), M[rows, cols].astype(np.float64))
+
+
+def spd_csr(rng: np.random.Generator, n: int, cond: float = 50.0, density: float = 1.0) -> Csr:
+    """Random symmetric positive definite matrix: Q diag(eigenvalues) Q^T with
+    eigenvalues log-spaced in [1, cond]; with density < 1, a sparse SPD matrix
+    instead (random symmetric pattern, diagonal dominance margin from cond)."""
+    if density >= 1.0:
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        return dense_csr((Q * np.geomspace(1.0, cond, n)) @ Q.T)
+    mask = np.triu(rng.random((n, n)) < density, 1)
+    off = np.where(mask, -rng.uniform(0.5, 1.5, (n, n)), 0.0)
+    off = off + off.T
+    M = off + np.diag(np.abs(off).sum(1) + np.abs(off).sum(1).max() / cond + 1e-3)
+    return dense_csr(M)
+
+
+def cg_rhs(n: int, seed: int = 6) -> np.ndarray:
+    """Right-hand side for the conjugate-gradient workload: U[-1, 1)."""
+    return rng_for(seed).uniform(-1.0, 1.0, n)

@@ -138,3 +138,26 @@ def test_empty_repetition_space_is_a_no_op_plan():
 def test_missing_library_fails_loudly(tmp_path):
     with pytest.raises(RuntimeError, match="not built"):
         _abi.load(str(tmp_path / "nope.so"))
+
+
+def test_cg_solve_host_checks():
+    # argument errors are reported before any device work
+    lib = _abi.load()
+    info = _abi.CgInfo()
+
+    def call(n=4, nnz=4, tol=1e-10, max_iter=4, check_every=1, info_p=ctypes.byref(info)):
+        return lib.rsm_cg_solve(n, nnz, None, None, None, None, None, tol, max_iter, check_every, 0,
+                                None, None, None, info_p, None)
+
+    name = lambda s: lib.rsm_status_string(s).decode()
+    assert name(call(info_p=None)) == "RSM_E_INVALID"
+    assert name(call(n=-1)) == "RSM_E_SHAPE"
+    assert name(call(nnz=1 << 31)) == "RSM_E_UNSUPPORTED"
+    assert name(call(tol=-1.0)) == "RSM_E_INVALID"
+    assert name(call(tol=float("nan"))) == "RSM_E_INVALID"
+    assert name(call(max_iter=-1)) == "RSM_E_INVALID"
+    assert name(call(check_every=0)) == "RSM_E_INVALID"
+    assert name(call()) == "RSM_E_INVALID"          # NULL device pointers
+    # an empty system is solved with no work
+    assert name(call(n=0, nnz=0)) == "RSM_OK"
+    assert info.iterations == 0 and info.converged == 1 and info.breakdown == 0
