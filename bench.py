@@ -124,18 +124,16 @@ def main():
     adj_bytes = x_bytes + out_bytes + x_bytes        # read x, read dL/dout, write dL/dx
 
     def step(k, ev=None):
+        # ev: events that the library records immediately around the fused
+        # forward kernel (ev[0], ev[1]) and the fused adjoint kernel (ev[2], ev[3])
         x = xs[k & 1]
         if ev is not None:
-            ev[0].record()
+            rsm.time_next_kernel(ev[0], ev[1])
         chain.forward(x, out)
-        if ev is not None:
-            ev[1].record()
         torch.mul(w2, out, out=gy)
         if ev is not None:
-            ev[2].record()
+            rsm.time_next_kernel(ev[2], ev[3])
         chain.adjoint(x, gy, gxs[k & 1], [gch, gcv])
-        if ev is not None:
-            ev[3].record()
 
     log("warmup %d steps" % args.warmup)
     for k in range(args.warmup):
@@ -178,9 +176,10 @@ def main():
                    "hbm_bytes_per_step": fwd_bytes + adj_bytes},
         "roofline": {"bound": "hbm", "achieved": adj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": adj_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "fir_chain_adjoint_kernel", "bytes_per_launch": adj_bytes,
+                     "kernel": "fir_chain_adjoint_pair_kernel<8>",
+                     "bytes_per_launch": adj_bytes,
                      "avg_us": adj_us},
-        "extra": {"forward_fused": {"kernel": "fir_chain_kernel", "avg_us": fwd_us,
+        "extra": {"forward_fused": {"kernel": "fir_chain_pair_kernel<8>", "avg_us": fwd_us,
                                     "bytes": fwd_bytes, "gbs": fwd_gbs,
                                     "frac": fwd_gbs / HBM_PEAK_GBS},
                   "adjoint_fused": {"avg_us": adj_us, "bytes": adj_bytes, "gbs": adj_gbs,
@@ -319,6 +318,33 @@ def extras(args, ts, xs, stages, ch, cv, w2, chain):
     ex["spmv_f64_stencil27_51cubed"] = {"avg_us": us, "bytes": b, "gbs": b / us / 1e3,
                                         "frac": b / us / 1e3 / HBM_PEAK_GBS, "n": A.n, "nnz": A.nnz}
     log("spmv %.1f us %.0f GB/s" % (us, b / us / 1e3))
+
+    # the case study's conjugate-gradient loop at its size, FP64, tol 1e-10;
+    # GFLOP/s by the flop model of the paper's Table 1: iterations x (2 NNZ + 10 N)
+    bv = torch.from_numpy(W.cg_rhs(A.n)).to(dev)
+    xc = torch.zeros(A.n, dtype=torch.float64, device=dev)
+
+    def solve():
+        xc.zero_()
+        return rsm.cg_solve(rp, ci, va, bv, xc, tol=1e-10, check_every=32)
+
+    info = solve()
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        info = solve()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    flops = info["iterations"] * (2 * A.nnz + 10 * A.n)
+    ex["cg_f64_stencil27_51cubed"] = {
+        "iterations": info["iterations"], "converged": info["converged"], "ms": ms,
+        "us_per_iteration": ms * 1e3 / max(info["iterations"], 1), "gflops": flops / ms / 1e6,
+        "tol": 1e-10, "n": A.n, "nnz": A.nnz,
+        "paper_1gpu_context": {"gflops": 1.45, "iterations": 116, "seconds": 0.659,
+                               "hardware": "Tesla T10, FEM matrix (Table 1)"}}
+    log("cg %d iterations %.2f ms (%.1f us/iter) %.1f GFLOP/s" %
+        (info["iterations"], ms, ms * 1e3 / max(info["iterations"], 1), flops / ms / 1e6))
     return ex
 
 

@@ -217,6 +217,43 @@ rsm_status rsm_run_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
                        int32_t dtype, uint32_t flags, void* hip_stream);
 
 /*
+ * rsm_cg_solve -- the conjugate-gradient loop of the paper's case study
+ * (Sec. 7) on one device, FP64: every matrix-vector product is the
+ * indirect-tiler task of rsm_run_csr, the inner products and vector updates
+ * are element-wise repetitions, and the loop runs while the continue
+ * condition ||r_k|| > tol ||b|| holds (the relative-residual rule of the
+ * paper's Table 1, tol = 1e-10 there) and k < max_iter.  Recurrences
+ * (Hestenes-Stiefel): r0 = b - A x0, p0 = r0; alpha = <r,r> / <p,Ap>;
+ * x += alpha p; r -= alpha A p; beta = <r',r'> / <r,r>; p = r' + beta p.
+ * The scalars stay on the device; the host reads a 32-byte state block after
+ * every check_every iterations (so the call is BLOCKING and synchronises the
+ * stream that often; iterations launched past the stop test do nothing).
+ * A: n x n CSR (d_row_ptr n + 1 int32, d_col_idx nnz int32, d_vals nnz
+ * FP64), symmetric positive definite.  d_b: n FP64.  d_x: n FP64, x0 on
+ * entry, the last iterate on return.  d_res (max_iter + 1), d_alpha and
+ * d_beta (max_iter each) are optional FP64 device buffers (NULL = skip) that
+ * receive ||r_k|| and the step scalars.  info (host) receives the iteration
+ * count, the final recursive residual norm, ||b||, converged and breakdown
+ * (<p, A p> <= 0 met: A not positive definite; x then holds the last
+ * iterate).  Inner products are reduced in a fixed order: repeated calls
+ * give identical bits.  Uses the library workspace (3 n + 3 * 2048 doubles);
+ * calls on one device must not overlap.  RSM_CHECK_INDICES validates the
+ * index arrays on the host first.  Limits: n, nnz < 2^31.
+ */
+typedef struct {
+  int64_t iterations;
+  double residual_norm;
+  double rhs_norm;
+  int32_t converged;
+  int32_t breakdown;
+} rsm_cg_info;
+
+rsm_status rsm_cg_solve(int64_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col_idx,
+                        const double* d_vals, const double* d_b, double* d_x, double tol,
+                        int64_t max_iter, int32_t check_every, uint32_t flags, double* d_res,
+                        double* d_alpha, double* d_beta, rsm_cg_info* info, void* hip_stream);
+
+/*
  * Batched execution of many independent single-input tasks in one launch.
  * rsm_batch_create copies the descriptions, chooses a tile shape per problem
  * (timing candidates on the given stream unless the tuning cache at
@@ -265,6 +302,18 @@ rsm_status rsm_batch_destroy(rsm_batch b); /* waits for the device, then frees *
 
 /* Tile shape chosen for problem k of a batch (rows, cols of outputs per tile). */
 rsm_status rsm_batch_tile(rsm_batch b, int32_t k, int32_t* tile_rows, int32_t* tile_cols);
+
+/*
+ * rsm_time_next_kernel -- measurement hook.  The next rsm_run_chain or
+ * rsm_run_chain_adjoint call made on this host thread records
+ * hip_event_start on its stream immediately before launching the fused
+ * chain kernel and hip_event_stop immediately after it (no other launch of
+ * the call lies between them), then forgets both; calls that take the
+ * unfused path forget them without recording.  The events are hipEvent_t
+ * handles created and owned by the caller (either may be NULL).  Passing
+ * NULL, NULL disarms the hook.  Always returns RSM_OK.
+ */
+rsm_status rsm_time_next_kernel(void* hip_event_start, void* hip_event_stop);
 
 const char* rsm_status_string(rsm_status s);
 const char* rsm_last_error(void); /* thread-local detail of the last failing call */

@@ -66,12 +66,18 @@ class BatchInfo(ctypes.Structure):
                 ("tuned_classes", ctypes.c_int64), ("cached_classes", ctypes.c_int64)]
 
 
+class CgInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("residual_norm", ctypes.c_double),
+                ("rhs_norm", ctypes.c_double), ("converged", ctypes.c_int32),
+                ("breakdown", ctypes.c_int32)]
+
+
 EXPORTS = [
     "rsm_validate", "rsm_plan", "rsm_indices", "rsm_run", "rsm_run_chain", "rsm_run_adjoint",
     "rsm_run_chain_adjoint", "rsm_batch_create", "rsm_batch_run", "rsm_batch_run_plain",
     "rsm_batch_query",
     "rsm_batch_tile", "rsm_batch_destroy", "rsm_status_string", "rsm_last_error",
-    "rsm_abi_version", "rsm_run_csr",
+    "rsm_abi_version", "rsm_run_csr", "rsm_cg_solve", "rsm_time_next_kernel",
 ]
 
 _lib = None
@@ -100,6 +106,8 @@ def load(path: str = LIB_PATH):
     lib.rsm_run_chain_adjoint.argtypes = [P(Stage), i32, vp, P(vp), vp, vp, P(vp), u32, vp]
     lib.rsm_run_csr.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp, vp,
                                 i32, u32, vp]
+    lib.rsm_cg_solve.argtypes = [ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp, vp, ctypes.c_double,
+                                 ctypes.c_int64, i32, u32, vp, vp, vp, P(CgInfo), vp]
     lib.rsm_batch_create.argtypes = [P(Problem), i32, ctypes.c_char_p, u32, vp, P(vp)]
     lib.rsm_batch_run.argtypes = [vp, vp]
     lib.rsm_batch_run_plain.argtypes = [vp, vp]
@@ -108,8 +116,10 @@ def load(path: str = LIB_PATH):
     lib.rsm_batch_destroy.argtypes = [vp]
     for name in ("rsm_validate", "rsm_plan", "rsm_indices", "rsm_run", "rsm_run_chain",
                  "rsm_run_adjoint", "rsm_run_chain_adjoint", "rsm_batch_create", "rsm_batch_run",
-                 "rsm_run_csr", "rsm_batch_run_plain", "rsm_batch_query", "rsm_batch_tile", "rsm_batch_destroy"):
+                 "rsm_run_csr", "rsm_cg_solve", "rsm_batch_run_plain", "rsm_batch_query", "rsm_batch_tile", "rsm_batch_destroy"):
         getattr(lib, name).restype = st
+    lib.rsm_time_next_kernel.argtypes = [vp, vp]
+    lib.rsm_time_next_kernel.restype = st
     lib.rsm_status_string.argtypes = [st]
     lib.rsm_status_string.restype = ctypes.c_char_p
     lib.rsm_last_error.argtypes = []

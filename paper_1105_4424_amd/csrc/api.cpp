@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -22,6 +23,30 @@ namespace rsm {
 // errors
 // ---------------------------------------------------------------------------
 static thread_local std::string g_last_error;
+
+// Measurement hook (rsm_time_next_kernel): events recorded around the main
+// kernel of the next chain call on this thread, then forgotten.
+struct KernelProbe {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+static thread_local KernelProbe g_probe;
+
+// Takes (and disarms) the probe; every chain call does this on entry.
+static KernelProbe take_probe() {
+  KernelProbe p = g_probe;
+  g_probe = KernelProbe{};
+  return p;
+}
+
+// Launches `launch` between the probe's events (either may be absent).
+template <typename F>
+static hipError_t probed(const KernelProbe& p, hipStream_t st, F launch) {
+  hipError_t e;
+  if (p.start && (e = hipEventRecord(p.start, st)) != hipSuccess) return e;
+  if ((e = launch()) != hipSuccess) return e;
+  if (p.stop && (e = hipEventRecord(p.stop, st)) != hipSuccess) return e;
+  return hipSuccess;
+}
 
 rsm_status fail(rsm_status s, const std::string& msg) {
   g_last_error = msg;
@@ -811,6 +836,32 @@ bool plan_filter2d(const rsm_space& rep, const rsm_tiler& in, const rsm_tiler& o
   return true;
 }
 
+// CSR arguments shared by the sparse entry points.
+rsm_status check_csr_sizes(int64_t n_rows, int64_t n_cols, int64_t nnz) {
+  if (n_rows < 0 || n_cols < 0 || nnz < 0) return fail(RSM_E_SHAPE, "negative CSR size");
+  const int64_t lim = int64_t(1) << 31;
+  if (n_rows >= lim || n_cols >= lim || nnz >= lim) return fail(RSM_E_UNSUPPORTED, "CSR sizes limited to 2^31");
+  return RSM_OK;
+}
+
+// Copies the index arrays to the host and checks them (blocking).
+rsm_status check_csr_indices(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t* d_row_ptr,
+                             const int32_t* d_col_idx, hipStream_t st) {
+  std::vector<int32_t> rp(static_cast<size_t>(n_rows + 1)), ci(static_cast<size_t>(nnz));
+  hipError_t e;
+  if ((e = hipMemcpyAsync(rp.data(), d_row_ptr, rp.size() * 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (nnz && (e = hipMemcpyAsync(ci.data(), d_col_idx, ci.size() * 4, hipMemcpyDeviceToHost, st)) != hipSuccess) ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
+    return hip_fail(e, "index copy for checking");
+  if (rp[0] != 0 || rp[size_t(n_rows)] != nnz) return fail(RSM_E_INVALID, "row_ptr must start at 0 and end at nnz");
+  for (int64_t r = 0; r < n_rows; ++r)
+    if (rp[size_t(r + 1)] < rp[size_t(r)]) return fail(RSM_E_INVALID, "row_ptr decreases at row " + std::to_string(r));
+  for (int64_t k = 0; k < nnz; ++k)
+    if (ci[size_t(k)] < 0 || ci[size_t(k)] >= n_cols)
+      return fail(RSM_E_INVALID, "column index out of range at entry " + std::to_string(k));
+  return RSM_OK;
+}
+
 }  // namespace rsm
 
 // ===========================================================================
@@ -829,6 +880,12 @@ using namespace rsm;
   }
 
 extern "C" {
+
+rsm_status rsm_time_next_kernel(void* hip_event_start, void* hip_event_stop) {
+  g_probe.start = static_cast<hipEvent_t>(hip_event_start);
+  g_probe.stop = static_cast<hipEvent_t>(hip_event_stop);
+  return RSM_OK;
+}
 
 int32_t rsm_abi_version(void) { return RSM_ABI_VERSION; }
 
@@ -905,6 +962,7 @@ rsm_status rsm_run(const rsm_space* rep, const rsm_tiler* in, const void* const*
 
 rsm_status rsm_run_chain(const rsm_stage* stages, int32_t n_stages, const void* d_in,
                          void* const* d_mid, void* d_out, uint32_t flags, void* hip_stream) {
+  const KernelProbe probe = take_probe();
   RSM_GUARD_BEGIN
   std::vector<Checked> cs;
   rsm_status s = check_chain(stages, n_stages, &cs);
@@ -927,7 +985,7 @@ rsm_status rsm_run_chain(const rsm_stage* stages, int32_t n_stages, const void* 
     a.y = static_cast<float*>(d_out);
     a.ch = static_cast<const float*>(stages[0].task.coeffs);
     a.cv = static_cast<const float*>(stages[1].task.coeffs);
-    hipError_t e = launch_fir_chain(a, vec4, st);
+    hipError_t e = probed(probe, st, [&] { return launch_fir_chain(a, vec4, st); });
     if (e != hipSuccess) return hip_fail(e, "fused chain launch");
     return RSM_OK;
   }
@@ -970,6 +1028,7 @@ rsm_status rsm_run_adjoint(const rsm_space* rep, const rsm_tiler* in, const void
 rsm_status rsm_run_chain_adjoint(const rsm_stage* stages, int32_t n_stages, const void* d_in,
                                  const void* const* d_mid, const void* d_gy, void* d_gx,
                                  void* const* d_gc, uint32_t flags, void* hip_stream) {
+  const KernelProbe probe = take_probe();
   RSM_GUARD_BEGIN
   std::vector<Checked> cs;
   rsm_status s = check_chain(stages, n_stages, &cs);
@@ -1019,7 +1078,8 @@ rsm_status rsm_run_chain_adjoint(const rsm_stage* stages, int32_t n_stages, cons
       if (s) return s;
       if (!reduce_in_kernel()) a.counter = nullptr;
     }
-    if ((e = launch_fir_chain_adjoint(a, vec4, st)) != hipSuccess) return hip_fail(e, "fused chain adjoint");
+    if ((e = probed(probe, st, [&] { return launch_fir_chain_adjoint(a, vec4, st); })) != hipSuccess)
+      return hip_fail(e, "fused chain adjoint");
     if (a.partial && !a.counter) {
       if (gch && (e = launch_reduce_partials(a.partial, grid, h.taps, nc, gch, accumulate, st)) != hipSuccess)
         return hip_fail(e, "weight-gradient reduction");
@@ -1083,30 +1143,90 @@ rsm_status rsm_run_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
                        const int32_t* d_col_idx, const void* d_vals, const void* d_x, void* d_y,
                        int32_t dtype, uint32_t flags, void* hip_stream) {
   RSM_GUARD_BEGIN
-  if (n_rows < 0 || n_cols < 0 || nnz < 0) return fail(RSM_E_SHAPE, "negative CSR size");
-  const int64_t lim = int64_t(1) << 31;
-  if (n_rows >= lim || n_cols >= lim || nnz >= lim) return fail(RSM_E_UNSUPPORTED, "CSR sizes limited to 2^31");
+  rsm_status s = check_csr_sizes(n_rows, n_cols, nnz);
+  if (s != RSM_OK) return s;
   if (dtype != RSM_F64 && dtype != RSM_F32) return fail(RSM_E_INVALID, "CSR dtype must be F64 or F32");
   if (n_rows == 0) return RSM_OK;
   if (!d_row_ptr || !d_y || (nnz > 0 && (!d_col_idx || !d_vals)) || (n_cols > 0 && !d_x))
     return fail(RSM_E_INVALID, "NULL device pointer");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  hipError_t e;
-  if (flags & RSM_CHECK_INDICES) {
-    std::vector<int32_t> rp(static_cast<size_t>(n_rows + 1)), ci(static_cast<size_t>(nnz));
-    if ((e = hipMemcpyAsync(rp.data(), d_row_ptr, rp.size() * 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-        (nnz && (e = hipMemcpyAsync(ci.data(), d_col_idx, ci.size() * 4, hipMemcpyDeviceToHost, st)) != hipSuccess) ||
-        (e = hipStreamSynchronize(st)) != hipSuccess)
-      return hip_fail(e, "index copy for checking");
-    if (rp[0] != 0 || rp[size_t(n_rows)] != nnz) return fail(RSM_E_INVALID, "row_ptr must start at 0 and end at nnz");
-    for (int64_t r = 0; r < n_rows; ++r)
-      if (rp[size_t(r + 1)] < rp[size_t(r)]) return fail(RSM_E_INVALID, "row_ptr decreases at row " + std::to_string(r));
-    for (int64_t k = 0; k < nnz; ++k)
-      if (ci[size_t(k)] < 0 || ci[size_t(k)] >= n_cols)
-        return fail(RSM_E_INVALID, "column index out of range at entry " + std::to_string(k));
-  }
+  if ((flags & RSM_CHECK_INDICES) &&
+      (s = check_csr_indices(n_rows, n_cols, nnz, d_row_ptr, d_col_idx, st)) != RSM_OK)
+    return s;
   CsrArgs a{n_rows, n_cols, nnz, d_row_ptr, d_col_idx, d_vals, d_x, d_y};
+  hipError_t e;
   if ((e = launch_csr(a, dtype, st)) != hipSuccess) return hip_fail(e, "csr launch");
+  return RSM_OK;
+  RSM_GUARD_END
+}
+
+rsm_status rsm_cg_solve(int64_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col_idx,
+                        const double* d_vals, const double* d_b, double* d_x, double tol, int64_t max_iter,
+                        int32_t check_every, uint32_t flags, double* d_res, double* d_alpha, double* d_beta,
+                        rsm_cg_info* info, void* hip_stream) {
+  RSM_GUARD_BEGIN
+  if (!info) return fail(RSM_E_INVALID, "NULL info");
+  *info = rsm_cg_info{};
+  rsm_status s = check_csr_sizes(n, n, nnz);
+  if (s != RSM_OK) return s;
+  if (!(tol >= 0.0)) return fail(RSM_E_INVALID, "tol must be >= 0");
+  if (max_iter < 0) return fail(RSM_E_INVALID, "max_iter must be >= 0");
+  if (check_every < 1) return fail(RSM_E_INVALID, "check_every must be >= 1");
+  if (n == 0) {
+    info->converged = 1;
+    return RSM_OK;
+  }
+  if (!d_row_ptr || !d_b || !d_x || (nnz > 0 && (!d_col_idx || !d_vals)))
+    return fail(RSM_E_INVALID, "NULL device pointer");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if ((flags & RSM_CHECK_INDICES) && (s = check_csr_indices(n, n, nnz, d_row_ptr, d_col_idx, st)) != RSM_OK)
+    return s;
+  const int grid = cg_grid(n, nnz);
+  const size_t vec = (size_t(n) * sizeof(double) + 255) & ~size_t(255);
+  const size_t part = (size_t(grid) * sizeof(double) + 255) & ~size_t(255);
+  char* ws = static_cast<char*>(workspace(3 * vec + 3 * part + 256, st, &s, nullptr));
+  if (s != RSM_OK) return s;
+  CgArgs a{};
+  a.n = n;
+  a.nnz = nnz;
+  a.row_ptr = d_row_ptr;
+  a.col_idx = d_col_idx;
+  a.vals = d_vals;
+  a.b = d_b;
+  a.x = d_x;
+  a.r = reinterpret_cast<double*>(ws);
+  a.p = reinterpret_cast<double*>(ws + vec);
+  a.q = reinterpret_cast<double*>(ws + 2 * vec);
+  a.part_pq = reinterpret_cast<double*>(ws + 3 * vec);
+  a.part_rr = reinterpret_cast<double*>(ws + 3 * vec + part);
+  a.part_bb = reinterpret_cast<double*>(ws + 3 * vec + 2 * part);
+  a.st = reinterpret_cast<CgState*>(ws + 3 * vec + 3 * part);
+  a.res = d_res;
+  a.alpha = d_alpha;
+  a.beta = d_beta;
+  a.tol = tol;
+  a.max_iter = max_iter;
+  a.grid = grid;
+  hipError_t e = launch_cg(a, true, 0, st);
+  if (e != hipSuccess) return hip_fail(e, "cg start launch");
+  // Launch batches of check_every iterations and read the state after each;
+  // the stop test fires by iteration max_iter at the latest, so the loop
+  // ends after at most max_iter / check_every + 2 batches.
+  CgState h{};
+  for (int64_t launched = 0;; launched += check_every) {
+    if ((e = launch_cg(a, false, check_every, st)) != hipSuccess) return hip_fail(e, "cg loop launch");
+    if ((e = hipMemcpyAsync(&h, a.st, sizeof(h), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+      return hip_fail(e, "cg state read");
+    if (h.done || h.breakdown) break;
+    if (launched > max_iter + 2 * int64_t(check_every))
+      return fail(RSM_E_HIP, "cg loop did not reach its stop test");
+  }
+  info->iterations = h.k;
+  info->residual_norm = std::sqrt(h.rho);
+  info->rhs_norm = h.bnorm;
+  info->breakdown = h.breakdown;
+  info->converged = !h.breakdown && !(std::sqrt(h.rho) > tol * h.bnorm);
   return RSM_OK;
   RSM_GUARD_END
 }

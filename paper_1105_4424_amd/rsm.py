@@ -237,6 +237,55 @@ def run_csr(row_ptr: torch.Tensor, col_idx: torch.Tensor, vals: torch.Tensor, x:
     return y
 
 
+def time_next_kernel(start: "torch.cuda.Event", stop: "torch.cuda.Event") -> None:
+    """Arm the measurement hook: the next chain call on this thread records
+    `start` / `stop` (timing events) immediately around its fused kernel."""
+    lib = _abi.load()
+    for ev in (start, stop):
+        if not ev.cuda_event:   # torch creates the event on its first record
+            ev.record()
+    _check(lib.rsm_time_next_kernel(ctypes.c_void_p(start.cuda_event), ctypes.c_void_p(stop.cuda_event)))
+
+
+def cg_solve(row_ptr: torch.Tensor, col_idx: torch.Tensor, vals: torch.Tensor, b: torch.Tensor,
+             x: torch.Tensor, tol: float = 1e-10, max_iter: Optional[int] = None, check_every: int = 16,
+             history: bool = False, check_indices: bool = False, stream=None) -> dict:
+    """Conjugate gradient on an SPD CSR matrix, FP64, in place on x (x0 in,
+    last iterate out).  Blocking: the host reads the device state every
+    check_every iterations.  Returns the iteration count, final residual
+    norm, ||b||, converged / breakdown flags and, with history=True, device
+    tensors res (||r_k||), alpha and beta."""
+    lib = _abi.load()
+    if row_ptr.dtype != torch.int32 or col_idx.dtype != torch.int32:
+        raise TypeError("row_ptr and col_idx must be int32")
+    if not (vals.dtype == b.dtype == x.dtype == torch.float64):
+        raise TypeError("vals, b and x must be float64")
+    n = b.numel()
+    if x.numel() != n or row_ptr.numel() != n + 1:
+        raise ValueError("shape mismatch: b, x need n entries and row_ptr n + 1")
+    if max_iter is None:
+        max_iter = n
+    res = alpha = beta = None
+    if history:
+        res = torch.zeros(max_iter + 1, dtype=torch.float64, device=b.device)
+        alpha = torch.zeros(max(max_iter, 1), dtype=torch.float64, device=b.device)
+        beta = torch.zeros(max(max_iter, 1), dtype=torch.float64, device=b.device)
+    info = _abi.CgInfo()
+    _check(lib.rsm_cg_solve(n, col_idx.numel(), _ptr(row_ptr), _ptr(col_idx), _ptr(vals), _ptr(b),
+                            _ptr(x), float(tol), int(max_iter), int(check_every),
+                            _abi.CHECK_INDICES if check_indices else 0,
+                            _ptr(res) if res is not None else None,
+                            _ptr(alpha) if alpha is not None else None,
+                            _ptr(beta) if beta is not None else None, ctypes.byref(info), _stream(stream)))
+    out = {"iterations": int(info.iterations), "residual_norm": float(info.residual_norm),
+           "rhs_norm": float(info.rhs_norm), "converged": bool(info.converged),
+           "breakdown": bool(info.breakdown)}
+    if history:
+        k = out["iterations"]
+        out["res"], out["alpha"], out["beta"] = res[:k + 1], alpha[:k], beta[:k]
+    return out
+
+
 # ---------------------------------------------------------------------------
 # autograd
 # ---------------------------------------------------------------------------
