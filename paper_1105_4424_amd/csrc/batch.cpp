@@ -33,7 +33,7 @@
 
 namespace {
 
-constexpr const char* kKernelRevision = "filter2d-r3";
+constexpr const char* kKernelRevision = "filter2d-r7";
 constexpr double kHbmBytesPerS = 8.0e12;
 constexpr double kFp32FmaPerS = 39.3e12;   // unpacked FP32 FMA issue rate of the chip
 
@@ -126,6 +126,7 @@ struct rsm_batch_s {
   uint32_t* d_tiles = nullptr;                 // [n_tiles][2]: problem (table row), tile
   int64_t n_tiles = 0;
   int grid = 0;
+  int buf_floats = 4;   // LDS of the persistent kernel (floats)
   int device = 0;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -146,43 +147,82 @@ using namespace rsm;
 namespace {
 
 // Times tile class tc over the given problems (plain launches), best of 3, in ms.
+// Times tile class tc for one class of problems the way the batch runs them:
+// a table of just these problems' tiles, walked by the persistent kernel
+// (three back-to-back launches after a warm-up, so the figure is GPU time).
 rsm_status time_class(rsm_batch_s* b, const std::vector<int>& idx, int tc, hipStream_t st, float* ms) {
-  hipEvent_t e0, e1;
+  std::vector<Filter2DProblem> probs;
+  std::vector<uint32_t> tiles;
+  for (int k : idx) {
+    Filter2DProblem p = b->fp[size_t(k)];
+    filter2d_set_tiles(&p, tc);
+    for (int64_t t = 0; t < p.n_tiles; ++t) {
+      tiles.push_back(uint32_t(probs.size()));
+      tiles.push_back(uint32_t(t));
+    }
+    probs.push_back(p);
+  }
+  const int64_t n_tiles = int64_t(tiles.size() / 2);
+  *ms = 0.0f;
+  if (n_tiles == 0) return RSM_OK;
+  void *d_probs = nullptr, *d_tiles = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e;
-  if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
-  if ((e = hipEventCreate(&e1)) != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    return hip_fail(e, "hipEventCreate");
-  }
-  float best = 1e30f;
   rsm_status s = RSM_OK;
-  for (int rep = 0; rep < 4 && s == RSM_OK; ++rep) {  // first pass warms up
-    (void)hipEventRecord(e0, st);
-    for (int k : idx) {
-      Filter2DProblem p = b->fp[size_t(k)];
-      filter2d_set_tiles(&p, tc);
-      if ((e = launch_filter2d(p, st)) != hipSuccess) {
-        s = hip_fail(e, "autotuner launch");
-        break;
-      }
+  if ((e = hipMalloc(&d_probs, sizeof(Filter2DProblem) * probs.size())) != hipSuccess ||
+      (e = hipMalloc(&d_tiles, sizeof(uint32_t) * tiles.size())) != hipSuccess) {
+    s = fail(RSM_E_NOMEM, std::string("autotuner tables: ") + hipGetErrorString(e));
+  } else if ((e = hipMemcpy(d_probs, probs.data(), sizeof(Filter2DProblem) * probs.size(),
+                            hipMemcpyHostToDevice)) != hipSuccess ||
+             (e = hipMemcpy(d_tiles, tiles.data(), sizeof(uint32_t) * tiles.size(), hipMemcpyHostToDevice)) !=
+                 hipSuccess ||
+             (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+    s = hip_fail(e, "autotuner setup");
+  } else {
+    const int bf = filter2d_buf_floats(probs[0].k, probs[0].s, tc);
+    const int grid = int(std::min<int64_t>(filter2d_persistent_grid(bf), n_tiles));
+    auto launch = [&] {
+      return launch_filter2d_persistent(static_cast<const Filter2DProblem*>(d_probs), d_tiles, n_tiles, grid, bf,
+                                        st);
+    };
+    if ((e = launch()) != hipSuccess || (e = hipEventRecord(e0, st)) != hipSuccess ||
+        (e = launch()) != hipSuccess || (e = launch()) != hipSuccess || (e = launch()) != hipSuccess ||
+        (e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) {
+      s = hip_fail(e, "autotuner launch");
+    } else {
+      float t = 0.0f;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      *ms = t / 3.0f;
     }
-    (void)hipEventRecord(e1, st);
-    if ((e = hipEventSynchronize(e1)) != hipSuccess) {
-      s = hip_fail(e, "autotuner timing");
-      break;
-    }
-    float t = 0.0f;
-    (void)hipEventElapsedTime(&t, e0, e1);
-    if (rep > 0) best = std::min(best, t);
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  *ms = best;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  // the launches above must be done before the tables go away
+  (void)hipStreamSynchronize(st);
+  if (d_probs) (void)hipFree(d_probs);
+  if (d_tiles) (void)hipFree(d_tiles);
   return s;
 }
 
+// Tile order: problems grouped by code path (k, s, tile class), groups in
+// decreasing order of their total estimated cost, problems inside a group in
+// decreasing cost.  The persistent kernel inlines one code path per group
+// and all of them together exceed the instruction cache that two CUs share;
+// since the workgroups in flight at any moment work on a window of
+// consecutive tiles, grouping keeps that window on one or two code paths.
 rsm_status build_queue(rsm_batch_s* b) {
+  auto path = [&](int i) {
+    const Filter2DProblem& f = b->fp[size_t(i)];
+    return (int64_t(f.k) << 16) | (int64_t(f.s) << 8) | int64_t(f.tc);
+  };
+  std::map<int64_t, double> group_cost;
+  for (int i : b->persistent) group_cost[path(i)] += est_cost(b->fp[size_t(i)]);
   std::stable_sort(b->persistent.begin(), b->persistent.end(), [&](int x, int y) {
+    const int64_t px = path(x), py = path(y);
+    if (px != py) {
+      const double cx = group_cost[px], cy = group_cost[py];
+      return cx != cy ? cx > cy : px < py;
+    }
     return est_cost(b->fp[size_t(x)]) > est_cost(b->fp[size_t(y)]);
   });
   const size_t n = b->persistent.size();
@@ -210,7 +250,9 @@ rsm_status build_queue(rsm_batch_s* b) {
       (e = hipMemcpy(b->d_tiles, tiles.data(), sizeof(uint32_t) * tiles.size(), hipMemcpyHostToDevice)) !=
           hipSuccess)
     return hip_fail(e, "batch table upload");
-  const int g = filter2d_persistent_grid();
+  b->buf_floats = 4;
+  for (const Filter2DProblem& f : table) b->buf_floats = std::max(b->buf_floats, filter2d_buf_floats(f.k, f.s, f.tc));
+  const int g = filter2d_persistent_grid(b->buf_floats);
   b->grid = int(std::max<int64_t>(1, std::min<int64_t>(g, b->n_tiles)));
   if ((e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess)
     return hip_fail(e, "hipStreamCreateWithFlags");
@@ -322,7 +364,7 @@ rsm_status rsm_batch_run(rsm_batch b, void* hip_stream) {
     if (!b->exec) {
       if ((e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
         return hip_fail(e, "hipStreamBeginCapture");
-      e = launch_filter2d_persistent(b->d_probs, b->d_tiles, b->n_tiles, b->grid, b->cap_stream);
+      e = launch_filter2d_persistent(b->d_probs, b->d_tiles, b->n_tiles, b->grid, b->buf_floats, b->cap_stream);
       hipGraph_t g = nullptr;
       const hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
       if (e != hipSuccess) {

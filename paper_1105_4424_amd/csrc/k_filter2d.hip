@@ -12,13 +12,12 @@
 //
 // Two launch forms share the tile body:
 //  * filter2d_kernel: one problem, one workgroup per tile (plain launches);
-//  * filter2d_persistent: a grid sized to the chip (seven workgroups per CU)
-//    walks a host-built table of (problem, tile) entries, ordered by
-//    decreasing problem cost, round-robin: workgroup b takes entries b,
-//    b + grid, ...  Each workgroup fetches the next entry and its problem
-//    descriptor before running the current tile, so no tile waits on a
-//    descriptor load; there is no atomic and nothing to reset between graph
-//    replays.
+//  * filter2d_persistent: a grid sized to the resident capacity walks a
+//    host-built table of (problem, tile) entries round-robin: workgroup b
+//    takes entries b, b + grid, ...  Each workgroup fetches the next entry
+//    and its problem descriptor before running the current tile, so no tile
+//    waits on a descriptor load; there is no atomic and nothing to reset
+//    between graph replays.
 #include <hip/hip_runtime.h>
 
 #include "rsm_internal.h"
@@ -38,26 +37,93 @@ __host__ __device__ constexpr int lds_pitch(int K, int S) {
   return 60 + 4 * seg4_of(K, S) + 4;
 }
 __host__ __device__ constexpr int lds_cols(int K, int S) { return (16 * rx_of(S) - 1) * S + K; }
+// The k x k weights follow the input region in LDS, one window row per 12
+// floats (three 16-byte broadcast reads per row); the region's size is a
+// multiple of 4 floats, so they start 16-byte aligned.
+constexpr int kWPitch = 12;
+__host__ __device__ constexpr int lds_floats(int K, int S, int RY) {
+  return lds_rows(K, S, RY) * lds_pitch(K, S) + kWPitch * K;
+}
 
 __device__ __forceinline__ int mod_pos(int v, int n) {
   // v >= 0 here; reduce into [0, n)
   return v < n ? v : v % n;
 }
 
+// Frame and tile coordinates of tile `local` of problem p.
+__device__ __forceinline__ void tile_pos(const Filter2DProblem& p, int64_t local, int* frame, int* ty, int* tx) {
+  const uint32_t tiles_pf = uint32_t(p.tiles_per_frame);
+  *frame = int(uint32_t(local) / tiles_pf);
+  const int rem = int(uint32_t(local) - uint32_t(*frame) * tiles_pf);
+  *ty = rem / p.tiles_w;
+  *tx = rem - *ty * p.tiles_w;
+}
+
+template <int K, int S, int RY>
+__device__ __forceinline__ void compute_tile(const Filter2DProblem& p, int64_t local, const float* lds) {
+  constexpr int RX = rx_of(S);
+  constexpr int TH = 16 * RY, TW = 16 * RX;
+  constexpr int LR = lds_rows(K, S, RY), LP = lds_pitch(K, S);
+  constexpr int SEG4 = seg4_of(K, S);
+  int frame, ty, tx;
+  tile_pos(p, local, &frame, &ty, &tx);
+  float* __restrict__ y = p.y + int64_t(frame) * p.RH * p.RW;
+  const float* lw = lds + LR * LP;
+  const int t = threadIdx.x;
+  const int tr = t >> 4, tc = t & 15;
+  float acc[RY][RX];
+#pragma unroll
+  for (int i = 0; i < RY; ++i)
+#pragma unroll
+    for (int j = 0; j < RX; ++j) acc[i][j] = 0.0f;
+  // one window row per trip: keeps live registers to one row segment per
+  // output row (full unrolling hoists K x RY segments and spills)
+#pragma unroll 1
+  for (int dy = 0; dy < K; ++dy) {
+    float w[kWPitch];
+#pragma unroll
+    for (int v = 0; v < (K + 3) / 4; ++v) {
+      const float4 q = *reinterpret_cast<const float4*>(lw + dy * kWPitch + 4 * v);
+      w[4 * v + 0] = q.x; w[4 * v + 1] = q.y; w[4 * v + 2] = q.z; w[4 * v + 3] = q.w;
+    }
+#pragma unroll
+    for (int i = 0; i < RY; ++i) {
+      const float* row = lds + ((tr * RY + i) * S + dy) * LP + tc * RX * S;
+      float seg[4 * SEG4];
+#pragma unroll
+      for (int v = 0; v < SEG4; ++v) {
+        const float4 q = *reinterpret_cast<const float4*>(row + 4 * v);
+        seg[4 * v + 0] = q.x; seg[4 * v + 1] = q.y; seg[4 * v + 2] = q.z; seg[4 * v + 3] = q.w;
+      }
+#pragma unroll
+      for (int j = 0; j < RX; ++j)
+#pragma unroll
+        for (int dx = 0; dx < K; ++dx) acc[i][j] = fmaf(w[dx], seg[j * S + dx], acc[i][j]);
+    }
+  }
+  const int oy0 = ty * TH + tr * RY, ox0 = tx * TW + tc * RX;
+#pragma unroll
+  for (int i = 0; i < RY; ++i) {
+    const int oy = oy0 + i;
+    if (oy >= p.RH) break;
+#pragma unroll
+    for (int j = 0; j < RX; ++j) {
+      const int ox = ox0 + j;
+      if (ox < p.RW) y[int64_t(oy) * p.RW + ox] = acc[i][j];
+    }
+  }
+}
+
+// One tile with register staging (plain launches: one workgroup per tile).
 template <int K, int S, int RY>
 __device__ __forceinline__ void filter_tile(const Filter2DProblem p, int64_t local, float* lds) {
   constexpr int RX = rx_of(S);
   constexpr int TH = 16 * RY, TW = 16 * RX;
   constexpr int LR = lds_rows(K, S, RY), LC = lds_cols(K, S), LP = lds_pitch(K, S);
-  constexpr int SEG4 = seg4_of(K, S);
 
-  const uint32_t tiles_pf = uint32_t(p.tiles_per_frame);
-  const int frame = int(uint32_t(local) / tiles_pf);
-  const int rem = int(uint32_t(local) - uint32_t(frame) * tiles_pf);
-  const int ty = rem / p.tiles_w;
-  const int tx = rem - ty * p.tiles_w;
+  int frame, ty, tx;
+  tile_pos(p, local, &frame, &ty, &tx);
   const float* __restrict__ x = p.x + int64_t(frame) * p.H * p.W;
-  float* __restrict__ y = p.y + int64_t(frame) * p.RH * p.RW;
 
   // ---- stage the tile's input region, wrapping modulo the array shape ----
   // Thread (rq, lane) stages rows rq, rq + 4, ... at columns lane and
@@ -74,6 +140,11 @@ __device__ __forceinline__ void filter_tile(const Filter2DProblem p, int64_t loc
   const int lane = t & 63, rq = t >> 6;
   const bool interior = iy0 + LR <= p.H && ix0 + LC <= p.W;
   float* ldst = lds + rq * LP + lane;
+  // weights: thread t < K*K fetches one with the tile's input (the compiler
+  // cannot prove the weights unaliased by the output, so reading them from
+  // memory inside the window loop would cost a global round trip per row)
+  float* lw = lds + LR * LP;
+  const float wt = t < K * K ? p.c[t] : 0.0f;
   if (interior) {
     const float* src = x + int64_t(iy0 + rq) * p.W + ix0 + lane;
     const int64_t step = 4 * int64_t(p.W);
@@ -122,49 +193,10 @@ __device__ __forceinline__ void filter_tile(const Filter2DProblem p, int64_t loc
       }
     }
   }
+  if (t < K * K) lw[(t / K) * kWPitch + t % K] = wt;  // after the staging barrier
   __syncthreads();
 
-  // ---- RY x RX outputs per thread ----
-  const int tr = t >> 4, tc = t & 15;
-  float acc[RY][RX];
-#pragma unroll
-  for (int i = 0; i < RY; ++i)
-#pragma unroll
-    for (int j = 0; j < RX; ++j) acc[i][j] = 0.0f;
-  const float* __restrict__ cw = p.c;
-  // one window row per trip: keeps live registers to one row segment per
-  // output row (full unrolling hoists K x RY segments and spills)
-#pragma unroll 1
-  for (int dy = 0; dy < K; ++dy) {
-    float w[K];
-#pragma unroll
-    for (int dx = 0; dx < K; ++dx) w[dx] = cw[dy * K + dx];
-#pragma unroll
-    for (int i = 0; i < RY; ++i) {
-      const float* row = lds + ((tr * RY + i) * S + dy) * LP + tc * RX * S;
-      float seg[4 * SEG4];
-#pragma unroll
-      for (int v = 0; v < SEG4; ++v) {
-        const float4 q = *reinterpret_cast<const float4*>(row + 4 * v);
-        seg[4 * v + 0] = q.x; seg[4 * v + 1] = q.y; seg[4 * v + 2] = q.z; seg[4 * v + 3] = q.w;
-      }
-#pragma unroll
-      for (int j = 0; j < RX; ++j)
-#pragma unroll
-        for (int dx = 0; dx < K; ++dx) acc[i][j] = fmaf(w[dx], seg[j * S + dx], acc[i][j]);
-    }
-  }
-  const int oy0 = ty * TH + tr * RY, ox0 = tx * TW + tc * RX;
-#pragma unroll
-  for (int i = 0; i < RY; ++i) {
-    const int oy = oy0 + i;
-    if (oy >= p.RH) break;
-#pragma unroll
-    for (int j = 0; j < RX; ++j) {
-      const int ox = ox0 + j;
-      if (ox < p.RW) y[int64_t(oy) * p.RW + ox] = acc[i][j];
-    }
-  }
+  compute_tile<K, S, RY>(p, local, lds);
 }
 
 // RY for tile class tc of stride S.  LDS per workgroup stays under 22 KB so
@@ -173,49 +205,43 @@ __host__ __device__ constexpr int ry_of(int S, int tc) {
   return S == 4 ? 1 : S == 2 ? (tc == 0 ? 1 : 2) : (tc == 0 ? 1 : tc == 1 ? 2 : 4);
 }
 
-template <int K, int S>
-__device__ __forceinline__ void dispatch_tc(const Filter2DProblem p, int64_t local, float* lds) {
-  // one case per distinct tile shape (tile classes that share a shape share the code)
-  if constexpr (S == 4) {
-    filter_tile<K, S, 1>(p, local, lds);
-  } else if constexpr (S == 2) {
-    if (ry_of(S, p.tc) == 1)
-      filter_tile<K, S, 1>(p, local, lds);
-    else
-      filter_tile<K, S, 2>(p, local, lds);
-  } else {
-    switch (ry_of(S, p.tc)) {
-      case 1: filter_tile<K, S, 1>(p, local, lds); break;
-      case 2: filter_tile<K, S, 2>(p, local, lds); break;
-      default: filter_tile<K, S, 4>(p, local, lds); break;
-    }
-  }
-}
-
-template <int K>
-__device__ __forceinline__ void dispatch_s(const Filter2DProblem p, int64_t local, float* lds) {
-  switch (p.s) {
-    case 1: dispatch_tc<K, 1>(p, local, lds); break;
-    case 2: dispatch_tc<K, 2>(p, local, lds); break;
-    default: dispatch_tc<K, 4>(p, local, lds); break;
-  }
-}
-
-__device__ __forceinline__ void dispatch_all(const Filter2DProblem p, int64_t local, float* lds) {
-  switch (p.k) {
-    case 3: dispatch_s<3>(p, local, lds); break;
-    case 5: dispatch_s<5>(p, local, lds); break;
-    case 7: dispatch_s<7>(p, local, lds); break;
-    default: dispatch_s<9>(p, local, lds); break;
-  }
-}
-
 template <int K, int S, int RY>
 __global__ void __launch_bounds__(kThreads) filter2d_kernel(Filter2DProblem p) {
   extern __shared__ float lds[];
   filter_tile<K, S, RY>(p, blockIdx.x, lds);
 }
 
+template <int K>
+__device__ __forceinline__ void tile_s(const Filter2DProblem& p, int64_t local, float* lds) {
+  switch (p.s) {
+    case 1:
+      if (ry_of(1, p.tc) == 1) filter_tile<K, 1, 1>(p, local, lds);
+      else if (ry_of(1, p.tc) == 2) filter_tile<K, 1, 2>(p, local, lds);
+      else filter_tile<K, 1, 4>(p, local, lds);
+      break;
+    case 2:
+      if (ry_of(2, p.tc) == 1) filter_tile<K, 2, 1>(p, local, lds);
+      else filter_tile<K, 2, 2>(p, local, lds);
+      break;
+    default: filter_tile<K, 4, 1>(p, local, lds); break;
+  }
+}
+
+__device__ __forceinline__ void tile_any(const Filter2DProblem& p, int64_t local, float* lds) {
+  switch (p.k) {
+    case 3: tile_s<3>(p, local, lds); break;
+    case 5: tile_s<5>(p, local, lds); break;
+    case 7: tile_s<7>(p, local, lds); break;
+    default: tile_s<9>(p, local, lds); break;
+  }
+}
+
+// Persistent form: workgroup b takes table entries b, b + grid, ...; the
+// next entry and its problem descriptor are fetched before the current tile
+// runs.  Each tile issues its staging loads before the barrier that waits
+// for the previous tile's LDS readers.  The grid must not exceed the
+// resident capacity (the launcher sizes it from the occupancy), so no
+// workgroup starts late.
 __global__ void __launch_bounds__(kThreads, 7) filter2d_persistent(const Filter2DProblem* __restrict__ probs,
                                                                    const uint2* __restrict__ tiles,
                                                                    int64_t n_tiles) {
@@ -233,7 +259,7 @@ __global__ void __launch_bounds__(kThreads, 7) filter2d_persistent(const Filter2
       en = tiles[tn];
       pn = probs[en.x];
     }
-    dispatch_all(p, e.y, lds);
+    tile_any(p, e.y, lds);
     if (!more) break;
     t = tn;
     e = en;
@@ -246,17 +272,17 @@ hipError_t launch_ks(const Filter2DProblem& p, int64_t n_tiles, hipStream_t st) 
   switch (p.tc) {
     case 0: {
       constexpr int RY = ry_of(S, 0);
-      filter2d_kernel<K, S, RY><<<unsigned(n_tiles), kThreads, lds_rows(K, S, RY) * lds_pitch(K, S) * 4, st>>>(p);
+      filter2d_kernel<K, S, RY><<<unsigned(n_tiles), kThreads, lds_floats(K, S, RY) * 4, st>>>(p);
       break;
     }
     case 1: {
       constexpr int RY = ry_of(S, 1);
-      filter2d_kernel<K, S, RY><<<unsigned(n_tiles), kThreads, lds_rows(K, S, RY) * lds_pitch(K, S) * 4, st>>>(p);
+      filter2d_kernel<K, S, RY><<<unsigned(n_tiles), kThreads, lds_floats(K, S, RY) * 4, st>>>(p);
       break;
     }
     default: {
       constexpr int RY = ry_of(S, 2);
-      filter2d_kernel<K, S, RY><<<unsigned(n_tiles), kThreads, lds_rows(K, S, RY) * lds_pitch(K, S) * 4, st>>>(p);
+      filter2d_kernel<K, S, RY><<<unsigned(n_tiles), kThreads, lds_floats(K, S, RY) * 4, st>>>(p);
       break;
     }
   }
@@ -282,16 +308,10 @@ int filter2d_tile_rows(int s, int tc) { return 16 * ry_of(s, tc); }
 int filter2d_tile_cols(int s) { return 16 * rx_of(s); }
 
 size_t filter2d_lds_bytes(int k, int s, int tc) {
-  return size_t(lds_rows(k, s, ry_of(s, tc))) * lds_pitch(k, s) * 4;
+  return size_t(lds_floats(k, s, ry_of(s, tc))) * 4;
 }
 
-size_t filter2d_max_lds_bytes() {
-  size_t m = 0;
-  for (int k = 3; k <= 9; k += 2)
-    for (int s = 1; s <= 4; s *= 2)
-      for (int tc = 0; tc < 3; ++tc) m = filter2d_lds_bytes(k, s, tc) > m ? filter2d_lds_bytes(k, s, tc) : m;
-  return m;
-}
+int filter2d_buf_floats(int k, int s, int tc) { return lds_floats(k, s, ry_of(s, tc)); }
 
 // Fills the tiling fields of p for tile class tc (0..2).
 void filter2d_set_tiles(Filter2DProblem* p, int tc) {
@@ -314,20 +334,27 @@ hipError_t launch_filter2d(const Filter2DProblem& p, hipStream_t st) {
   }
 }
 
-int filter2d_persistent_grid() {
-  int dev = 0, cus = 256;
+// Resident workgroups of the persistent kernel with an LDS buffer of
+// buf_floats, times the CU count.
+int filter2d_persistent_grid(int buf_floats) {
+  int dev = 0, cus = 256, per_cu = 0;
   if (hipGetDevice(&dev) == hipSuccess) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
       cus = v;
   }
-  return 7 * cus;
+  const size_t lds = size_t(buf_floats) * sizeof(float);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&filter2d_persistent),
+                                                   kThreads, lds) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return per_cu * cus;
 }
 
 hipError_t launch_filter2d_persistent(const Filter2DProblem* d_probs, const void* d_tiles, int64_t n_tiles,
-                                      int grid, hipStream_t st) {
-  filter2d_persistent<<<grid, kThreads, filter2d_max_lds_bytes(), st>>>(
-      d_probs, static_cast<const uint2*>(d_tiles), n_tiles);
+                                      int grid, int buf_floats, hipStream_t st) {
+  const size_t lds = size_t(buf_floats) * sizeof(float);
+  filter2d_persistent<<<grid, kThreads, lds, st>>>(d_probs, static_cast<const uint2*>(d_tiles), n_tiles);
   return hipGetLastError();
 }
 

@@ -289,14 +289,16 @@ int csr_group_size(int64_t n_rows, int64_t nnz);
 // init: r = b - A x, p = r, fresh state; then `iters` loop iterations
 hipError_t launch_cg(const CgArgs& a, bool init, int iters, hipStream_t st);
 int cg_grid(int64_t n, int64_t nnz);
-// d_tiles: n_tiles entries of two uint32 (problem index, tile within the problem)
+// d_tiles: n_tiles entries of two uint32 (problem index, tile within the
+// problem); buf_floats: the LDS buffer, at least filter2d_buf_floats() of
+// every problem's tile class
 hipError_t launch_filter2d_persistent(const Filter2DProblem* d_probs, const void* d_tiles, int64_t n_tiles,
-                                      int grid, hipStream_t st);
-int filter2d_persistent_grid();
+                                      int grid, int buf_floats, hipStream_t st);
+int filter2d_persistent_grid(int buf_floats);
+int filter2d_buf_floats(int k, int s, int tc);
 bool filter2d_supported(int k, int s);
 void filter2d_set_tiles(Filter2DProblem* p, int tc);
 size_t filter2d_lds_bytes(int k, int s, int tc);
-size_t filter2d_max_lds_bytes();
 
 // Planner hook shared with the batch: true when (rep, in, out, task) is a
 // k x k weighted window the 2-D filter kernels handle; fills everything in
