@@ -54,7 +54,7 @@ def parse():
     return ap.parse_args()
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fir_chain_adjoint_two_stage_30x1080x1920_traffic.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fir_chain_train_two_stage_30x1080x1920_traffic.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1105_4424_amd", "csrc", "k_window.hip")
 
 
@@ -65,7 +65,7 @@ def kernel_source_hash():
 
 
 def measured_traffic():
-    """HBM bytes per launch of the adjoint kernel from the committed counter
+    """HBM bytes per launch of the training-step kernel from the committed counter
     summary, or None when the summary is missing or was taken on a different
     revision of the kernel source."""
     try:
@@ -120,12 +120,22 @@ def main():
     tiled_per_step = 2 * (n_h + n_v)
     x_bytes = xs[0].numel() * 4
     out_bytes = out.numel() * 4
+    train_bytes = x_bytes + out_bytes + out_bytes + x_bytes  # read x, w; write out, dL/dx
     fwd_bytes = x_bytes + out_bytes                  # read x, write out
     adj_bytes = x_bytes + out_bytes + x_bytes        # read x, read dL/dout, write dL/dx
+    wd = torch.from_numpy(w).to(dev)
 
     def step(k, ev=None):
-        # ev: events that the library records immediately around the fused
-        # forward kernel (ev[0], ev[1]) and the fused adjoint kernel (ev[2], ev[3])
+        # one training step: forward, dL/dout = 2 w out and the adjoint of both
+        # stages, fused into one pass over x; ev: events the library records
+        # immediately around that kernel
+        if ev is not None:
+            rsm.time_next_kernel(ev[0], ev[1])
+        chain.train(xs[k & 1], wd, out, gxs[k & 1], [gch, gcv])
+
+    def step_separate(k, ev=None):
+        # the same step as three calls: fused forward, torch's 2 w * out,
+        # fused adjoint (events around the forward and the adjoint kernels)
         x = xs[k & 1]
         if ev is not None:
             rsm.time_next_kernel(ev[0], ev[1])
@@ -135,27 +145,32 @@ def main():
             rsm.time_next_kernel(ev[2], ev[3])
         chain.adjoint(x, gy, gxs[k & 1], [gch, gcv])
 
-    log("warmup %d steps" % args.warmup)
-    for k in range(args.warmup):
-        step(k)
-    torch.cuda.synchronize()
+    def timed(fn, n_ev):
+        for k in range(args.warmup):
+            fn(k)
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(n_ev)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            fn(k, evs[k])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        us = [float(np.mean([e[2 * i].elapsed_time(e[2 * i + 1]) for e in evs])) * 1e3
+              for i in range(n_ev // 2)]
+        return ms, us
 
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
-    log("timing %d steps" % args.steps)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(k, evs[k])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    fwd_us = float(np.mean([e[0].elapsed_time(e[1]) for e in evs])) * 1e3
-    adj_us = float(np.mean([e[2].elapsed_time(e[3]) for e in evs])) * 1e3
+    log("warmup %d + %d timed steps (fused training step)" % (args.warmup, args.steps))
+    ms_per_step, (train_us,) = timed(step, 2)
     value = tiled_per_step / (ms_per_step * 1e-3)
-    adj_gbs = adj_bytes / (adj_us * 1e-6) / 1e9
+    train_gbs = train_bytes / (train_us * 1e-6) / 1e9
+    log("step %.3f ms | fused training step kernel %.1f us %.0f GB/s"
+        % (ms_per_step, train_us, train_gbs))
+    sep_ms, (fwd_us, adj_us) = timed(step_separate, 4)
     fwd_gbs = fwd_bytes / (fwd_us * 1e-6) / 1e9
-    log("step %.3f ms | fused fwd %.1f us %.0f GB/s | fused adjoint %.1f us %.0f GB/s"
-        % (ms_per_step, fwd_us, fwd_gbs, adj_us, adj_gbs))
+    adj_gbs = adj_bytes / (adj_us * 1e-6) / 1e9
+    log("separate path: step %.3f ms | fwd %.1f us %.0f GB/s | adjoint %.1f us %.0f GB/s"
+        % (sep_ms, fwd_us, fwd_gbs, adj_us, adj_gbs))
 
     result = {
         "metric": "tiled elems/s + HBM GB/s (fwd, adjoint); batched vs plain on 1 MI355X",
@@ -170,19 +185,22 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "two-stage 8-tap downscaler filter, fused forward + adjoint, "
-                               "30 frames 1080x1920 FP32", "frames": F, "rows": H, "cols": Wd,
-                   "taps": T, "paving": T, "tiled_elems_per_step": tiled_per_step,
-                   "hbm_bytes_per_step": fwd_bytes + adj_bytes},
-        "roofline": {"bound": "hbm", "achieved": adj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": adj_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "fir_chain_adjoint_pair_kernel<8>",
-                     "bytes_per_launch": adj_bytes,
-                     "avg_us": adj_us},
-        "extra": {"forward_fused": {"kernel": "fir_chain_pair_kernel<8>", "avg_us": fwd_us,
+        "config": {"workload": "two-stage 8-tap downscaler filter, training step (forward, "
+                               "loss sum(w*out^2), adjoint), 30 frames 1080x1920 FP32",
+                   "frames": F, "rows": H, "cols": Wd, "taps": T, "paving": T,
+                   "tiled_elems_per_step": tiled_per_step, "hbm_bytes_per_step": train_bytes},
+        "roofline": {"bound": "hbm", "achieved": train_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": train_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "kernel": "fir_chain_train_pair_kernel<8>",
+                     "bytes_per_launch": train_bytes,
+                     "avg_us": train_us},
+        "extra": {"separate_path": {"ms_per_step": sep_ms,
+                                    "value": tiled_per_step / (sep_ms * 1e-3)},
+                  "forward_fused": {"kernel": "fir_chain_pair_kernel<8>", "avg_us": fwd_us,
                                     "bytes": fwd_bytes, "gbs": fwd_gbs,
                                     "frac": fwd_gbs / HBM_PEAK_GBS},
-                  "adjoint_fused": {"avg_us": adj_us, "bytes": adj_bytes, "gbs": adj_gbs,
+                  "adjoint_fused": {"kernel": "fir_chain_adjoint_pair_kernel<8>", "avg_us": adj_us,
+                                    "bytes": adj_bytes, "gbs": adj_gbs,
                                     "frac": adj_gbs / HBM_PEAK_GBS}},
     }
 

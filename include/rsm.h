@@ -197,6 +197,24 @@ rsm_status rsm_run_chain_adjoint(const rsm_stage* stages, int32_t n_stages, cons
                                  void* const* d_gc, uint32_t flags, void* hip_stream);
 
 /*
+ * rsm_run_chain_train -- one training step of a two-stage chain under the
+ * loss L = sum over output elements o of w[o] * y[o]^2 (y the chain's output):
+ * the forward (Sec. 3 and 6.1 repetitive tasks chained, as rsm_run_chain),
+ * dL/dy = 2 w y, and the adjoint of both stages (as rsm_run_chain_adjoint),
+ * fused into one pass over the input: d_in is read once, dL/dy is formed in
+ * registers and never stored.  d_w: loss weights, FP32, shaped like the
+ * output; d_out: receives y; d_gx (nullable): dL/dx, input-shaped;
+ * d_gc (HOST array of 2 DEVICE pointers, nullable, entries nullable): the
+ * stages' weight gradients.  RSM_ACCUMULATE adds into d_gx and d_gc.
+ * Supported: the pair the fused chain kernels handle with 8 taps per stage,
+ * weighted sums, injective tilers and 16-byte aligned input rows (the
+ * two-stage 8-tap filter); anything else returns RSM_E_UNSUPPORTED.  Weight
+ * gradients are reduced in a fixed order (deterministic).
+ */
+rsm_status rsm_run_chain_train(const rsm_stage* stages, int32_t n_stages, const void* d_in, const void* d_w,
+                               void* d_out, void* d_gx, void* const* d_gc, uint32_t flags, void* hip_stream);
+
+/*
  * rsm_run_csr -- the repetitive task with data-dependent (indirect) tilers
  * that the paper's conjugate-gradient case study runs on the GPU (Sec. 7,
  * the sparse DGEMV): for every row r of a CSR matrix the pattern is the
@@ -304,8 +322,9 @@ rsm_status rsm_batch_destroy(rsm_batch b); /* waits for the device, then frees *
 rsm_status rsm_batch_tile(rsm_batch b, int32_t k, int32_t* tile_rows, int32_t* tile_cols);
 
 /*
- * rsm_time_next_kernel -- measurement hook.  The next rsm_run_chain or
- * rsm_run_chain_adjoint call made on this host thread records
+ * rsm_time_next_kernel -- measurement hook.  The next rsm_run_chain,
+ * rsm_run_chain_adjoint or rsm_run_chain_train call made on this host thread
+ * records
  * hip_event_start on its stream immediately before launching the fused
  * chain kernel and hip_event_stop immediately after it (no other launch of
  * the call lies between them), then forgets both; calls that take the

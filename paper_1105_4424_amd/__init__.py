@@ -9,7 +9,7 @@ package only marshals torch tensors (device memory and streams) into that
 ABI.
 """
 from .rsm import (Batch, Chain, RsmError, TiledChain, TiledTask, indices, plan, run, run_adjoint,
-                  run_chain, run_chain_adjoint, run_csr, cg_solve, time_next_kernel, validate)
+                  run_chain, run_chain_adjoint, run_chain_train, run_csr, cg_solve, time_next_kernel, validate)
 
 __all__ = ["Batch", "Chain", "RsmError", "TiledChain", "TiledTask", "indices", "plan", "run",
-           "run_adjoint", "run_chain", "run_chain_adjoint", "run_csr", "cg_solve", "time_next_kernel", "validate"]
+           "run_adjoint", "run_chain", "run_chain_adjoint", "run_chain_train", "run_csr", "cg_solve", "time_next_kernel", "validate"]

@@ -1139,6 +1139,67 @@ rsm_status rsm_run_chain_adjoint(const rsm_stage* stages, int32_t n_stages, cons
   RSM_GUARD_END
 }
 
+rsm_status rsm_run_chain_train(const rsm_stage* stages, int32_t n_stages, const void* d_in, const void* d_w,
+                               void* d_out, void* d_gx, void* const* d_gc, uint32_t flags, void* hip_stream) {
+  const KernelProbe probe = take_probe();
+  RSM_GUARD_BEGIN
+  std::vector<Checked> cs;
+  rsm_status s = check_chain(stages, n_stages, &cs);
+  if (s) return s;
+  for (int k = 0; k < n_stages; ++k) {
+    Checked tmp;
+    s = check_adjoint(&stages[k].rep, &stages[k].in, &stages[k].out, &stages[k].task, &tmp);
+    if (s) return fail(s, "stage " + std::to_string(k) + ": " + g_last_error);
+    if (d_gc && d_gc[k] && stages[k].task.kind != RSM_TASK_WSUM)
+      return fail(RSM_E_INVALID, "weight gradient needs a WSUM stage");
+  }
+  if (!d_in || !d_w || !d_out) return fail(RSM_E_INVALID, "NULL device pointer");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int accumulate = (flags & RSM_ACCUMULATE) ? 1 : 0;
+  Win3 h{}, v{};
+  bool vec4 = false;
+  if (n_stages != 2 || !chain_fusable(stages, n_stages, d_in, &h, &v, &vec4) || !fir_injective(h) ||
+      !fir_injective(v) || h.taps != 8 || v.taps != 8 || !vec4 || !fir_vec4(h, d_gx) ||
+      stages[0].task.kind != RSM_TASK_WSUM || stages[1].task.kind != RSM_TASK_WSUM)
+    return fail(RSM_E_UNSUPPORTED,
+                "fused training step needs a fusable pair of 8-tap weighted sums with 16-byte rows");
+  if (cs[1].n_rep == 0) return RSM_OK;
+  hipError_t e;
+  if (d_gx && !accumulate && !(fir_exact_cover(h) && fir_exact_cover(v))) {
+    if ((e = launch_zero(d_gx, int64_t(h.A[0]) * h.A[1] * h.A[2] * 4, st)) != hipSuccess)
+      return hip_fail(e, "zero gx");
+  }
+  FirChainAdjArgs a{};
+  a.h = h;
+  a.v = v;
+  a.div_rc = make_fastdiv(uint32_t(v.rep[2]));
+  a.div_rr = make_fastdiv(uint32_t(v.rep[1]));
+  a.n_out = uint32_t(cs[1].n_rep);
+  a.x = static_cast<const float*>(d_in);
+  a.gx = static_cast<float*>(d_gx);
+  a.ch = static_cast<const float*>(stages[0].task.coeffs);
+  a.cv = static_cast<const float*>(stages[1].task.coeffs);
+  a.accumulate = accumulate;
+  a.wl = static_cast<const float*>(d_w);
+  a.y = static_cast<float*>(d_out);
+  float* gch = d_gc ? static_cast<float*>(d_gc[0]) : nullptr;
+  float* gcv = d_gc ? static_cast<float*>(d_gc[1]) : nullptr;
+  const int grid = fir_chain_adjoint_grid(a, true);
+  const int nc = h.taps + v.taps;
+  if (gch || gcv) {
+    a.partial = static_cast<float*>(workspace(size_t(grid) * nc * sizeof(float), st, &s, nullptr));
+    if (s) return s;
+  }
+  if ((e = probed(probe, st, [&] { return launch_fir_chain_train(a, st); })) != hipSuccess)
+    return hip_fail(e, "fused training step");
+  if (gch && (e = launch_reduce_partials(a.partial, grid, h.taps, nc, gch, accumulate, st)) != hipSuccess)
+    return hip_fail(e, "weight-gradient reduction");
+  if (gcv && (e = launch_reduce_partials(a.partial + h.taps, grid, v.taps, nc, gcv, accumulate, st)) != hipSuccess)
+    return hip_fail(e, "weight-gradient reduction");
+  return RSM_OK;
+  RSM_GUARD_END
+}
+
 rsm_status rsm_run_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t* d_row_ptr,
                        const int32_t* d_col_idx, const void* d_vals, const void* d_x, void* d_y,
                        int32_t dtype, uint32_t flags, void* hip_stream) {

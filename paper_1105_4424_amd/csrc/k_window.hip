@@ -861,6 +861,158 @@ __global__ void __launch_bounds__(kBlock) fir_chain_adjoint_pair_kernel(FirChain
   }
 }
 
+// ---------------------------------------------------------------------------
+// training step of the fused chain under the loss L = sum_o wl[o] y[o]^2:
+// one pass over x computes y (stored), dL/dy = 2 wl y in registers, and the
+// adjoint (dL/dx stored, weight-gradient partials), so the step reads x once
+// instead of twice and never writes or reads dL/dy.  Same lane-pair layout
+// and software pipeline as the adjoint kernel; the stage-1 sums of the
+// forward are the ones the weight gradient of stage 2 needs.
+// ---------------------------------------------------------------------------
+template <int T1>
+__device__ __forceinline__ void train_fetch(const FirChainAdjArgs& a, uint32_t gidx, int hh, PairBlock<T1>& b) {
+  b.o = gidx >> 1;
+  const OutPos q = decode(b.o, a.v, a.div_rc, a.div_rr);
+  b.fast = chain_rows<8, T1>(a.h, a.v, q, b.off);
+  b.g = a.wl[b.o];
+  if (b.fast) {
+#pragma unroll
+    for (int j = 0; j < T1; ++j) b.x[j] = *reinterpret_cast<const float4*>(a.x + b.off[j] + 4 * hh);
+  }
+}
+
+template <int T1>
+__global__ void __launch_bounds__(kBlock, 4) fir_chain_train_pair_kernel(FirChainAdjArgs a) {
+  const Win3& h = a.h;
+  const Win3& v = a.v;
+  const uint32_t n_half = 2u * a.n_out;
+  const uint32_t stride = gridDim.x * kBlock;
+  const int hh = threadIdx.x & 1;
+  float c4[4], cv[T1], g4[4], gv[T1];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    c4[e] = a.ch[4 * hh + e];
+    g4[e] = 0.0f;
+  }
+#pragma unroll
+  for (int j = 0; j < T1; ++j) {
+    cv[j] = a.cv[j];
+    gv[j] = 0.0f;
+  }
+  uint32_t gi = blockIdx.x * kBlock + threadIdx.x;
+  PairBlock<T1> cur;
+  if (gi < n_half) train_fetch<T1>(a, gi, hh, cur);
+  while (gi < n_half) {
+    const uint32_t gn = gi + stride;
+    PairBlock<T1> nxt;
+    if (gn < n_half) train_fetch<T1>(a, gn, hh, nxt);
+    if (cur.fast) {
+      // forward: stage-1 sums per row (lane 2m: taps 0-3, lane 2m+1: 4-7,
+      // added in that order on both lanes), then the stage-2 sum
+      float mid[T1];
+      float y = 0.0f;
+#pragma unroll
+      for (int j = 0; j < T1; ++j) {
+        float part = c4[0] * cur.x[j].x;
+        part = fmaf(c4[1], cur.x[j].y, part);
+        part = fmaf(c4[2], cur.x[j].z, part);
+        part = fmaf(c4[3], cur.x[j].w, part);
+        const float other = __shfl_xor(part, 1);
+        mid[j] = hh ? other + part : part + other;
+        y = fmaf(cv[j], mid[j], y);
+      }
+      if (hh == 0) a.y[cur.o] = y;
+      const float g = 2.0f * (cur.g * y);
+#pragma unroll
+      for (int j = 0; j < T1; ++j) {
+        const float gm = cv[j] * g;
+        if (hh == 0) gv[j] = fmaf(g, mid[j], gv[j]);
+        g4[0] = fmaf(gm, cur.x[j].x, g4[0]);
+        g4[1] = fmaf(gm, cur.x[j].y, g4[1]);
+        g4[2] = fmaf(gm, cur.x[j].z, g4[2]);
+        g4[3] = fmaf(gm, cur.x[j].w, g4[3]);
+      }
+      if (a.gx) {
+#pragma unroll
+        for (int j = 0; j < T1; ++j) {
+          const float gm = cv[j] * g;
+          float4 w4 = make_float4(c4[0] * gm, c4[1] * gm, c4[2] * gm, c4[3] * gm);
+          float4* d4 = reinterpret_cast<float4*>(a.gx + cur.off[j] + 4 * hh);
+          if (a.accumulate) {
+            const float4 old = *d4;
+            w4.x += old.x; w4.y += old.y; w4.z += old.z; w4.w += old.w;
+          }
+          *d4 = w4;
+        }
+      }
+    } else {
+      // window wraps: each lane reads its own four taps of every row on the
+      // modular path, keeps them for the adjoint, and both lanes form y
+      const OutPos q = decode(cur.o, v, a.div_rc, a.div_rr);
+      const int mb = v.o[0] + v.p[0] * q.b;
+      const int mc = v.o[2] + v.p[2] * q.c;
+      const int xb = h.o[0] + h.p[0] * mb;
+      const int xstart = h.o[2] + h.p[2] * mc;
+      const int mr0 = wrap_mod(int64_t(v.o[1]) + int64_t(v.p[1]) * q.r, v.A[1]);
+      const int col0 = wrap_mod(int64_t(xstart) + 4 * hh, h.A[2]);
+      float xs[T1][4], mid[T1];
+      float y = 0.0f;
+      int mr = mr0;
+#pragma unroll
+      for (int j = 0; j < T1; ++j) {
+        const int row_base = (xb * h.A[1] + h.o[1] + h.p[1] * mr) * h.A[2];
+        int col = col0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          xs[j][e] = a.x[row_base + col];
+          if (++col == h.A[2]) col = 0;
+        }
+        float part = c4[0] * xs[j][0];
+        part = fmaf(c4[1], xs[j][1], part);
+        part = fmaf(c4[2], xs[j][2], part);
+        part = fmaf(c4[3], xs[j][3], part);
+        const float other = __shfl_xor(part, 1);
+        mid[j] = hh ? other + part : part + other;
+        y = fmaf(cv[j], mid[j], y);
+        if (++mr == v.A[1]) mr = 0;
+      }
+      if (hh == 0) a.y[cur.o] = y;
+      const float g = 2.0f * (cur.g * y);
+      mr = mr0;
+#pragma unroll
+      for (int j = 0; j < T1; ++j) {
+        const int row_base = (xb * h.A[1] + h.o[1] + h.p[1] * mr) * h.A[2];
+        const float gm = cv[j] * g;
+        if (hh == 0) gv[j] = fmaf(g, mid[j], gv[j]);
+        int col = col0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          g4[e] = fmaf(gm, xs[j][e], g4[e]);
+          if (a.gx) {
+            float* d = a.gx + row_base + col;
+            *d = a.accumulate ? *d + c4[e] * gm : c4[e] * gm;
+          }
+          if (++col == h.A[2]) col = 0;
+        }
+        if (++mr == v.A[1]) mr = 0;
+      }
+    }
+    cur = nxt;
+    gi = gn;
+  }
+  if (a.partial) {
+    float packed[8 + T1];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      packed[e] = hh ? 0.0f : g4[e];
+      packed[4 + e] = hh ? g4[e] : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < T1; ++j) packed[8 + j] = gv[j];
+    block_reduce_store<8 + T1>(packed, 8 + T1, a.partial + int64_t(blockIdx.x) * (8 + T1), false);
+  }
+}
+
 int stream_grid(uint32_t work, int waves_per_cu = 8) {
   // enough resident blocks to cover the chip several times, grid-stride beyond
   const int cap = 256 * waves_per_cu;
@@ -956,6 +1108,11 @@ hipError_t launch_fir_chain_adjoint(const FirChainAdjArgs& a, bool vec4, hipStre
     fir_chain_adjoint_kernel<true, 0, 0><<<grid, kBlock, 0, st>>>(a);
   else
     fir_chain_adjoint_kernel<false, 0, 0><<<grid, kBlock, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fir_chain_train(const FirChainAdjArgs& a, hipStream_t st) {
+  fir_chain_train_pair_kernel<8><<<fir_chain_adjoint_grid(a, true), kBlock, 0, st>>>(a);
   return hipGetLastError();
 }
 

@@ -140,6 +140,10 @@ struct FirChainAdjArgs {
   float* gcv;
   uint32_t* counter;   // as in FirAdjArgs
   int32_t accumulate;
+  // training step (launch_fir_chain_train): gy is not read but formed per
+  // output as 2 wl[o] y[o] from the forward value y[o], which is stored to y
+  const float* wl;
+  float* y;
 };
 
 // Small-pattern reduction: a group of G lanes (G = 2^k >= |pattern|, G <= 64)
@@ -286,6 +290,9 @@ bool gemm_supported(const GemmArgs& a, int compute);
 hipError_t launch_filter2d(const Filter2DProblem& p, hipStream_t st);
 hipError_t launch_csr(const CsrArgs& a, int dtype, hipStream_t st);
 int csr_group_size(int64_t n_rows, int64_t nnz);
+// forward + loss gradient + adjoint of a fused 8-tap pair (vec4 layout only);
+// same grid and partial rows as launch_fir_chain_adjoint
+hipError_t launch_fir_chain_train(const FirChainAdjArgs& a, hipStream_t st);
 // init: r = b - A x, p = r, fresh state; then `iters` loop iterations
 hipError_t launch_cg(const CgArgs& a, bool init, int iters, hipStream_t st);
 int cg_grid(int64_t n, int64_t nnz);

@@ -223,6 +223,13 @@ def run_chain_adjoint(stages, x: torch.Tensor, gy: torch.Tensor, gx: Optional[to
                                      _stream(stream)))
 
 
+def run_chain_train(stages, x: torch.Tensor, w: torch.Tensor, out: torch.Tensor, gx: Optional[torch.Tensor],
+                    coeffs: Sequence[torch.Tensor], gcs=None, flags: int = 0, stream=None) -> torch.Tensor:
+    """Forward, dL/dout = 2 w out and the adjoint of a two-stage chain in one
+    pass (loss sum(w * out^2)); see Chain.train."""
+    return Chain(stages, coeffs).train(x, w, out, gx, gcs, flags=flags, stream=stream)
+
+
 def run_csr(row_ptr: torch.Tensor, col_idx: torch.Tensor, vals: torch.Tensor, x: torch.Tensor,
             y: torch.Tensor, check_indices: bool = False, stream=None) -> torch.Tensor:
     """y = A x for a CSR matrix (indirect tilers; int32 indices on the GPU)."""
@@ -429,3 +436,14 @@ class Chain:
             gp = (ctypes.c_void_p * self._n)(*[(_ptr(g).value if g is not None else None) for g in gcs])
         _check(self._lib.rsm_run_chain_adjoint(self._arr, self._n, _ptr(x), mp, _ptr(gy), _ptr(gx),
                                                gp, flags, _stream(stream)))
+
+    def train(self, x, w, out, gx, gcs, flags: int = 0, stream=None):
+        """One fused training step under the loss sum(w * out^2): writes out,
+        gx (may be None) and the weight gradients gcs (list, entries may be
+        None) in one pass over x."""
+        gp = None
+        if gcs is not None:
+            gp = (ctypes.c_void_p * self._n)(*[(_ptr(g).value if g is not None else None) for g in gcs])
+        _check(self._lib.rsm_run_chain_train(self._arr, self._n, _ptr(x), _ptr(w), _ptr(out), _ptr(gx), gp,
+                                             flags, _stream(stream)))
+        return out
