@@ -71,8 +71,8 @@ def measured_traffic():
     try:
         fields = {}
         for line in open(TRAFFIC_SUMMARY):
-            if ":" in line and line.startswith("- "):
-                k, v = line[2:].split(":", 1)
+            if ": " in line and line.startswith("- "):
+                k, v = line[2:].split(": ", 1)
                 fields[k.strip()] = v.strip().strip("`")
         if fields.get("kernel source sha256[:16]") != kernel_source_hash():
             return None

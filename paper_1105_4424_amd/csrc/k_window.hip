@@ -882,7 +882,7 @@ __device__ __forceinline__ void train_fetch(const FirChainAdjArgs& a, uint32_t g
 }
 
 template <int T1>
-__global__ void __launch_bounds__(kBlock, 4) fir_chain_train_pair_kernel(FirChainAdjArgs a) {
+__global__ void __launch_bounds__(kBlock) fir_chain_train_pair_kernel(FirChainAdjArgs a) {
   const Win3& h = a.h;
   const Win3& v = a.v;
   const uint32_t n_half = 2u * a.n_out;
