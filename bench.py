@@ -271,6 +271,25 @@ def extras(args, ts, xs, stages, ch, cv, w2, chain):
     ex["adjoint_unfused"] = {"avg_us": us, "bytes": b, "gbs": b / us / 1e3, "frac": b / us / 1e3 / HBM_PEAK_GBS}
     log("unfused fwd %.1f us, unfused adjoint %.1f us" % (ex["forward_unfused"]["avg_us"], us))
 
+    # fused forward alone over four input copies (about 1 GB, so the 256 MiB
+    # Infinity Cache serves none of its reads and no adjoint's dirty lines
+    # are pending), events around the kernel
+    xr = list(xs) + [xs[0].clone(), xs[0].clone()]
+    evs = []
+    for k in range(24):
+        e = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        rsm.time_next_kernel(*e)
+        chain.forward(xr[k % 4], out)
+        if k >= 4:
+            evs.append(e)
+    torch.cuda.synchronize()
+    us = float(np.median([a.elapsed_time(b) for a, b in evs])) * 1e3
+    b = xs[0].numel() * 4 + out.numel() * 4
+    ex["forward_fused_standalone"] = {"kernel": "fir_chain_pair_kernel<8>", "avg_us": us, "bytes": b,
+                                      "gbs": b / us / 1e3, "frac": b / us / 1e3 / HBM_PEAK_GBS}
+    log("fused forward alone %.1f us %.0f GB/s" % (us, b / us / 1e3))
+    del xr
+
     # small plain task: 64x64 -> 16x16 sums
     x0, p0 = W.small_sum()
     xd = torch.from_numpy(x0).to(dev)

@@ -1242,9 +1242,9 @@ rsm_status rsm_cg_solve(int64_t n, int64_t nnz, const int32_t* d_row_ptr, const 
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   if ((flags & RSM_CHECK_INDICES) && (s = check_csr_indices(n, n, nnz, d_row_ptr, d_col_idx, st)) != RSM_OK)
     return s;
-  const int grid = cg_grid(n, nnz);
+  const int grid_rows = cg_grid(n, nnz), grid_vec = cg_vec_grid(n);
   const size_t vec = (size_t(n) * sizeof(double) + 255) & ~size_t(255);
-  const size_t part = (size_t(grid) * sizeof(double) + 255) & ~size_t(255);
+  const size_t part = (size_t(std::max(grid_rows, grid_vec)) * sizeof(double) + 255) & ~size_t(255);
   char* ws = static_cast<char*>(workspace(3 * vec + 3 * part + 256, st, &s, nullptr));
   if (s != RSM_OK) return s;
   CgArgs a{};
@@ -1267,7 +1267,8 @@ rsm_status rsm_cg_solve(int64_t n, int64_t nnz, const int32_t* d_row_ptr, const 
   a.beta = d_beta;
   a.tol = tol;
   a.max_iter = max_iter;
-  a.grid = grid;
+  a.grid_rows = grid_rows;
+  a.grid_vec = grid_vec;
   hipError_t e = launch_cg(a, true, 0, st);
   if (e != hipSuccess) return hip_fail(e, "cg start launch");
   // Launch batches of check_every iterations and read the state after each;

@@ -14,7 +14,9 @@
 //
 // Every workgroup rebuilds a scalar from the previous kernel's per-workgroup
 // partials in one fixed order, so all workgroups hold the same bits and the
-// loop is deterministic for a given launch shape.  Each field of the state
+// loop is deterministic for a given launch shape.  The sparse product runs
+// on a large grid (latency hiding); the vector kernels on at most 256
+// workgroups, so the partials every workgroup re-sums stay few.  Each field of the state
 // block is written by workgroup 0 of one kernel only and read by the other
 // kernels, never by the kernel that writes it: rho / done by cg_spmv,
 // breakdown by cg_xr, k by cg_p.  After the stop test has fired, every kernel
@@ -126,10 +128,15 @@ __global__ void __launch_bounds__(kBlock) cg_init_kernel(CgArgs a) {
   }
 }
 
-// One workgroup: ||b|| and a fresh state block.
+// One workgroup: ||b||, a fresh state block, and the <r0,r0> partials of
+// cg_init (one per row workgroup) folded into part_rr[0] with zeros after
+// it, the layout cg_spmv reads (one per vector workgroup); adding zeros
+// leaves the fixed-order sum unchanged.
 __global__ void __launch_bounds__(kBlock) cg_start_kernel(CgArgs a) {
   __shared__ double lds[kBlock];
-  const double bb = partial_sum(a.part_bb, a.grid, lds);
+  const double bb = partial_sum(a.part_bb, a.grid_rows, lds);
+  const double rr = partial_sum(a.part_rr, a.grid_rows, lds);
+  for (int i = threadIdx.x; i < a.grid_vec; i += kBlock) a.part_rr[i] = i == 0 ? rr : 0.0;
   if (threadIdx.x == 0) {
     a.st->bnorm = sqrt(bb);
     a.st->rho = 0.0;
@@ -142,7 +149,7 @@ __global__ void __launch_bounds__(kBlock) cg_start_kernel(CgArgs a) {
 template <int G>
 __global__ void __launch_bounds__(kBlock) cg_spmv_kernel(CgArgs a) {
   __shared__ double lds[kBlock];
-  const double rho = partial_sum(a.part_rr, a.grid, lds);
+  const double rho = partial_sum(a.part_rr, a.grid_vec, lds);
   const int64_t k = a.st->k;
   const bool stop = a.st->breakdown != 0 || k >= a.max_iter || !(sqrt(rho) > a.tol * a.st->bnorm);
   if (lead()) {
@@ -163,7 +170,7 @@ __global__ void __launch_bounds__(kBlock) cg_spmv_kernel(CgArgs a) {
 __global__ void __launch_bounds__(kBlock) cg_xr_kernel(CgArgs a) {
   __shared__ double lds[kBlock];
   if (a.st->done) return;
-  const double pq = partial_sum(a.part_pq, a.grid, lds);
+  const double pq = partial_sum(a.part_pq, a.grid_rows, lds);
   if (!(pq > 0.0)) {  // A is not positive definite along p
     if (lead()) a.st->breakdown = 1;
     return;
@@ -185,7 +192,7 @@ __global__ void __launch_bounds__(kBlock) cg_xr_kernel(CgArgs a) {
 __global__ void __launch_bounds__(kBlock) cg_p_kernel(CgArgs a) {
   __shared__ double lds[kBlock];
   if (a.st->done || a.st->breakdown) return;
-  const double rho_next = partial_sum(a.part_rr, a.grid, lds);
+  const double rho_next = partial_sum(a.part_rr, a.grid_vec, lds);
   const double beta = rho_next / a.st->rho;
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < a.n; i += int64_t(gridDim.x) * kBlock)
     a.p[i] = a.r[i] + beta * a.p[i];
@@ -198,15 +205,15 @@ __global__ void __launch_bounds__(kBlock) cg_p_kernel(CgArgs a) {
 
 template <int G>
 hipError_t launch_g(const CgArgs& a, bool init, int iters, hipStream_t st) {
-  const unsigned grid = unsigned(a.grid);
+  const unsigned gr = unsigned(a.grid_rows), gv = unsigned(a.grid_vec);
   if (init) {
-    cg_init_kernel<G><<<grid, kBlock, 0, st>>>(a);
+    cg_init_kernel<G><<<gr, kBlock, 0, st>>>(a);
     cg_start_kernel<<<1, kBlock, 0, st>>>(a);
   }
   for (int i = 0; i < iters; ++i) {
-    cg_spmv_kernel<G><<<grid, kBlock, 0, st>>>(a);
-    cg_xr_kernel<<<grid, kBlock, 0, st>>>(a);
-    cg_p_kernel<<<grid, kBlock, 0, st>>>(a);
+    cg_spmv_kernel<G><<<gr, kBlock, 0, st>>>(a);
+    cg_xr_kernel<<<gv, kBlock, 0, st>>>(a);
+    cg_p_kernel<<<gv, kBlock, 0, st>>>(a);
   }
   return hipGetLastError();
 }
@@ -228,6 +235,15 @@ int cg_grid(int64_t n, int64_t nnz) {
   const int64_t lanes = ((n + 1) / 2) * cg_group_size(n, nnz);
   int64_t g = (lanes + kBlock - 1) / kBlock;
   if (g > 2048) g = 2048;
+  if (g < 1) g = 1;
+  return int(g);
+}
+
+// Vector kernels: at most 256 workgroups (the next kernel re-sums their
+// partials in every workgroup, so few partials keep that cheap).
+int cg_vec_grid(int64_t n) {
+  int64_t g = (n + kBlock - 1) / kBlock;
+  if (g > 256) g = 256;
   if (g < 1) g = 1;
   return int(g);
 }

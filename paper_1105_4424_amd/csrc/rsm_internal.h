@@ -250,16 +250,17 @@ struct CgArgs {
   double* r;                // n, workspace
   double* p;                // n, workspace
   double* q;                // n, workspace
-  double* part_pq;          // grid, workspace
-  double* part_rr;          // grid, workspace
-  double* part_bb;          // grid, workspace
+  double* part_pq;          // grid_rows, workspace
+  double* part_rr;          // max(grid_rows, grid_vec), workspace
+  double* part_bb;          // grid_rows, workspace
   CgState* st;              // workspace
   double* res;              // nullable, max_iter + 1
   double* alpha;            // nullable, max_iter
   double* beta;             // nullable, max_iter
   double tol;
   int64_t max_iter;
-  int32_t grid;             // workgroups of every loop kernel
+  int32_t grid_rows;        // workgroups of the sparse-product kernels (cg_init, cg_spmv)
+  int32_t grid_vec;         // workgroups of the vector kernels (cg_xr, cg_p)
 };
 
 // ---------------------------------------------------------------------------
@@ -296,6 +297,7 @@ hipError_t launch_fir_chain_train(const FirChainAdjArgs& a, hipStream_t st);
 // init: r = b - A x, p = r, fresh state; then `iters` loop iterations
 hipError_t launch_cg(const CgArgs& a, bool init, int iters, hipStream_t st);
 int cg_grid(int64_t n, int64_t nnz);
+int cg_vec_grid(int64_t n);
 // d_tiles: n_tiles entries of two uint32 (problem index, tile within the
 // problem); buf_floats: the LDS buffer, at least filter2d_buf_floats() of
 // every problem's tile class
