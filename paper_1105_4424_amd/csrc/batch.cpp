@@ -234,13 +234,43 @@ rsm_status build_queue(rsm_batch_s* b) {
   }
   b->n_tiles = total;
   if (b->n_tiles >= (int64_t(1) << 31)) return fail(RSM_E_UNSUPPORTED, "batch has more than 2^31 tiles");
-  std::vector<uint32_t> tiles(size_t(2 * std::max<int64_t>(total, 1)));
-  size_t pos = 0;
-  for (size_t i = 0; i < n; ++i)
-    for (int64_t k = 0; k < table[i].n_tiles; ++k) {
-      tiles[pos++] = uint32_t(i);
-      tiles[pos++] = uint32_t(k);
-    }
+  // XCD-aware layout.  Workgroup b runs table entries b, b + grid, ... and
+  // the hardware deals workgroups round-robin to the 8 XCDs, so with grid a
+  // multiple of 8 entry p runs on XCD p mod 8, and each XCD has its own L2.
+  // Each problem's tiles (row-major over the tile grid) are cut into 8
+  // contiguous bands, band x going to XCD x (remainder tiles to the XCDs
+  // with the fewest tiles so far), and entry 8 j + x holds the j-th tile of
+  // XCD x: spatial neighbours, which share halo rows and cache lines, share
+  // an L2, and every XCD gets an eighth of every problem in the same order.
+  constexpr int kXcd = 8;
+  std::vector<std::vector<uint32_t>> band(kXcd);
+  std::vector<int64_t> len(kXcd, 0);
+  for (size_t i = 0; i < n; ++i) {
+    const int64_t nt = table[i].n_tiles, q = nt / kXcd;
+    int rem = int(nt % kXcd);
+    std::vector<int> order(kXcd);
+    for (int x = 0; x < kXcd; ++x) order[size_t(x)] = x;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return len[size_t(a)] < len[size_t(c)]; });
+    std::vector<int64_t> size(kXcd, q);
+    for (int r = 0; r < rem; ++r) size[size_t(order[size_t(r)])] += 1;
+    int64_t k = 0;
+    for (int x = 0; x < kXcd; ++x)
+      for (int64_t c = 0; c < size[size_t(x)]; ++c, ++k) {
+        band[size_t(x)].push_back(uint32_t(i));
+        band[size_t(x)].push_back(uint32_t(k));
+        len[size_t(x)] += 1;
+      }
+  }
+  std::vector<uint32_t> tiles;
+  tiles.reserve(size_t(2 * std::max<int64_t>(total, 1)));
+  const int64_t longest = *std::max_element(len.begin(), len.end());
+  for (int64_t j = 0; j < longest; ++j)
+    for (int x = 0; x < kXcd; ++x)
+      if (j < len[size_t(x)]) {
+        tiles.push_back(band[size_t(x)][size_t(2 * j)]);
+        tiles.push_back(band[size_t(x)][size_t(2 * j + 1)]);
+      }
+  if (tiles.empty()) tiles.assign(2, 0u);
   hipError_t e;
   if ((e = hipMalloc(&b->d_probs, sizeof(Filter2DProblem) * std::max<size_t>(n, 1))) != hipSuccess ||
       (e = hipMalloc(&b->d_tiles, sizeof(uint32_t) * tiles.size())) != hipSuccess)
