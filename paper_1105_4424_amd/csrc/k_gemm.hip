@@ -386,11 +386,51 @@ __global__ void __launch_bounds__(256) transpose_kernel(const E* __restrict__ sr
   }
 }
 
+// The same with 16-byte accesses on both sides (V = 16 / sizeof(E) elements):
+// a 64 x 64 tile is loaded row by row in 16-byte pieces into LDS (rows padded
+// by one piece) and written column by column, each output piece gathering V
+// elements of one LDS column.  Needs cols % V == 0, rows % V == 0 and
+// 16-byte aligned bases (the launcher checks), so a piece is wholly in or
+// out of range.
+template <typename E>
+__global__ void __launch_bounds__(256) transpose_vec_kernel(const E* __restrict__ src, E* __restrict__ dst,
+                                                            int rows, int cols) {
+  constexpr int V = 16 / int(sizeof(E));
+  constexpr int P = 64 / V;         // pieces per tile row
+  constexpr int R = 256 / P;        // tile rows per pass
+  __shared__ __attribute__((aligned(16))) E tile[64][64 + V];
+  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+  const int piece = threadIdx.x % P, rr = threadIdx.x / P;
+#pragma unroll
+  for (int r = rr; r < 64; r += R) {
+    const int gr = r0 + r, gc = c0 + piece * V;
+    if (gr < rows && gc < cols)
+      *reinterpret_cast<uint4*>(&tile[r][piece * V]) =
+          *reinterpret_cast<const uint4*>(src + int64_t(gr) * cols + gc);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = rr; c < 64; c += R) {
+    const int gc = c0 + c, gr = r0 + piece * V;
+    if (gc < cols && gr < rows) {
+      E v[V];
+#pragma unroll
+      for (int i = 0; i < V; ++i) v[i] = tile[piece * V + i][c];
+      *reinterpret_cast<uint4*>(dst + int64_t(gc) * rows + gr) = *reinterpret_cast<const uint4*>(v);
+    }
+  }
+}
+
 template <typename E>
 hipError_t transpose(const void* src, void* dst, int rows, int cols, hipStream_t st) {
+  constexpr int V = 16 / int(sizeof(E));
   dim3 grid((cols + 63) / 64, (rows + 63) / 64);
-  transpose_kernel<E><<<grid, 256, 0, st>>>(static_cast<const E*>(src), static_cast<E*>(dst), rows,
-                                            cols, cols, rows);
+  if (cols % V == 0 && rows % V == 0 &&
+      !((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15))
+    transpose_vec_kernel<E><<<grid, 256, 0, st>>>(static_cast<const E*>(src), static_cast<E*>(dst), rows, cols);
+  else
+    transpose_kernel<E><<<grid, 256, 0, st>>>(static_cast<const E*>(src), static_cast<E*>(dst), rows, cols,
+                                              cols, rows);
   return hipGetLastError();
 }
 
