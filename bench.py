@@ -172,6 +172,22 @@ def main():
     log("separate path: step %.3f ms | fwd %.1f us %.0f GB/s | adjoint %.1f us %.0f GB/s"
         % (sep_ms, fwd_us, fwd_gbs, adj_us, adj_gbs))
 
+    # a device copy of the same size (x into dL/dx, alternating buffers), the
+    # practical ceiling for a kernel that reads and writes once
+    cev = []
+    for k in range(14):
+        e = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        e[0].record()
+        gxs[k & 1].copy_(xs[k & 1])
+        e[1].record()
+        if k >= 4:
+            cev.append(e)
+    torch.cuda.synchronize()
+    copy_us = float(np.median([a.elapsed_time(b) for a, b in cev])) * 1e3
+    copy_gbs = 2 * x_bytes / (copy_us * 1e-6) / 1e9
+    props = torch.cuda.get_device_properties(0)
+    log("device copy of %.1f MB: %.1f us %.0f GB/s" % (x_bytes / 1e6, copy_us, copy_gbs))
+
     result = {
         "metric": "tiled elems/s + HBM GB/s (fwd, adjoint); batched vs plain on 1 MI355X",
         "value": value,
@@ -193,8 +209,11 @@ def main():
                      "frac": train_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "fir_chain_train_pair_kernel<8>",
                      "bytes_per_launch": train_bytes,
-                     "avg_us": train_us},
-        "extra": {"separate_path": {"ms_per_step": sep_ms,
+                     "avg_us": train_us, "measured_copy_gbs": copy_gbs,
+                     "frac_of_measured_copy": train_gbs / copy_gbs},
+        "extra": {"device": {"name": props.name, "arch": getattr(props, "gcnArchName", ""),
+                             "compute_units": props.multi_processor_count},
+                  "separate_path": {"ms_per_step": sep_ms,
                                     "value": tiled_per_step / (sep_ms * 1e-3)},
                   "forward_fused": {"kernel": "fir_chain_pair_kernel<8>", "avg_us": fwd_us,
                                     "bytes": fwd_bytes, "gbs": fwd_gbs,

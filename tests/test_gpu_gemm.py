@@ -79,3 +79,29 @@ def test_gemm_full_size_sampled_and_error_report():
     check_close(got32, y32[:, 0], ya32[:, 0], what="f32 4096^3")
     assert np.all(np.isfinite(host(out32)))
     assert np.all(np.isfinite(host(out)))
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f32"])
+def test_gemm_large_ragged_all_layouts_sampled(dtype):
+    # large enough for the 256 x 256 tiles (M N >= 200 of them); M, N and K
+    # all ragged (K not a multiple of the 64-element k-tile); B stored [K][N]
+    # in "nn" / "tn" takes the in-kernel transpose for BF16
+    M, N, K = 3000, 4504, 1000
+    a, b, ab, bb = W.matmul_inputs(M, N, K, seed=77)
+    rng = W.rng_for(78)
+    sel = np.concatenate([rng.choice(M * N, 384, replace=False),
+                          [0, N - 1, (M - 1) * N, M * N - 1, 255 * N + 255, 256 * N + 256]])
+    for name, ta, tb, fa, fb in _layouts(M, N, K):
+        p = W.Problem((M, N), [ta, tb], W.identity_output((M, N)), W.DOT, compute=dtype)
+        if dtype == "bf16":
+            xa, xb = fa(ab), fb(bb)
+            da, db = bf16_dev(xa), bf16_dev(xb)
+        else:
+            xa, xb = fa(a), fb(b)
+            da, db = dev(xa), dev(xb)
+        out = torch.full((M, N), float("nan"), device="cuda")
+        rsm.run(p, [da, db], out)
+        full = host(out)
+        assert np.all(np.isfinite(full)), name
+        y, ya = oracle.run_sample(p, [xa, xb], sel)
+        check_close(full.reshape(-1)[sel], y[:, 0], ya[:, 0], what="%s %s %dx%dx%d" % (dtype, name, M, N, K))
