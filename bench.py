@@ -309,6 +309,36 @@ def extras(args, ts, xs, stages, ch, cv, w2, chain):
     log("fused forward alone %.1f us %.0f GB/s" % (us, b / us / 1e3))
     del xr
 
+    # adjoint of an overlapping horizontal stage (13 taps every 8 columns,
+    # centred origin -6: windows overlap by 5 and wrap at both borders) on the
+    # same 30 frames: the input gradient as a per-element gather plus the
+    # per-repetition weight-gradient kernel, against the generic atomic
+    # scatter-add.  Algorithmic bytes: x and dL/dy read, dL/dx written once.
+    F, H, Wd = xs[0].shape
+    to = W.h_stage(F, H, Wd, taps=13, pave=8, origin=-6)
+    rep_o = (F, H, -(-Wd // 8))
+    po = W.Problem(rep_o, [to], W.identity_output(rep_o), W.WSUM)
+    co = torch.from_numpy(W.normalised_coeffs(W.rng_for(7), 13)).to(dev)
+    gyo = torch.rand(rep_o, device=dev)
+    gco = torch.empty(13, device=dev)
+
+    def overlap_adj(flags):
+        def run():
+            k = state["k"] = state["k"] + 1
+            rsm.run_adjoint(po, xs[k & 1], gyo, gx, gco, co, flags=flags)
+        return run
+
+    us_g = time_fn(overlap_adj(0))
+    us_a = time_fn(overlap_adj(_abi.FORCE_GENERIC), reps=5, warm=1)
+    b = 2 * xs[0].numel() * 4 + gyo.numel() * 4
+    ex["adjoint_overlapping_13tap_step8"] = {
+        "kernels": rsm.plan(po, flags=_abi.PLAN_ADJOINT),
+        "avg_us": us_g, "bytes": b, "gbs": b / us_g / 1e3, "frac": b / us_g / 1e3 / HBM_PEAK_GBS,
+        "generic_atomic_us": us_a, "speedup_vs_generic": us_a / us_g}
+    log("overlapping adjoint: gather %.1f us (%.0f GB/s), generic atomic %.1f us"
+        % (us_g, b / us_g / 1e3, us_a))
+    del gyo
+
     # small plain task: 64x64 -> 16x16 sums
     x0, p0 = W.small_sum()
     xd = torch.from_numpy(x0).to(dev)

@@ -74,6 +74,7 @@ typedef enum {
 #define RSM_ACCUMULATE 0x2u          /* adjoint: add into gx / gc instead of overwrite */
 #define RSM_NO_FUSE 0x4u             /* chains: run stages one by one                  */
 #define RSM_FORCE_GENERIC 0x8u       /* use the generic gather kernel (any tiler)      */
+#define RSM_PLAN_ADJOINT 0x20u       /* rsm_plan: name the adjoint's kernel family      */
 
 /* Repetition space: the Shaped multiplicity of the repeated task. rank 0 = one repetition. */
 typedef struct {
@@ -125,7 +126,11 @@ rsm_status rsm_validate(const rsm_space* rep, const rsm_tiler* in, int32_t n_in,
 /*
  * rsm_plan -- name of the kernel family the planner picks for a task
  * (e.g. "fir_cols_vec4", "filter2d_k5_s2", "pattern_reduce", "gemm_mfma_bf16_nn",
- * "generic").
+ * "generic").  With RSM_PLAN_ADJOINT in flags (n_in = 1): the family
+ * rsm_run_adjoint picks for the task's input gradient ("fir_adjoint",
+ * "fir_adjoint_vec4", "fir_adjoint_overlap_cols", "fir_adjoint_gather" or
+ * "generic_adjoint"), judged
+ * on shapes alone (16-byte aligned buffers assumed).
  * Host only.  Writes a NUL-terminated string of at most len bytes.
  */
 rsm_status rsm_plan(const rsm_space* rep, const rsm_tiler* in, int32_t n_in,
@@ -176,9 +181,12 @@ rsm_status rsm_run_chain(const rsm_stage* stages, int32_t n_stages, const void* 
  * and d_gc (pattern-shaped, WSUM only) are FP32 device buffers, each NULL to
  * skip it.  Without RSM_ACCUMULATE they are overwritten (gx elements no
  * repetition reads become 0); with it the result is added.  The weight
- * gradient is reduced deterministically (fixed-order tree); gx is
- * deterministic except on the generic path for tilers whose reads overlap,
- * which adds with atomics.
+ * gradient is reduced deterministically (fixed-order tree).  gx is
+ * deterministic on the tap-tiler paths: a plain store per element where no
+ * element is read twice, and a gather over the (repetition, tap) pairs that
+ * reach each element, in a fixed order, where 1-D windows overlap or wrap
+ * onto each other; only the generic path for other tilers whose reads
+ * overlap adds with atomics.
  */
 rsm_status rsm_run_adjoint(const rsm_space* rep, const rsm_tiler* in, const void* d_x,
                            const rsm_tiler* out, const void* d_gy, const rsm_task* task,

@@ -23,6 +23,7 @@ CHECK_SINGLE_ASSIGN = 0x1
 ACCUMULATE = 0x2
 NO_FUSE = 0x4
 FORCE_GENERIC = 0x8
+PLAN_ADJOINT = 0x20
 CHECK_INDICES = 0x10
 
 I64x8 = ctypes.c_int64 * MAX_RANK

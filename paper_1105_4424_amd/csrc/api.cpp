@@ -657,8 +657,31 @@ struct AdjPlan {
   bool fir = false;
   bool vec4 = false;
   bool exact = false;
+  bool gather = false;   // windows overlap or wrap: input gradient as a gather
+  bool overlap_cols = false;   // ... along columns, steps <= 16: one fused kernel
   Win3 w{};
 };
+
+// Chunks of 256 repetitions per row for the fused column kernel: enough to
+// own every column (256 p columns each) and to hold every repetition.
+int64_t overlap_chunks(const Win3& w) {
+  const int64_t own = (int64_t(w.A[2]) + 256 * int64_t(w.p[2]) - 1) / (256 * int64_t(w.p[2]));
+  const int64_t reps = (int64_t(w.rep[2]) + 255) / 256;
+  return std::max<int64_t>(std::max(own, reps), 1);
+}
+
+int64_t overlap_items(const Win3& w) { return int64_t(w.A[0]) * w.A[1] * overlap_chunks(w); }
+
+// Input gradient of a 1-D tap tiler as a gather over input elements: the tap
+// axis steps forward (or has one repetition) and no two repetitions share an
+// index along the other axes.
+bool fir_gather_ok(const Win3& w) {
+  for (int d = 0; d < 3; ++d) {
+    if (d == w.ax) continue;
+    if (w.rep[d] > 1 && w.p[d] < 1) return false;
+  }
+  return w.p[w.ax] >= 1 || w.rep[w.ax] == 1;
+}
 
 AdjPlan plan_adjoint(const rsm_space& rep, const rsm_tiler& in, const rsm_tiler& out,
                      const rsm_task& task, uint32_t flags, const void* x, const void* gx) {
@@ -666,11 +689,21 @@ AdjPlan plan_adjoint(const rsm_space& rep, const rsm_tiler& in, const rsm_tiler&
   if (flags & RSM_FORCE_GENERIC) return a;
   Win3 w{};
   if (task.kind == RSM_TASK_WSUM && is_identity_out(rep, out) && canon_win3(rep, in, &w) &&
-      w.ax >= 1 && w.taps <= 16 && outer_axes_inside(w, w.ax) && fir_injective(w)) {
-    a.fir = true;
-    a.w = w;
-    a.exact = fir_exact_cover(w);
-    a.vec4 = fir_vec4(w, x) && fir_vec4(w, gx);
+      w.ax >= 1 && w.taps <= 16 && outer_axes_inside(w, w.ax)) {
+    if (fir_injective(w)) {
+      a.fir = true;
+      a.w = w;
+      a.exact = fir_exact_cover(w);
+      a.vec4 = fir_vec4(w, x) && fir_vec4(w, gx);
+    } else if (fir_gather_ok(w)) {
+      // the weight gradient keeps the per-repetition kernel (it reads x only)
+      a.fir = true;
+      a.gather = true;
+      a.w = w;
+      a.vec4 = fir_vec4(w, x);
+      a.overlap_cols = w.ax == 2 && w.p[2] >= 1 && w.p[2] <= 16 && w.A[2] < (1 << 28) &&
+                       w.rep[2] < (1 << 28) && overlap_items(w) < (int64_t(1) << 31);
+    }
   }
   return a;
 }
@@ -678,6 +711,8 @@ AdjPlan plan_adjoint(const rsm_space& rep, const rsm_tiler& in, const rsm_tiler&
 // Workspace bytes the adjoint of one stage needs.
 size_t adjoint_ws_bytes(const AdjPlan& ap, int64_t n_rep, int64_t n_pat, bool want_gc) {
   if (!want_gc) return 0;
+  if (ap.overlap_cols)
+    return size_t(fir_overlap_cols_grid(uint32_t(overlap_items(ap.w)))) * size_t(ap.w.taps) * sizeof(float);
   if (ap.fir) {
     FirAdjArgs tmp{};
     tmp.n_rep = uint32_t(n_rep);
@@ -705,6 +740,48 @@ rsm_status exec_adjoint(const rsm_space& rep, const rsm_tiler& in, const void* d
     return RSM_OK;
   }
   const int64_t n_arr = prod(in.array_shape, in.array_rank);
+  if (ap.overlap_cols) {
+    const Win3& w = ap.w;
+    FirOverlapArgs o{};
+    o.w = w;
+    o.div_a1 = make_fastdiv(uint32_t(w.A[1]));
+    o.div_a2 = make_fastdiv(uint32_t(w.A[2]));
+    o.div_p = make_fastdiv(uint32_t(w.p[2]));
+    o.n_chunks = int32_t(overlap_chunks(w));
+    o.div_chunks = make_fastdiv(uint32_t(o.n_chunks));
+    o.div_p0 = make_fastdiv(uint32_t(std::max(w.p[0], 1)));
+    o.div_p1 = make_fastdiv(uint32_t(std::max(w.p[1], 1)));
+    o.o_mod = int32_t(floor_mod(w.o[2], w.A[2]));
+    o.n_items = uint32_t(overlap_items(w));
+    o.x = static_cast<const float*>(d_x);
+    o.gy = static_cast<const float*>(d_gy);
+    o.gx = static_cast<float*>(d_gx);
+    o.c = static_cast<const float*>(task.coeffs);
+    o.partial = d_gc ? static_cast<float*>(ws) : nullptr;
+    o.accumulate = accumulate;
+    if ((e = launch_fir_adjoint_overlap_cols(o, st)) != hipSuccess) return hip_fail(e, "fir overlap adjoint");
+    if (d_gc &&
+        (e = launch_reduce_partials(o.partial, fir_overlap_cols_grid(o.n_items), w.taps, w.taps,
+                                    static_cast<float*>(d_gc), accumulate, st)) != hipSuccess)
+      return hip_fail(e, "weight-gradient reduction");
+    return RSM_OK;
+  }
+  if (ap.gather && d_gx) {
+    FirGatherArgs g{};
+    g.w = ap.w;
+    g.div_a2 = make_fastdiv(uint32_t(ap.w.A[2]));
+    g.div_a1 = make_fastdiv(uint32_t(ap.w.A[1]));
+    for (int d = 0; d < 3; ++d) g.div_p[d] = make_fastdiv(uint32_t(std::max(ap.w.p[d], 1)));
+    g.o_mod = int32_t(floor_mod(ap.w.o[ap.w.ax], ap.w.A[ap.w.ax]));
+    g.n_arr = uint32_t(n_arr);
+    g.gy = static_cast<const float*>(d_gy);
+    g.gx = static_cast<float*>(d_gx);
+    g.c = static_cast<const float*>(task.coeffs);
+    g.accumulate = accumulate;
+    if ((e = launch_fir_gx_gather(g, st)) != hipSuccess) return hip_fail(e, "fir gather adjoint");
+    if (!d_gc) return RSM_OK;
+    d_gx = nullptr;   // the per-repetition kernel below forms the weight gradient only
+  }
   if (ap.fir) {
     if (d_gx && !accumulate && !ap.exact) {
       if ((e = launch_zero(d_gx, n_arr * 4, st)) != hipSuccess) return hip_fail(e, "zero gx");
@@ -918,6 +995,19 @@ rsm_status rsm_plan(const rsm_space* rep, const rsm_tiler* in, int32_t n_in, con
                     const rsm_task* task, uint32_t flags, char* name, int32_t len) {
   RSM_GUARD_BEGIN
   Checked c;
+  if (flags & RSM_PLAN_ADJOINT) {
+    if (n_in != 1) return fail(RSM_E_INVALID, "the adjoint takes one input tiler");
+    rsm_status s = check_adjoint(rep, in, out, task, &c);
+    if (s) return s;
+    if (!name || len <= 0) return fail(RSM_E_INVALID, "name buffer is NULL");
+    const AdjPlan ap = plan_adjoint(*rep, *in, *out, *task, flags, nullptr, nullptr);
+    const char* fam = ap.overlap_cols ? "fir_adjoint_overlap_cols"
+                      : ap.gather ? "fir_adjoint_gather"
+                      : ap.fir  ? (ap.vec4 ? "fir_adjoint_vec4" : "fir_adjoint")
+                                : "generic_adjoint";
+    std::snprintf(name, size_t(len), "%s", fam);
+    return RSM_OK;
+  }
   rsm_status s = check_task(rep, in, n_in, out, task, flags & ~RSM_CHECK_SINGLE_ASSIGN, &c);
   if (s) return s;
   if (!name || len <= 0) return fail(RSM_E_INVALID, "name buffer is NULL");

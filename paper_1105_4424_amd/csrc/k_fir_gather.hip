@@ -1,0 +1,284 @@
+// k_fir_gather.hip -- input gradient of a 1-D tap tiler whose windows
+// overlap (pattern longer than the paving step) or wrap onto each other,
+// written as a gather: one thread per input element.
+//
+// The transposed tiler sends c_i gy[r] to element (o + p r + i) mod A along
+// the tap axis (the tiler's index function, origin o, paving p, fitting 1).
+// For an element a the pairs (r, i) that reach it are found by lifting a to
+// the unwrapped positions u = a + m A that lie in [o, o + p (R - 1) + T - 1]
+// (several lifts when the windows cover the axis more than once); for each
+// lift, v = u - o = p r + i with 0 <= i < T, so r runs down from
+// min(R - 1, floor(v / p)) while i = v - p r stays below T.  Every pair is
+// visited exactly once, in a fixed order (lifts ascending, taps ascending),
+// so the result is deterministic without atomics; elements that no window
+// reads get zero.  The two outer axes do not wrap (their windows are single
+// points): an element is read only if (a_d - o_d) is a non-negative multiple
+// of p_d below p_d rep_d.
+#include <hip/hip_runtime.h>
+
+#include "rsm_internal.h"
+
+namespace rsm {
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ int wrap_mod(int v, int n) {
+  const int q = v % n;
+  return q < 0 ? q + n : q;
+}
+
+// Repetition index along a non-tap axis for array index a_d, or -1 if no
+// repetition reads it.
+__device__ __forceinline__ int outer_rep(int a_d, int o, int p, int rep, const FastDiv& dp) {
+  const int v = a_d - o;
+  if (v < 0) return -1;
+  if (rep == 1) return v == 0 ? 0 : -1;
+  const int q = int(fdiv(uint32_t(v), dp));
+  return (q * p == v && q < rep) ? q : -1;
+}
+
+template <int AX>
+__global__ void __launch_bounds__(kBlock) fir_gx_gather_kernel(FirGatherArgs a) {
+  const Win3& w = a.w;
+  const int n_ax = w.A[AX], R = w.rep[AX], p = w.p[AX], T = w.taps;
+  const int span = p * (R - 1) + T;   // unwrapped positions covered, v in [0, span)
+  const uint32_t stride = gridDim.x * kBlock;
+  for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < a.n_arr; e += stride) {
+    const uint32_t row = fdiv(e, a.div_a2);
+    const int ac = int(e - row * uint32_t(w.A[2]));
+    const uint32_t b = fdiv(row, a.div_a1);
+    const int ar = int(row - b * uint32_t(w.A[1]));
+    const int ab = int(b);
+    const int rb = outer_rep(ab, w.o[0], w.p[0], w.rep[0], a.div_p[0]);
+    int ro, at;   // the other outer axis' repetition; the tap-axis index
+    if (AX == 2) {
+      ro = outer_rep(ar, w.o[1], w.p[1], w.rep[1], a.div_p[1]);
+      at = ac;
+    } else {
+      ro = outer_rep(ac, w.o[2], w.p[2], w.rep[2], a.div_p[2]);
+      at = ar;
+    }
+    float acc = 0.0f;
+    if (rb >= 0 && ro >= 0) {
+      // gy offset of repetition r along the tap axis: g0 + r * gs
+      const int g0 = AX == 2 ? (rb * w.rep[1] + ro) * w.rep[2] : rb * w.rep[1] * w.rep[2] + ro;
+      const int gs = AX == 2 ? 1 : w.rep[2];
+      int v = at - a.o_mod;   // first lift: v = (a - o) mod A
+      if (v < 0) v += n_ax;
+      for (; v < span; v += n_ax) {
+        int r = int(fdiv(uint32_t(v), a.div_p[AX]));
+        if (r > R - 1) r = R - 1;
+        for (int i = v - p * r; r >= 0 && i < T; --r, i += p) acc = fmaf(a.c[i], a.gy[g0 + r * gs], acc);
+      }
+    }
+    a.gx[e] = a.accumulate ? a.gx[e] + acc : acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Taps along columns with steps of at most 16: input gradient and weight
+// gradient in one pass.  Work items are (array row, chunk of kRC repetitions
+// along the row).  For each item a workgroup stages the chunk's gy values
+// (with the K - 1 before it) in LDS, then
+//   * writes gx for the positions it owns: v = (a - o) mod A, the first lift
+//     of column a, in [chunk p kRC, (chunk + 1) p kRC); further lifts (rows
+//     that the windows go round more than once) read gy from memory;
+//   * adds gy[r] x[(o + p r + i) mod A] over the chunk's pairs (r, i) into
+//     one partial per lane, each lane keeping one tap i for the whole run,
+//     so the partials reduce in a fixed order.
+// The next item's gy values and x taps are loaded into registers while the
+// current item is computed, so the two memory round trips of an item overlap
+// the previous item's work.  x is read once and gx written once; nothing is
+// atomic.
+// ---------------------------------------------------------------------------
+constexpr int kRC = 256;        // repetitions per chunk
+constexpr int kMaxTaps = 16;
+constexpr int kXR = 16;         // x taps per lane per item: ceil(kRC / (kBlock / taps)) <= 16
+constexpr uint32_t kBufferWord3 = 0x00020000;   // 32-bit data format, raw access
+constexpr uint32_t kOutOfRange = 0x80000000u;   // a read here returns zero
+
+// Work item -> array row, chunk, and the row's repetition offset in gy (-1 if
+// no repetition reads the row).
+__device__ __forceinline__ void overlap_item(const FirOverlapArgs& a, uint32_t item, int& row, int& chunk,
+                                             int& g0) {
+  const Win3& w = a.w;
+  const uint32_t r = fdiv(item, a.div_chunks);
+  row = int(r);
+  chunk = int(item - r * uint32_t(a.n_chunks));
+  const uint32_t b = fdiv(r, a.div_a1);
+  const int ar = int(r - b * uint32_t(w.A[1]));
+  const int rb = outer_rep(int(b), w.o[0], w.p[0], w.rep[0], a.div_p0);
+  const int ro = outer_rep(ar, w.o[1], w.p[1], w.rep[1], a.div_p1);
+  g0 = (rb >= 0 && ro >= 0) ? (rb * w.rep[1] + ro) * w.rep[2] : -1;
+}
+
+// This thread's loads for one item, all issued unconditionally (a position
+// outside the row reads zero through the buffer range check): staged gy
+// values j = tid and tid + kBlock of repetition rs + j, and the x taps of
+// its weight-gradient pairs.
+__device__ __forceinline__ void overlap_fetch(const FirOverlapArgs& a, int row, int chunk, int g0, int K,
+                                              int per, int li, int lr, float& g0v, float& g1v,
+                                              float (&xr)[kXR]) {
+  const Win3& w = a.w;
+  const int R = w.rep[2], A2 = w.A[2];
+  const bool read = g0 >= 0;
+  const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(a.gy) + (read ? g0 : 0), short(0), read ? R * 4 : 0, int(kBufferWord3));
+  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(a.x) + int64_t(row) * A2, short(0), (read && a.partial) ? A2 * 4 : 0,
+      int(kBufferWord3));
+  const int r0 = chunk * kRC, rs = r0 - (K - 1);
+  const int j0 = int(threadIdx.x), j1 = j0 + kBlock;
+  const int q0 = rs + j0, q1 = rs + j1;
+  const uint32_t o0 = (j0 < kRC + K - 1 && q0 >= 0 && q0 < R) ? uint32_t(q0) * 4u : kOutOfRange;
+  const uint32_t o1 = (j1 < kRC + K - 1 && q1 >= 0 && q1 < R) ? uint32_t(q1) * 4u : kOutOfRange;
+  g0v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, o0, 0, 0));
+  g1v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, o1, 0, 0));
+  const int r_end = min(r0 + kRC, R);
+#pragma unroll
+  for (int m = 0; m < kXR; ++m) {
+    const int r = r0 + lr + m * per;
+    // (o + p r + li) mod A2, from the non-negative o mod A2
+    const uint32_t u = uint32_t(a.o_mod + w.p[2] * r + li);
+    const uint32_t e = u - uint32_t(A2) * fdiv(u, a.div_a2);
+    const uint32_t off = (lr < per && r < r_end) ? e * 4u : kOutOfRange;
+    xr[m] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, off, 0, 0));
+  }
+}
+
+template <bool ACC>
+__global__ void __launch_bounds__(kBlock) fir_adjoint_overlap_cols_kernel(FirOverlapArgs a) {
+  const Win3& w = a.w;
+  const int A2 = w.A[2], R = w.rep[2], p = w.p[2], T = w.taps;
+  const int K = (T + p - 1) / p;   // taps of one lift that can meet an element
+  const int span = p * (R - 1) + T;
+  const int W = p * kRC;           // positions owned by one chunk
+  __shared__ float cs[kMaxTaps];
+  __shared__ float gys[kRC + kMaxTaps];
+  __shared__ float red[kBlock];
+  if (threadIdx.x < kMaxTaps) cs[threadIdx.x] = int(threadIdx.x) < T ? a.c[threadIdx.x] : 0.0f;
+  const int per = kBlock / T;      // repetitions per weight-gradient pass
+  const int li = int(threadIdx.x) % T, lr = int(threadIdx.x) / T;
+  const bool gc_lane = lr < per && a.partial != nullptr;
+  float gacc = 0.0f;
+
+  // Per item: stage gy, use the x taps, then issue the next item's loads
+  // into the same registers (a past-the-end item loads nothing: every
+  // offset is out of range) and write this item's gx while they travel.
+  uint32_t item = blockIdx.x;
+  int row, chunk, g0;
+  overlap_item(a, item, row, chunk, g0);
+  float gv0, gv1, xr[kXR];
+  overlap_fetch(a, row, chunk, g0, K, per, li, lr, gv0, gv1, xr);
+  for (; item < a.n_items; item += gridDim.x) {
+    const bool read = g0 >= 0;
+    const int r0 = chunk * kRC, rs = r0 - (K - 1);
+    __syncthreads();               // the previous item's readers of gys are done
+    if (int(threadIdx.x) < kRC + K - 1) gys[threadIdx.x] = gv0;
+    if (int(threadIdx.x) + kBlock < kRC + K - 1) gys[threadIdx.x + kBlock] = gv1;
+    __syncthreads();
+    if (read && gc_lane) {
+      const int r_end = min(r0 + kRC, R);
+#pragma unroll
+      for (int m = 0; m < kXR; ++m) {
+        const int r = r0 + lr + m * per;
+        if (r < r_end) gacc = fmaf(gys[r - rs], xr[m], gacc);
+      }
+    }
+    const int cur_row = row, cur_chunk = chunk, cur_g0 = g0;
+    const uint32_t nxt = item + gridDim.x;
+    g0 = -1;
+    if (nxt < a.n_items) overlap_item(a, nxt, row, chunk, g0);
+    overlap_fetch(a, row, chunk, g0, K, per, li, lr, gv0, gv1, xr);
+    if (a.gx) {
+      float* gxrow = a.gx + int64_t(cur_row) * A2;
+      const int v_end = min((cur_chunk + 1) * W, A2);
+      for (int v = cur_chunk * W + int(threadIdx.x); v < v_end; v += kBlock) {
+        float acc = 0.0f;
+        if (read) {
+          if (v < span) {
+            const int q = int(fdiv(uint32_t(v), a.div_p));
+            int i = v - q * p;
+            for (int k = 0; k < K; ++k, i += p) {
+              const int r = q - k;
+              if (i < T && r >= 0 && r < R) acc = fmaf(cs[i], gys[r - rs], acc);
+            }
+          }
+          // further lifts: with one chunk per row every repetition is staged
+          // in LDS, otherwise gy is read from memory
+          if (a.n_chunks == 1) {
+            for (int u = v + A2; u < span; u += A2) {
+              int r = int(fdiv(uint32_t(u), a.div_p));
+              if (r > R - 1) r = R - 1;
+              for (int i = u - p * r; r >= 0 && i < T; --r, i += p) acc = fmaf(cs[i], gys[r - rs], acc);
+            }
+          } else {
+            for (int u = v + A2; u < span; u += A2) {
+              int r = int(fdiv(uint32_t(u), a.div_p));
+              if (r > R - 1) r = R - 1;
+              for (int i = u - p * r; r >= 0 && i < T; --r, i += p) acc = fmaf(cs[i], a.gy[cur_g0 + r], acc);
+            }
+          }
+        }
+        int e = a.o_mod + v;
+        if (e >= A2) e -= A2;
+        if (ACC) acc += gxrow[e];
+        gxrow[e] = acc;
+      }
+    }
+  }
+  if (a.partial) {
+    red[threadIdx.x] = gc_lane ? gacc : 0.0f;
+    __syncthreads();
+    if (int(threadIdx.x) < T) {
+      float s = 0.0f;
+      for (int l = threadIdx.x; l < per * T; l += T) s += red[l];
+      a.partial[int64_t(blockIdx.x) * T + threadIdx.x] = s;
+    }
+  }
+}
+
+}  // namespace
+
+// One resident wave of workgroups (occupancy x compute units), at most one
+// per item.  The weight-gradient workspace holds one partial row per
+// workgroup, so the planner sizes it with this same function.
+int fir_overlap_cols_grid(uint32_t n_items) {
+  static const int resident = [] {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fir_adjoint_overlap_cols_kernel<false>, kBlock, 0) !=
+            hipSuccess || per_cu < 1) {
+      (void)hipGetLastError();   // a failed query must not surface as a launch error
+      per_cu = 4;
+    }
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+      (void)hipGetLastError();
+      cus = 256;
+    }
+    return per_cu * cus;
+  }();
+  return int(n_items < uint32_t(resident) ? (n_items ? n_items : 1) : uint32_t(resident));
+}
+
+hipError_t launch_fir_adjoint_overlap_cols(const FirOverlapArgs& a, hipStream_t st) {
+  const int grid = fir_overlap_cols_grid(a.n_items);
+  if (a.accumulate)
+    fir_adjoint_overlap_cols_kernel<true><<<grid, kBlock, 0, st>>>(a);
+  else
+    fir_adjoint_overlap_cols_kernel<false><<<grid, kBlock, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fir_gx_gather(const FirGatherArgs& a, hipStream_t st) {
+  const uint32_t need = (a.n_arr + kBlock - 1) / kBlock;
+  const int grid = int(need < 256u * 16u ? (need ? need : 1) : 256u * 16u);
+  if (a.w.ax == 2)
+    fir_gx_gather_kernel<2><<<grid, kBlock, 0, st>>>(a);
+  else
+    fir_gx_gather_kernel<1><<<grid, kBlock, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace rsm

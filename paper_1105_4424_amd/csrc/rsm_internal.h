@@ -126,6 +126,43 @@ struct FirAdjArgs {
   int32_t accumulate;
 };
 
+// Input gradient of a 1-D tap tiler in gather form (overlapping or wrapping
+// windows): one thread per input element.
+struct FirGatherArgs {
+  Win3 w;              // ax = 1 or 2; outer axes do not wrap
+  FastDiv div_a2;      // divide by A[2]
+  FastDiv div_a1;      // divide by A[1]
+  FastDiv div_p[3];    // divide by max(p[d], 1)
+  int32_t o_mod;       // o[ax] mod A[ax], in [0, A[ax])
+  uint32_t n_arr;      // A[0] A[1] A[2]
+  const float* gy;     // [rep[0], rep[1], rep[2]]
+  float* gx;           // [A[0], A[1], A[2]], every element written
+  const float* c;      // [taps]
+  int32_t accumulate;
+};
+
+// Both gradients of a 1-D tap tiler along columns whose windows overlap or
+// wrap (1 <= p[2] <= 16, taps <= 16, A[2] and rep[2] below 2^28): work items
+// (array row, chunk of 256 repetitions).
+struct FirOverlapArgs {
+  Win3 w;              // ax = 2; outer axes do not wrap
+  FastDiv div_a1;      // divide by A[1]
+  FastDiv div_a2;      // divide by A[2]
+  FastDiv div_p;       // divide by p[2]
+  FastDiv div_chunks;  // divide by n_chunks
+  FastDiv div_p0;      // divide by max(p[0], 1)
+  FastDiv div_p1;      // divide by max(p[1], 1)
+  int32_t o_mod;       // o[2] mod A[2]
+  int32_t n_chunks;    // max(ceil(A[2] / (256 p[2])), ceil(rep[2] / 256))
+  uint32_t n_items;    // A[0] A[1] n_chunks
+  const float* x;      // needed when partial is set
+  const float* gy;
+  float* gx;           // nullable; every element written
+  const float* c;
+  float* partial;      // [grid][taps] weight-gradient partials, nullable
+  int32_t accumulate;
+};
+
 struct FirChainAdjArgs {
   Win3 h, v;
   FastDiv div_rc, div_rr;
@@ -274,6 +311,9 @@ hipError_t launch_pattern_reduce(const PatternReduceArgs& a, int max_rank, hipSt
 hipError_t launch_fir(const FirArgs& a, bool vec4, hipStream_t st);
 hipError_t launch_fir_chain(const FirChainArgs& a, bool vec4, hipStream_t st);
 hipError_t launch_fir_adjoint(const FirAdjArgs& a, bool vec4, int* grid_out, hipStream_t st);
+hipError_t launch_fir_gx_gather(const FirGatherArgs& a, hipStream_t st);
+hipError_t launch_fir_adjoint_overlap_cols(const FirOverlapArgs& a, hipStream_t st);
+int fir_overlap_cols_grid(uint32_t n_items);
 int fir_adjoint_grid(const FirAdjArgs& a);
 hipError_t launch_fir_chain_adjoint(const FirChainAdjArgs& a, bool vec4, hipStream_t st);
 int fir_chain_adjoint_grid(const FirChainAdjArgs& a, bool vec4);

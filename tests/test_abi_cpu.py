@@ -129,6 +129,34 @@ def test_planner_routes_workloads_to_their_kernels():
     assert name in ("generic", "pattern_reduce")
 
 
+def test_planner_routes_adjoints_to_their_kernels():
+    A = _abi.PLAN_ADJOINT
+    ts = W.two_stage_filter(frames=2, rows=16, cols=32)
+    assert rsm.plan(ts.h, flags=A) == "fir_adjoint_vec4"        # exact paving, injective
+    assert rsm.plan(ts.v, flags=A) == "fir_adjoint"
+    assert rsm.plan(ts.h, flags=A | _abi.FORCE_GENERIC) == "generic_adjoint"
+    # 13 taps every 8 columns / rows: windows overlap (and wrap at the origin)
+    tw = W.two_stage_filter(frames=1, rows=24, cols=40, taps=13, pave=8, h_origin=-6, v_origin=-6)
+    assert rsm.plan(tw.h, flags=A) == "fir_adjoint_overlap_cols"   # taps along columns
+    assert rsm.plan(tw.v, flags=A) == "fir_adjoint_gather"         # taps along rows
+    # windows that wrap onto each other without overlapping: 8 taps every 8
+    # columns, 6 windows on 40 columns
+    t6 = W.Tiler((2, 4, 40), [0, 0, 0], np.diag([1, 1, 8]), [[0], [0], [1]], (8,))
+    assert rsm.plan(W.Problem((2, 4, 6), [t6], W.identity_output((2, 4, 6)), W.WSUM),
+                    flags=A) == "fir_adjoint_overlap_cols"
+    # column steps above 16: the per-element gather
+    t20 = W.Tiler((2, 4, 40), [0, 0, 0], np.diag([1, 1, 20]), [[0], [0], [1]], (8,))
+    assert rsm.plan(W.Problem((2, 4, 3), [t20], W.identity_output((2, 4, 3)), W.WSUM),
+                    flags=A) == "fir_adjoint_gather"
+    # two repetitions reading the same rows (zero row step): no gather form
+    t0 = W.Tiler((2, 4, 40), [0, 0, 0], np.diag([1, 0, 8]), [[0], [0], [1]], (8,))
+    assert rsm.plan(W.Problem((2, 3, 5), [t0], W.identity_output((2, 3, 5)), W.WSUM),
+                    flags=A) == "generic_adjoint"
+    # 2-D windows: generic
+    p2 = W.filter2d_problem(20, 24, 3, 1)
+    assert rsm.plan(p2, flags=A) == "generic_adjoint"
+
+
 def test_empty_repetition_space_is_a_no_op_plan():
     t = W.Tiler((8,), [0], [[1]], [[1]], (2,))
     assert rsm.plan(W.Problem((0,), [t], W.identity_output((0,)) if False else

@@ -55,7 +55,7 @@ def test_stage_adjoints_two_frames(force_generic):
 
 @pytest.mark.parametrize("taps,pave,ho,vo,rows,cols", [
     (8, 8, -3, -3, 64, 96),      # injective, wrapping: tap kernels
-    (13, 8, -6, 0, 48, 80),      # overlapping reads: generic atomic scatter-add
+    (13, 8, -6, 0, 48, 80),      # overlapping reads: gather-form input gradient
     (5, 7, 0, -2, 31, 47),       # gaps between windows (elements never read get 0)
 ])
 def test_stage_adjoint_variants(taps, pave, ho, vo, rows, cols):
@@ -66,6 +66,95 @@ def test_stage_adjoint_variants(taps, pave, ho, vo, rows, cols):
         x = ts.x if name == "h" else oracle.run(ts.h, [ts.x]).out.astype(np.float32)
         gy = rng.uniform(-1, 1, st.rep_shape).astype(np.float32)
         _adjoint_check(st, x, gy, 0, "variant %s %s" % (name, (taps, pave, ho, vo)))
+
+
+def _random_window(rng):
+    """A 1-D tap tiler on a 3-D array: taps along axis 1 or 2 with any step
+    (overlapping, gapped or wrapping several times round the axis), the other
+    two axes stepped without wrapping."""
+    ax = int(rng.integers(1, 3))
+    A = [int(rng.integers(1, 4)), int(rng.integers(1, 24)), int(rng.integers(1, 40))]
+    T = int(rng.integers(1, 17))
+    rep, o, p = [0, 0, 0], [0, 0, 0], [0, 0, 0]
+    for d in range(3):
+        if d == ax:
+            p[d] = int(rng.integers(1, 9)) if rng.random() < 0.8 else int(rng.integers(9, 21))
+            rep[d] = int(rng.integers(1, 12))
+            o[d] = int(rng.integers(-30, 30))
+        else:
+            p[d] = int(rng.integers(1, 4))
+            rep[d] = int(rng.integers(1, A[d] + 1))
+            while p[d] * (rep[d] - 1) >= A[d]:
+                rep[d] -= 1
+            o[d] = int(rng.integers(0, A[d] - p[d] * (rep[d] - 1)))
+    F = np.zeros((3, 1), np.int64)
+    F[ax, 0] = 1
+    t = W.Tiler(tuple(A), o, np.diag(p).astype(np.int64), F, (T,))
+    c = rng.uniform(-1, 1, T).astype(np.float32)
+    return W.Problem(tuple(rep), [t], W.identity_output(tuple(rep)), W.WSUM, c)
+
+
+def test_gather_adjoint_random_windows():
+    rng = W.rng_for(93)
+    fams = {}
+    for trial in range(80):
+        p = _random_window(rng)
+        fam = rsm.plan(p, flags=_abi.PLAN_ADJOINT)
+        assert fam.startswith("fir_adjoint"), (trial, fam)
+        fams[fam] = fams.get(fam, 0) + 1
+        x = W.random_array(rng, p.inputs[0].array_shape)
+        gy = rng.uniform(-1, 1, p.rep_shape).astype(np.float32)
+        _adjoint_check(p, x, gy, 0, "window %d %s" % (trial, fam))
+    say("families", fams)
+    assert fams.get("fir_adjoint_gather", 0) >= 20 and fams.get("fir_adjoint_overlap_cols", 0) >= 20
+
+
+# long rows: several 256-repetition chunks per row, and windows that go round
+# a short row many times (every column has many lifts; the second chunk of
+# each row owns no column, only repetitions)
+@pytest.mark.parametrize("A,R,pave,taps,origin", [((2, 3, 5000), 700, 7, 13, -6),
+                                                   ((1, 4, 3001), 300, 16, 16, 5),
+                                                   ((3, 2, 50), 300, 3, 13, -7),
+                                                   ((1, 1, 7), 1, 1, 16, -20)])
+def test_overlap_cols_chunks_and_laps(A, R, pave, taps, origin):
+    rng = W.rng_for(95 + R)
+    t = W.Tiler(A, [0, 0, origin], np.diag([1, 1, pave]), [[0], [0], [1]], (taps,))
+    rep = (A[0], A[1], R)
+    c = rng.uniform(-1, 1, taps).astype(np.float32)
+    p = W.Problem(rep, [t], W.identity_output(rep), W.WSUM, c)
+    assert rsm.plan(p, flags=_abi.PLAN_ADJOINT) == "fir_adjoint_overlap_cols"
+    x = W.random_array(rng, A)
+    gy = rng.uniform(-1, 1, rep).astype(np.float32)
+    _adjoint_check(p, x, gy, 0, "overlap cols %s R=%d p=%d T=%d o=%d" % (A, R, pave, taps, origin))
+
+
+@pytest.mark.parametrize("stage", ["h", "v"])
+def test_gather_adjoint_overlapping_full_frames(stage):
+    # 13 taps every 8 columns (rows), centred origin -6: windows overlap by 5
+    # and wrap at both borders; 30 x 1080 x 1920
+    ts = W.two_stage_filter(taps=13, pave=8, h_origin=-6, v_origin=-6)
+    st = ts.h if stage == "h" else ts.v
+    assert rsm.plan(st, flags=_abi.PLAN_ADJOINT) == ("fir_adjoint_overlap_cols" if stage == "h"
+                                                     else "fir_adjoint_gather")
+    x = ts.x if stage == "h" else oracle.run(ts.h, [ts.x]).out.astype(np.float32)
+    gy = W.rng_for(94).uniform(-1, 1, st.rep_shape).astype(np.float32)
+    say("oracle adjoint, overlapping", stage, x.shape)
+    a = oracle.adjoint(st, x, gy)
+    xd, gyd, cd = dev(x), dev(gy), dev(st.coeffs)
+    runs = []
+    for _ in range(2):
+        gx = torch.full(x.shape, float("nan"), device="cuda")
+        gc = torch.full((13,), float("nan"), device="cuda")
+        rsm.run_adjoint(st, xd, gyd, gx, gc, cd)
+        runs.append((gx, gc))
+    check_close(host(runs[0][0]), a.gx, a.gx_abs, what="overlap %s gx" % stage)
+    check_close(host(runs[0][1]), a.gc, a.gc_abs, what="overlap %s gc" % stage)
+    # deterministic: no atomics anywhere on this path
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+    # input gradient alone (no weight gradient) gives the same bits
+    gx1 = torch.full(x.shape, float("nan"), device="cuda")
+    rsm.run_adjoint(st, xd, gyd, gx1, None, cd)
+    assert torch.equal(gx1, runs[0][0])
 
 
 def test_adjoint_random_tilers_generic():
