@@ -752,6 +752,7 @@ rsm_status exec_adjoint(const rsm_space& rep, const rsm_tiler& in, const void* d
     o.div_p0 = make_fastdiv(uint32_t(std::max(w.p[0], 1)));
     o.div_p1 = make_fastdiv(uint32_t(std::max(w.p[1], 1)));
     o.o_mod = int32_t(floor_mod(w.o[2], w.A[2]));
+    o.step_mod = int32_t((int64_t(w.p[2]) * (256 / w.taps)) % w.A[2]);
     o.n_items = uint32_t(overlap_items(w));
     o.x = static_cast<const float*>(d_x);
     o.gy = static_cast<const float*>(d_gy);

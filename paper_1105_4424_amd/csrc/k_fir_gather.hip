@@ -115,8 +115,11 @@ __device__ __forceinline__ void overlap_item(const FirOverlapArgs& a, uint32_t i
 
 // This thread's loads for one item, all issued unconditionally (a position
 // outside the row reads zero through the buffer range check): staged gy
-// values j = tid and tid + kBlock of repetition rs + j, and the x taps of
-// its weight-gradient pairs.
+// values j = tid and tid + kBlock of repetition rs + j, and (GC) the x taps
+// of its weight-gradient pairs.  Pair m of lane (lr, li) is repetition
+// r0 + lr + m per, tap li, at column (o + p r + li) mod A2: the column
+// advances by (p per) mod A2 from one pair to the next.
+template <bool GC>
 __device__ __forceinline__ void overlap_fetch(const FirOverlapArgs& a, int row, int chunk, int g0, int K,
                                               int per, int li, int lr, float& g0v, float& g1v,
                                               float (&xr)[kXR]) {
@@ -125,9 +128,6 @@ __device__ __forceinline__ void overlap_fetch(const FirOverlapArgs& a, int row, 
   const bool read = g0 >= 0;
   const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float*>(a.gy) + (read ? g0 : 0), short(0), read ? R * 4 : 0, int(kBufferWord3));
-  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<float*>(a.x) + int64_t(row) * A2, short(0), (read && a.partial) ? A2 * 4 : 0,
-      int(kBufferWord3));
   const int r0 = chunk * kRC, rs = r0 - (K - 1);
   const int j0 = int(threadIdx.x), j1 = j0 + kBlock;
   const int q0 = rs + j0, q1 = rs + j1;
@@ -135,32 +135,42 @@ __device__ __forceinline__ void overlap_fetch(const FirOverlapArgs& a, int row, 
   const uint32_t o1 = (j1 < kRC + K - 1 && q1 >= 0 && q1 < R) ? uint32_t(q1) * 4u : kOutOfRange;
   g0v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, o0, 0, 0));
   g1v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, o1, 0, 0));
-  const int r_end = min(r0 + kRC, R);
+  if (GC) {
+    const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(a.x) + int64_t(row) * A2, short(0), read ? A2 * 4 : 0, int(kBufferWord3));
+    // pairs of this lane inside the chunk: m < n_m
+    const int left = min(r0 + kRC, R) - r0 - lr;
+    const int n_m = (lr < per && left > 0) ? (left + per - 1) / per : 0;
+    const uint32_t u0 = uint32_t(a.o_mod + w.p[2] * (r0 + lr) + li);
+    uint32_t e = u0 - uint32_t(A2) * fdiv(u0, a.div_a2);
 #pragma unroll
-  for (int m = 0; m < kXR; ++m) {
-    const int r = r0 + lr + m * per;
-    // (o + p r + li) mod A2, from the non-negative o mod A2
-    const uint32_t u = uint32_t(a.o_mod + w.p[2] * r + li);
-    const uint32_t e = u - uint32_t(A2) * fdiv(u, a.div_a2);
-    const uint32_t off = (lr < per && r < r_end) ? e * 4u : kOutOfRange;
-    xr[m] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, off, 0, 0));
+    for (int m = 0; m < kXR; ++m) {
+      xr[m] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, m < n_m ? e * 4u : kOutOfRange,
+                                                                            0, 0));
+      e += uint32_t(a.step_mod);
+      if (e >= uint32_t(A2)) e -= uint32_t(A2);
+    }
   }
 }
 
-template <bool ACC>
+// KS: taps per lift K as a compile-time constant (1..4), or 0 for any K.
+// GC: the weight gradient is wanted (a.partial set).
+template <bool ACC, int KS, bool GC>
 __global__ void __launch_bounds__(kBlock) fir_adjoint_overlap_cols_kernel(FirOverlapArgs a) {
   const Win3& w = a.w;
   const int A2 = w.A[2], R = w.rep[2], p = w.p[2], T = w.taps;
-  const int K = (T + p - 1) / p;   // taps of one lift that can meet an element
+  const int K = KS ? KS : (T + p - 1) / p;   // taps of one lift that can meet an element
   const int span = p * (R - 1) + T;
   const int W = p * kRC;           // positions owned by one chunk
-  __shared__ float cs[kMaxTaps];
+  // coefficients padded with zeros to 2 kMaxTaps: j + k p < K p <= T + p - 1
+  // is always a valid index, so the tap loop needs no bound test
+  __shared__ float cs[2 * kMaxTaps];
   __shared__ float gys[kRC + kMaxTaps];
   __shared__ float red[kBlock];
-  if (threadIdx.x < kMaxTaps) cs[threadIdx.x] = int(threadIdx.x) < T ? a.c[threadIdx.x] : 0.0f;
+  if (threadIdx.x < 2 * kMaxTaps) cs[threadIdx.x] = int(threadIdx.x) < T ? a.c[threadIdx.x] : 0.0f;
   const int per = kBlock / T;      // repetitions per weight-gradient pass
   const int li = int(threadIdx.x) % T, lr = int(threadIdx.x) / T;
-  const bool gc_lane = lr < per && a.partial != nullptr;
+  const bool gc_lane = GC && lr < per;
   float gacc = 0.0f;
 
   // Per item: stage gy, use the x taps, then issue the next item's loads
@@ -170,7 +180,7 @@ __global__ void __launch_bounds__(kBlock) fir_adjoint_overlap_cols_kernel(FirOve
   int row, chunk, g0;
   overlap_item(a, item, row, chunk, g0);
   float gv0, gv1, xr[kXR];
-  overlap_fetch(a, row, chunk, g0, K, per, li, lr, gv0, gv1, xr);
+  overlap_fetch<GC>(a, row, chunk, g0, K, per, li, lr, gv0, gv1, xr);
   for (; item < a.n_items; item += gridDim.x) {
     const bool read = g0 >= 0;
     const int r0 = chunk * kRC, rs = r0 - (K - 1);
@@ -178,7 +188,7 @@ __global__ void __launch_bounds__(kBlock) fir_adjoint_overlap_cols_kernel(FirOve
     if (int(threadIdx.x) < kRC + K - 1) gys[threadIdx.x] = gv0;
     if (int(threadIdx.x) + kBlock < kRC + K - 1) gys[threadIdx.x + kBlock] = gv1;
     __syncthreads();
-    if (read && gc_lane) {
+    if (GC && read && gc_lane) {
       const int r_end = min(r0 + kRC, R);
 #pragma unroll
       for (int m = 0; m < kXR; ++m) {
@@ -190,21 +200,25 @@ __global__ void __launch_bounds__(kBlock) fir_adjoint_overlap_cols_kernel(FirOve
     const uint32_t nxt = item + gridDim.x;
     g0 = -1;
     if (nxt < a.n_items) overlap_item(a, nxt, row, chunk, g0);
-    overlap_fetch(a, row, chunk, g0, K, per, li, lr, gv0, gv1, xr);
+    overlap_fetch<GC>(a, row, chunk, g0, K, per, li, lr, gv0, gv1, xr);
     if (a.gx) {
       float* gxrow = a.gx + int64_t(cur_row) * A2;
       const int v_end = min((cur_chunk + 1) * W, A2);
       for (int v = cur_chunk * W + int(threadIdx.x); v < v_end; v += kBlock) {
         float acc = 0.0f;
-        if (read) {
-          if (v < span) {
-            const int q = int(fdiv(uint32_t(v), a.div_p));
-            int i = v - q * p;
-            for (int k = 0; k < K; ++k, i += p) {
-              const int r = q - k;
-              if (i < T && r >= 0 && r < R) acc = fmaf(cs[i], gys[r - rs], acc);
-            }
+        // first lift: r = q - k, i = j + k p.  q - k - rs lies in
+        // [0, kRC + K - 1) for every owned v, and the staged gy is zero for
+        // r outside [0, R) and in rows no repetition reads
+        if (v < span) {
+          const int q = int(fdiv(uint32_t(v), a.div_p));
+          const int j = v - q * p;
+#pragma unroll
+          for (int k = 0; k < (KS ? KS : kMaxTaps); ++k) {
+            if (!KS && k >= K) break;
+            acc = fmaf(cs[j + k * p], gys[q - k - rs], acc);
           }
+        }
+        if (read) {
           // further lifts: with one chunk per row every repetition is staged
           // in LDS, otherwise gy is read from memory
           if (a.n_chunks == 1) {
@@ -228,7 +242,7 @@ __global__ void __launch_bounds__(kBlock) fir_adjoint_overlap_cols_kernel(FirOve
       }
     }
   }
-  if (a.partial) {
+  if (GC) {
     red[threadIdx.x] = gc_lane ? gacc : 0.0f;
     __syncthreads();
     if (int(threadIdx.x) < T) {
@@ -244,10 +258,27 @@ __global__ void __launch_bounds__(kBlock) fir_adjoint_overlap_cols_kernel(FirOve
 // One resident wave of workgroups (occupancy x compute units), at most one
 // per item.  The weight-gradient workspace holds one partial row per
 // workgroup, so the planner sizes it with this same function.
+namespace {
+template <bool GC>
+void launch_overlap(const FirOverlapArgs& a, int grid, int K, hipStream_t st) {
+  if (a.accumulate) {
+    fir_adjoint_overlap_cols_kernel<true, 0, GC><<<grid, kBlock, 0, st>>>(a);
+    return;
+  }
+  switch (K) {
+    case 1: fir_adjoint_overlap_cols_kernel<false, 1, GC><<<grid, kBlock, 0, st>>>(a); break;
+    case 2: fir_adjoint_overlap_cols_kernel<false, 2, GC><<<grid, kBlock, 0, st>>>(a); break;
+    case 3: fir_adjoint_overlap_cols_kernel<false, 3, GC><<<grid, kBlock, 0, st>>>(a); break;
+    case 4: fir_adjoint_overlap_cols_kernel<false, 4, GC><<<grid, kBlock, 0, st>>>(a); break;
+    default: fir_adjoint_overlap_cols_kernel<false, 0, GC><<<grid, kBlock, 0, st>>>(a); break;
+  }
+}
+}  // namespace
+
 int fir_overlap_cols_grid(uint32_t n_items) {
   static const int resident = [] {
     int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fir_adjoint_overlap_cols_kernel<false>, kBlock, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fir_adjoint_overlap_cols_kernel<false, 0, true>, kBlock, 0) !=
             hipSuccess || per_cu < 1) {
       (void)hipGetLastError();   // a failed query must not surface as a launch error
       per_cu = 4;
@@ -264,10 +295,11 @@ int fir_overlap_cols_grid(uint32_t n_items) {
 
 hipError_t launch_fir_adjoint_overlap_cols(const FirOverlapArgs& a, hipStream_t st) {
   const int grid = fir_overlap_cols_grid(a.n_items);
-  if (a.accumulate)
-    fir_adjoint_overlap_cols_kernel<true><<<grid, kBlock, 0, st>>>(a);
+  const int K = (a.w.taps + a.w.p[2] - 1) / a.w.p[2];
+  if (a.partial)
+    launch_overlap<true>(a, grid, K, st);
   else
-    fir_adjoint_overlap_cols_kernel<false><<<grid, kBlock, 0, st>>>(a);
+    launch_overlap<false>(a, grid, K, st);
   return hipGetLastError();
 }
 

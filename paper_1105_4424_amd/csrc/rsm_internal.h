@@ -153,6 +153,7 @@ struct FirOverlapArgs {
   FastDiv div_p0;      // divide by max(p[0], 1)
   FastDiv div_p1;      // divide by max(p[1], 1)
   int32_t o_mod;       // o[2] mod A[2]
+  int32_t step_mod;    // (p[2] (256 / taps)) mod A[2]: column step between a lane's pairs
   int32_t n_chunks;    // max(ceil(A[2] / (256 p[2])), ceil(rep[2] / 256))
   uint32_t n_items;    // A[0] A[1] n_chunks
   const float* x;      // needed when partial is set
