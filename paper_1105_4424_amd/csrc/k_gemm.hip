@@ -3,9 +3,12 @@
 // C[m, n] = sum_k A(m, k) B(k, n), FP32 accumulation on the matrix cores:
 //   * BF16 operands: v_mfma_f32_32x32x16_bf16 (products exact in FP32)
 //   * FP32 operands: v_mfma_f32_32x32x2_f32
-// The kernel wants both operands with k contiguous ("A[m][k]", "Bt[n][k]").
-// An operand whose tiler walks k along a strided axis is first transposed
-// into the library workspace by an LDS-tiled transpose kernel.
+// The kernels want both operands with k contiguous ("A[m][k]", "Bt[n][k]"),
+// except that the large-tile BF16 kernel also takes B stored [K][N] as it is
+// and transposes its fragments on the way out of LDS (gfx950's
+// ds_read_b64_tr_b16).  Any other operand whose tiler walks k along a
+// strided axis is first transposed into the library workspace by an
+// LDS-tiled transpose kernel.
 //
 // Tiling: 128 x 128 outputs per workgroup of 4 waves (2 x 2), 64 x 64 per
 // wave as 2 x 2 MFMA tiles of 32 x 32; the k-loop stages 128-byte rows of
@@ -202,47 +205,92 @@ constexpr uint32_t kOutOfRange = 0x80000000u;
 
 struct BigTile {
   __amdgpu_buffer_rsrc_t ra, rb;
-  uint32_t va, vb;       // thread's byte offset within a 32-row block
-  uint32_t sa, sb;       // bytes between consecutive 32-row blocks
-  uint32_t a0, b0;       // byte offset of the tile's first row
+  uint32_t va, vb;       // thread's byte offset within a 32-row block (B [K][N]: within an 8-row block)
+  uint32_t sa, sb;       // bytes between consecutive 32-row blocks (B [K][N]: 8-row blocks)
+  uint32_t a0, b0;       // byte offset of the tile's first row (B [K][N]: first column)
   uint32_t kbytes_thr;   // thread's k offset in bytes
   uint32_t kbytes;       // K in bytes
+  uint32_t b_krow;       // B [K][N]: bytes between k rows
+  uint32_t b_rr;         // B [K][N]: thread's row within an 8-row block
+  uint32_t K;            // k extent in elements
 };
+
+// B stored [K][N] (BF16): a k-tile of B is 64 k rows x 256 columns, kept in
+// LDS with that orientation at a row pitch of kPitchBN bytes (576 = 512 +
+// 64: the four rows read by one 16-lane group of a transposing read start
+// 64 bytes apart in the banks, and the two groups of a half-wave 32 bytes
+// apart, so a half-wave touches every bank once).  MFMA B fragments (8
+// consecutive k of one column per lane) come from two ds_read_b64_tr_b16:
+// in each 16-lane group, lane L reads 4 columns at row kb + L / 4, column
+// nb + 4 (L % 4), and lane i receives the 4 rows of column nb + i.
+constexpr int kPitchBN = 576;
+static_assert(64 * kPitchBN == kBig * kPitch, "B [K][N] tile must fill the B half of a k-tile buffer");
+
+typedef short short4_t __attribute__((ext_vector_type(4)));
 
 // Loads staging registers j in [J0, J0 + NJ) of both operands (rows
 // (t >> 3) + 32 j of the tile) for the k-tile at byte offset k0_bytes.
-template <int J0, int NJ>
+template <int J0, int NJ, bool BN>
 __device__ __forceinline__ void big_load(const BigTile& b, uint32_t k0_bytes, uint4 (&r)[16]) {
   const bool ok = k0_bytes + b.kbytes_thr < b.kbytes;
   const uint32_t va = ok ? b.va : kOutOfRange;
   const uint32_t vb = ok ? b.vb : kOutOfRange;
+  const uint32_t k0 = k0_bytes / 2;   // B [K][N] is BF16
 #pragma unroll
   for (int j = J0; j < J0 + NJ; ++j) {
     r[j] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
                                          b.ra, va, b.a0 + j * b.sa + k0_bytes, 0));
-    r[8 + j] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
-                                             b.rb, vb, b.b0 + j * b.sb + k0_bytes, 0));
+    if (BN) {
+      // k row k0 + rr + 8 j of columns n0 + 8 (t % 32) ..; rows past K read zero
+      const uint32_t vbj = k0 + b.b_rr + 8u * uint32_t(j) < b.K ? b.vb : kOutOfRange;
+      r[8 + j] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                               b.rb, vbj, b.b0 + k0 * b.b_krow + j * b.sb, 0));
+    } else {
+      r[8 + j] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                               b.rb, vb, b.b0 + j * b.sb + k0_bytes, 0));
+    }
   }
 }
 
-template <int J0, int NJ>
+template <int J0, int NJ, bool BN>
 __device__ __forceinline__ void big_store(unsigned char* buf, int t, const uint4 (&r)[16]) {
   constexpr int kOp = kBig * kPitch;
 #pragma unroll
   for (int j = J0; j < J0 + NJ; ++j) {
     const int off = ((t >> 3) + 32 * j) * kPitch + (t & 7) * 16;
     *reinterpret_cast<uint4*>(buf + off) = r[j];
-    *reinterpret_cast<uint4*>(buf + kOp + off) = r[8 + j];
+    const int off_b = BN ? ((t >> 5) + 8 * j) * kPitchBN + (t & 31) * 16 : off;
+    *reinterpret_cast<uint4*>(buf + kOp + off_b) = r[8 + j];
   }
 }
 
-__device__ __forceinline__ void big_frags(const unsigned char* la, int wm, int wn, int li, int off,
-                                          uint4 (&fa)[4], uint4 (&fb)[4]) {
+// Fragments of k-group g (16 k values): A rows (and B rows when B is stored
+// Bt[n][k]) by 16-byte reads; B stored [K][N] by pairs of transposing reads
+// from lane offset bfo (rows 8 lh + L / 4, columns wn + 16 ((lane / 16) % 2)
+// + 4 (L % 4)).
+template <bool BN>
+__device__ __forceinline__ void big_frags(const unsigned char* la, int wm, int wn, int li, int lh, int bfo,
+                                          int g, uint4 (&fa)[4], uint4 (&fb)[4]) {
   constexpr int kOp = kBig * kPitch;
+  const int off = (2 * g + lh) * 16;
 #pragma unroll
   for (int i = 0; i < 4; ++i) fa[i] = *reinterpret_cast<const uint4*>(la + (wm + 32 * i + li) * kPitch + off);
+  if (BN) {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) fb[j] = *reinterpret_cast<const uint4*>(la + kOp + (wn + 32 * j + li) * kPitch + off);
+    for (int j = 0; j < 4; ++j) {
+      const unsigned char* q = la + kOp + bfo + 16 * g * kPitchBN + 64 * j;
+      const short4_t lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+          (__attribute__((address_space(3))) short4_t*)(q));
+      const short4_t hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+          (__attribute__((address_space(3))) short4_t*)(q + 4 * kPitchBN));
+      const uint2 l2 = __builtin_bit_cast(uint2, lo), h2 = __builtin_bit_cast(uint2, hi);
+      fb[j] = make_uint4(l2.x, l2.y, h2.x, h2.y);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      fb[j] = *reinterpret_cast<const uint4*>(la + kOp + (wn + 32 * j + li) * kPitch + off);
+  }
 }
 
 // MFMAs of one LDS k-tile.  With `refill` set, the staged tile is written
@@ -254,38 +302,48 @@ __device__ __forceinline__ void big_frags(const unsigned char* la, int wm, int w
 // group G + 1's fragments, a quarter of the refill (LDS writes of staged
 // data) and the reload of that quarter slotted between them, one memory
 // instruction after each MFMA.
-template <typename T, int G>
+template <typename T, int G, bool BN>
 __device__ __forceinline__ void big_group(const unsigned char* la, unsigned char* refill, uint32_t k_next,
                                           const BigTile& bt, int t, uint4 (&stage)[16], int wm, int wn,
-                                          int li, int lh, uint4 (&fa)[2][4], uint4 (&fb)[2][4],
+                                          int li, int lh, int bfo, uint4 (&fa)[2][4], uint4 (&fb)[2][4],
                                           floatx16 (&acc)[4][4]) {
   constexpr int c = G & 1;
-  if (G < 3) big_frags(la, wm, wn, li, (2 * (G + 1) + lh) * 16, fa[c ^ 1], fb[c ^ 1]);
+  constexpr int kReads = BN ? 12 : 8;   // LDS read instructions per fragment set
+  if (G < 3) big_frags<BN>(la, wm, wn, li, lh, bfo, G + 1, fa[c ^ 1], fb[c ^ 1]);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<T>::step(fa[c][i], fb[c][j], acc[i][j]);
-  big_store<2 * G, 2>(refill, t, stage);
-  big_load<2 * G, 2>(bt, k_next, stage);
+  big_store<2 * G, 2, BN>(refill, t, stage);
+  big_load<2 * G, 2, BN>(bt, k_next, stage);
   // instruction classes: 0x008 MFMA, 0x020 VMEM read, 0x100 DS read, 0x200 DS write
   if (G < 3) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < kReads; ++k) {
       __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
     }
   }
+  if (BN && G < 3) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
-    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-  }
+    for (int k = 0; k < 4; ++k) {
+      __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    }
+  } else {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
-    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    for (int k = 0; k < 4; ++k) {
+      __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, G < 3 ? 0 : 8, 0);
   }
-  __builtin_amdgcn_sched_group_barrier(0x008, G < 3 ? 0 : 8, 0);
   __builtin_amdgcn_sched_barrier(0);
 }
 
@@ -293,19 +351,20 @@ __device__ __forceinline__ void big_group(const unsigned char* la, unsigned char
 // quarter per k-group and each quarter of the staging set is reloaded from k
 // byte offset `k_next` (K bytes once no k-tile is left: all out of range,
 // and the writes then go to a buffer that is not read again).
-template <typename T>
+template <typename T, bool BN>
 __device__ __forceinline__ void big_compute(const unsigned char* la, unsigned char* refill, uint32_t k_next,
                                             const BigTile& bt, int t, uint4 (&stage)[16], int wm, int wn,
-                                            int li, int lh, floatx16 (&acc)[4][4]) {
+                                            int li, int lh, int bfo, floatx16 (&acc)[4][4]) {
   uint4 fa[2][4], fb[2][4];
-  big_frags(la, wm, wn, li, lh * 16, fa[0], fb[0]);
-  big_group<T, 0>(la, refill, k_next, bt, t, stage, wm, wn, li, lh, fa, fb, acc);
-  big_group<T, 1>(la, refill, k_next, bt, t, stage, wm, wn, li, lh, fa, fb, acc);
-  big_group<T, 2>(la, refill, k_next, bt, t, stage, wm, wn, li, lh, fa, fb, acc);
-  big_group<T, 3>(la, refill, k_next, bt, t, stage, wm, wn, li, lh, fa, fb, acc);
+  big_frags<BN>(la, wm, wn, li, lh, bfo, 0, fa[0], fb[0]);
+  big_group<T, 0, BN>(la, refill, k_next, bt, t, stage, wm, wn, li, lh, bfo, fa, fb, acc);
+  big_group<T, 1, BN>(la, refill, k_next, bt, t, stage, wm, wn, li, lh, bfo, fa, fb, acc);
+  big_group<T, 2, BN>(la, refill, k_next, bt, t, stage, wm, wn, li, lh, bfo, fa, fb, acc);
+  big_group<T, 3, BN>(la, refill, k_next, bt, t, stage, wm, wn, li, lh, bfo, fa, fb, acc);
 }
 
-template <typename T>
+// BN: B is stored [K][N] (p.ldb = elements between k rows, BF16 only).
+template <typename T, bool BN>
 __global__ void __launch_bounds__(kThreads, 1) gemm_tn_big_kernel(TnArgs p) {
   extern __shared__ __attribute__((aligned(16))) unsigned char dyn[];
   constexpr int kBuf = 2 * kBig * kPitch;   // one k-tile: A rows then B rows
@@ -319,18 +378,33 @@ __global__ void __launch_bounds__(kThreads, 1) gemm_tn_big_kernel(TnArgs p) {
   const int m0 = tm * kBig, n0 = tn * kBig;
   constexpr uint32_t S = sizeof(T);
   const uint32_t a_span = uint32_t((int64_t(p.M - 1) * p.lda + p.K) * S);
-  const uint32_t b_span = uint32_t((int64_t(p.N - 1) * p.ldb + p.K) * S);
+  const uint32_t b_span = BN ? uint32_t((int64_t(p.K - 1) * p.ldb + p.N) * S)
+                             : uint32_t((int64_t(p.N - 1) * p.ldb + p.K) * S);
   BigTile bt;
   bt.ra = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p.a), short(0), int(a_span), int(kBufferWord3));
   bt.rb = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p.b), short(0), int(b_span), int(kBufferWord3));
   bt.kbytes_thr = uint32_t(t & 7) * 16u;
   bt.va = uint32_t(t >> 3) * uint32_t(p.lda) * S + bt.kbytes_thr;
-  bt.vb = uint32_t(t >> 3) * uint32_t(p.ldb) * S + bt.kbytes_thr;
   bt.sa = 32u * uint32_t(p.lda) * S;
-  bt.sb = 32u * uint32_t(p.ldb) * S;
   bt.a0 = uint32_t(m0) * uint32_t(p.lda) * S;
-  bt.b0 = uint32_t(n0) * uint32_t(p.ldb) * S;
   bt.kbytes = uint32_t(p.K) * S;
+  bt.K = uint32_t(p.K);
+  if (BN) {
+    bt.b_rr = uint32_t(t >> 5);
+    bt.b_krow = uint32_t(p.ldb) * S;
+    bt.vb = bt.b_rr * bt.b_krow + uint32_t(t & 31) * 16u;
+    bt.sb = 8u * bt.b_krow;
+    bt.b0 = uint32_t(n0) * S;
+  } else {
+    bt.b_rr = 0;
+    bt.b_krow = 0;
+    bt.vb = uint32_t(t >> 3) * uint32_t(p.ldb) * S + bt.kbytes_thr;
+    bt.sb = 32u * uint32_t(p.ldb) * S;
+    bt.b0 = uint32_t(n0) * uint32_t(p.ldb) * S;
+  }
+  // transposing-read lane offset within the B half of a k-tile buffer
+  const int L = lane & 15;
+  const int bfo = (8 * lh + (L >> 2)) * kPitchBN + (wn + 16 * ((lane >> 4) & 1) + 4 * (L & 3)) * 2;
 
   floatx16 acc[4][4];
 #pragma unroll
@@ -342,15 +416,15 @@ __global__ void __launch_bounds__(kThreads, 1) gemm_tn_big_kernel(TnArgs p) {
 
   const int n_k = int((bt.kbytes + kRowBytes - 1) / kRowBytes);
   uint4 stage[16];
-  big_load<0, 8>(bt, 0, stage);
-  big_store<0, 8>(dyn, t, stage);
-  if (n_k > 1) big_load<0, 8>(bt, kRowBytes, stage);
+  big_load<0, 8, BN>(bt, 0, stage);
+  big_store<0, 8, BN>(dyn, t, stage);
+  if (n_k > 1) big_load<0, 8, BN>(bt, kRowBytes, stage);
   __syncthreads();
   for (int kt = 0; kt < n_k; ++kt) {
     const unsigned char* la = dyn + (kt & 1) * kBuf;
     unsigned char* refill = dyn + ((kt + 1) & 1) * kBuf;
-    big_compute<T>(la, refill, kt + 2 < n_k ? uint32_t(kt + 2) * kRowBytes : bt.kbytes, bt, t, stage, wm,
-                   wn, li, lh, acc);
+    big_compute<T, BN>(la, refill, kt + 2 < n_k ? uint32_t(kt + 2) * kRowBytes : bt.kbytes, bt, t, stage, wm,
+                       wn, li, lh, bfo, acc);
     __syncthreads();
   }
 
@@ -463,8 +537,16 @@ hipError_t launch_gemm(const GemmArgs& g, int compute, hipStream_t st) {
   (void)hipGetLastError();  // clear a stale error left by an unrelated earlier call
   const size_t es = compute == RSM_BF16 ? 2 : 4;
   const bool ta = g.a_sk != 1, tb = g.b_sk != 1;
+  // large tiles once the output has at least 200 tiles of 256 x 256
+  const bool big_shape = int64_t(g.M) * g.N >= int64_t(256) * 256 * 200;
+  // BF16 B stored [K][N] with 16-byte aligned rows goes to the large-tile
+  // kernel as it is (transposing LDS reads), without a transposed copy; its
+  // 32-bit buffer offsets reach (K + 64) k rows plus N columns
+  const bool bn = compute == RSM_BF16 && tb && g.b_sn == 1 && big_shape &&
+                  !(reinterpret_cast<uintptr_t>(g.b) & 15) && !((g.b_sk * 2) & 15) &&
+                  (int64_t(g.K + 64) * g.b_sk + g.N) * 2 + 4096 < (int64_t(1) << 31);
   const size_t a_bytes = ta ? ((size_t(g.M) * g.K * es + 255) & ~size_t(255)) : 0;
-  const size_t b_bytes = tb ? ((size_t(g.N) * g.K * es + 255) & ~size_t(255)) : 0;
+  const size_t b_bytes = tb && !bn ? ((size_t(g.N) * g.K * es + 255) & ~size_t(255)) : 0;
   char* ws = nullptr;
   if (a_bytes + b_bytes) {
     rsm_status s;
@@ -491,7 +573,9 @@ hipError_t launch_gemm(const GemmArgs& g, int compute, hipStream_t st) {
     p.a = ws;
     p.lda = g.K;
   }
-  if (tb) {  // B stored [K][N]: make Bt[n][k]
+  if (bn) {
+    p.ldb = g.b_sk;   // elements between k rows of B [K][N]
+  } else if (tb) {  // B stored [K][N]: make Bt[n][k]
     e = es == 2 ? transpose<uint16_t>(g.b, ws + a_bytes, g.K, g.N, st)
                 : transpose<float>(g.b, ws + a_bytes, g.K, g.N, st);
     if (e != hipSuccess) {
@@ -508,27 +592,33 @@ hipError_t launch_gemm(const GemmArgs& g, int compute, hipStream_t st) {
                         ", ldb " + std::to_string(p.ldb) + ")");
     return hipErrorInvalidValue;
   }
-  // large tiles once the output has at least one 256 x 256 tile per CU
-  // (its buffer loads use 32-bit offsets, which must stay below 2 GiB up to
-  // the last row of the last, padded 256-row block plus K)
+  // large tiles: their buffer loads use 32-bit offsets, which must stay
+  // below 2 GiB up to the last row of the last, padded 256-row block plus K
   const int64_t a_span = (int64_t(g.M + kBig) * p.lda + g.K) * int64_t(es);
-  const int64_t b_span = (int64_t(g.N + kBig) * p.ldb + g.K) * int64_t(es);
-  const bool big = int64_t(g.M) * g.N >= int64_t(256) * 256 * 200 && a_span < (int64_t(1) << 31) &&
-                   b_span < (int64_t(1) << 31);
+  const int64_t b_span = bn ? 0 : (int64_t(g.N + kBig) * p.ldb + g.K) * int64_t(es);
+  const bool big = big_shape && a_span < (int64_t(1) << 31) && b_span < (int64_t(1) << 31);
+  if (bn && !big) {
+    fail(RSM_E_HIP, "gemm: internal: [K][N] operand planned for the large-tile kernel");
+    return hipErrorInvalidValue;
+  }
   const int tile = big ? kBig : kBM;
   p.tiles_m = (g.M + tile - 1) / tile;
   p.tiles_n = (g.N + tile - 1) / tile;
   const int grid = p.tiles_m * p.tiles_n;
   const size_t lds_big = size_t(2) * 2 * kBig * kPitch;
   if (big) {
-    if (compute == RSM_BF16) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_tn_big_kernel<uint16_t>),
+    if (compute == RSM_BF16 && bn) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_tn_big_kernel<uint16_t, true>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_big));
-      gemm_tn_big_kernel<uint16_t><<<grid, kThreads, lds_big, st>>>(p);
+      gemm_tn_big_kernel<uint16_t, true><<<grid, kThreads, lds_big, st>>>(p);
+    } else if (compute == RSM_BF16) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_tn_big_kernel<uint16_t, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_big));
+      gemm_tn_big_kernel<uint16_t, false><<<grid, kThreads, lds_big, st>>>(p);
     } else {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_tn_big_kernel<float>),
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_tn_big_kernel<float, false>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_big));
-      gemm_tn_big_kernel<float><<<grid, kThreads, lds_big, st>>>(p);
+      gemm_tn_big_kernel<float, false><<<grid, kThreads, lds_big, st>>>(p);
     }
   } else if (compute == RSM_BF16) {
     gemm_tn_kernel<uint16_t><<<grid, kThreads, 0, st>>>(p);

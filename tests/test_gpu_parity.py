@@ -146,6 +146,66 @@ def test_sum_wsum_random_tilers(kind, force_generic):
         check_close(host(out), r.out, r.abs_sum, what="trial %d" % trial)
 
 
+def _scattered_output(rng, rep):
+    """A single-assignment output tiler that is not the identity: each
+    repetition axis goes to a different array axis (a random permutation),
+    with a random stride s >= 1 and direction and a random origin, on an
+    array s times longer along that axis (modular), so the strided writes
+    are distinct and the elements between them are never written."""
+    d = len(rep)
+    perm = rng.permutation(d)
+    stride = rng.integers(1, 4, d)
+    sign = rng.choice([-1, 1], d)
+    shape = tuple(int(stride[k] * rep[perm[k]]) for k in range(d))
+    P = np.zeros((d, d), np.int64)
+    for k in range(d):
+        P[k, perm[k]] = sign[k] * stride[k]
+    origin = [int(rng.integers(-20, 20)) for _ in range(d)]
+    return W.Tiler(shape, origin, P, np.zeros((d, 0), np.int64), ())
+
+
+@pytest.mark.parametrize("kind", [W.SUM, W.WSUM])
+def test_sum_wsum_scattered_outputs(kind):
+    # reductions written through permuted, strided, reversed output tilers:
+    # covered elements match the oracle, the others keep their prior value
+    rng = W.rng_for(57 + kind)
+    for trial in range(30):
+        rep = _rep(rng, lo=1, side=6)
+        t = W.random_tiler(rng, len(rep), max_side=9, max_origin=30, max_pattern_side=5)
+        out_t = _scattered_output(rng, rep)
+        c = rng.uniform(-1, 1, t.pattern_shape).astype(np.float32)
+        p = W.Problem(rep, [t], out_t, kind, c if kind == W.WSUM else None)
+        x = W.random_array(rng, t.array_shape)
+        prior = np.full(out_t.array_shape, -7.0, np.float32)
+        out = dev(prior)
+        rsm.run(p, [dev(x)], out, coeffs=dev(c) if kind == W.WSUM else None)
+        r = oracle.run(p, [x], prior=prior)
+        assert np.all(r.hits <= 1)
+        got = host(out)
+        cov = r.hits == 1
+        assert np.all(got[~cov] == -7.0), trial
+        check_close(got[cov], r.out[cov], r.abs_sum[cov], what="trial %d" % trial)
+
+
+def test_adjoint_scattered_outputs():
+    # the adjoint reads dL/dy through the same non-identity output tiler
+    rng = W.rng_for(59)
+    for trial in range(20):
+        rep = _rep(rng, lo=1, side=6)
+        t = W.random_tiler(rng, len(rep), max_side=9, max_origin=30, max_pattern_side=5)
+        out_t = _scattered_output(rng, rep)
+        c = rng.uniform(-1, 1, t.pattern_shape).astype(np.float32)
+        p = W.Problem(rep, [t], out_t, W.WSUM, c)
+        x = W.random_array(rng, t.array_shape)
+        gy = rng.uniform(-1, 1, out_t.array_shape).astype(np.float32)
+        a = oracle.adjoint(p, x, gy)
+        gx = torch.full(t.array_shape, float("nan"), device="cuda")
+        gc = torch.full(t.pattern_shape, float("nan"), device="cuda")
+        rsm.run_adjoint(p, dev(x), dev(gy), gx, gc, dev(c))
+        check_close(host(gx), a.gx, a.gx_abs, what="trial %d gx" % trial)
+        check_close(host(gc), a.gc, a.gc_abs, what="trial %d gc" % trial)
+
+
 def test_dot_random_tilers_f32_bf16_f64():
     rng = W.rng_for(61)
     for trial in range(30):
