@@ -165,8 +165,11 @@ rsm_status rsm_run(const rsm_space* rep, const rsm_tiler* in, const void* const*
  * pointers for the intermediate arrays.  When the planner can fuse two
  * consecutive weighted-sum stages (1-D patterns along different axes, identity
  * output tilers) and d_mid is NULL or d_mid[k] is NULL, the intermediate is
- * never written to memory; otherwise every d_mid[k] must be given and is
- * written.  RSM_NO_FUSE forces stage-by-stage execution.
+ * never written to memory.  Otherwise the stages run one by one: into the
+ * given d_mid[k] (written; elements a stage's output tiler does not cover
+ * keep their contents), or, when d_mid or one of its entries is NULL, into
+ * intermediate arrays in the library's workspace, zero-filled first.
+ * RSM_NO_FUSE forces stage-by-stage execution.
  */
 rsm_status rsm_run_chain(const rsm_stage* stages, int32_t n_stages, const void* d_in,
                          void* const* d_mid, void* d_out, uint32_t flags, void* hip_stream);
@@ -195,10 +198,13 @@ rsm_status rsm_run_adjoint(const rsm_space* rep, const rsm_tiler* in, const void
 /*
  * rsm_run_chain_adjoint -- adjoint of a chain of SUM/WSUM stages.
  * d_in: the chain's input array; d_mid: forward intermediates (HOST array of
- * DEVICE pointers; may be NULL when the pair is fused: the intermediate is
- * recomputed on chip); d_gy: gradient w.r.t. the last output; d_gx: gradient
- * w.r.t. d_in (nullable); d_gc: HOST array of n_stages DEVICE pointers to
- * per-stage weight gradients (array nullable, entries nullable).
+ * DEVICE pointers).  d_mid may be NULL (or hold a NULL entry): a fused pair
+ * recomputes the intermediate on chip, and a chain run stage by stage first
+ * recomputes every intermediate into the library's workspace (zero-filled,
+ * as rsm_run_chain does without d_mid).  d_gy: gradient w.r.t. the last
+ * output; d_gx: gradient w.r.t. d_in (nullable); d_gc: HOST array of
+ * n_stages DEVICE pointers to per-stage weight gradients (array nullable,
+ * entries nullable).
  */
 rsm_status rsm_run_chain_adjoint(const rsm_stage* stages, int32_t n_stages, const void* d_in,
                                  const void* const* d_mid, const void* d_gy, void* d_gx,

@@ -1051,6 +1051,45 @@ rsm_status rsm_run(const rsm_space* rep, const rsm_tiler* in, const void* const*
   RSM_GUARD_END
 }
 
+namespace rsm {
+namespace {
+
+// Bytes of workspace for the intermediate arrays of a chain (outputs of
+// stages 0 .. n - 2), each rounded to 256 bytes; offs[k] = offset of the
+// array of stage k.
+size_t chain_mid_bytes(const rsm_stage* stages, int n, std::vector<size_t>* offs) {
+  size_t total = 0;
+  offs->assign(size_t(n > 1 ? n - 1 : 0), 0);
+  for (int k = 0; k + 1 < n; ++k) {
+    (*offs)[size_t(k)] = total;
+    const rsm_tiler& o = stages[k].out;
+    total += (size_t(prod(o.array_shape, o.array_rank)) * elem_size(o.dtype) + 255) & ~size_t(255);
+  }
+  return total;
+}
+
+// Runs stages 0 .. n - 2 of a chain into the intermediate arrays mids[k]
+// (zero-filled first: elements a stage's output tiler does not cover read
+// as zero in the next stage).  Chain stages are SUM / WSUM tasks, whose
+// forward kernels take no workspace, so mids may live in the workspace.
+rsm_status chain_forward_mids(const rsm_stage* stages, int n, const void* d_in, void* const* mids,
+                              const std::vector<Checked>& cs, uint32_t flags, hipStream_t st) {
+  for (int k = 0; k + 1 < n; ++k) {
+    const rsm_stage& sg = stages[k];
+    const int64_t bytes = prod(sg.out.array_shape, sg.out.array_rank) * int64_t(elem_size(sg.out.dtype));
+    hipError_t e = launch_zero(mids[k], bytes, st);
+    if (e != hipSuccess) return hip_fail(e, "zero intermediate");
+    const void* src = k == 0 ? d_in : mids[k - 1];
+    rsm_status s = exec_run(sg.rep, &sg.in, &src, 1, sg.out, mids[k], sg.task, flags & RSM_FORCE_GENERIC,
+                            cs[size_t(k)], st);
+    if (s) return s;
+  }
+  return RSM_OK;
+}
+
+}  // namespace
+}  // namespace rsm
+
 rsm_status rsm_run_chain(const rsm_stage* stages, int32_t n_stages, const void* d_in,
                          void* const* d_mid, void* d_out, uint32_t flags, void* hip_stream) {
   const KernelProbe probe = take_probe();
@@ -1080,11 +1119,25 @@ rsm_status rsm_run_chain(const rsm_stage* stages, int32_t n_stages, const void* 
     if (e != hipSuccess) return hip_fail(e, "fused chain launch");
     return RSM_OK;
   }
-  if (n_stages > 1 && (!d_mid || !ptrs_ok(const_cast<const void* const*>(d_mid), n_stages - 1)))
-    return fail(RSM_E_INVALID, "unfused chain needs every intermediate buffer");
+  std::vector<void*> mids(d_mid ? d_mid : nullptr, d_mid ? d_mid + (n_stages - 1) : nullptr);
+  if (n_stages > 1 && (!d_mid || !ptrs_ok(const_cast<const void* const*>(d_mid), n_stages - 1))) {
+    // no intermediate buffers given: the library's workspace holds them
+    // (zero-filled first, as in chain_forward_mids)
+    std::vector<size_t> offs;
+    const size_t bytes = chain_mid_bytes(stages, n_stages, &offs);
+    char* ws = static_cast<char*>(workspace(bytes, st, &s, nullptr));
+    if (s) return s;
+    mids.resize(size_t(n_stages - 1));
+    for (int k = 0; k + 1 < n_stages; ++k) {
+      mids[size_t(k)] = ws + offs[size_t(k)];
+      const rsm_tiler& o = stages[k].out;
+      hipError_t e = launch_zero(mids[size_t(k)], prod(o.array_shape, o.array_rank) * elem_size(o.dtype), st);
+      if (e != hipSuccess) return hip_fail(e, "zero intermediate");
+    }
+  }
   for (int k = 0; k < n_stages; ++k) {
-    const void* src = k == 0 ? d_in : d_mid[k - 1];
-    void* dst = k == n_stages - 1 ? d_out : d_mid[k];
+    const void* src = k == 0 ? d_in : mids[size_t(k - 1)];
+    void* dst = k == n_stages - 1 ? d_out : mids[size_t(k)];
     const rsm_stage& sg = stages[k];
     s = exec_run(sg.rep, &sg.in, &src, 1, sg.out, dst, sg.task, flags, cs[size_t(k)], st);
     if (s) return s;
@@ -1180,14 +1233,22 @@ rsm_status rsm_run_chain_adjoint(const rsm_stage* stages, int32_t n_stages, cons
     }
     return RSM_OK;
   }
-  // stage by stage, in reverse; intermediate gradients live in the workspace
-  if (n_stages > 1 && (!d_mid || !ptrs_ok(d_mid, n_stages - 1)))
-    return fail(RSM_E_INVALID, "unfused chain adjoint needs every forward intermediate");
+  // stage by stage, in reverse; intermediate gradients live in the workspace,
+  // and so do the forward intermediates when the caller gives none (they are
+  // recomputed first)
+  const bool have_mid = n_stages == 1 || (d_mid && ptrs_ok(d_mid, n_stages - 1));
+  std::vector<size_t> mid_offs;
+  const size_t fwd_bytes = have_mid ? 0 : chain_mid_bytes(stages, n_stages, &mid_offs);
+  std::vector<void*> fwd_mid(size_t(n_stages > 1 ? n_stages - 1 : 0), nullptr);
+  if (have_mid)
+    for (int k = 0; k + 1 < n_stages; ++k) fwd_mid[size_t(k)] = const_cast<void*>(d_mid[k]);
   size_t max_mid = 0, max_part = 0;
   std::vector<AdjPlan> aps(static_cast<size_t>(n_stages));
   for (int k = 0; k < n_stages; ++k) {
     const rsm_stage& sg = stages[k];
-    const void* xk = k == 0 ? d_in : d_mid[k - 1];
+    // a recomputed intermediate lives in the workspace, 256-byte aligned:
+    // planned as aligned (no pointer)
+    const void* xk = k == 0 ? d_in : (have_mid ? d_mid[k - 1] : nullptr);
     aps[size_t(k)] = plan_adjoint(sg.rep, sg.in, sg.out, sg.task, flags, xk, nullptr);
     max_part = std::max(max_part, adjoint_ws_bytes(aps[size_t(k)], cs[size_t(k)].n_rep,
                                                    cs[size_t(k)].n_pat_in[0], d_gc && d_gc[k]));
@@ -1196,14 +1257,18 @@ rsm_status rsm_run_chain_adjoint(const rsm_stage* stages, int32_t n_stages, cons
   max_mid = (max_mid + 255) & ~size_t(255);
   max_part = (max_part + 255) & ~size_t(255);
   uint32_t* counter = nullptr;
-  char* ws = static_cast<char*>(workspace(2 * max_mid + max_part + 256, st, &s, &counter));
+  char* ws = static_cast<char*>(workspace(2 * max_mid + max_part + fwd_bytes + 256, st, &s, &counter));
   if (s) return s;
   char* gbuf[2] = {ws, ws + max_mid};
   void* part = ws + 2 * max_mid;
+  if (!have_mid) {
+    for (int k = 0; k + 1 < n_stages; ++k) fwd_mid[size_t(k)] = ws + 2 * max_mid + max_part + mid_offs[size_t(k)];
+    if ((s = chain_forward_mids(stages, n_stages, d_in, fwd_mid.data(), cs, flags, st)) != RSM_OK) return s;
+  }
   const void* g = d_gy;
   for (int k = n_stages - 1; k >= 0; --k) {
     const rsm_stage& sg = stages[k];
-    const void* xk = k == 0 ? d_in : d_mid[k - 1];
+    const void* xk = k == 0 ? d_in : fwd_mid[size_t(k - 1)];
     void* gxk = k == 0 ? d_gx : gbuf[k & 1];
     void* gck = d_gc ? d_gc[k] : nullptr;
     // intermediate gradients are overwritten; the caller's buffers follow the flags

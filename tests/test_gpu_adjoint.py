@@ -198,10 +198,15 @@ def test_chain_adjoint_full_size(fused):
     check_close(host(gcv), av.gc, abs_v.gc, what="chain gc_v fused=%s" % fused)
 
 
+# (8, 8, 0): the workload's exact paving; (13, 8, -6): windows overlapping by
+# five and wrapping round the 32-element crop on both axes (the adjoint then
+# runs stage by stage, recomputing the intermediate when fused=True)
+@pytest.mark.parametrize("taps,pave,origin", [(8, 8, 0), (13, 8, -6)])
 @pytest.mark.parametrize("fused", [True, False])
-def test_crop_loss_autograd_vs_finite_differences(fused):
+def test_crop_loss_autograd_vs_finite_differences(fused, taps, pave, origin):
     """32x32 crop of frame 0 as its own [1,32,32] array; loss sum(w out^2)."""
-    ts = W.two_stage_filter(frames=1, rows=32, cols=32)
+    ts = W.two_stage_filter(frames=1, rows=32, cols=32, taps=taps, pave=pave, h_origin=origin,
+                            v_origin=origin)
     w = W.loss_weights((1, 4, 4))
     stages = [ts.h, ts.v]
     x = dev(ts.x).requires_grad_(True)
@@ -232,8 +237,8 @@ def test_crop_loss_autograd_vs_finite_differences(fused):
         fd[j] = (L(xp.reshape(x64.shape), ch64, cv64) - L(xm.reshape(x64.shape), ch64, cv64)) / (2 * h)
     fdc = []
     for which in range(2):
-        g = np.zeros(8)
-        for k in range(8):
+        g = np.zeros(taps)
+        for k in range(taps):
             cp = [ch64.copy(), cv64.copy()]
             cm = [ch64.copy(), cv64.copy()]
             cp[which][k] += h
@@ -261,6 +266,52 @@ def test_tiled_task_autograd_single_stage():
     a = oracle.adjoint(ts.h, ts.x, gy)
     check_close(host(x.grad), a.gx, a.gx_abs, what="TiledTask gx")
     check_close(host(c.grad), a.gc, a.gc_abs, what="TiledTask gc")
+
+
+def test_chains_without_intermediate_buffers():
+    # an overlapping chain (13 taps every 8, wrapping): the adjoint cannot
+    # fuse, so without d_mid it recomputes the intermediate in the workspace
+    ts = W.two_stage_filter(frames=3, rows=96, cols=200, taps=13, pave=8, h_origin=-6, v_origin=-6,
+                            seed=21)
+    stages = [ts.h, ts.v]
+    gy = W.rng_for(22).uniform(-1, 1, ts.v.rep_shape).astype(np.float32)
+    fw = oracle.chain_forward(stages, ts.x)
+    av = oracle.adjoint(ts.v, fw[0].out, gy)
+    ah = oracle.adjoint(ts.h, ts.x, av.gx)
+    abs_v = oracle.adjoint(_abs_problem(ts.v), np.abs(fw[0].out), np.abs(gy))
+    abs_h = oracle.adjoint(_abs_problem(ts.h), np.abs(ts.x), abs_v.gx)
+    x, c = dev(ts.x), [dev(ts.c_h), dev(ts.c_v)]
+    res = {}
+    for name, mids, flags in (("recomputed", None, 0), ("given", "mid", _abi.NO_FUSE)):
+        mid = None
+        if mids:
+            mid = torch.empty(ts.h.rep_shape, device="cuda")
+            rsm.run(ts.h, [x], mid, coeffs=c[0])
+        gx = torch.full(ts.x.shape, float("nan"), device="cuda")
+        gcs = [torch.full((13,), float("nan"), device="cuda") for _ in range(2)]
+        rsm.run_chain_adjoint(stages, x, dev(gy), gx, gcs, c, mids=None if mid is None else [mid], flags=flags)
+        check_close(host(gx), ah.gx, abs_h.gx, what=name + " gx")
+        check_close(host(gcs[0]), ah.gc, abs_h.gc, what=name + " gc_h")
+        check_close(host(gcs[1]), av.gc, abs_v.gc, what=name + " gc_v")
+        res[name] = (gx, gcs)
+    # the same kernels on the same intermediate: the same bits
+    assert torch.equal(res["recomputed"][0], res["given"][0])
+    # a chain the planner cannot fuse (both stages along columns), run
+    # without intermediate buffers
+    t1 = W.h_stage(2, 40, 96, taps=5, pave=3, origin=-2)
+    r1 = (2, 40, 32)
+    t2 = W.h_stage(2, 40, 32, taps=3, pave=2, origin=0)
+    r2 = (2, 40, 16)
+    rng = W.rng_for(23)
+    c1, c2 = rng.uniform(-1, 1, 5).astype(np.float32), rng.uniform(-1, 1, 3).astype(np.float32)
+    st2 = [W.Problem(r1, [t1], W.identity_output(r1), W.WSUM, c1),
+           W.Problem(r2, [t2], W.identity_output(r2), W.WSUM, c2)]
+    x2 = rng.uniform(-1, 1, (2, 40, 96)).astype(np.float32)
+    out = torch.full(r2, float("nan"), device="cuda")
+    rsm.run_chain(st2, dev(x2), out, [dev(c1), dev(c2)])
+    want = oracle.chain_forward(st2, x2)
+    bound = oracle.chain_forward([_abs_problem(q) for q in st2], np.abs(x2))[-1].out
+    check_close(host(out), want[-1].out, bound, what="unfusable chain without intermediates")
 
 
 def test_deterministic_weight_gradient():
