@@ -38,6 +38,7 @@ static KernelProbe take_probe() {
   return p;
 }
 
+
 // Launches `launch` between the probe's events (either may be absent).
 template <typename F>
 static hipError_t probed(const KernelProbe& p, hipStream_t st, F launch) {
@@ -1054,6 +1055,17 @@ rsm_status rsm_run(const rsm_space* rep, const rsm_tiler* in, const void* const*
 namespace rsm {
 namespace {
 
+// Both stages' weight gradients from a fused pair's partial rows
+// [grid][taps0 + taps1] in one launch; a null output skips its columns.
+hipError_t reduce_chain_partials(const float* partial, int grid, int taps0, float* g0, int taps1, float* g1,
+                                 int row_stride, int accumulate, hipStream_t st) {
+  if (g0 && g1) return launch_reduce_partial_pair(partial, grid, taps0, g0, taps1, g1, row_stride, accumulate, st);
+  if (g0) return launch_reduce_partial_pair(partial, grid, taps0, g0, 0, nullptr, row_stride, accumulate, st);
+  if (g1)
+    return launch_reduce_partial_pair(partial + taps0, grid, 0, nullptr, taps1, g1, row_stride, accumulate, st);
+  return hipSuccess;
+}
+
 // Bytes of workspace for the intermediate arrays of a chain (outputs of
 // stages 0 .. n - 2), each rounded to 256 bytes; offs[k] = offset of the
 // array of stage k.
@@ -1224,13 +1236,10 @@ rsm_status rsm_run_chain_adjoint(const rsm_stage* stages, int32_t n_stages, cons
     }
     if ((e = probed(probe, st, [&] { return launch_fir_chain_adjoint(a, vec4, st); })) != hipSuccess)
       return hip_fail(e, "fused chain adjoint");
-    if (a.partial && !a.counter) {
-      if (gch && (e = launch_reduce_partials(a.partial, grid, h.taps, nc, gch, accumulate, st)) != hipSuccess)
-        return hip_fail(e, "weight-gradient reduction");
-      if (gcv && (e = launch_reduce_partials(a.partial + h.taps, grid, v.taps, nc, gcv, accumulate, st)) !=
-                     hipSuccess)
-        return hip_fail(e, "weight-gradient reduction");
-    }
+    if (a.partial && !a.counter &&
+        (e = reduce_chain_partials(a.partial, grid, h.taps, gch, v.taps, gcv, nc, accumulate, st)) !=
+            hipSuccess)
+      return hip_fail(e, "weight-gradient reduction");
     return RSM_OK;
   }
   // stage by stage, in reverse; intermediate gradients live in the workspace,
@@ -1348,9 +1357,8 @@ rsm_status rsm_run_chain_train(const rsm_stage* stages, int32_t n_stages, const 
   }
   if ((e = probed(probe, st, [&] { return launch_fir_chain_train(a, st); })) != hipSuccess)
     return hip_fail(e, "fused training step");
-  if (gch && (e = launch_reduce_partials(a.partial, grid, h.taps, nc, gch, accumulate, st)) != hipSuccess)
-    return hip_fail(e, "weight-gradient reduction");
-  if (gcv && (e = launch_reduce_partials(a.partial + h.taps, grid, v.taps, nc, gcv, accumulate, st)) != hipSuccess)
+  if ((gch || gcv) && (e = reduce_chain_partials(a.partial, grid, h.taps, gch, v.taps, gcv, nc, accumulate,
+                                                 st)) != hipSuccess)
     return hip_fail(e, "weight-gradient reduction");
   return RSM_OK;
   RSM_GUARD_END

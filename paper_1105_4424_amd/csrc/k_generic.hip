@@ -320,6 +320,27 @@ __global__ void __launch_bounds__(kBlock) reduce_strided_kernel(const float* src
   if (threadIdx.x == 0) out[i] = accumulate ? out[i] + red[0] : red[0];
 }
 
+// Two weight gradients from one partial table [n][row_stride]: column
+// blockIdx.x < n0 goes to out0[blockIdx.x], the next n1 columns to out1.
+// Each column is reduced by the same fixed-order tree as reduce_strided_kernel.
+__global__ void __launch_bounds__(kBlock) reduce_pair_kernel(const float* src, int64_t n, int64_t row_stride,
+                                                             int n0, float* out0, float* out1, int accumulate) {
+  __shared__ float red[kBlock];
+  const int i = int(blockIdx.x);
+  float acc = 0.0f;
+  for (int64_t j = threadIdx.x; j < n; j += kBlock) acc += src[i + j * row_stride];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (int(threadIdx.x) < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    float* o = i < n0 ? out0 + i : out1 + (i - n0);
+    *o = accumulate ? *o + red[0] : red[0];
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) zero_kernel(uint32_t* p, int64_t n_words) {
   const int64_t stride = int64_t(gridDim.x) * kBlock;
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n_words; i += stride) p[i] = 0u;
@@ -375,6 +396,17 @@ hipError_t launch_reduce_rows(const float* partial, int64_t n_rows, int64_t n_co
   if (n_rows <= 0) return hipSuccess;
   reduce_strided_kernel<<<unsigned(n_rows), kBlock, 0, st>>>(partial, n_cols, n_cols, 1, out,
                                                              accumulate);
+  return hipGetLastError();
+}
+
+// partial is [n_blocks][row_stride]; out0[j] = sum_b partial[b][j] for
+// j < n0 and out1[j] = sum_b partial[b][n0 + j] for j < n1, in one launch
+// (out0 or out1 may be null when its count is zero)
+hipError_t launch_reduce_partial_pair(const float* partial, int n_blocks, int n0, float* out0, int n1,
+                                      float* out1, int row_stride, int accumulate, hipStream_t st) {
+  if (n0 + n1 <= 0) return hipSuccess;
+  reduce_pair_kernel<<<unsigned(n0 + n1), kBlock, 0, st>>>(partial, n_blocks, row_stride, n0, out0, out1,
+                                                            accumulate);
   return hipGetLastError();
 }
 

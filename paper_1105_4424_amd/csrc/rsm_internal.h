@@ -318,6 +318,8 @@ int fir_overlap_cols_grid(uint32_t n_items);
 int fir_adjoint_grid(const FirAdjArgs& a);
 hipError_t launch_fir_chain_adjoint(const FirChainAdjArgs& a, bool vec4, hipStream_t st);
 int fir_chain_adjoint_grid(const FirChainAdjArgs& a, bool vec4);
+hipError_t launch_reduce_partial_pair(const float* partial, int n_blocks, int n0, float* out0, int n1,
+                                      float* out1, int row_stride, int accumulate, hipStream_t st);
 hipError_t launch_reduce_partials(const float* partial, int n_blocks, int n_coef, int row_stride,
                                   float* out, int accumulate, hipStream_t st);
 hipError_t launch_generic_adjoint(const GenericAdjArgs& a, int max_rank, hipStream_t st);
