@@ -244,6 +244,7 @@ rsm_status rsm_run_chain_train(const rsm_stage* stages, int32_t n_stages, const 
  * (RSM_E_INVALID) instead.  Limits: n_rows, n_cols, nnz < 2^31.
  */
 #define RSM_CHECK_INDICES 0x10u
+#define RSM_NO_GRAPH 0x40u   /* rsm_cg_solve: launch iteration batches directly, no graph replay */
 rsm_status rsm_run_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t* d_row_ptr,
                        const int32_t* d_col_idx, const void* d_vals, const void* d_x, void* d_y,
                        int32_t dtype, uint32_t flags, void* hip_stream);
@@ -268,9 +269,13 @@ rsm_status rsm_run_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
  * count, the final recursive residual norm, ||b||, converged and breakdown
  * (<p, A p> <= 0 met: A not positive definite; x then holds the last
  * iterate).  Inner products are reduced in a fixed order: repeated calls
- * give identical bits.  Uses the library workspace (3 n + 3 * 2048 doubles);
+ * give identical bits.  Uses the library workspace (4 n + 3 * 2048 doubles);
  * calls on one device must not overlap.  RSM_CHECK_INDICES validates the
- * index arrays on the host first.  Limits: n, nnz < 2^31.
+ * index arrays on the host first.  Each batch of check_every iterations is
+ * replayed from a HIP graph that the library captures once and keeps per
+ * device while the call's arguments (buffers, sizes, tol, max_iter,
+ * check_every) stay the same; RSM_NO_GRAPH launches the batches directly
+ * instead (the same kernels: the same bits).  Limits: n, nnz < 2^31.
  */
 typedef struct {
   int64_t iterations;

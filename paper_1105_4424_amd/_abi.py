@@ -25,6 +25,7 @@ NO_FUSE = 0x4
 FORCE_GENERIC = 0x8
 PLAN_ADJOINT = 0x20
 CHECK_INDICES = 0x10
+NO_GRAPH = 0x40
 
 I64x8 = ctypes.c_int64 * MAX_RANK
 I64x8x8 = (ctypes.c_int64 * MAX_RANK) * MAX_RANK

@@ -1385,6 +1385,62 @@ rsm_status rsm_run_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
   RSM_GUARD_END
 }
 
+namespace rsm {
+namespace {
+
+// One captured batch of CG iterations per device, replayed while the launch
+// arguments stay the same (a solver called again on the same buffers, as in
+// a time-stepping loop).  Captured on a library stream (capture is not
+// allowed on the null stream) and replayed on the caller's.  The graph holds
+// kernel launches only.
+struct CgGraph {
+  unsigned char key[sizeof(CgArgs)];
+  int iters = 0;
+  bool valid = false;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;
+};
+CgGraph g_cg_graph[64];
+std::mutex g_cg_mutex;
+
+hipError_t cg_graph_launch(const CgArgs& a, int iters, hipStream_t st) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_cg_mutex);
+  CgGraph& g = g_cg_graph[dev];
+  if (!(g.valid && g.iters == iters && std::memcmp(g.key, &a, sizeof(CgArgs)) == 0)) {
+    if (g.exec) {
+      (void)hipGraphExecDestroy(g.exec);
+      g.exec = nullptr;
+    }
+    g.valid = false;
+    if (!g.cap && (e = hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipStreamBeginCapture(g.cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+    const hipError_t le = launch_cg(a, false, iters, g.cap);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(g.cap, &graph);
+    if (le != hipSuccess || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return le != hipSuccess ? le : e;
+    }
+    e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      g.exec = nullptr;
+      return e;
+    }
+    std::memcpy(g.key, &a, sizeof(CgArgs));
+    g.iters = iters;
+    g.valid = true;
+  }
+  return hipGraphLaunch(g.exec, st);
+}
+
+}  // namespace
+}  // namespace rsm
+
 rsm_status rsm_cg_solve(int64_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col_idx,
                         const double* d_vals, const double* d_b, double* d_x, double tol, int64_t max_iter,
                         int32_t check_every, uint32_t flags, double* d_res, double* d_alpha, double* d_beta,
@@ -1409,7 +1465,7 @@ rsm_status rsm_cg_solve(int64_t n, int64_t nnz, const int32_t* d_row_ptr, const 
   const int grid_rows = cg_grid(n, nnz), grid_vec = cg_vec_grid(n);
   const size_t vec = (size_t(n) * sizeof(double) + 255) & ~size_t(255);
   const size_t part = (size_t(std::max(grid_rows, grid_vec)) * sizeof(double) + 255) & ~size_t(255);
-  char* ws = static_cast<char*>(workspace(3 * vec + 3 * part + 256, st, &s, nullptr));
+  char* ws = static_cast<char*>(workspace(4 * vec + 3 * part + 256, st, &s, nullptr));
   if (s != RSM_OK) return s;
   CgArgs a{};
   a.n = n;
@@ -1420,12 +1476,13 @@ rsm_status rsm_cg_solve(int64_t n, int64_t nnz, const int32_t* d_row_ptr, const 
   a.b = d_b;
   a.x = d_x;
   a.r = reinterpret_cast<double*>(ws);
-  a.p = reinterpret_cast<double*>(ws + vec);
-  a.q = reinterpret_cast<double*>(ws + 2 * vec);
-  a.part_pq = reinterpret_cast<double*>(ws + 3 * vec);
-  a.part_rr = reinterpret_cast<double*>(ws + 3 * vec + part);
-  a.part_bb = reinterpret_cast<double*>(ws + 3 * vec + 2 * part);
-  a.st = reinterpret_cast<CgState*>(ws + 3 * vec + 3 * part);
+  a.p0 = reinterpret_cast<double*>(ws + vec);
+  a.p1 = reinterpret_cast<double*>(ws + 2 * vec);
+  a.q = reinterpret_cast<double*>(ws + 3 * vec);
+  a.part_pq = reinterpret_cast<double*>(ws + 4 * vec);
+  a.part_rr = reinterpret_cast<double*>(ws + 4 * vec + part);
+  a.part_bb = reinterpret_cast<double*>(ws + 4 * vec + 2 * part);
+  a.st = reinterpret_cast<CgState*>(ws + 4 * vec + 3 * part);
   a.res = d_res;
   a.alpha = d_alpha;
   a.beta = d_beta;
@@ -1440,7 +1497,8 @@ rsm_status rsm_cg_solve(int64_t n, int64_t nnz, const int32_t* d_row_ptr, const 
   // ends after at most max_iter / check_every + 2 batches.
   CgState h{};
   for (int64_t launched = 0;; launched += check_every) {
-    if ((e = launch_cg(a, false, check_every, st)) != hipSuccess) return hip_fail(e, "cg loop launch");
+    e = (flags & RSM_NO_GRAPH) ? launch_cg(a, false, check_every, st) : cg_graph_launch(a, check_every, st);
+    if (e != hipSuccess) return hip_fail(e, "cg loop launch");
     if ((e = hipMemcpyAsync(&h, a.st, sizeof(h), hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
       return hip_fail(e, "cg state read");
@@ -1448,11 +1506,12 @@ rsm_status rsm_cg_solve(int64_t n, int64_t nnz, const int32_t* d_row_ptr, const 
     if (launched > max_iter + 2 * int64_t(check_every))
       return fail(RSM_E_HIP, "cg loop did not reach its stop test");
   }
+  const double rho = h.rho[h.k & 1];
   info->iterations = h.k;
-  info->residual_norm = std::sqrt(h.rho);
+  info->residual_norm = std::sqrt(rho);
   info->rhs_norm = h.bnorm;
   info->breakdown = h.breakdown;
-  info->converged = !h.breakdown && !(std::sqrt(h.rho) > tol * h.bnorm);
+  info->converged = !h.breakdown && !(std::sqrt(rho) > tol * h.bnorm);
   return RSM_OK;
   RSM_GUARD_END
 }

@@ -6,21 +6,28 @@
 // (a reduction over the element repetitions) and the vector updates
 // (element-wise repetitions).  The paper runs the scalar steps on the CPU
 // between launches; here they stay on the device so the loop never waits for
-// the host.  One iteration is three kernels:
+// the host.  One iteration k is two kernels:
 //
-//   cg_spmv  rho_k from the <r,r> partials; stop test; q = A p; <p,q> partials
-//   cg_xr    alpha = rho_k / <p,q>; x += alpha p; r -= alpha q; <r,r> partials
-//   cg_p     beta = rho_{k+1} / rho_k; p = r + beta p; k += 1
+//   cg_spmv  rho_k from the <r,r> partials; stop test; beta_{k-1} =
+//            rho_k / rho_{k-1}; p_k = r_k + beta_{k-1} p_{k-1}, formed on
+//            the fly for every gathered column and stored for the own rows;
+//            q = A p_k; <p_k,q> partials
+//   cg_xr    alpha = rho_k / <p_k,q>; x += alpha p_k; r -= alpha q;
+//            <r,r> partials; k += 1
 //
-// Every workgroup rebuilds a scalar from the previous kernel's per-workgroup
-// partials in one fixed order, so all workgroups hold the same bits and the
-// loop is deterministic for a given launch shape.  The sparse product runs
-// on a large grid (latency hiding); the vector kernels on at most 256
-// workgroups, so the partials every workgroup re-sums stay few.  Each field of the state
-// block is written by workgroup 0 of one kernel only and read by the other
-// kernels, never by the kernel that writes it: rho / done by cg_spmv,
-// breakdown by cg_xr, k by cg_p.  After the stop test has fired, every kernel
-// returns at once, so surplus launched iterations change nothing.
+// The directions alternate between two buffers (p_k in P[k mod 2]), so the
+// product reads p_{k-1} while it writes p_k.  Every workgroup rebuilds a
+// scalar from the previous kernel's per-workgroup partials in one fixed
+// order, so all workgroups hold the same bits and the loop is deterministic
+// for a given launch shape; the iterates are those of the textbook order
+// (p = r + beta p after the update of r) bit for bit.  The sparse product
+// runs on a large grid (latency hiding); the vector kernel on at most 256
+// workgroups, so the partials every workgroup re-sums stay few.  Each field
+// of the state block is written by workgroup 0 of one kernel only and read
+// by other kernels, never by the kernel that writes it: rho[k mod 2], done,
+// k_spmv by cg_spmv; breakdown, k by cg_xr.  After the stop test has fired,
+// every kernel writes what it wrote before or nothing, so surplus launched
+// iterations change nothing.
 #include <hip/hip_runtime.h>
 
 #include "rsm_internal.h"
@@ -55,16 +62,16 @@ __device__ __forceinline__ double partial_sum(const double* part, int n, double*
 
 __device__ __forceinline__ bool lead() { return blockIdx.x == 0 && threadIdx.x == 0; }
 
-// y[r] = sum_k vals[k] x[col_idx[k]] for the rows of this group of G lanes,
+// y[r] = sum_k vals[k] v(col_idx[k]) for the rows of this group of G lanes,
 // two rows at a time; calls f(r, y_r) on lane 0 of the group.  Each lane
 // takes entries lane, lane + G, ..., lane + (E - 1) G of a row chunk and
-// issues all index and value loads of both rows before the gathers of x, so
+// issues all index and value loads of both rows before the gathers of v, so
 // a lane has 4 E loads in flight.  Row bounds are clamped into [0, nnz] and
 // columns outside [0, n) contribute nothing.
 constexpr int kEntries = 4;   // E
 
-template <int G, typename F>
-__device__ __forceinline__ void spmv_rows(const CgArgs& a, const double* __restrict__ x, F f) {
+template <int G, typename V, typename F>
+__device__ __forceinline__ void spmv_rows(const CgArgs& a, V v, F f) {
   constexpr int E = kEntries;
   const int lane = threadIdx.x & (G - 1);
   const int64_t groups = int64_t(gridDim.x) * (kBlock / G);
@@ -91,8 +98,8 @@ __device__ __forceinline__ void spmv_rows(const CgArgs& a, const double* __restr
       }
 #pragma unroll
       for (int j = 0; j < E; ++j) {
-        if (uint32_t(c0[j]) < uint32_t(a.n)) acc0 += v0[j] * x[c0[j]];
-        if (uint32_t(c1[j]) < uint32_t(a.n)) acc1 += v1[j] * x[c1[j]];
+        if (uint32_t(c0[j]) < uint32_t(a.n)) acc0 += v0[j] * v(c0[j]);
+        if (uint32_t(c1[j]) < uint32_t(a.n)) acc1 += v1[j] * v(c1[j]);
       }
     }
 #pragma unroll
@@ -107,19 +114,22 @@ __device__ __forceinline__ void spmv_rows(const CgArgs& a, const double* __restr
   }
 }
 
-// r = b - A x0, p = r; partials of <r,r> and <b,b>.
+// r = b - A x0; P[1] = 0 (p_{-1}: p_0 = r_0 + 0 p_{-1}); partials of <r,r>
+// and <b,b>.
 template <int G>
 __global__ void __launch_bounds__(kBlock) cg_init_kernel(CgArgs a) {
   __shared__ double lds[kBlock];
   double rr = 0.0, bb = 0.0;
-  spmv_rows<G>(a, a.x, [&](int64_t r, double ax) {
+  const double* __restrict__ x = a.x;
+  spmv_rows<G>(a, [&](int32_t c) { return x[c]; }, [&](int64_t r, double ax) {
     const double b = a.b[r];
     const double res = b - ax;
     a.r[r] = res;
-    a.p[r] = res;
     rr += res * res;
     bb += b * b;
   });
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < a.n; i += int64_t(gridDim.x) * kBlock)
+    a.p1[i] = 0.0;
   rr = block_sum(rr, lds);
   bb = block_sum(bb, lds);
   if (threadIdx.x == 0) {
@@ -139,8 +149,10 @@ __global__ void __launch_bounds__(kBlock) cg_start_kernel(CgArgs a) {
   for (int i = threadIdx.x; i < a.grid_vec; i += kBlock) a.part_rr[i] = i == 0 ? rr : 0.0;
   if (threadIdx.x == 0) {
     a.st->bnorm = sqrt(bb);
-    a.st->rho = 0.0;
+    a.st->rho[0] = 0.0;
+    a.st->rho[1] = 0.0;
     a.st->k = 0;
+    a.st->k_spmv = 0;
     a.st->done = 0;
     a.st->breakdown = 0;
   }
@@ -152,16 +164,24 @@ __global__ void __launch_bounds__(kBlock) cg_spmv_kernel(CgArgs a) {
   const double rho = partial_sum(a.part_rr, a.grid_vec, lds);
   const int64_t k = a.st->k;
   const bool stop = a.st->breakdown != 0 || k >= a.max_iter || !(sqrt(rho) > a.tol * a.st->bnorm);
+  const double beta = k > 0 ? rho / a.st->rho[(k - 1) & 1] : 0.0;
   if (lead()) {
-    a.st->rho = rho;
+    a.st->rho[k & 1] = rho;
+    a.st->k_spmv = k;
     a.st->done = stop ? 1 : 0;
     if (a.res) a.res[k] = sqrt(rho);
+    if (k > 0 && a.beta) a.beta[k - 1] = beta;
   }
   if (stop) return;
+  const double* __restrict__ r = a.r;
+  const double* __restrict__ p_old = (k & 1) ? a.p0 : a.p1;
+  double* __restrict__ p_new = (k & 1) ? a.p1 : a.p0;
   double pq = 0.0;
-  spmv_rows<G>(a, a.p, [&](int64_t r, double q) {
-    a.q[r] = q;
-    pq += a.p[r] * q;
+  spmv_rows<G>(a, [&](int32_t c) { return fma(beta, p_old[c], r[c]); }, [&](int64_t i, double q) {
+    const double p = fma(beta, p_old[i], r[i]);
+    p_new[i] = p;
+    a.q[i] = q;
+    pq += p * q;
   });
   pq = block_sum(pq, lds);
   if (threadIdx.x == 0) a.part_pq[blockIdx.x] = pq;
@@ -175,32 +195,20 @@ __global__ void __launch_bounds__(kBlock) cg_xr_kernel(CgArgs a) {
     if (lead()) a.st->breakdown = 1;
     return;
   }
-  const double alpha = a.st->rho / pq;
-  if (lead() && a.alpha) a.alpha[a.st->k] = alpha;
+  const int64_t k = a.st->k_spmv;
+  const double alpha = a.st->rho[k & 1] / pq;
+  if (lead() && a.alpha) a.alpha[k] = alpha;
+  const double* __restrict__ p = (k & 1) ? a.p1 : a.p0;
   double rr = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < a.n; i += int64_t(gridDim.x) * kBlock) {
-    const double p = a.p[i];
-    a.x[i] += alpha * p;
+    a.x[i] += alpha * p[i];
     const double res = a.r[i] - alpha * a.q[i];
     a.r[i] = res;
     rr += res * res;
   }
   rr = block_sum(rr, lds);
   if (threadIdx.x == 0) a.part_rr[blockIdx.x] = rr;
-}
-
-__global__ void __launch_bounds__(kBlock) cg_p_kernel(CgArgs a) {
-  __shared__ double lds[kBlock];
-  if (a.st->done || a.st->breakdown) return;
-  const double rho_next = partial_sum(a.part_rr, a.grid_vec, lds);
-  const double beta = rho_next / a.st->rho;
-  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < a.n; i += int64_t(gridDim.x) * kBlock)
-    a.p[i] = a.r[i] + beta * a.p[i];
-  if (lead()) {
-    const int64_t k = a.st->k;
-    if (a.beta) a.beta[k] = beta;
-    a.st->k = k + 1;
-  }
+  if (lead()) a.st->k = k + 1;
 }
 
 template <int G>
@@ -213,7 +221,6 @@ hipError_t launch_g(const CgArgs& a, bool init, int iters, hipStream_t st) {
   for (int i = 0; i < iters; ++i) {
     cg_spmv_kernel<G><<<gr, kBlock, 0, st>>>(a);
     cg_xr_kernel<<<gv, kBlock, 0, st>>>(a);
-    cg_p_kernel<<<gv, kBlock, 0, st>>>(a);
   }
   return hipGetLastError();
 }

@@ -271,9 +271,10 @@ struct CsrArgs {
 
 // Device-resident state of one conjugate-gradient solve (library workspace).
 struct CgState {
-  double rho;          // rho_k = <r_k, r_k>        (written by cg_spmv)
+  double rho[2];       // rho_k = <r_k, r_k> in slot k mod 2 (written by cg_spmv)
   double bnorm;        // ||b||                     (written once at start)
-  int64_t k;           // iterations completed      (written by cg_p)
+  int64_t k;           // iterations completed      (written by cg_xr)
+  int64_t k_spmv;      // iteration of the last cg_spmv (written by cg_spmv)
   int32_t done;        // stop test fired           (written by cg_spmv)
   int32_t breakdown;   // <p, A p> <= 0 was met     (written by cg_xr)
 };
@@ -286,7 +287,8 @@ struct CgArgs {
   const double* b;          // n
   double* x;                // n: x0 in, iterate out
   double* r;                // n, workspace
-  double* p;                // n, workspace
+  double* p0;               // n, workspace: directions p_k of even k
+  double* p1;               // n, workspace: directions p_k of odd k (p_{-1} = 0)
   double* q;                // n, workspace
   double* part_pq;          // grid_rows, workspace
   double* part_rr;          // max(grid_rows, grid_vec), workspace
@@ -298,7 +300,7 @@ struct CgArgs {
   double tol;
   int64_t max_iter;
   int32_t grid_rows;        // workgroups of the sparse-product kernels (cg_init, cg_spmv)
-  int32_t grid_vec;         // workgroups of the vector kernels (cg_xr, cg_p)
+  int32_t grid_vec;         // workgroups of the vector kernel (cg_xr)
 };
 
 // ---------------------------------------------------------------------------

@@ -256,7 +256,7 @@ def time_next_kernel(start: "torch.cuda.Event", stop: "torch.cuda.Event") -> Non
 
 def cg_solve(row_ptr: torch.Tensor, col_idx: torch.Tensor, vals: torch.Tensor, b: torch.Tensor,
              x: torch.Tensor, tol: float = 1e-10, max_iter: Optional[int] = None, check_every: int = 16,
-             history: bool = False, check_indices: bool = False, stream=None) -> dict:
+             history: bool = False, check_indices: bool = False, graph: bool = True, stream=None) -> dict:
     """Conjugate gradient on an SPD CSR matrix, FP64, in place on x (x0 in,
     last iterate out).  Blocking: the host reads the device state every
     check_every iterations.  Returns the iteration count, final residual
@@ -280,7 +280,7 @@ def cg_solve(row_ptr: torch.Tensor, col_idx: torch.Tensor, vals: torch.Tensor, b
     info = _abi.CgInfo()
     _check(lib.rsm_cg_solve(n, col_idx.numel(), _ptr(row_ptr), _ptr(col_idx), _ptr(vals), _ptr(b),
                             _ptr(x), float(tol), int(max_iter), int(check_every),
-                            _abi.CHECK_INDICES if check_indices else 0,
+                            (_abi.CHECK_INDICES if check_indices else 0) | (0 if graph else _abi.NO_GRAPH),
                             _ptr(res) if res is not None else None,
                             _ptr(alpha) if alpha is not None else None,
                             _ptr(beta) if beta is not None else None, ctypes.byref(info), _stream(stream)))

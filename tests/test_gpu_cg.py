@@ -146,6 +146,38 @@ def test_cadence_and_repeat_give_identical_bits():
         assert np.array_equal(host(info["res"]), host(runs[0][0]["res"]))
 
 
+def test_graph_replays_match_direct_launches():
+    # the iteration batches replay a captured graph (kept while the call's
+    # arguments repeat); every replay, with other GPU work and host
+    # synchronisations in between, gives the bits of direct launches
+    A = W.stencil27_csr(12, seed=5)
+    b = W.cg_rhs(A.n, seed=6)
+    rp, ci, va = _dev_csr(A)
+    bd = dev(b, torch.float64)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+
+    def solve(graph):
+        x.zero_()
+        info = rsm.cg_solve(rp, ci, va, bd, x, tol=1e-10, check_every=3, history=True, graph=graph)
+        return info["iterations"], host(x), host(info["res"]), host(info["alpha"])
+
+    ref = solve(False)
+    y = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        got = solve(True)
+        assert got[0] == ref[0], rep
+        for g, r in zip(got[1:], ref[1:]):
+            assert np.array_equal(g, r), rep
+        rsm.run_csr(rp, ci, va, x, y)        # other work between replays
+        torch.cuda.synchronize()
+    # new arguments (another tolerance) capture a new graph
+    x.zero_()
+    info = rsm.cg_solve(rp, ci, va, bd, x, tol=1e-6, check_every=3)
+    x2 = torch.zeros_like(x)
+    info2 = rsm.cg_solve(rp, ci, va, bd, x2, tol=1e-6, check_every=3, graph=False)
+    assert info["iterations"] == info2["iterations"] and torch.equal(x, x2)
+
+
 def test_indefinite_matrix_reports_breakdown():
     A = W.dense_csr(np.diag([1.0, -2.0, 3.0, 4.0]))
     b = np.ones(4)
