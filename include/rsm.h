@@ -138,6 +138,37 @@ rsm_status rsm_plan(const rsm_space* rep, const rsm_tiler* in, int32_t n_in,
                     char* name, int32_t len);
 
 /*
+ * rsm_plan_ports -- where the planned kernel keeps each port's working set,
+ * in the memory spaces of the paper's platform model (the MemoryMapping of
+ * Sec. 5-6, which maps every flowPort to an OpenCL address space) as they
+ * exist on gfx950.  One entry per port, in order: inputs 0 .. n_in - 1,
+ * the output, then (WSUM only) the coefficients.  `space` is where a
+ * workgroup holds the port's data while it computes; `bytes_per_workgroup`
+ * is how much of it one workgroup holds there (0: the port is streamed
+ * through registers element by element, nothing is staged).  Host only;
+ * judged on shapes alone, like rsm_plan.  Writes min(max_ports, count)
+ * entries and the count to *n_ports (RSM_E_INVALID if ports is too short).
+ */
+typedef enum {
+  RSM_MEM_GLOBAL = 0,    /* device memory (HBM): read or written in place, per element */
+  RSM_MEM_CONSTANT = 1,  /* uniform across the workgroup: scalar registers / scalar cache */
+  RSM_MEM_LOCAL = 2,     /* LDS: staged once per workgroup, shared by its threads */
+  RSM_MEM_PRIVATE = 3    /* per-thread registers (VGPR / AGPR) */
+} rsm_mem_space;
+
+typedef struct {
+  int32_t port;                 /* 0 .. n_in - 1 inputs, n_in output, n_in + 1 coefficients */
+  int32_t is_output;            /* 1 for the output port */
+  int32_t space;                /* rsm_mem_space */
+  int32_t reserved;
+  int64_t bytes_per_workgroup;
+} rsm_port_placement;
+
+rsm_status rsm_plan_ports(const rsm_space* rep, const rsm_tiler* in, int32_t n_in,
+                          const rsm_tiler* out, const rsm_task* task, uint32_t flags,
+                          rsm_port_placement* ports, int32_t max_ports, int32_t* n_ports);
+
+/*
  * rsm_indices -- the index table of one tiler (the index step of the
  * definition above): d_idx[r * |s_p| + i] = linear offset of e(r, i) in the
  * tiler's array, int64, r and i flat row-major.  d_idx is a device buffer of

@@ -74,12 +74,20 @@ class CgInfo(ctypes.Structure):
                 ("breakdown", ctypes.c_int32)]
 
 
+class PortPlacement(ctypes.Structure):
+    _fields_ = [("port", ctypes.c_int32), ("is_output", ctypes.c_int32), ("space", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("bytes_per_workgroup", ctypes.c_int64)]
+
+
+MEM_SPACES = {0: "global", 1: "constant", 2: "local", 3: "private"}
+
 EXPORTS = [
     "rsm_validate", "rsm_plan", "rsm_indices", "rsm_run", "rsm_run_chain", "rsm_run_adjoint",
     "rsm_run_chain_adjoint", "rsm_batch_create", "rsm_batch_run", "rsm_batch_run_plain",
     "rsm_batch_query",
     "rsm_batch_tile", "rsm_batch_destroy", "rsm_status_string", "rsm_last_error",
     "rsm_abi_version", "rsm_run_csr", "rsm_cg_solve", "rsm_time_next_kernel", "rsm_run_chain_train",
+    "rsm_plan_ports",
 ]
 
 _lib = None
@@ -101,6 +109,8 @@ def load(path: str = LIB_PATH):
     i32 = ctypes.c_int32
     lib.rsm_validate.argtypes = [P(Space), P(Tiler), i32, P(Tiler), P(Task), u32]
     lib.rsm_plan.argtypes = [P(Space), P(Tiler), i32, P(Tiler), P(Task), u32, ctypes.c_char_p, i32]
+    lib.rsm_plan_ports.argtypes = [P(Space), P(Tiler), i32, P(Tiler), P(Task), u32, P(PortPlacement), i32,
+                                   P(i32)]
     lib.rsm_indices.argtypes = [P(Space), P(Tiler), vp, vp]
     lib.rsm_run.argtypes = [P(Space), P(Tiler), P(vp), i32, P(Tiler), vp, P(Task), u32, vp]
     lib.rsm_run_chain.argtypes = [P(Stage), i32, vp, P(vp), vp, u32, vp]
@@ -117,7 +127,7 @@ def load(path: str = LIB_PATH):
     lib.rsm_batch_query.argtypes = [vp, P(BatchInfo)]
     lib.rsm_batch_tile.argtypes = [vp, i32, P(i32), P(i32)]
     lib.rsm_batch_destroy.argtypes = [vp]
-    for name in ("rsm_validate", "rsm_plan", "rsm_indices", "rsm_run", "rsm_run_chain",
+    for name in ("rsm_validate", "rsm_plan", "rsm_plan_ports", "rsm_indices", "rsm_run", "rsm_run_chain",
                  "rsm_run_adjoint", "rsm_run_chain_adjoint", "rsm_batch_create", "rsm_batch_run",
                  "rsm_run_csr", "rsm_cg_solve", "rsm_run_chain_train", "rsm_batch_run_plain", "rsm_batch_query", "rsm_batch_tile", "rsm_batch_destroy"):
         getattr(lib, name).restype = st

@@ -1019,6 +1019,72 @@ rsm_status rsm_plan(const rsm_space* rep, const rsm_tiler* in, int32_t n_in, con
   RSM_GUARD_END
 }
 
+rsm_status rsm_plan_ports(const rsm_space* rep, const rsm_tiler* in, int32_t n_in, const rsm_tiler* out,
+                          const rsm_task* task, uint32_t flags, rsm_port_placement* ports, int32_t max_ports,
+                          int32_t* n_ports) {
+  RSM_GUARD_BEGIN
+  Checked c;
+  rsm_status s = check_task(rep, in, n_in, out, task, flags & ~RSM_CHECK_SINGLE_ASSIGN, &c);
+  if (s) return s;
+  if (!n_ports) return fail(RSM_E_INVALID, "n_ports is NULL");
+  const bool coeffs = task->kind == RSM_TASK_WSUM;
+  const int count = n_in + 1 + (coeffs ? 1 : 0);
+  *n_ports = count;
+  if (!ports || max_ports < count) return fail(RSM_E_INVALID, "ports array too short");
+  const Plan p = make_plan(*rep, in, n_in, *out, *task, flags, nullptr, c.n_rep, c.n_pat_in[0]);
+  constexpr int kThreadsPerWg = 256;
+  std::vector<rsm_port_placement> v(static_cast<size_t>(count));
+  for (int k = 0; k < count; ++k) {
+    v[size_t(k)] = rsm_port_placement{};
+    v[size_t(k)].port = k;
+    v[size_t(k)].is_output = k == n_in ? 1 : 0;
+    v[size_t(k)].space = RSM_MEM_GLOBAL;
+  }
+  auto set = [&](int k, int space, int64_t bytes) {
+    v[size_t(k)].space = space;
+    v[size_t(k)].bytes_per_workgroup = bytes;
+  };
+  const int64_t in_es = elem_size(in[0].dtype);
+  switch (p.fam) {
+    case Fam::Empty:
+    case Fam::Generic:
+      break;   // every element read and written in place
+    case Fam::PatternReduce:
+      // one pattern element per lane, reduced across the lane group
+      set(0, RSM_MEM_PRIVATE, kThreadsPerWg * in_es);
+      if (coeffs) set(n_in + 1, RSM_MEM_PRIVATE, kThreadsPerWg * 4);
+      break;
+    case Fam::Fir:
+      // each thread holds the taps of its window; the taps' weights are
+      // uniform across the workgroup
+      set(0, RSM_MEM_PRIVATE, int64_t(kThreadsPerWg) * p.win.taps * in_es);
+      if (coeffs) set(n_in + 1, RSM_MEM_CONSTANT, int64_t(p.win.taps) * 4);
+      break;
+    case Fam::Filter2D: {
+      // the tile's input region (halo included) and the k x k weights in LDS
+      const int64_t lds = int64_t(filter2d_lds_bytes(p.f2d.k, p.f2d.s, 1));
+      const int64_t wbytes = int64_t(12) * p.f2d.k * 4;
+      set(0, RSM_MEM_LOCAL, lds - wbytes);
+      if (coeffs) set(n_in + 1, RSM_MEM_LOCAL, wbytes);
+      break;
+    }
+    case Fam::Gemm: {
+      // double-buffered k-tiles of both operands in LDS; the output tile in
+      // accumulator registers for the whole k loop
+      const int compute = in[0].dtype == RSM_BF16 ? RSM_BF16 : RSM_F32;
+      const int64_t lds = gemm_lds_bytes_per_operand(p.gemm, compute);
+      const int64_t side = gemm_tile_side(p.gemm, compute);
+      set(0, RSM_MEM_LOCAL, lds);
+      if (n_in > 1) set(1, RSM_MEM_LOCAL, lds);
+      set(n_in, RSM_MEM_PRIVATE, side * side * 4);
+      break;
+    }
+  }
+  for (int k = 0; k < count; ++k) ports[k] = v[size_t(k)];
+  return RSM_OK;
+  RSM_GUARD_END
+}
+
 rsm_status rsm_indices(const rsm_space* rep, const rsm_tiler* t, int64_t* d_idx, void* hip_stream) {
   RSM_GUARD_BEGIN
   int64_t n_rep = 0, n_pat = 0;

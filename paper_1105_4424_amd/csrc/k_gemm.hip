@@ -533,18 +533,47 @@ const char* gemm_variant_name(const GemmArgs& a, int compute) {
   return "gemm_mfma_f32_nt";
 }
 
+namespace {
+
+// Kernel shape of a product: large tiles once the output has at least 200
+// tiles of 256 x 256 and the large kernel's 32-bit buffer offsets reach;
+// bn: BF16 B stored [K][N] with 16-byte aligned rows, read in place by the
+// large kernel (transposing LDS reads) without a transposed copy (its
+// offsets reach (K + 64) k rows plus N columns).
+struct GemmShape {
+  bool ta, tb, bn, big;
+};
+
+GemmShape gemm_shape(const GemmArgs& g, int compute, bool check_b_alignment) {
+  GemmShape s{};
+  const int64_t es = compute == RSM_BF16 ? 2 : 4;
+  s.ta = g.a_sk != 1;
+  s.tb = g.b_sk != 1;
+  const bool big_shape = int64_t(g.M) * g.N >= int64_t(256) * 256 * 200;
+  s.bn = compute == RSM_BF16 && s.tb && g.b_sn == 1 && big_shape &&
+         !(check_b_alignment && (reinterpret_cast<uintptr_t>(g.b) & 15)) && !((g.b_sk * 2) & 15) &&
+         (int64_t(g.K + 64) * g.b_sk + g.N) * 2 + 4096 < (int64_t(1) << 31);
+  const int64_t lda = s.ta ? g.K : g.a_sm;
+  const int64_t ldb = s.tb ? g.K : g.b_sn;
+  const int64_t a_span = (int64_t(g.M + kBig) * lda + g.K) * es;
+  const int64_t b_span = s.bn ? 0 : (int64_t(g.N + kBig) * ldb + g.K) * es;
+  s.big = big_shape && a_span < (int64_t(1) << 31) && b_span < (int64_t(1) << 31);
+  return s;
+}
+
+}  // namespace
+
+int64_t gemm_lds_bytes_per_operand(const GemmArgs& g, int compute) {
+  return gemm_shape(g, compute, false).big ? int64_t(2) * kBig * kPitch : int64_t(2) * kBM * kPitch;
+}
+
+int gemm_tile_side(const GemmArgs& g, int compute) { return gemm_shape(g, compute, false).big ? kBig : kBM; }
+
 hipError_t launch_gemm(const GemmArgs& g, int compute, hipStream_t st) {
   (void)hipGetLastError();  // clear a stale error left by an unrelated earlier call
   const size_t es = compute == RSM_BF16 ? 2 : 4;
-  const bool ta = g.a_sk != 1, tb = g.b_sk != 1;
-  // large tiles once the output has at least 200 tiles of 256 x 256
-  const bool big_shape = int64_t(g.M) * g.N >= int64_t(256) * 256 * 200;
-  // BF16 B stored [K][N] with 16-byte aligned rows goes to the large-tile
-  // kernel as it is (transposing LDS reads), without a transposed copy; its
-  // 32-bit buffer offsets reach (K + 64) k rows plus N columns
-  const bool bn = compute == RSM_BF16 && tb && g.b_sn == 1 && big_shape &&
-                  !(reinterpret_cast<uintptr_t>(g.b) & 15) && !((g.b_sk * 2) & 15) &&
-                  (int64_t(g.K + 64) * g.b_sk + g.N) * 2 + 4096 < (int64_t(1) << 31);
+  const GemmShape shape = gemm_shape(g, compute, true);
+  const bool ta = shape.ta, tb = shape.tb, bn = shape.bn;
   const size_t a_bytes = ta ? ((size_t(g.M) * g.K * es + 255) & ~size_t(255)) : 0;
   const size_t b_bytes = tb && !bn ? ((size_t(g.N) * g.K * es + 255) & ~size_t(255)) : 0;
   char* ws = nullptr;
@@ -594,9 +623,7 @@ hipError_t launch_gemm(const GemmArgs& g, int compute, hipStream_t st) {
   }
   // large tiles: their buffer loads use 32-bit offsets, which must stay
   // below 2 GiB up to the last row of the last, padded 256-row block plus K
-  const int64_t a_span = (int64_t(g.M + kBig) * p.lda + g.K) * int64_t(es);
-  const int64_t b_span = bn ? 0 : (int64_t(g.N + kBig) * p.ldb + g.K) * int64_t(es);
-  const bool big = big_shape && a_span < (int64_t(1) << 31) && b_span < (int64_t(1) << 31);
+  const bool big = shape.big;
   if (bn && !big) {
     fail(RSM_E_HIP, "gemm: internal: [K][N] operand planned for the large-tile kernel");
     return hipErrorInvalidValue;

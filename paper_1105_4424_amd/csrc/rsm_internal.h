@@ -330,6 +330,8 @@ hipError_t launch_generic_coef_grad(const GenericCoefGradArgs& a, int max_rank, 
 hipError_t launch_reduce_rows(const float* partial, int64_t n_rows, int64_t n_cols,
                               float* out, int accumulate, hipStream_t st);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
+int64_t gemm_lds_bytes_per_operand(const GemmArgs& g, int compute);   // LDS per workgroup, one operand
+int gemm_tile_side(const GemmArgs& g, int compute);                   // output tile side (128 or 256)
 hipError_t launch_gemm(const GemmArgs& a, int compute, hipStream_t st);
 const char* gemm_variant_name(const GemmArgs& a, int compute);
 bool gemm_supported(const GemmArgs& a, int compute);

@@ -130,6 +130,26 @@ def validate(problem, dtypes: Sequence[torch.dtype] = (torch.float32,),
                             _abi.CHECK_SINGLE_ASSIGN if check_single_assign else 0))
 
 
+def plan_ports(problem, dtypes: Sequence[torch.dtype] = (torch.float32,), flags: int = 0):
+    """Where the planned kernel keeps each port (inputs, output, then the
+    coefficients of a weighted sum): a list of (space, bytes per workgroup)
+    with space one of "global", "constant", "local", "private"."""
+    lib = _abi.load()
+    codes = [_DTYPES[d] for d in dtypes]
+    tin = (_abi.Tiler * len(problem.inputs))(*[_tiler(t, codes[min(i, len(codes) - 1)])
+                                               for i, t in enumerate(problem.inputs)])
+    c0 = codes[0]
+    out_code = c0 if problem.task == _abi.TASK_COPY else (_abi.F64 if c0 == _abi.F64 else _abi.F32)
+    comp = _abi.F64 if c0 == _abi.F64 else _COMPUTE.get(getattr(problem, "compute", "f32"))
+    task = _abi.Task(problem.task, comp, ctypes.c_void_p(1).value)
+    ports = (_abi.PortPlacement * 8)()
+    n = ctypes.c_int32(0)
+    _check(lib.rsm_plan_ports(ctypes.byref(_space(problem.rep_shape)), tin, len(problem.inputs),
+                              ctypes.byref(_tiler(problem.output, out_code)), ctypes.byref(task), flags,
+                              ports, 8, ctypes.byref(n)))
+    return [(_abi.MEM_SPACES[ports[k].space], int(ports[k].bytes_per_workgroup)) for k in range(n.value)]
+
+
 def plan(problem, dtypes: Sequence[torch.dtype] = (torch.float32,), flags: int = 0,
          compute: str = None) -> str:
     """Kernel family the planner picks (host only)."""

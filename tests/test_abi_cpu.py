@@ -40,8 +40,8 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "rsm.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(rsm_space), sizeof(rsm_tiler), sizeof(rsm_task),
-         sizeof(rsm_stage), sizeof(rsm_problem), sizeof(rsm_batch_info));
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(rsm_space), sizeof(rsm_tiler), sizeof(rsm_task),
+         sizeof(rsm_stage), sizeof(rsm_problem), sizeof(rsm_batch_info), sizeof(rsm_port_placement));
   printf("%zu %zu %zu %zu %zu %zu\n", offsetof(rsm_tiler, pattern_rank), offsetof(rsm_tiler, origin),
          offsetof(rsm_tiler, paving), offsetof(rsm_tiler, fitting), offsetof(rsm_problem, d_in),
          offsetof(rsm_task, coeffs));
@@ -53,7 +53,7 @@ int main(void) {
     sizes, offs = [list(map(int, l.split())) for l in
                    subprocess.check_output([str(exe)]).decode().strip().splitlines()]
     assert sizes == [ctypes.sizeof(c) for c in (_abi.Space, _abi.Tiler, _abi.Task, _abi.Stage,
-                                                _abi.Problem, _abi.BatchInfo)]
+                                                _abi.Problem, _abi.BatchInfo, _abi.PortPlacement)]
     assert offs == [_abi.Tiler.pattern_rank.offset, _abi.Tiler.origin.offset,
                     _abi.Tiler.paving.offset, _abi.Tiler.fitting.offset, _abi.Problem.d_in.offset,
                     _abi.Task.coeffs.offset]
@@ -155,6 +155,48 @@ def test_planner_routes_adjoints_to_their_kernels():
     # 2-D windows: generic
     p2 = W.filter2d_problem(20, 24, 3, 1)
     assert rsm.plan(p2, flags=A) == "generic_adjoint"
+
+
+def test_port_placement_follows_the_planned_kernel():
+    # the memory space of every port (the paper's MemoryMapping, realised on
+    # gfx950) for each kernel family, with the staged bytes per workgroup
+    import torch
+    x, p0 = W.small_sum()
+    assert rsm.plan_ports(p0) == [("private", 1024), ("global", 0)]
+    ts = W.two_stage_filter(frames=2, rows=16, cols=32)
+    # 8 column taps: each thread's window in registers, weights uniform
+    assert rsm.plan_ports(ts.h) == [("private", 256 * 8 * 4), ("global", 0), ("constant", 32)]
+    # forced onto the generic kernel: every port read and written in place
+    assert rsm.plan_ports(ts.h, flags=_abi.FORCE_GENERIC) == [("global", 0)] * 3
+    # k x k windows: input region and weights staged in LDS
+    f = W.filter2d_problem(200, 300, 9, 1)
+    ports = rsm.plan_ports(f)
+    assert [sp for sp, _ in ports] == ["local", "global", "local"]
+    assert ports[2][1] == 12 * 9 * 4
+    # region rows x padded pitch of the tile class a single run uses:
+    # (32 - 1) + 9 rows, pitch 60 + 4 * 3 + 4 floats
+    assert ports[0][1] == (31 + 9) * 76 * 4
+    # matrix products: both operands double-buffered in LDS, the output tile
+    # in accumulators (256 x 256 tiles from 200 tiles of output upward)
+    mm = W.matmul_tilers(4096, 4096, 4096)
+    mm.compute = "bf16"
+    assert rsm.plan_ports(mm, dtypes=(torch.bfloat16,)) == [("local", 2 * 256 * 144)] * 2 + [
+        ("private", 256 * 256 * 4)]
+    small = W.matmul_tilers(256, 256, 256)
+    small.compute = "bf16"
+    assert rsm.plan_ports(small, dtypes=(torch.bfloat16,)) == [("local", 2 * 128 * 144)] * 2 + [
+        ("private", 128 * 128 * 4)]
+    # a too-short port array is an error
+    lib = _abi.load()
+    n = ctypes.c_int32(0)
+    ports1 = (_abi.PortPlacement * 1)()
+    import paper_1105_4424_amd.rsm as R
+    task = _abi.Task(W.SUM, _abi.F32, None)
+    tin = (_abi.Tiler * 1)(R._tiler(p0.inputs[0], _abi.F32))
+    st = lib.rsm_plan_ports(ctypes.byref(R._space(p0.rep_shape)), tin, 1,
+                            ctypes.byref(R._tiler(p0.output, _abi.F32)), ctypes.byref(task), 0, ports1, 1,
+                            ctypes.byref(n))
+    assert st != 0 and n.value == 2
 
 
 def test_empty_repetition_space_is_a_no_op_plan():
