@@ -306,7 +306,9 @@ rsm_status rsm_run_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
  * replayed from a HIP graph that the library captures once and keeps per
  * device while the call's arguments (buffers, sizes, tol, max_iter,
  * check_every) stay the same; RSM_NO_GRAPH launches the batches directly
- * instead (the same kernels: the same bits).  Limits: n, nnz < 2^31.
+ * instead (the same kernels: the same bits).  The library keeps, per device,
+ * one capture stream (default priority) and the last captured graph until
+ * the process ends.  Limits: n, nnz < 2^31.
  */
 typedef struct {
   int64_t iterations;
