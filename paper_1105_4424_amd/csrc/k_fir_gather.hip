@@ -80,23 +80,25 @@ __global__ void __launch_bounds__(kBlock) fir_gx_gather_kernel(FirGatherArgs a) 
 // Taps along columns with steps of at most 16: input gradient and weight
 // gradient in one pass.  Work items are (array row, chunk of kRC repetitions
 // along the row).  For each item a workgroup stages the chunk's gy values
-// (with the K - 1 before it) in LDS, then
-//   * writes gx for the positions it owns: v = (a - o) mod A, the first lift
-//     of column a, in [chunk p kRC, (chunk + 1) p kRC); further lifts (rows
-//     that the windows go round more than once) read gy from memory;
-//   * adds gy[r] x[(o + p r + i) mod A] over the chunk's pairs (r, i) into
-//     one partial per lane, each lane keeping one tap i for the whole run,
-//     so the partials reduce in a fixed order.
-// The next item's gy values and x taps are loaded into registers while the
-// current item is computed, so the two memory round trips of an item overlap
-// the previous item's work.  x is read once and gx written once; nothing is
-// atomic.
+// (with the K - 1 before it) in LDS; then each lane walks the positions v it
+// owns, v = (a - o) mod A (the first lift of column a) in [chunk p kRC,
+// (chunk + 1) p kRC), in steps of p (kBlock / p), so that its phase
+// j = v mod p never changes.  At each position the pairs of the first lift
+// are r = floor(v / p) - k, i = j + k p (k < K): the lane adds c_i gy[r]
+// into dL/dx and x[a] gy[r] into its weight-gradient slot k, whose tap
+// j + k p is fixed for the lane.  Pairs of further lifts (windows that go
+// round the row more than once) take a per-lane loop: lane (li, lr) keeps
+// tap li for the repetitions of the chunk whose pair lies past A.  x is read
+// once, coalesced, and dL/dx written once; the partials of a tap are summed
+// over fixed lanes in a fixed order, so nothing is atomic and every bit is
+// reproducible.  The next item's gy values are loaded while the current
+// item is computed.
 // ---------------------------------------------------------------------------
 constexpr int kRC = 256;        // repetitions per chunk
 constexpr int kMaxTaps = 16;
-constexpr int kXR = 16;         // x taps per lane per item: ceil(kRC / (kBlock / taps)) <= 16
 constexpr uint32_t kBufferWord3 = 0x00020000;   // 32-bit data format, raw access
 constexpr uint32_t kOutOfRange = 0x80000000u;   // a read here returns zero
+constexpr int kPos = 16;        // positions per lane per item: ceil(256 p / (p floor(256 / p))) <= 16
 
 // Work item -> array row, chunk, and the row's repetition offset in gy (-1 if
 // no repetition reads the row).
@@ -113,44 +115,22 @@ __device__ __forceinline__ void overlap_item(const FirOverlapArgs& a, uint32_t i
   g0 = (rb >= 0 && ro >= 0) ? (rb * w.rep[1] + ro) * w.rep[2] : -1;
 }
 
-// This thread's loads for one item, all issued unconditionally (a position
-// outside the row reads zero through the buffer range check): staged gy
-// values j = tid and tid + kBlock of repetition rs + j, and (GC) the x taps
-// of its weight-gradient pairs.  Pair m of lane (lr, li) is repetition
-// r0 + lr + m per, tap li, at column (o + p r + li) mod A2: the column
-// advances by (p per) mod A2 from one pair to the next.
-template <bool GC>
-__device__ __forceinline__ void overlap_fetch(const FirOverlapArgs& a, int row, int chunk, int g0, int K,
-                                              int per, int li, int lr, float& g0v, float& g1v,
-                                              float (&xr)[kXR]) {
-  const Win3& w = a.w;
-  const int R = w.rep[2], A2 = w.A[2];
+// This thread's staged gy values of an item (j = tid and tid + kBlock of
+// repetition rs + j), loaded unconditionally: a repetition outside [0, R),
+// or any repetition of a row nothing reads, reads zero.
+__device__ __forceinline__ void overlap_fetch_gy(const FirOverlapArgs& a, int chunk, int g0, int K, float& g0v,
+                                                 float& g1v) {
+  const int R = a.w.rep[2];
   const bool read = g0 >= 0;
   const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float*>(a.gy) + (read ? g0 : 0), short(0), read ? R * 4 : 0, int(kBufferWord3));
-  const int r0 = chunk * kRC, rs = r0 - (K - 1);
+  const int rs = chunk * kRC - (K - 1);
   const int j0 = int(threadIdx.x), j1 = j0 + kBlock;
   const int q0 = rs + j0, q1 = rs + j1;
   const uint32_t o0 = (j0 < kRC + K - 1 && q0 >= 0 && q0 < R) ? uint32_t(q0) * 4u : kOutOfRange;
   const uint32_t o1 = (j1 < kRC + K - 1 && q1 >= 0 && q1 < R) ? uint32_t(q1) * 4u : kOutOfRange;
   g0v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, o0, 0, 0));
   g1v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, o1, 0, 0));
-  if (GC) {
-    const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float*>(a.x) + int64_t(row) * A2, short(0), read ? A2 * 4 : 0, int(kBufferWord3));
-    // pairs of this lane inside the chunk: m < n_m
-    const int left = min(r0 + kRC, R) - r0 - lr;
-    const int n_m = (lr < per && left > 0) ? (left + per - 1) / per : 0;
-    const uint32_t u0 = uint32_t(a.o_mod + w.p[2] * (r0 + lr) + li);
-    uint32_t e = u0 - uint32_t(A2) * fdiv(u0, a.div_a2);
-#pragma unroll
-    for (int m = 0; m < kXR; ++m) {
-      xr[m] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, m < n_m ? e * 4u : kOutOfRange,
-                                                                            0, 0));
-      e += uint32_t(a.step_mod);
-      if (e >= uint32_t(A2)) e -= uint32_t(A2);
-    }
-  }
 }
 
 // KS: taps per lift K as a compile-time constant (1..4), or 0 for any K.
@@ -160,95 +140,138 @@ __global__ void __launch_bounds__(kBlock) fir_adjoint_overlap_cols_kernel(FirOve
   const Win3& w = a.w;
   const int A2 = w.A[2], R = w.rep[2], p = w.p[2], T = w.taps;
   const int K = KS ? KS : (T + p - 1) / p;   // taps of one lift that can meet an element
+  constexpr int KM = KS ? KS : kMaxTaps;
   const int span = p * (R - 1) + T;
-  const int W = p * kRC;           // positions owned by one chunk
+  const int W = p * kRC;                     // positions owned by one chunk
+  const int qstep = kBlock / p;              // repetitions per position step
+  const int step = p * qstep;                // positions per step: a multiple of p
   // coefficients padded with zeros to 2 kMaxTaps: j + k p < K p <= T + p - 1
   // is always a valid index, so the tap loop needs no bound test
   __shared__ float cs[2 * kMaxTaps];
   __shared__ float gys[kRC + kMaxTaps];
   __shared__ float red[kBlock];
-  if (threadIdx.x < 2 * kMaxTaps) cs[threadIdx.x] = int(threadIdx.x) < T ? a.c[threadIdx.x] : 0.0f;
-  const int per = kBlock / T;      // repetitions per weight-gradient pass
-  const int li = int(threadIdx.x) % T, lr = int(threadIdx.x) / T;
-  const bool gc_lane = GC && lr < per;
-  float gacc = 0.0f;
+  const int t = int(threadIdx.x);
+  if (t < 2 * kMaxTaps) cs[t] = t < T ? a.c[t] : 0.0f;
+  const int jph = t % p;                     // this lane's position phase
+  const int per = kBlock / T;                // further-lift pairs: repetitions per pass
+  const int li = t % T, lr = t / T;
+  float gcl[KM];                             // first-lift slots: tap jph + k p
+#pragma unroll
+  for (int k = 0; k < KM; ++k) gcl[k] = 0.0f;
+  float gext = 0.0f;                         // further-lift pairs: tap li
 
-  // Per item: stage gy, use the x taps, then issue the next item's loads
-  // into the same registers (a past-the-end item loads nothing: every
-  // offset is out of range) and write this item's gx while they travel.
   uint32_t item = blockIdx.x;
   int row, chunk, g0;
   overlap_item(a, item, row, chunk, g0);
-  float gv0, gv1, xr[kXR];
-  overlap_fetch<GC>(a, row, chunk, g0, K, per, li, lr, gv0, gv1, xr);
+  float gv0, gv1;
+  overlap_fetch_gy(a, chunk, g0, K, gv0, gv1);
   for (; item < a.n_items; item += gridDim.x) {
     const bool read = g0 >= 0;
     const int r0 = chunk * kRC, rs = r0 - (K - 1);
-    __syncthreads();               // the previous item's readers of gys are done
-    if (int(threadIdx.x) < kRC + K - 1) gys[threadIdx.x] = gv0;
-    if (int(threadIdx.x) + kBlock < kRC + K - 1) gys[threadIdx.x + kBlock] = gv1;
-    __syncthreads();
-    if (GC && read && gc_lane) {
-      const int r_end = min(r0 + kRC, R);
+    // this item's x values at the lane's positions, all loads issued before
+    // any is used (positions past the chunk, or rows nothing reads, read zero)
+    float xr[kPos];
+    if (GC) {
+      const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float*>(a.x) + int64_t(row) * A2, short(0), read ? A2 * 4 : 0, int(kBufferWord3));
+      const int v_end = min((chunk + 1) * W, A2);
 #pragma unroll
-      for (int m = 0; m < kXR; ++m) {
-        const int r = r0 + lr + m * per;
-        if (r < r_end) gacc = fmaf(gys[r - rs], xr[m], gacc);
+      for (int m = 0; m < kPos; ++m) {
+        const int v = chunk * W + t + m * step;
+        int e = a.o_mod + v;
+        if (e >= A2) e -= A2;
+        const uint32_t off = (t < step && v < v_end) ? uint32_t(e) * 4u : kOutOfRange;
+        xr[m] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, off, 0, 0));
       }
     }
+    __syncthreads();               // the previous item's readers of gys are done
+    if (t < kRC + K - 1) gys[t] = gv0;
+    if (t + kBlock < kRC + K - 1) gys[t + kBlock] = gv1;
+    __syncthreads();
     const int cur_row = row, cur_chunk = chunk, cur_g0 = g0;
     const uint32_t nxt = item + gridDim.x;
     g0 = -1;
     if (nxt < a.n_items) overlap_item(a, nxt, row, chunk, g0);
-    overlap_fetch<GC>(a, row, chunk, g0, K, per, li, lr, gv0, gv1, xr);
-    if (a.gx) {
-      float* gxrow = a.gx + int64_t(cur_row) * A2;
-      const int v_end = min((cur_chunk + 1) * W, A2);
-      for (int v = cur_chunk * W + int(threadIdx.x); v < v_end; v += kBlock) {
-        float acc = 0.0f;
-        // first lift: r = q - k, i = j + k p.  q - k - rs lies in
-        // [0, kRC + K - 1) for every owned v, and the staged gy is zero for
-        // r outside [0, R) and in rows no repetition reads
-        if (v < span) {
-          const int q = int(fdiv(uint32_t(v), a.div_p));
-          const int j = v - q * p;
+    overlap_fetch_gy(a, chunk, g0, K, gv0, gv1);   // the next item's gy travels meanwhile
+
+    const float* __restrict__ xrow = GC ? a.x + int64_t(cur_row) * A2 : nullptr;
+    float* gxrow = a.gx ? a.gx + int64_t(cur_row) * A2 : nullptr;
+    const int v_end = min((cur_chunk + 1) * W, A2);
+    const int v0 = cur_chunk * W + t;
+    const int q0 = int(fdiv(uint32_t(v0), a.div_p));
 #pragma unroll
-          for (int k = 0; k < (KS ? KS : kMaxTaps); ++k) {
-            if (!KS && k >= K) break;
-            acc = fmaf(cs[j + k * p], gys[q - k - rs], acc);
-          }
-        }
-        if (read) {
-          // further lifts: with one chunk per row every repetition is staged
-          // in LDS, otherwise gy is read from memory
-          if (a.n_chunks == 1) {
-            for (int u = v + A2; u < span; u += A2) {
-              int r = int(fdiv(uint32_t(u), a.div_p));
-              if (r > R - 1) r = R - 1;
-              for (int i = u - p * r; r >= 0 && i < T; --r, i += p) acc = fmaf(cs[i], gys[r - rs], acc);
-            }
-          } else {
-            for (int u = v + A2; u < span; u += A2) {
-              int r = int(fdiv(uint32_t(u), a.div_p));
-              if (r > R - 1) r = R - 1;
-              for (int i = u - p * r; r >= 0 && i < T; --r, i += p) acc = fmaf(cs[i], a.gy[cur_g0 + r], acc);
-            }
-          }
-        }
+    for (int m = 0; m < kPos; ++m) {
+      const int v = v0 + m * step;
+      if (!(t < step && v < v_end && (gxrow || (GC && read)))) continue;
+      const int q = q0 + m * qstep;
+      {
         int e = a.o_mod + v;
         if (e >= A2) e -= A2;
-        if (ACC) acc += gxrow[e];
-        gxrow[e] = acc;
+        const float xv = GC ? xr[m] : 0.0f;
+        float acc = 0.0f;
+        // r = q - k: q - k - rs lies in [0, kRC + K - 1) for every owned v,
+        // and the staged gy is zero for r outside [0, R)
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+          if (!KS && k >= K) break;
+          const float g = gys[q - k - rs];
+          acc = fmaf(cs[jph + k * p], g, acc);
+          if (GC) gcl[k] = fmaf(xv, g, gcl[k]);
+        }
+        if (gxrow) {
+          if (read) {
+            // further lifts: with one chunk per row every repetition is
+            // staged in LDS, otherwise gy is read from memory
+            if (a.n_chunks == 1) {
+              for (int u = v + A2; u < span; u += A2) {
+                int r = int(fdiv(uint32_t(u), a.div_p));
+                if (r > R - 1) r = R - 1;
+                for (int i = u - p * r; r >= 0 && i < T; --r, i += p) acc = fmaf(cs[i], gys[r - rs], acc);
+              }
+            } else {
+              for (int u = v + A2; u < span; u += A2) {
+                int r = int(fdiv(uint32_t(u), a.div_p));
+                if (r > R - 1) r = R - 1;
+                for (int i = u - p * r; r >= 0 && i < T; --r, i += p)
+                  acc = fmaf(cs[i], a.gy[cur_g0 + r], acc);
+              }
+            }
+          }
+          if (ACC) acc += gxrow[e];
+          gxrow[e] = acc;
+        }
+      }
+    }
+    if (GC && read && lr < per && span > A2) {
+      // weight-gradient pairs past the row's end (u = p r + li >= A2) of
+      // this chunk's repetitions: r >= ceil((A2 - li) / p)
+      const int r_end = min(r0 + kRC, R);
+      const int r_lo = (A2 - li + p - 1) / p;
+      int r = r0 + lr;
+      if (r < r_lo) r += ((r_lo - r + per - 1) / per) * per;
+      for (; r < r_end; r += per) {
+        const int e = (a.o_mod + p * r + li) % A2;
+        gext = fmaf(gys[r - rs], xrow[e], gext);
       }
     }
   }
   if (GC) {
-    red[threadIdx.x] = gc_lane ? gacc : 0.0f;
+    // tap i = j + k p: slot k of the lanes of phase j, then the further-lift
+    // sums of the lanes keeping tap i; each in ascending lane order
+    float s = 0.0f;
+    for (int k = 0; k < K; ++k) {
+      __syncthreads();
+      red[t] = t < step ? gcl[k] : 0.0f;
+      __syncthreads();
+      if (t < T && t / p == k)
+        for (int l = t % p; l < step; l += p) s += red[l];
+    }
     __syncthreads();
-    if (int(threadIdx.x) < T) {
-      float s = 0.0f;
-      for (int l = threadIdx.x; l < per * T; l += T) s += red[l];
-      a.partial[int64_t(blockIdx.x) * T + threadIdx.x] = s;
+    red[t] = lr < per ? gext : 0.0f;
+    __syncthreads();
+    if (t < T) {
+      for (int l = t; l < per * T; l += T) s += red[l];
+      a.partial[int64_t(blockIdx.x) * T + t] = s;
     }
   }
 }
