@@ -65,21 +65,38 @@ __device__ __forceinline__ bool lead() { return blockIdx.x == 0 && threadIdx.x =
 // y[r] = sum_k vals[k] v(col_idx[k]) for the rows of this group of G lanes,
 // two rows at a time; calls f(r, y_r) on lane 0 of the group.  Each lane
 // takes entries lane, lane + G, ..., lane + (E - 1) G of a row chunk and
-// issues all index and value loads of both rows before the gathers of v, so
-// a lane has 4 E loads in flight.  Row bounds are clamped into [0, nnz] and
-// columns outside [0, n) contribute nothing.
+// issues all index and value loads of both rows, then all gathers of v,
+// before the first product, so a lane has 4 E loads in flight.  Row bounds
+// are clamped into [0, nnz] and columns outside [0, n) contribute nothing.
+// BUF (matrix and vectors under 2 GiB): raw buffer loads, all issued
+// unconditionally; an entry past its row reads a zero value and column and
+// gathers zero (v(c, false) must return 0), so no load waits on a branch.
 constexpr int kEntries = 4;   // E
+constexpr uint32_t kBufferWord3 = 0x00020000;   // 32-bit data format, raw access
+constexpr uint32_t kOutOfRange = 0x80000000u;   // a read here returns zero
 
-template <int G, typename V, typename F>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), short(0), int(bytes), int(kBufferWord3));
+}
+
+__device__ __forceinline__ double load_f64(__amdgpu_buffer_rsrc_t r, int32_t c, bool ok) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, ok ? uint32_t(c) * 8u : kOutOfRange, 0, 0));
+}
+
+template <int G, bool BUF, typename V, typename F>
 __device__ __forceinline__ void spmv_rows(const CgArgs& a, V v, F f) {
   constexpr int E = kEntries;
   const int lane = threadIdx.x & (G - 1);
   const int64_t groups = int64_t(gridDim.x) * (kBlock / G);
+  const __amdgpu_buffer_rsrc_t rc = rsrc(a.col_idx, BUF ? a.nnz * 4 : 0);
+  const __amdgpu_buffer_rsrc_t rv = rsrc(a.vals, BUF ? a.nnz * 8 : 0);
   for (int64_t r0 = (int64_t(blockIdx.x) * kBlock + threadIdx.x) / G; r0 < a.n; r0 += 2 * groups) {
     const int64_t r1 = r0 + groups;
     const bool has1 = r1 < a.n;
+    const int64_t r1c = has1 ? r1 : r0;
     int64_t b0 = a.row_ptr[r0], e0 = a.row_ptr[r0 + 1];
-    int64_t b1 = has1 ? a.row_ptr[r1] : 0, e1 = has1 ? a.row_ptr[r1 + 1] : 0;
+    int64_t b1 = a.row_ptr[r1c], e1 = a.row_ptr[r1c + 1];
+    if (!has1) e1 = b1;
     b0 = b0 < 0 ? 0 : (b0 > a.nnz ? a.nnz : b0);
     e0 = e0 < b0 ? b0 : (e0 > a.nnz ? a.nnz : e0);
     b1 = b1 < 0 ? 0 : (b1 > a.nnz ? a.nnz : b1);
@@ -91,15 +108,32 @@ __device__ __forceinline__ void spmv_rows(const CgArgs& a, V v, F f) {
 #pragma unroll
       for (int j = 0; j < E; ++j) {
         const int64_t q0 = k0 + j * G, q1 = k1 + j * G;
-        c0[j] = q0 < e0 ? a.col_idx[q0] : -1;
-        v0[j] = q0 < e0 ? a.vals[q0] : 0.0;
-        c1[j] = q1 < e1 ? a.col_idx[q1] : -1;
-        v1[j] = q1 < e1 ? a.vals[q1] : 0.0;
+        if (BUF) {
+          const bool in0 = q0 < e0, in1 = q1 < e1;
+          c0[j] = int32_t(__builtin_amdgcn_raw_buffer_load_b32(rc, in0 ? uint32_t(q0) * 4u : kOutOfRange, 0, 0));
+          v0[j] = __builtin_bit_cast(
+              double, __builtin_amdgcn_raw_buffer_load_b64(rv, in0 ? uint32_t(q0) * 8u : kOutOfRange, 0, 0));
+          c1[j] = int32_t(__builtin_amdgcn_raw_buffer_load_b32(rc, in1 ? uint32_t(q1) * 4u : kOutOfRange, 0, 0));
+          v1[j] = __builtin_bit_cast(
+              double, __builtin_amdgcn_raw_buffer_load_b64(rv, in1 ? uint32_t(q1) * 8u : kOutOfRange, 0, 0));
+        } else {
+          c0[j] = q0 < e0 ? a.col_idx[q0] : -1;
+          v0[j] = q0 < e0 ? a.vals[q0] : 0.0;
+          c1[j] = q1 < e1 ? a.col_idx[q1] : -1;
+          v1[j] = q1 < e1 ? a.vals[q1] : 0.0;
+        }
       }
+      double x0[E], x1[E];
 #pragma unroll
       for (int j = 0; j < E; ++j) {
-        if (uint32_t(c0[j]) < uint32_t(a.n)) acc0 += v0[j] * v(c0[j]);
-        if (uint32_t(c1[j]) < uint32_t(a.n)) acc1 += v1[j] * v(c1[j]);
+        x0[j] = v(c0[j], k0 + j * G < e0 && uint32_t(c0[j]) < uint32_t(a.n));
+        x1[j] = v(c1[j], k1 + j * G < e1 && uint32_t(c1[j]) < uint32_t(a.n));
+      }
+      if (BUF) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        if (BUF || uint32_t(c0[j]) < uint32_t(a.n)) acc0 += v0[j] * x0[j];
+        if (BUF || uint32_t(c1[j]) < uint32_t(a.n)) acc1 += v1[j] * x1[j];
       }
     }
 #pragma unroll
@@ -116,12 +150,14 @@ __device__ __forceinline__ void spmv_rows(const CgArgs& a, V v, F f) {
 
 // r = b - A x0; P[1] = 0 (p_{-1}: p_0 = r_0 + 0 p_{-1}); partials of <r,r>
 // and <b,b>.
-template <int G>
+template <int G, bool BUF>
 __global__ void __launch_bounds__(kBlock) cg_init_kernel(CgArgs a) {
   __shared__ double lds[kBlock];
   double rr = 0.0, bb = 0.0;
   const double* __restrict__ x = a.x;
-  spmv_rows<G>(a, [&](int32_t c) { return x[c]; }, [&](int64_t r, double ax) {
+  const __amdgpu_buffer_rsrc_t rx = rsrc(x, BUF ? a.n * 8 : 0);
+  auto gather = [&](int32_t c, bool ok) { return BUF ? load_f64(rx, c, ok) : (ok ? x[c] : 0.0); };
+  spmv_rows<G, BUF>(a, gather, [&](int64_t r, double ax) {
     const double b = a.b[r];
     const double res = b - ax;
     a.r[r] = res;
@@ -158,7 +194,7 @@ __global__ void __launch_bounds__(kBlock) cg_start_kernel(CgArgs a) {
   }
 }
 
-template <int G>
+template <int G, bool BUF>
 __global__ void __launch_bounds__(kBlock) cg_spmv_kernel(CgArgs a) {
   __shared__ double lds[kBlock];
   const double rho = partial_sum(a.part_rr, a.grid_vec, lds);
@@ -177,7 +213,11 @@ __global__ void __launch_bounds__(kBlock) cg_spmv_kernel(CgArgs a) {
   const double* __restrict__ p_old = (k & 1) ? a.p0 : a.p1;
   double* __restrict__ p_new = (k & 1) ? a.p1 : a.p0;
   double pq = 0.0;
-  spmv_rows<G>(a, [&](int32_t c) { return fma(beta, p_old[c], r[c]); }, [&](int64_t i, double q) {
+  const __amdgpu_buffer_rsrc_t rr_ = rsrc(r, BUF ? a.n * 8 : 0), rp_ = rsrc(p_old, BUF ? a.n * 8 : 0);
+  auto gather = [&](int32_t c, bool ok) {
+    return BUF ? fma(beta, load_f64(rp_, c, ok), load_f64(rr_, c, ok)) : (ok ? fma(beta, p_old[c], r[c]) : 0.0);
+  };
+  spmv_rows<G, BUF>(a, gather, [&](int64_t i, double q) {
     const double p = fma(beta, p_old[i], r[i]);
     p_new[i] = p;
     a.q[i] = q;
@@ -211,18 +251,26 @@ __global__ void __launch_bounds__(kBlock) cg_xr_kernel(CgArgs a) {
   if (lead()) a.st->k = k + 1;
 }
 
-template <int G>
-hipError_t launch_g(const CgArgs& a, bool init, int iters, hipStream_t st) {
+template <int G, bool BUF>
+hipError_t launch_gb(const CgArgs& a, bool init, int iters, hipStream_t st) {
   const unsigned gr = unsigned(a.grid_rows), gv = unsigned(a.grid_vec);
   if (init) {
-    cg_init_kernel<G><<<gr, kBlock, 0, st>>>(a);
+    cg_init_kernel<G, BUF><<<gr, kBlock, 0, st>>>(a);
     cg_start_kernel<<<1, kBlock, 0, st>>>(a);
   }
   for (int i = 0; i < iters; ++i) {
-    cg_spmv_kernel<G><<<gr, kBlock, 0, st>>>(a);
+    cg_spmv_kernel<G, BUF><<<gr, kBlock, 0, st>>>(a);
     cg_xr_kernel<<<gv, kBlock, 0, st>>>(a);
   }
   return hipGetLastError();
+}
+
+// buffer offsets are 32-bit: values (8 B per entry) and vectors under 2 GiB
+template <int G>
+hipError_t launch_g(const CgArgs& a, bool init, int iters, hipStream_t st) {
+  const int64_t lim = int64_t(1) << 31;
+  if (a.nnz * 8 < lim && a.n * 8 < lim) return launch_gb<G, true>(a, init, iters, st);
+  return launch_gb<G, false>(a, init, iters, st);
 }
 
 }  // namespace
