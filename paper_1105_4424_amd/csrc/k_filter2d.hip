@@ -45,6 +45,16 @@ __host__ __device__ constexpr int lds_floats(int K, int S, int RY) {
   return lds_rows(K, S, RY) * lds_pitch(K, S) + kWPitch * K;
 }
 
+// The problem's arrays live in device global memory.  Their pointers come
+// out of a descriptor read from memory, so without these casts the compiler
+// addresses them as generic ("flat") memory, whose accesses count against
+// the LDS wait counter too: every LDS read of a tile would then also wait
+// for the tile's outstanding global loads and stores.
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) const float gcfloat;
+__device__ __forceinline__ gcfloat* global_in(const float* p) { return (gcfloat*)(p); }
+__device__ __forceinline__ gfloat* global_out(float* p) { return (gfloat*)(p); }
+
 __device__ __forceinline__ int mod_pos(int v, int n) {
   // v >= 0 here; reduce into [0, n)
   return v < n ? v : v % n;
@@ -67,7 +77,7 @@ __device__ __forceinline__ void compute_tile(const Filter2DProblem& p, int64_t l
   constexpr int SEG4 = seg4_of(K, S);
   int frame, ty, tx;
   tile_pos(p, local, &frame, &ty, &tx);
-  float* __restrict__ y = p.y + int64_t(frame) * p.RH * p.RW;
+  gfloat* __restrict__ y = global_out(p.y) + int64_t(frame) * p.RH * p.RW;
   const float* lw = lds + LR * LP;
   const int t = threadIdx.x;
   const int tr = t >> 4, tc = t & 15;
@@ -123,7 +133,7 @@ __device__ __forceinline__ void filter_tile(const Filter2DProblem p, int64_t loc
 
   int frame, ty, tx;
   tile_pos(p, local, &frame, &ty, &tx);
-  const float* __restrict__ x = p.x + int64_t(frame) * p.H * p.W;
+  gcfloat* __restrict__ x = global_in(p.x) + int64_t(frame) * p.H * p.W;
 
   // ---- stage the tile's input region, wrapping modulo the array shape ----
   // Thread (rq, lane) stages rows rq, rq + 4, ... at columns lane and
@@ -144,9 +154,9 @@ __device__ __forceinline__ void filter_tile(const Filter2DProblem p, int64_t loc
   // cannot prove the weights unaliased by the output, so reading them from
   // memory inside the window loop would cost a global round trip per row)
   float* lw = lds + LR * LP;
-  const float wt = t < K * K ? p.c[t] : 0.0f;
+  const float wt = t < K * K ? global_in(p.c)[t] : 0.0f;
   if (interior) {
-    const float* src = x + int64_t(iy0 + rq) * p.W + ix0 + lane;
+    gcfloat* src = x + int64_t(iy0 + rq) * p.W + ix0 + lane;
     const int64_t step = 4 * int64_t(p.W);
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
@@ -178,7 +188,7 @@ __device__ __forceinline__ void filter_tile(const Filter2DProblem p, int64_t loc
 #pragma unroll
       for (int i = 0; i < CR; ++i) {
         const int r = rq + 4 * (ch * CR + i);
-        const float* row = x + int64_t(mod_pos(iy0 + r, p.H)) * p.W;
+        gcfloat* row = x + int64_t(mod_pos(iy0 + r, p.H)) * p.W;
 #pragma unroll
         for (int u = 0; u < NC; ++u)
           v[i][u] = (r < LR && lane + 64 * u < LC) ? row[gcol[u]] : 0.0f;
