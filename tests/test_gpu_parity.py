@@ -105,6 +105,37 @@ def test_copy_bit_exact_random_tilers(dtype):
             assert np.array_equal(host(out).astype(np.float64), r.out), trial
 
 
+def test_indices_beyond_2_31():
+    # an array of 2^31 + 8191 FP32 elements (8.6 GB) holding x[i] = i mod 65536,
+    # so every expected value follows from the tiler definition itself; the
+    # tilers wrap past the end of the array (64-bit index path)
+    N = (1 << 31) + 8191
+    x = (torch.arange(N, dtype=torch.int64, device="cuda") % 65536).to(torch.float32)
+    torch.cuda.synchronize()
+    R = 1000
+    o = N - 3000
+    # COPY of every 7th element from 3000 before the end, wrapping round
+    tc = W.Tiler((N,), [o], [[7]], np.zeros((1, 0)), ())
+    pc = W.Problem((R,), [tc], W.identity_output((R,)), W.COPY)
+    want_idx = (o + 7 * np.arange(R, dtype=np.int64)) % N
+    out = torch.full((R,), -1.0, device="cuda")
+    rsm.run(pc, [x], out)
+    assert np.array_equal(host(out), (want_idx % 65536).astype(np.float32))
+    idx = rsm.indices(pc.rep_shape, tc)
+    assert np.array_equal(host(idx)[:, 0], want_idx)
+    # SUM of three elements 10^9 apart from each repetition's start
+    ts = W.Tiler((N,), [o], [[7]], [[10 ** 9]], (3,))
+    ps = W.Problem((R,), [ts], W.identity_output((R,)), W.SUM)
+    assert rsm.plan(ps) in ("generic", "pattern_reduce")
+    out = torch.full((R,), -1.0, device="cuda")
+    rsm.run(ps, [x], out)
+    e = (o + 7 * np.arange(R, dtype=np.int64)[:, None] + 10 ** 9 * np.arange(3)[None, :]) % N
+    want = (e % 65536).astype(np.float64).sum(1)
+    assert np.array_equal(host(out).astype(np.float64), want)   # integers below 2^24: exact
+    del x
+    torch.cuda.empty_cache()
+
+
 def test_uncovered_output_elements_untouched():
     x = np.arange(6, dtype=np.float32)
     tin = W.Tiler((6,), [0], [[1]], np.zeros((1, 0)), ())
