@@ -75,6 +75,8 @@ typedef enum {
 #define RSM_NO_FUSE 0x4u             /* chains: run stages one by one                  */
 #define RSM_FORCE_GENERIC 0x8u       /* use the generic gather kernel (any tiler)      */
 #define RSM_PLAN_ADJOINT 0x20u       /* rsm_plan: name the adjoint's kernel family      */
+#define RSM_REDUCE_IN_KERNEL 0x80u   /* adjoint: weight gradients summed by the last    */
+                                     /* workgroup of the same launch (tap kernels)      */
 
 /* Repetition space: the Shaped multiplicity of the repeated task. rank 0 = one repetition. */
 typedef struct {
@@ -216,7 +218,9 @@ rsm_status rsm_run_chain(const rsm_stage* stages, int32_t n_stages, const void* 
  * skip it.  Without RSM_ACCUMULATE they are overwritten (gx elements no
  * repetition reads become 0); with it the result is added.  The weight
  * gradient is reduced deterministically (fixed-order tree).  gx is
- * deterministic on the tap-tiler paths: a plain store per element where no
+ * deterministic on the tap-tiler paths (with RSM_REDUCE_IN_KERNEL the
+ * weight gradient is summed by the launch's last workgroup, in the same
+ * order: the same bits): a plain store per element where no
  * element is read twice, and a gather over the (repetition, tap) pairs that
  * reach each element, in a fixed order, where 1-D windows overlap or wrap
  * onto each other; only the generic path for other tilers whose reads

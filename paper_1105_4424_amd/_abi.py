@@ -26,6 +26,7 @@ FORCE_GENERIC = 0x8
 PLAN_ADJOINT = 0x20
 CHECK_INDICES = 0x10
 NO_GRAPH = 0x40
+REDUCE_IN_KERNEL = 0x80
 
 I64x8 = ctypes.c_int64 * MAX_RANK
 I64x8x8 = (ctypes.c_int64 * MAX_RANK) * MAX_RANK

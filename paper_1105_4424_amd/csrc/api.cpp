@@ -54,13 +54,6 @@ rsm_status fail(rsm_status s, const std::string& msg) {
   return s;
 }
 
-bool reduce_in_kernel() {
-  static const bool v = [] {
-    const char* e = std::getenv("RSM_ADJOINT_REDUCE");
-    return e && std::string(e) == "inkernel";
-  }();
-  return v;
-}
 
 rsm_status hip_fail(hipError_t e, const char* what) {
   g_last_error = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
@@ -799,7 +792,7 @@ rsm_status exec_adjoint(const rsm_space& rep, const rsm_tiler& in, const void* d
     a.c = static_cast<const float*>(task.coeffs);
     a.partial = d_gc ? static_cast<float*>(ws) : nullptr;
     a.gc = static_cast<float*>(d_gc);
-    a.counter = reduce_in_kernel() ? counter : nullptr;
+    a.counter = (flags & RSM_REDUCE_IN_KERNEL) ? counter : nullptr;
     a.accumulate = accumulate;
     int grid = 0;
     if ((e = launch_fir_adjoint(a, ap.vec4, &grid, st)) != hipSuccess) return hip_fail(e, "fir adjoint");
@@ -1298,7 +1291,7 @@ rsm_status rsm_run_chain_adjoint(const rsm_stage* stages, int32_t n_stages, cons
     if (gch || gcv) {
       a.partial = static_cast<float*>(workspace(size_t(grid) * nc * sizeof(float), st, &s, &a.counter));
       if (s) return s;
-      if (!reduce_in_kernel()) a.counter = nullptr;
+      if (!(flags & RSM_REDUCE_IN_KERNEL)) a.counter = nullptr;
     }
     if ((e = probed(probe, st, [&] { return launch_fir_chain_adjoint(a, vec4, st); })) != hipSuccess)
       return hip_fail(e, "fused chain adjoint");
@@ -1347,7 +1340,7 @@ rsm_status rsm_run_chain_adjoint(const rsm_stage* stages, int32_t n_stages, cons
     void* gxk = k == 0 ? d_gx : gbuf[k & 1];
     void* gck = d_gc ? d_gc[k] : nullptr;
     // intermediate gradients are overwritten; the caller's buffers follow the flags
-    uint32_t fk = flags & RSM_FORCE_GENERIC;
+    uint32_t fk = flags & (RSM_FORCE_GENERIC | RSM_REDUCE_IN_KERNEL);
     if (accumulate) fk |= RSM_ACCUMULATE;
     if (k > 0 && accumulate) {
       // accumulate applies to the caller's gc, not to the intermediate gradient

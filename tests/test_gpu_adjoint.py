@@ -314,6 +314,35 @@ def test_chains_without_intermediate_buffers():
     check_close(host(out), want[-1].out, bound, what="unfusable chain without intermediates")
 
 
+def test_in_kernel_reduction_gives_the_same_bits():
+    # RSM_REDUCE_IN_KERNEL: the last workgroup of the launch (completion
+    # counter, agent-scope ordering) sums the partial rows in the same fixed
+    # order as the second kernel; three calls in a row check that the
+    # counter is left at zero
+    ts = W.two_stage_filter(frames=3, rows=96, cols=256, seed=31)
+    x = dev(ts.x)
+    c = [dev(ts.c_h), dev(ts.c_v)]
+    gy = dev(W.rng_for(32).uniform(-1, 1, ts.v.rep_shape).astype(np.float32))
+    gyh = dev(W.rng_for(33).uniform(-1, 1, ts.h.rep_shape).astype(np.float32))
+    res = {}
+    for flag in (0, _abi.REDUCE_IN_KERNEL):
+        runs = []
+        for _ in range(3):
+            gx = torch.empty_like(x)
+            gcs = [torch.empty(8, device="cuda"), torch.empty(8, device="cuda")]
+            rsm.run_chain_adjoint([ts.h, ts.v], x, gy, gx, gcs, c, flags=flag)
+            g1 = torch.empty_like(x)
+            gc1 = torch.empty(8, device="cuda")
+            rsm.run_adjoint(ts.h, x, gyh, g1, gc1, c[0], flags=flag)
+            runs.append([host(t) for t in (gx, gcs[0], gcs[1], g1, gc1)])
+        for r in runs[1:]:
+            for a_, b_ in zip(r, runs[0]):
+                assert np.array_equal(a_, b_)
+        res[flag] = runs[0]
+    for a_, b_ in zip(res[0], res[_abi.REDUCE_IN_KERNEL]):
+        assert np.array_equal(a_, b_)
+
+
 def test_deterministic_weight_gradient():
     ts = W.two_stage_filter(frames=4)
     gy = dev(W.rng_for(6).uniform(-1, 1, ts.v.rep_shape).astype(np.float32))
