@@ -76,7 +76,8 @@ typedef enum {
 #define RSM_FORCE_GENERIC 0x8u       /* use the generic gather kernel (any tiler)      */
 #define RSM_PLAN_ADJOINT 0x20u       /* rsm_plan: name the adjoint's kernel family      */
 #define RSM_REDUCE_IN_KERNEL 0x80u   /* adjoint: weight gradients summed by the last    */
-                                     /* workgroup of the same launch (tap kernels)      */
+                                     /* workgroup of the same launch (tap kernels; one  */
+                                     /* launch, but slower than the default second one) */
 
 /* Repetition space: the Shaped multiplicity of the repeated task. rank 0 = one repetition. */
 typedef struct {
