@@ -132,8 +132,8 @@ rsm_status rsm_validate(const rsm_space* rep, const rsm_tiler* in, int32_t n_in,
  * "generic").  With RSM_PLAN_ADJOINT in flags (n_in = 1): the family
  * rsm_run_adjoint picks for the task's input gradient ("fir_adjoint",
  * "fir_adjoint_vec4", "fir_adjoint_overlap_cols", "fir_adjoint_gather" or
- * "generic_adjoint"), judged
- * on shapes alone (16-byte aligned buffers assumed).
+ * "generic_adjoint"), decided from shapes alone (16-byte aligned buffers
+ * assumed).
  * Host only.  Writes a NUL-terminated string of at most len bytes.
  */
 rsm_status rsm_plan(const rsm_space* rep, const rsm_tiler* in, int32_t n_in,
@@ -149,7 +149,7 @@ rsm_status rsm_plan(const rsm_space* rep, const rsm_tiler* in, int32_t n_in,
  * workgroup holds the port's data while it computes; `bytes_per_workgroup`
  * is how much of it one workgroup holds there (0: the port is streamed
  * through registers element by element, nothing is staged).  Host only;
- * judged on shapes alone, like rsm_plan.  Writes min(max_ports, count)
+ * decided from shapes alone, like rsm_plan.  Writes min(max_ports, count)
  * entries and the count to *n_ports (RSM_E_INVALID if ports is too short).
  */
 typedef enum {

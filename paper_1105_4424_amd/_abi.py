@@ -100,8 +100,7 @@ def load(path: str = LIB_PATH):
     if _lib is not None and path == LIB_PATH:
         return _lib
     if not os.path.exists(path):
-        raise RuntimeError("librsm.so is not built (%s); run __graft_entry__.build() or "
-                           "python -m paper_1105_4424_amd.build" % path)
+        raise RuntimeError("librsm.so is not built (%s); run python -m paper_1105_4424_amd.build" % path)
     lib = ctypes.CDLL(path)
     P = ctypes.POINTER
     vp = ctypes.c_void_p
