@@ -81,12 +81,14 @@ def test_gemm_full_size_sampled_and_error_report():
     assert np.all(np.isfinite(host(out)))
 
 
-@pytest.mark.parametrize("dtype", ["bf16", "f32"])
-def test_gemm_large_ragged_all_layouts_sampled(dtype):
-    # large enough for the 256 x 256 tiles (M N >= 200 of them); M, N and K
-    # all ragged (K not a multiple of the 64-element k-tile); B stored [K][N]
-    # in "nn" / "tn" takes the in-kernel transpose for BF16
-    M, N, K = 3000, 4504, 1000
+# large enough for the 256 x 256 tiles (M N >= 200 of them); M, N and K all
+# ragged (K not a multiple of the 64-element k-tile).  BF16 B stored [K][N]
+# ("nn" / "tn") is read in place through transposing LDS reads when its rows
+# are 16-byte aligned (N = 4504), and transposed into the workspace when
+# they are not (N = 4500)
+@pytest.mark.parametrize("dtype,N", [("bf16", 4504), ("bf16", 4500), ("f32", 4504)])
+def test_gemm_large_ragged_all_layouts_sampled(dtype, N):
+    M, K = 3000, 1000
     a, b, ab, bb = W.matmul_inputs(M, N, K, seed=77)
     rng = W.rng_for(78)
     sel = np.concatenate([rng.choice(M * N, 384, replace=False),
