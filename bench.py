@@ -216,8 +216,8 @@ def main():
                      "kernel": "fir_chain_train_pair_kernel<8>",
                      "bytes_per_launch": train_bytes,
                      "avg_us": train_us, "timed_launches": len(range(0, args.steps, SAMPLE)),
-                     "measured_copy_gbs": copy_gbs,
-                     "frac_of_measured_copy": train_gbs / copy_gbs},
+                     "torch_copy_gbs": copy_gbs,
+                     "frac_of_torch_copy": train_gbs / copy_gbs},
         "extra": {"device": {"name": props.name, "arch": getattr(props, "gcnArchName", ""),
                              "compute_units": props.multi_processor_count},
                   "separate_path": {"ms_per_step": sep_ms,

@@ -303,14 +303,31 @@ RSM_UNROLL_R
   }
 }
 
+// Sum of src[j * stride] over j = t, t + kBlock, t + 2 kBlock, ... < n
+// (t = threadIdx.x), added in that order.  The loads are issued eight at a
+// time so that their latencies overlap; the order of the additions, and so
+// the result, is that of the plain loop.
+__device__ __forceinline__ float strided_sum(const float* src, int64_t n, int64_t stride) {
+  float acc = 0.0f;
+  int64_t j = threadIdx.x;
+  for (; j + 7 * kBlock < n; j += 8 * kBlock) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src[(j + u * kBlock) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
+  for (; j < n; j += kBlock) acc += src[j * stride];
+  return acc;
+}
+
 // out[i] (=|+=) sum_j src[i*si + j*sj], j < n, fixed-order tree per i
 __global__ void __launch_bounds__(kBlock) reduce_strided_kernel(const float* src, int64_t n,
                                                                int64_t si, int64_t sj,
                                                                float* out, int accumulate) {
   __shared__ float red[kBlock];
   const int64_t i = blockIdx.x;
-  float acc = 0.0f;
-  for (int64_t j = threadIdx.x; j < n; j += kBlock) acc += src[i * si + j * sj];
+  const float acc = strided_sum(src + i * si, n, sj);
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int s = kBlock / 2; s > 0; s >>= 1) {
@@ -327,8 +344,7 @@ __global__ void __launch_bounds__(kBlock) reduce_pair_kernel(const float* src, i
                                                              int n0, float* out0, float* out1, int accumulate) {
   __shared__ float red[kBlock];
   const int i = int(blockIdx.x);
-  float acc = 0.0f;
-  for (int64_t j = threadIdx.x; j < n; j += kBlock) acc += src[i + j * row_stride];
+  const float acc = strided_sum(src + i, n, row_stride);
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int s = kBlock / 2; s > 0; s >>= 1) {
