@@ -593,6 +593,78 @@ __global__ void __launch_bounds__(kBlock) fir_adjoint_kernel(FirAdjArgs a) {
   }
 }
 
+// 8 taps along columns, 16-byte aligned windows: lanes 2m and 2m+1 share one
+// repetition and take four taps each, so every load and store instruction of
+// a wavefront covers 1 KiB of contiguous x or dL/dx (one lane per repetition
+// leaves each instruction every other 16 bytes of its span).  Interior
+// windows stream x and dL/dx with the nontemporal policy; a window that
+// crosses the border takes the modular path, four taps per lane.  Lane 2m
+// accumulates the weight gradient of taps 0-3, lane 2m+1 of taps 4-7.
+__global__ void __launch_bounds__(kBlock) fir_adjoint_pair_kernel(FirAdjArgs a) {
+  const Win3& w = a.w;
+  const int hh = threadIdx.x & 1;
+  float c4[4], g4[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    c4[e] = a.c[4 * hh + e];
+    g4[e] = 0.0f;
+  }
+  const uint32_t n_half = 2u * a.n_rep;
+  const uint32_t stride = gridDim.x * kBlock;
+  const int n = w.A[2];
+  for (uint32_t gi = blockIdx.x * kBlock + threadIdx.x; gi < n_half; gi += stride) {
+    const uint32_t o = gi >> 1;
+    const OutPos q = decode(o, w, a.div_rc, a.div_rr);
+    const float g = a.gy[o];
+    const int ib = w.o[0] + w.p[0] * q.b;
+    const int base = (ib * w.A[1] + w.o[1] + w.p[1] * q.r) * n;
+    const int pos = w.o[2] + w.p[2] * q.c;
+    if (pos >= 0 && pos + 8 <= n) {
+      const int at = base + pos + 4 * hh;
+      if (a.x) {
+        const float4 xv = load_stream4(a.x + at);
+        g4[0] = fmaf(g, xv.x, g4[0]);
+        g4[1] = fmaf(g, xv.y, g4[1]);
+        g4[2] = fmaf(g, xv.z, g4[2]);
+        g4[3] = fmaf(g, xv.w, g4[3]);
+      }
+      if (a.gx) {
+        float4 gv = make_float4(c4[0] * g, c4[1] * g, c4[2] * g, c4[3] * g);
+        if (a.accumulate) {
+          const float4 old = *reinterpret_cast<const float4*>(a.gx + at);
+          gv.x += old.x; gv.y += old.y; gv.z += old.z; gv.w += old.w;
+        }
+        store_stream4(a.gx + at, gv);
+      }
+    } else {
+      int e = wrap_mod(int64_t(pos) + 4 * hh, n);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int off = base + e;
+        if (a.x) g4[k] = fmaf(g, a.x[off], g4[k]);
+        if (a.gx) {
+          const float gv = c4[k] * g;
+          a.gx[off] = a.accumulate ? a.gx[off] + gv : gv;
+        }
+        if (++e == n) e = 0;
+      }
+    }
+  }
+  if (a.partial) {
+    float packed[8];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      packed[e] = hh ? 0.0f : g4[e];
+      packed[4 + e] = hh ? g4[e] : 0.0f;
+    }
+    block_reduce_store<8>(packed, 8, a.partial + int64_t(blockIdx.x) * 8, a.counter != nullptr);
+    if (a.counter && arrive_last(a.counter)) {
+      reduce_rows_fixed(a.partial, gridDim.x, 8, 0, 8, a.gc, a.accumulate);
+      if (threadIdx.x == 0) __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // adjoint of the fused chain (both stages injective)
 // ---------------------------------------------------------------------------
@@ -1099,14 +1171,16 @@ hipError_t launch_fir_chain(const FirChainArgs& a, bool vec4, hipStream_t st) {
   return hipGetLastError();
 }
 
-int fir_adjoint_grid(const FirAdjArgs& a) { return stream_grid(a.n_rep, 8); }
+// sized for two lanes per repetition (the lane-pair kernel); the other
+// variants run one lane per repetition over the same grid
+int fir_adjoint_grid(const FirAdjArgs& a) { return stream_grid(2u * a.n_rep, 8); }
 
 hipError_t launch_fir_adjoint(const FirAdjArgs& a, bool vec4, int* grid_out, hipStream_t st) {
   const int grid = fir_adjoint_grid(a);
   if (grid_out) *grid_out = grid;
   if (a.w.ax == 2) {
     if (vec4 && a.w.taps == 8)
-      fir_adjoint_kernel<2, true, 8><<<grid, kBlock, 0, st>>>(a);
+      fir_adjoint_pair_kernel<<<grid, kBlock, 0, st>>>(a);
     else if (vec4)
       fir_adjoint_kernel<2, true, 0><<<grid, kBlock, 0, st>>>(a);
     else
