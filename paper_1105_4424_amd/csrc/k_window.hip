@@ -246,6 +246,47 @@ __global__ void __launch_bounds__(kBlock) fir_kernel(FirArgs a) {
   }
 }
 
+// 8 taps along columns, 16-byte aligned windows: lanes 2m and 2m+1 share one
+// output and load four taps each, so every load instruction covers 1 KiB of
+// contiguous input; the half sums (taps 0-3 + taps 4-7, each accumulated in
+// tap order) meet through a lane shuffle, the order the fused chain uses for
+// its first stage.  A window that crosses the border takes the modular path.
+__global__ void __launch_bounds__(kBlock) fir_pair_kernel(FirArgs a) {
+  const Win3& w = a.w;
+  const int hh = threadIdx.x & 1;
+  float c4[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) c4[e] = a.c[4 * hh + e];
+  const uint32_t n_half = 2u * a.n_out;
+  const uint32_t stride = gridDim.x * kBlock;
+  const int n = w.A[2];
+  for (uint32_t gi = blockIdx.x * kBlock + threadIdx.x; gi < n_half; gi += stride) {
+    const uint32_t o = gi >> 1;
+    const OutPos q = decode(o, w, a.div_rc, a.div_rr);
+    const int ib = w.o[0] + w.p[0] * q.b;
+    const int row_base = (ib * w.A[1] + w.o[1] + w.p[1] * q.r) * n;
+    const int pos = w.o[2] + w.p[2] * q.c;
+    float part;
+    if (pos >= 0 && pos + 8 <= n) {
+      const float4 xv = *reinterpret_cast<const float4*>(a.x + row_base + pos + 4 * hh);
+      part = c4[0] * xv.x;
+      part = fmaf(c4[1], xv.y, part);
+      part = fmaf(c4[2], xv.z, part);
+      part = fmaf(c4[3], xv.w, part);
+    } else {
+      int e = wrap_mod(int64_t(pos) + 4 * hh, n);
+      part = c4[0] * a.x[row_base + e];
+#pragma unroll
+      for (int k = 1; k < 4; ++k) {
+        if (++e == n) e = 0;
+        part = fmaf(c4[k], a.x[row_base + e], part);
+      }
+    }
+    const float other = __shfl_xor(part, 1);
+    if (hh == 0) a.y[o] = part + other;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // fused chain: out = V(H(x))
 // ---------------------------------------------------------------------------
@@ -1141,7 +1182,9 @@ hipError_t launch_pattern_reduce(const PatternReduceArgs& a, int max_rank, hipSt
 hipError_t launch_fir(const FirArgs& a, bool vec4, hipStream_t st) {
   const int grid = stream_grid(a.n_out, 16);
   if (a.w.ax == 2) {
-    if (vec4 && a.w.taps == 8)
+    if (vec4 && a.w.taps == 8 && a.n_out < (1u << 30))
+      fir_pair_kernel<<<stream_grid(2u * a.n_out, 16), kBlock, 0, st>>>(a);
+    else if (vec4 && a.w.taps == 8)
       fir_kernel<2, true, 8><<<grid, kBlock, 0, st>>>(a);
     else if (vec4)
       fir_kernel<2, true, 0><<<grid, kBlock, 0, st>>>(a);

@@ -33,6 +33,10 @@ def _adjoint_check(p, x, gy, flags=0, what=""):
     check_close(host(gx), a.gx, a.gx_abs, what=what + " gx")
     if gc is not None:
         check_close(host(gc), a.gc, a.gc_abs, what=what + " gc")
+        # the input gradient alone (x is not read) gives the same bits
+        gx1 = torch.full(p.inputs[0].array_shape, float("nan"), device="cuda")
+        rsm.run_adjoint(p, dev(x), dev(gy), gx1, None, dev(p.coeffs), flags=flags)
+        assert torch.equal(gx1, gx), what + " gx without gc"
     # accumulate: adds onto the previous contents
     if gc is not None:
         gx2 = gx.clone()
@@ -55,6 +59,8 @@ def test_stage_adjoints_two_frames(force_generic):
 
 @pytest.mark.parametrize("taps,pave,ho,vo,rows,cols", [
     (8, 8, -3, -3, 64, 96),      # injective, wrapping: tap kernels
+    (8, 8, -4, -5, 40, 64),      # 16-byte aligned windows, left border wraps: lane-pair kernel
+    (8, 8, 4, 3, 40, 64),        # aligned, right border wraps
     (13, 8, -6, 0, 48, 80),      # overlapping reads: gather-form input gradient
     (5, 7, 0, -2, 31, 47),       # gaps between windows (elements never read get 0)
 ])
