@@ -59,6 +59,8 @@ def test_chain_full_size(fused):
 
 @pytest.mark.parametrize("taps,pave,ho,vo,rows,cols", [
     (8, 8, -3, -3, 64, 96),       # centred taps: windows wrap at both borders
+    (8, 8, -4, -5, 40, 64),       # 16-byte aligned windows (lane-pair kernels), left border wraps
+    (8, 8, 4, 3, 40, 64),         # aligned, right border wraps
     (13, 8, -6, 0, 48, 80),       # overlapping taps with wrap
     (8, 8, 0, 0, 40, 52),         # ragged: 52 columns (not a multiple of 8 after paving -> 7 cols)
     (4, 4, 2, 1, 33, 68),         # origin not a multiple of 4: scalar path
