@@ -53,10 +53,20 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
 }
 
 // Sum of part[0..n) in a fixed order (thread t adds t, t + 256, ..., then the
-// tree): identical bits in every workgroup.
+// tree): identical bits in every workgroup.  The loads are issued eight at a
+// time, so a workgroup waits for one round trip per 2048 partials instead of
+// one per 256; the additions keep the order of the plain loop.
 __device__ __forceinline__ double partial_sum(const double* part, int n, double* lds) {
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += kBlock) s += part[i];
+  int i = threadIdx.x;
+  for (; i + 7 * kBlock < n; i += 8 * kBlock) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[i + u * kBlock];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; i < n; i += kBlock) s += part[i];
   return block_sum(s, lds);
 }
 
