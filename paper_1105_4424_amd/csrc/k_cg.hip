@@ -37,20 +37,21 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// Sum of v over the workgroup, fixed tree order; the result is returned to
-// every thread.
+// Sum of v over the workgroup in a fixed order, returned to every thread: a
+// butterfly inside each wavefront (lane i adds lane i xor 32, 16, ..., 1, so
+// every lane pairs the same operands and holds the same bits), then the four
+// wavefront sums in wavefront order.  Two barriers instead of one per level
+// of an LDS tree.
 __device__ __forceinline__ double block_sum(double v, double* lds) {
-  lds[threadIdx.x] = v;
-  __syncthreads();
 #pragma unroll
-  for (int w = kBlock / 2; w > 0; w >>= 1) {
-    if (int(threadIdx.x) < w) lds[threadIdx.x] += lds[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double s = lds[0];
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
   __syncthreads();
+  const double s = ((lds[0] + lds[1]) + lds[2]) + lds[3];
+  __syncthreads();   // lds is written again by the next call
   return s;
 }
+static_assert(kBlock == 256, "block_sum adds four wavefront sums");
 
 // Sum of part[0..n) in a fixed order (thread t adds t, t + 256, ..., then the
 // tree): identical bits in every workgroup.  The loads are issued eight at a
