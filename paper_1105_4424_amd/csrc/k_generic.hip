@@ -321,39 +321,41 @@ __device__ __forceinline__ float strided_sum(const float* src, int64_t n, int64_
   return acc;
 }
 
-// out[i] (=|+=) sum_j src[i*si + j*sj], j < n, fixed-order tree per i
+// Sum over the workgroup of each thread's v, returned to thread 0: a
+// butterfly inside each wavefront (every lane pairs the same operands), then
+// the four wavefront sums in wavefront order.  The in-kernel weight-gradient
+// reduction of the tap kernels uses the same order, so both give the same
+// bits.
+__device__ __forceinline__ float block_total(float v, float* red) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return ((red[0] + red[1]) + red[2]) + red[3];
+}
+static_assert(kBlock == 256, "block_total adds four wavefront sums");
+
+// out[i] (=|+=) sum_j src[i*si + j*sj], j < n, in a fixed order per i
 __global__ void __launch_bounds__(kBlock) reduce_strided_kernel(const float* src, int64_t n,
                                                                int64_t si, int64_t sj,
                                                                float* out, int accumulate) {
-  __shared__ float red[kBlock];
+  __shared__ float red[kBlock / 64];
   const int64_t i = blockIdx.x;
-  const float acc = strided_sum(src + i * si, n, sj);
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (int(threadIdx.x) < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[i] = accumulate ? out[i] + red[0] : red[0];
+  const float tot = block_total(strided_sum(src + i * si, n, sj), red);
+  if (threadIdx.x == 0) out[i] = accumulate ? out[i] + tot : tot;
 }
 
 // Two weight gradients from one partial table [n][row_stride]: column
 // blockIdx.x < n0 goes to out0[blockIdx.x], the next n1 columns to out1.
-// Each column is reduced by the same fixed-order tree as reduce_strided_kernel.
+// Each column is reduced in the same fixed order as reduce_strided_kernel.
 __global__ void __launch_bounds__(kBlock) reduce_pair_kernel(const float* src, int64_t n, int64_t row_stride,
                                                              int n0, float* out0, float* out1, int accumulate) {
-  __shared__ float red[kBlock];
+  __shared__ float red[kBlock / 64];
   const int i = int(blockIdx.x);
-  const float acc = strided_sum(src + i, n, row_stride);
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (int(threadIdx.x) < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
+  const float tot = block_total(strided_sum(src + i, n, row_stride), red);
   if (threadIdx.x == 0) {
     float* o = i < n0 ? out0 + i : out1 + (i - n0);
-    *o = accumulate ? *o + red[0] : red[0];
+    *o = accumulate ? *o + tot : tot;
   }
 }
 

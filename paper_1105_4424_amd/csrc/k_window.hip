@@ -504,7 +504,7 @@ __device__ __forceinline__ bool arrive_last(uint32_t* counter) {
 // out[j] (=|+=) sum over rows b < n_rows of partial[b * row + col0 + j], j < count
 __device__ __forceinline__ void reduce_rows_fixed(const float* partial, int n_rows, int row,
                                                   int col0, int count, float* out, int accumulate) {
-  __shared__ float red[kBlock];
+  __shared__ float red[kBlock / 64];
   for (int j = 0; j < count; ++j) {
     // rows t, t + kBlock, ... added in that order, loads issued eight at a time
     const float* col = partial + col0 + j;
@@ -518,13 +518,16 @@ __device__ __forceinline__ void reduce_rows_fixed(const float* partial, int n_ro
       for (int u = 0; u < 8; ++u) acc += v[u];
     }
     for (; b < n_rows; b += kBlock) acc += load_agent(col + int64_t(b) * row);
-    red[threadIdx.x] = acc;
+    // the order of the second-kernel reduction: a butterfly inside each
+    // wavefront, then the four wavefront sums in order
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) acc += __shfl_xor(acc, m);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-      if (int(threadIdx.x) < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
+    if (threadIdx.x == 0) {
+      const float tot = ((red[0] + red[1]) + red[2]) + red[3];
+      out[j] = accumulate ? out[j] + tot : tot;
     }
-    if (threadIdx.x == 0) out[j] = accumulate ? out[j] + red[0] : red[0];
     __syncthreads();
   }
 }
