@@ -15,9 +15,10 @@
 //  * filter2d_persistent: a grid sized to the resident capacity walks a
 //    host-built table of (problem, tile) entries round-robin: workgroup b
 //    takes entries b, b + grid, ...  Each workgroup fetches the next entry
-//    and its problem descriptor before running the current tile, so no tile
-//    waits on a descriptor load; there is no atomic and nothing to reset
-//    between graph replays.
+//    before running the current tile and loads that entry's problem
+//    descriptor after it (a second descriptor held across the tile pushed
+//    the kernel's scalar registers into memory spills and cost 15 %); there
+//    is no atomic and nothing to reset between graph replays.
 #include <hip/hip_runtime.h>
 
 #include "rsm_internal.h"
@@ -247,8 +248,7 @@ __device__ __forceinline__ void tile_any(const Filter2DProblem& p, int64_t local
 }
 
 // Persistent form: workgroup b takes table entries b, b + grid, ...; the
-// next entry and its problem descriptor are fetched before the current tile
-// runs.  Each tile issues its staging loads before the barrier that waits
+// next entry is fetched before the current tile runs, its descriptor after.  Each tile issues its staging loads before the barrier that waits
 // for the previous tile's LDS readers.  The grid must not exceed the
 // resident capacity (the launcher sizes it from the occupancy), so no
 // workgroup starts late.
@@ -264,16 +264,12 @@ __global__ void __launch_bounds__(kThreads, 7) filter2d_persistent(const Filter2
     const int64_t tn = t + gridDim.x;
     const bool more = tn < n_tiles;
     uint2 en = e;
-    Filter2DProblem pn = p;
-    if (more) {
-      en = tiles[tn];
-      pn = probs[en.x];
-    }
+    if (more) en = tiles[tn];
     tile_any(p, e.y, lds);
     if (!more) break;
     t = tn;
     e = en;
-    p = pn;
+    p = probs[e.x];
   }
 }
 
