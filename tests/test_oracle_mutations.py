@@ -1,6 +1,7 @@
 """The pins catch plausible slips in the oracle.
 
-Each case plants one mistake in a private copy of the oracle's C source (on
+Each case plants one mistake (in the arithmetic or in the |term| sums
+that the parity gates divide by) in a private copy of the oracle's C source (on
 the CPU, in a temporary directory), builds it, swaps it in for the real
 oracle, and checks that at least one pin of test_oracle_pins.py fails.  The
 real oracle is restored afterwards.
@@ -42,6 +43,23 @@ MUTATIONS = {
                          "const double beta = rho / rho_next;"),
     "cg_direction_from_residual": ("p[i] = r[i] + beta * p[i];", "p[i] = r[i] + beta * r[i];"),
     "cg_absolute_stop": ("sqrt(rho) > tol * bnorm", "sqrt(rho) > tol"),
+    # slips in the |term| sums that every FP32 parity gate divides by
+    "wsum_bound_drops_weight": ("            if (kind == OR_WSUM) term *= coeffs[pf];\n"
+                                "            acc += term;\n"
+                                "            aabs += fabs(term);",
+                                "            aabs += fabs(term);\n"
+                                "            if (kind == OR_WSUM) term *= coeffs[pf];\n"
+                                "            acc += term;"),
+    "dot_bound_abs_of_sum": ("* x[1][element_offset(&in[1], rep_rank, r, i2)];\n"
+                             "            acc += term;\n"
+                             "            aabs += fabs(term);",
+                             "* x[1][element_offset(&in[1], rep_rank, r, i2)];\n"
+                             "            acc += term;\n"
+                             "            aabs = fabs(acc);"),
+    "adjoint_gx_bound_scaled": ("gx_abs[a] += fabs(c * g);", "gx_abs[a] += 10.0 * fabs(c * g);"),
+    "adjoint_gc_bound_scaled": ("gc_abs[pf] += fabs(g * x[a]);",
+                                "gc_abs[pf] += 10.0 * fabs(g * x[a]);"),
+    "copy_bound_signed": ("yabs[pf] = fabs(y[pf]);", "yabs[pf] = y[pf];"),
 }
 
 PINS = [
@@ -57,6 +75,12 @@ PINS = [
     pins.test_cg_solution_matches_dense_solve,
     pins.test_cg_iterates_match_scipy,
     pins.test_cg_stopping_rule_is_relative,
+    pins.test_wsum_and_sum_abs_sums_match_index_table_random_tilers,
+    pins.test_dot_abs_sum_equals_naive_loop_on_absolutes,
+    pins.test_dot_abs_sum_random_tiler_pairs,
+    pins.test_copy_abs_sum_is_magnitude,
+    pins.test_adjoint_abs_sums_match_index_table_random_tilers,
+    pins.test_adjoint_abs_sums_two_stage_closed_form,
 ]
 
 

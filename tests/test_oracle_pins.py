@@ -357,6 +357,157 @@ def test_adjoint_of_sum_is_broadcast():
 
 
 # ---------------------------------------------------------------------------
+# P4/P5 tolerance sums: every FP32 parity gate bounds an element's error by
+# 1e-5 times the oracle's sum of |terms|.  Those sums are pinned here against
+# index tables built without the oracle (NumPy's wrapping ravel) and against
+# closed forms on |x| and |c|: a bound that drops the weight, takes |sum|
+# instead of sum|.|, or is scaled, fails one of these.
+# ---------------------------------------------------------------------------
+
+def _abs_terms_by_table(rep, t, x, c):
+    """sum_i |c_i| |x[e(r, i)]| per repetition, from the NumPy index table."""
+    idx = numpy_indices(rep, t)
+    xa = np.abs(x.astype(np.float64)).reshape(-1)
+    ca = np.ones(idx.shape[1]) if c is None else np.abs(np.asarray(c, np.float64)).reshape(-1)
+    return (xa[idx] * ca[None, :]).sum(axis=1)
+
+
+def test_wsum_and_sum_abs_sums_match_index_table_random_tilers():
+    rng = W.rng_for(4242)
+    for trial in range(120):
+        dr = int(rng.integers(1, 4))
+        rep = tuple(int(v) for v in rng.integers(1, 5, dr))
+        t = W.random_tiler(rng, dr, pattern_rank=int(rng.integers(0, 3)))
+        x = W.random_array(rng, t.array_shape)
+        weighted = trial % 3 != 0
+        c = (rng.uniform(-2, 2, t.pattern_shape).astype(np.float32) if weighted else None)
+        p = W.Problem(rep, [t], W.identity_output(rep), W.WSUM if weighted else W.SUM, c)
+        want = _abs_terms_by_table(rep, t, x, c).reshape(rep)
+        got = oracle.run(p, [x]).abs_sum
+        assert np.allclose(got, want, rtol=1e-14, atol=0), (trial, t)
+        ys, yas = oracle.run_sample(p, [x], np.arange(int(np.prod(rep)))[::2])
+        assert np.allclose(yas[:, 0], want.reshape(-1)[::2], rtol=1e-14, atol=0), trial
+
+
+def test_wsum_abs_sum_two_stage_closed_form():
+    ts = W.two_stage_filter(frames=2, rows=24, cols=48)
+    xa = np.abs(ts.x.astype(np.float64))
+    ch, cv = np.abs(ts.c_h.astype(np.float64)), np.abs(ts.c_v.astype(np.float64))
+    want_h = np.einsum("fhwk,k->fhw", xa.reshape(2, 24, 6, 8), ch)
+    fh = oracle.run(ts.h, [ts.x])
+    assert np.allclose(fh.abs_sum, want_h, rtol=1e-14, atol=0)
+    mid = fh.out
+    want_v = np.einsum("fhkw,k->fhw", np.abs(mid).reshape(2, 3, 8, 6), cv)
+    assert np.allclose(oracle.run(ts.v, [mid]).abs_sum, want_v, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("H,W_,k,s", [(17, 23, 3, 1), (19, 33, 7, 4), (9, 14, 9, 2)])
+def test_filter2d_abs_sum_equals_fft_of_absolutes(H, W_, k, s):
+    rng = W.rng_for(H * 7 + W_)
+    x = rng.standard_normal((H, W_)).astype(np.float32)
+    c = (rng.uniform(-1, 1, (k, k)) / (k * k)).astype(np.float32)
+    p = W.filter2d_problem(H, W_, k, s, c)
+    want = _circular_filter_fft(np.abs(x.astype(np.float64)), np.abs(c.astype(np.float64)),
+                                -(k // 2), s)
+    assert np.allclose(oracle.run(p, [x]).abs_sum, want, rtol=1e-12, atol=1e-13)
+
+
+def test_dot_abs_sum_equals_naive_loop_on_absolutes():
+    a, b, _, _ = W.matmul_inputs(12, 10, 16, seed=15)
+    p = W.matmul_tilers(12, 10, 16)
+    want = _naive_matmul(np.abs(a), np.abs(b))
+    r = oracle.run(p, [a, b])
+    assert np.allclose(r.abs_sum, want, rtol=1e-14, atol=0)
+    # the bound is never below |y| and is strictly above it where signs mix
+    assert np.all(r.abs_sum >= np.abs(r.out))
+    assert np.any(r.abs_sum > 1.5 * np.abs(r.out))
+
+
+def test_dot_abs_sum_random_tiler_pairs():
+    rng = W.rng_for(4343)
+    for trial in range(60):
+        dr = int(rng.integers(1, 3))
+        rep = tuple(int(v) for v in rng.integers(1, 5, dr))
+        dp = int(rng.integers(1, 3))
+        t1 = W.random_tiler(rng, dr, pattern_rank=dp)
+        t2 = W.random_tiler(rng, dr, pattern_rank=dp)
+        t2 = W.Tiler(t2.array_shape, t2.origin, t2.paving,
+                     rng.integers(-9, 10, (len(t2.array_shape), dp)), t1.pattern_shape)
+        x1 = W.random_array(rng, t1.array_shape)
+        x2 = W.random_array(rng, t2.array_shape)
+        i1, i2 = numpy_indices(rep, t1), numpy_indices(rep, t2)
+        v1, v2 = x1.astype(np.float64).reshape(-1)[i1], x2.astype(np.float64).reshape(-1)[i2]
+        p = W.Problem(rep, [t1, t2], W.identity_output(rep), W.DOT)
+        r = oracle.run(p, [x1, x2])
+        assert np.allclose(r.out.reshape(-1), (v1 * v2).sum(1), rtol=0, atol=1e-13), trial
+        assert np.allclose(r.abs_sum.reshape(-1), np.abs(v1 * v2).sum(1), rtol=1e-14, atol=0), trial
+
+
+def test_copy_abs_sum_is_magnitude():
+    rng = W.rng_for(17)
+    x = W.random_array(rng, (5, 7))
+    p = W.Problem((5, 7), [W.identity_output((5, 7))], W.identity_output((5, 7)), W.COPY)
+    r = oracle.run(p, [x])
+    assert np.array_equal(r.abs_sum, np.abs(x.astype(np.float64)))
+
+
+def test_adjoint_abs_sums_match_index_table_random_tilers():
+    rng = W.rng_for(4444)
+    for trial in range(80):
+        dr = int(rng.integers(1, 4))
+        rep = tuple(int(v) for v in rng.integers(1, 5, dr))
+        t = W.random_tiler(rng, dr, pattern_rank=int(rng.integers(0, 3)))
+        c = rng.uniform(-2, 2, t.pattern_shape).astype(np.float32)
+        p = W.Problem(rep, [t], W.identity_output(rep), W.WSUM, c)
+        x = W.random_array(rng, t.array_shape)
+        g = rng.uniform(-1, 1, rep)
+        idx = numpy_indices(rep, t)                       # [nr, np]
+        ca = np.abs(c.astype(np.float64)).reshape(-1)
+        ga = np.abs(g).reshape(-1)
+        xa = np.abs(x.astype(np.float64)).reshape(-1)
+        want_gx = np.zeros(xa.size)
+        np.add.at(want_gx, idx.reshape(-1), (ga[:, None] * ca[None, :]).reshape(-1))
+        want_gc = (ga[:, None] * xa[idx]).sum(axis=0)
+        a = oracle.adjoint(p, x, g)
+        assert np.allclose(a.gx_abs.reshape(-1), want_gx, rtol=1e-14, atol=0), trial
+        assert np.allclose(a.gc_abs.reshape(-1), want_gc, rtol=1e-14, atol=0), trial
+        # the values themselves by the same tables (signed)
+        gx = np.zeros(xa.size)
+        np.add.at(gx, idx.reshape(-1), (g.reshape(-1)[:, None] * c.astype(np.float64).reshape(-1)[None, :]).reshape(-1))
+        assert np.allclose(a.gx.reshape(-1), gx, rtol=0, atol=1e-13), trial
+
+
+def test_adjoint_abs_sums_two_stage_closed_form():
+    # exact paving: gx_abs[f,h,w] = |c_h[w mod 8]| |gy[f,h,w//8]| and
+    # gc_abs[k] = sum_{f,h,q} |gy[f,h,q]| |x[f,h,8q+k]|
+    ts = W.two_stage_filter(frames=2, rows=16, cols=40)
+    g = W.rng_for(18).uniform(-1, 1, ts.h.rep_shape)
+    a = oracle.adjoint(ts.h, ts.x, g)
+    ch = np.abs(ts.c_h.astype(np.float64))
+    want_gx = np.einsum("fhq,k->fhqk", np.abs(g), ch).reshape(ts.x.shape)
+    want_gc = np.einsum("fhq,fhqk->k", np.abs(g), np.abs(ts.x.astype(np.float64)).reshape(2, 16, 5, 8))
+    assert np.allclose(a.gx_abs, want_gx, rtol=1e-14, atol=0)
+    assert np.allclose(a.gc_abs, want_gc, rtol=1e-14, atol=0)
+    # unit weights (SUM): gx_abs is the broadcast of |gy|
+    x, p = W.small_sum()
+    g2 = W.rng_for(19).uniform(-1, 1, (16, 16))
+    a2 = oracle.adjoint(p, x, g2)
+    assert np.array_equal(a2.gx_abs, np.repeat(np.repeat(np.abs(g2), 4, 0), 4, 1))
+
+
+def test_chain_bound_on_absolutes_equals_einsum():
+    # the chain tolerance (both stages run on |x| with |c|) is the closed form
+    # of the two einsums on absolute values
+    ts = W.two_stage_filter(frames=1, rows=16, cols=32)
+    absp = [W.Problem(s.rep_shape, s.inputs, s.output, s.task, np.abs(s.coeffs)) for s in (ts.h, ts.v)]
+    got = oracle.chain_forward(absp, np.abs(ts.x))[-1].out
+    xa = np.abs(ts.x.astype(np.float64))
+    mid = np.einsum("fhwk,k->fhw", xa.reshape(1, 16, 4, 8), np.abs(ts.c_h.astype(np.float64)))
+    want = np.einsum("fhkw,k->fhw", mid.reshape(1, 2, 8, 4), np.abs(ts.c_v.astype(np.float64)))
+    assert np.allclose(got, want, rtol=1e-14, atol=0)
+
+
+# ---------------------------------------------------------------------------
 # P6: finite differences are exact for L = sum(w * out^2)
 # ---------------------------------------------------------------------------
 
