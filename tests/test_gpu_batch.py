@@ -3,7 +3,8 @@
 Instances follow the batched workload's recipe (sides log-uniform in
 [32, 2048], k in {3,5,7,9}, stride in {1,2,4}, centred origin so windows wrap
 on every border).  Small batches are checked whole against the oracle; the
-full 512-instance batch on sampled outputs of every instance, and the batched
+full 512-instance batch on every tile's corners and centre and on every
+border output of every instance, and the batched
 launch must equal the plain launches (same kernels, same tile shapes) bit for
 bit, on every graph replay.
 """
@@ -104,7 +105,26 @@ def test_tuning_cache_round_trip(tmp_path):
     json.load(open(path))
 
 
-def test_full_batch_sampled_and_replays_bit_identical():
+def _tile_samples(out_shape, tile):
+    """Flat output indices: the four corners and the centre of every tile of
+    the problem's tiling (tile = (rows, cols) of outputs per tile), plus the
+    whole first and last output row and column (whose windows wrap)."""
+    R, C = out_shape
+    tr, tc = tile
+    assert tr > 0 and tc > 0
+    r0 = np.arange(0, R, tr)
+    c0 = np.arange(0, C, tc)
+    r1 = np.minimum(r0 + tr, R) - 1
+    c1 = np.minimum(c0 + tc, C) - 1
+    rm, cm = (r0 + r1) // 2, (c0 + c1) // 2
+    pts = []
+    for rr, cc in ((r0, c0), (r0, c1), (r1, c0), (r1, c1), (rm, cm)):
+        pts.append((rr[:, None] * C + cc[None, :]).reshape(-1))
+    pts += [np.arange(C), (R - 1) * C + np.arange(C), np.arange(R) * C, np.arange(R) * C + C - 1]
+    return np.unique(np.concatenate(pts))
+
+
+def test_full_batch_stratified_and_replays_bit_identical():
     say("generating 512 instances")
     insts = W.filter_batch(512)
     b, probs, xs, outs = _make_batch(insts)
@@ -114,13 +134,15 @@ def test_full_batch_sampled_and_replays_bit_identical():
     b.run()
     torch.cuda.synchronize()
     first = [host(o).copy() for o in outs]
-    rng = W.rng_for(99)
-    say("sampled oracle check")
+    say("stratified oracle check: every tile's corners and centre, every border output")
+    n_checked = 0
     for j, inst in enumerate(insts):
-        n_out = first[j].size
-        sel = np.unique(np.concatenate([rng.integers(0, n_out, 6), [0, n_out - 1]]))
+        sel = _tile_samples(inst.out_shape, b.tile(j))
         y, ya = oracle.run_sample(probs[j], [inst.x], sel)
         check_close(first[j].reshape(-1)[sel], y[:, 0], ya[:, 0], what="instance %d" % j)
+        assert np.all(np.isfinite(first[j])), j
+        n_checked += sel.size
+    say("%d outputs checked against the oracle" % n_checked)
     # graph replays, with eager work in between, reproduce the first result bit for bit
     for rep in range(3):
         for o in outs:
