@@ -23,9 +23,16 @@
  *
  * Conventions for every call below:
  *  - Ownership: the caller owns every buffer passed in.  The library owns only
- *    opaque handles (rsm_batch) and an internal device workspace that it
- *    grows on demand (used by the adjoint's weight-gradient reduction and by
- *    unfused chains); descriptor structs are copied at call time.
+ *    opaque handles (rsm_batch) and internal device workspaces, one per
+ *    (device, stream), grown on demand (weight-gradient partial rows of the
+ *    adjoints, unfused chain intermediates, transposed matrix operands, CG
+ *    vectors); descriptor structs are copied at call time.  Calls on one
+ *    stream share that stream's workspace (the stream orders them); calls on
+ *    different streams use different workspaces and may run concurrently.
+ *    Growing a workspace synchronises its stream and allocates; while the
+ *    stream is being captured into a graph that is impossible, and the call
+ *    returns RSM_E_UNSUPPORTED instead (make the same call once before
+ *    capturing).
  *  - Streams: compute calls are asynchronous on the given hipStream_t (NULL =
  *    the null stream).  Errors detectable on the host are returned before any
  *    launch, with nothing written.  A failed HIP call returns RSM_E_HIP; the
@@ -305,8 +312,9 @@ rsm_status rsm_run_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
  * count, the final recursive residual norm, ||b||, converged and breakdown
  * (<p, A p> <= 0 met: A not positive definite; x then holds the last
  * iterate).  Inner products are reduced in a fixed order: repeated calls
- * give identical bits.  Uses the library workspace (4 n + 3 * 2048 doubles);
- * calls on one device must not overlap.  RSM_CHECK_INDICES validates the
+ * give identical bits.  Uses the stream's library workspace (4 n + 3 * 2048
+ * doubles); the captured graph is kept per device, so CG solves on one
+ * device must not run concurrently.  RSM_CHECK_INDICES validates the
  * index arrays on the host first.  Each batch of check_every iterations is
  * replayed from a HIP graph that the library captures once and keeps per
  * device while the call's arguments (buffers, sizes, tol, max_iter,

@@ -61,19 +61,34 @@ rsm_status hip_fail(hipError_t e, const char* what) {
 }
 
 // ---------------------------------------------------------------------------
-// workspace: one grow-only device buffer per device
+// workspace: one grow-only device buffer per (device, stream)
 // ---------------------------------------------------------------------------
+// Calls on one stream are ordered by the stream, so they may share a buffer;
+// calls on different streams get different buffers and never see each
+// other's partial results, intermediates or completion counter.
 namespace {
 struct Workspace {
+  int dev = -1;
+  hipStream_t stream = nullptr;
   void* ptr = nullptr;
   size_t bytes = 0;
 };
 std::mutex g_ws_mutex;
-Workspace g_ws[64];
+std::vector<Workspace> g_ws;  // one entry per (device, stream) that has used it
+
+bool stream_capturing(hipStream_t st, rsm_status* err) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  const hipError_t e = hipStreamIsCapturing(st, &cs);
+  if (e != hipSuccess) {
+    *err = hip_fail(e, "hipStreamIsCapturing");
+    return true;
+  }
+  return cs != hipStreamCaptureStatusNone;
+}
 }  // namespace
 
 // Layout: [256 bytes: completion counter, kept at zero between kernels][data]
-void* workspace(size_t bytes, hipStream_t /*st*/, rsm_status* err, uint32_t** counter) {
+void* workspace(size_t bytes, hipStream_t st, rsm_status* err, uint32_t** counter) {
   *err = RSM_OK;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -81,41 +96,56 @@ void* workspace(size_t bytes, hipStream_t /*st*/, rsm_status* err, uint32_t** co
     *err = hip_fail(e, "hipGetDevice");
     return nullptr;
   }
-  if (dev < 0 || dev >= 64) {
-    *err = fail(RSM_E_UNSUPPORTED, "device index beyond 63");
-    return nullptr;
-  }
   constexpr size_t kHead = 256;
   std::lock_guard<std::mutex> lock(g_ws_mutex);
-  Workspace& w = g_ws[dev];
-  if (!(w.ptr && w.bytes >= bytes)) {
+  Workspace* w = nullptr;
+  for (Workspace& c : g_ws)
+    if (c.dev == dev && c.stream == st) w = &c;
+  if (!w) {
+    g_ws.push_back(Workspace{});
+    w = &g_ws.back();
+    w->dev = dev;
+    w->stream = st;
+  }
+  if (!(w->ptr && w->bytes >= bytes)) {
+    // allocation is not allowed while the stream is being captured: the
+    // caller runs the same call once outside capture first
+    if (stream_capturing(st, err)) {
+      if (*err == RSM_OK)
+        *err = fail(RSM_E_UNSUPPORTED,
+                    "the library workspace of this stream must grow (to " + std::to_string(bytes) +
+                        " bytes), which is not possible while the stream is being captured; run the "
+                        "same call once before capturing");
+      return nullptr;
+    }
     size_t want = bytes < (size_t(1) << 20) ? (size_t(1) << 20) : bytes;
-    if (w.ptr) {
-      // earlier launches on any stream may still use the old buffer
-      e = hipDeviceSynchronize();
+    if (w->ptr) {
+      // earlier launches on this stream may still use the old buffer
+      e = hipStreamSynchronize(st);
       if (e != hipSuccess) {
-        *err = hip_fail(e, "hipDeviceSynchronize (workspace growth)");
+        *err = hip_fail(e, "hipStreamSynchronize (workspace growth)");
         return nullptr;
       }
-      (void)hipFree(w.ptr);
-      w.ptr = nullptr;
-      w.bytes = 0;
+      (void)hipFree(w->ptr);
+      w->ptr = nullptr;
+      w->bytes = 0;
     }
-    e = hipMalloc(&w.ptr, want + kHead);
+    e = hipMalloc(&w->ptr, want + kHead);
     if (e != hipSuccess) {
-      w.ptr = nullptr;
+      w->ptr = nullptr;
       *err = fail(RSM_E_NOMEM, std::string("workspace hipMalloc failed: ") + hipGetErrorString(e));
       return nullptr;
     }
-    e = hipMemset(w.ptr, 0, kHead);
+    // zeroed on the stream itself, so the stream's next kernels see it
+    e = launch_zero(w->ptr, kHead, st);
     if (e != hipSuccess) {
-      *err = hip_fail(e, "hipMemset (workspace counter)");
+      *err = hip_fail(e, "zero fill (workspace counter)");
       return nullptr;
     }
-    w.bytes = want;
+    w->bytes = want;
   }
-  if (counter) *counter = static_cast<uint32_t*>(w.ptr);
-  return static_cast<char*>(w.ptr) + kHead;
+  if (counter) *counter = static_cast<uint32_t*>(w->ptr);
+  return static_cast<char*>(w->ptr) + kHead;
 }
 
 // ---------------------------------------------------------------------------

@@ -362,7 +362,8 @@ size_t filter2d_lds_bytes(int k, int s, int tc);
 bool plan_filter2d(const rsm_space& rep, const rsm_tiler& in, const rsm_tiler& out,
                    const rsm_task& task, Filter2DProblem* fp);
 
-// Device workspace owned by the library (per device, grown on demand).
+// Device workspace owned by the library, one per (device, stream), grown on
+// demand (never while the stream is being captured: RSM_E_UNSUPPORTED).
 // *counter (if given) receives a 32-bit completion counter that is zero
 // between kernels (kernels that use it leave it at zero).
 void* workspace(size_t bytes, hipStream_t st, rsm_status* err, uint32_t** counter = nullptr);

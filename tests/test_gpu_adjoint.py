@@ -362,3 +362,38 @@ def test_deterministic_weight_gradient():
         res.append((host(gx), host(gch), host(gcv)))
     for a, b in zip(res[0], res[1]):
         assert np.array_equal(a, b)
+
+
+def test_calls_on_two_streams_use_separate_workspaces():
+    # Unfused chain adjoints keep intermediate gradients and weight-gradient
+    # partial rows in the library workspace.  Issued on two streams with no
+    # ordering between them, each must give what it gives alone.
+    cases = []
+    for seed in (31, 32):
+        ts = W.two_stage_filter(frames=4, rows=256, cols=512, seed=seed)
+        x = dev(ts.x)
+        chain = rsm.Chain([ts.h, ts.v], [dev(ts.c_h), dev(ts.c_v)])
+        gy = dev(W.rng_for(seed).uniform(-1, 1, ts.v.rep_shape).astype(np.float32))
+        cases.append((chain, x, gy))
+    want = []
+    for chain, x, gy in cases:
+        gx = torch.empty_like(x)
+        gcs = [torch.empty(8, device="cuda") for _ in range(2)]
+        chain.adjoint(x, gy, gx, gcs, flags=_abi.NO_FUSE)
+        want.append((gx, gcs))
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    got = []
+    for (chain, x, gy), s in zip(cases, streams):
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            gx = torch.full_like(x, float("nan"))
+            gcs = [torch.full((8,), float("nan"), device="cuda") for _ in range(2)]
+            got.append((gx, gcs))
+    for _ in range(3):
+        for (chain, x, gy), s, (gx, gcs) in zip(cases, streams, got):
+            chain.adjoint(x, gy, gx, gcs, flags=_abi.NO_FUSE, stream=s)
+    torch.cuda.synchronize()
+    for (gx, gcs), (wx, wcs) in zip(got, want):
+        assert torch.equal(gx, wx)
+        assert torch.equal(gcs[0], wcs[0]) and torch.equal(gcs[1], wcs[1])
