@@ -272,6 +272,26 @@ rsm_status rsm_run_chain_train(const rsm_stage* stages, int32_t n_stages, const 
                                void* d_out, void* d_gx, void* const* d_gc, uint32_t flags, void* hip_stream);
 
 /*
+ * rsm_run_chain_train_noalloc -- rsm_run_chain_train for callers that cannot
+ * allocate device memory: code being captured into a graph, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments, supported chains,
+ * results (the same kernels: the same bits) and errors as
+ * rsm_run_chain_train, but the weight-gradient partial rows live in a fixed
+ * 256 KiB array of device memory inside the library instead of the stream's
+ * workspace, so the call never allocates (no hipMalloc, hipFree or
+ * allocating library routine); a step whose partial rows would not fit
+ * returns RSM_E_UNSUPPORTED.  Every device holds its own copy of the array
+ * until the process ends, and every call on a device shares that copy (it
+ * keeps the last call's contents; nothing in it needs to start at zero):
+ * calls that may overlap on one device -- on different streams, or from
+ * different host threads without ordering -- race on it and must not be
+ * made.  The first call on each device looks up the array's address there.
+ */
+rsm_status rsm_run_chain_train_noalloc(const rsm_stage* stages, int32_t n_stages, const void* d_in,
+                                       const void* d_w, void* d_out, void* d_gx, void* const* d_gc,
+                                       uint32_t flags, void* hip_stream);
+
+/*
  * rsm_run_csr -- the repetitive task with data-dependent (indirect) tilers
  * that the paper's conjugate-gradient case study runs on the GPU (Sec. 7,
  * the sparse DGEMV): for every row r of a CSR matrix the pattern is the

@@ -88,7 +88,7 @@ EXPORTS = [
     "rsm_batch_query",
     "rsm_batch_tile", "rsm_batch_destroy", "rsm_status_string", "rsm_last_error",
     "rsm_abi_version", "rsm_run_csr", "rsm_cg_solve", "rsm_time_next_kernel", "rsm_run_chain_train",
-    "rsm_plan_ports",
+    "rsm_plan_ports", "rsm_run_chain_train_noalloc",
 ]
 
 _lib = None
@@ -119,6 +119,7 @@ def load(path: str = LIB_PATH):
     lib.rsm_run_csr.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp, vp,
                                 i32, u32, vp]
     lib.rsm_run_chain_train.argtypes = [P(Stage), i32, vp, vp, vp, vp, P(vp), u32, vp]
+    lib.rsm_run_chain_train_noalloc.argtypes = [P(Stage), i32, vp, vp, vp, vp, P(vp), u32, vp]
     lib.rsm_cg_solve.argtypes = [ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp, vp, ctypes.c_double,
                                  ctypes.c_int64, i32, u32, vp, vp, vp, P(CgInfo), vp]
     lib.rsm_batch_create.argtypes = [P(Problem), i32, ctypes.c_char_p, u32, vp, P(vp)]
@@ -129,7 +130,8 @@ def load(path: str = LIB_PATH):
     lib.rsm_batch_destroy.argtypes = [vp]
     for name in ("rsm_validate", "rsm_plan", "rsm_plan_ports", "rsm_indices", "rsm_run", "rsm_run_chain",
                  "rsm_run_adjoint", "rsm_run_chain_adjoint", "rsm_batch_create", "rsm_batch_run",
-                 "rsm_run_csr", "rsm_cg_solve", "rsm_run_chain_train", "rsm_batch_run_plain", "rsm_batch_query", "rsm_batch_tile", "rsm_batch_destroy"):
+                 "rsm_run_csr", "rsm_cg_solve", "rsm_run_chain_train", "rsm_run_chain_train_noalloc",
+                 "rsm_batch_run_plain", "rsm_batch_query", "rsm_batch_tile", "rsm_batch_destroy"):
         getattr(lib, name).restype = st
     lib.rsm_time_next_kernel.argtypes = [vp, vp]
     lib.rsm_time_next_kernel.restype = st

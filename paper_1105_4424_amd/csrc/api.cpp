@@ -1395,6 +1395,16 @@ rsm_status rsm_run_chain_adjoint(const rsm_stage* stages, int32_t n_stages, cons
 
 rsm_status rsm_run_chain_train(const rsm_stage* stages, int32_t n_stages, const void* d_in, const void* d_w,
                                void* d_out, void* d_gx, void* const* d_gc, uint32_t flags, void* hip_stream) {
+  return rsm::chain_train_step(stages, n_stages, d_in, d_w, d_out, d_gx, d_gc, flags, hip_stream, nullptr, 0);
+}
+
+}  // extern "C"
+
+namespace rsm {
+
+rsm_status chain_train_step(const rsm_stage* stages, int32_t n_stages, const void* d_in, const void* d_w,
+                            void* d_out, void* d_gx, void* const* d_gc, uint32_t flags, void* hip_stream,
+                            float* fixed_partial, size_t fixed_bytes) {
   const KernelProbe probe = take_probe();
   RSM_GUARD_BEGIN
   std::vector<Checked> cs;
@@ -1441,8 +1451,18 @@ rsm_status rsm_run_chain_train(const rsm_stage* stages, int32_t n_stages, const 
   const int grid = fir_chain_adjoint_grid(a, true);
   const int nc = h.taps + v.taps;
   if (gch || gcv) {
-    a.partial = static_cast<float*>(workspace(size_t(grid) * nc * sizeof(float), st, &s, nullptr));
-    if (s) return s;
+    const size_t need = size_t(grid) * nc * sizeof(float);
+    if (fixed_partial) {
+      // the caller's fixed buffer (no allocation on this path)
+      if (need > fixed_bytes)
+        return fail(RSM_E_UNSUPPORTED, "weight-gradient partial rows need " + std::to_string(need) +
+                                           " bytes, more than the fixed scratch buffer's " +
+                                           std::to_string(fixed_bytes));
+      a.partial = fixed_partial;
+    } else {
+      a.partial = static_cast<float*>(workspace(need, st, &s, nullptr));
+      if (s) return s;
+    }
   }
   if ((e = probed(probe, st, [&] { return launch_fir_chain_train(a, st); })) != hipSuccess)
     return hip_fail(e, "fused training step");
@@ -1452,6 +1472,10 @@ rsm_status rsm_run_chain_train(const rsm_stage* stages, int32_t n_stages, const 
   return RSM_OK;
   RSM_GUARD_END
 }
+
+}  // namespace rsm
+
+extern "C" {
 
 rsm_status rsm_run_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t* d_row_ptr,
                        const int32_t* d_col_idx, const void* d_vals, const void* d_x, void* d_y,

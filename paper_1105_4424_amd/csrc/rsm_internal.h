@@ -341,6 +341,14 @@ int csr_group_size(int64_t n_rows, int64_t nnz);
 // forward + loss gradient + adjoint of a fused 8-tap pair (vec4 layout only);
 // same grid and partial rows as launch_fir_chain_adjoint
 hipError_t launch_fir_chain_train(const FirChainAdjArgs& a, hipStream_t st);
+
+// The training step behind rsm_run_chain_train.  With fixed_partial set, the
+// weight-gradient partial rows go to that device buffer of fixed_bytes
+// (RSM_E_UNSUPPORTED if they need more) instead of the stream's workspace, so
+// the call allocates nothing.
+rsm_status chain_train_step(const rsm_stage* stages, int32_t n_stages, const void* d_in, const void* d_w,
+                            void* d_out, void* d_gx, void* const* d_gc, uint32_t flags, void* hip_stream,
+                            float* fixed_partial, size_t fixed_bytes);
 // init: r = b - A x, p = r, fresh state; then `iters` loop iterations
 hipError_t launch_cg(const CgArgs& a, bool init, int iters, hipStream_t st);
 int cg_grid(int64_t n, int64_t nnz);

@@ -467,3 +467,14 @@ class Chain:
         _check(self._lib.rsm_run_chain_train(self._arr, self._n, _ptr(x), _ptr(w), _ptr(out), _ptr(gx), gp,
                                              flags, _stream(stream)))
         return out
+
+    def train_noalloc(self, x, w, out, gx, gcs, flags: int = 0, stream=None):
+        """train() through rsm_run_chain_train_noalloc: the library allocates
+        nothing (its partial rows live in a fixed per-device array, shared by
+        every such call on the device)."""
+        gp = None
+        if gcs is not None:
+            gp = (ctypes.c_void_p * self._n)(*[(_ptr(g).value if g is not None else None) for g in gcs])
+        _check(self._lib.rsm_run_chain_train_noalloc(self._arr, self._n, _ptr(x), _ptr(w), _ptr(out), _ptr(gx),
+                                                     gp, flags, _stream(stream)))
+        return out

@@ -1,0 +1,84 @@
+"""rsm_run_chain_train_noalloc (the training step that allocates nothing)
+against rsm_run_chain_train.
+
+Both run the same kernels; only where the weight-gradient partial rows live
+differs (a fixed per-device array instead of the stream's workspace).  Two
+calls in a row on the fixed array: the full 30 x 1080 x 1920 step (the
+largest grid, so the most partial rows), then a smaller step whose windows
+wrap at the borders, which reuses the array the first call left filled.
+Each result must equal the workspace entry point's bit for bit, and the
+small step is also held to the FP64 oracle at 1e-5 of each value's |term|
+sum.  The no-allocation call comes first in each pair, so in a fresh
+process it is the first call of the library on the device.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import rsm_workloads as W
+from paper_1105_4424_amd import rsm
+
+from .helpers import check_close, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _abs_problem(p):
+    return W.Problem(p.rep_shape, [W.Tiler(t.array_shape, t.origin, t.paving, t.fitting, t.pattern_shape)
+                                   for t in p.inputs], p.output, p.task,
+                     None if p.coeffs is None else np.abs(p.coeffs))
+
+
+def _step(chain, x, w, out_shape, noalloc):
+    out = torch.full(out_shape, float("nan"), device="cuda")
+    gx = torch.full(tuple(x.shape), float("nan"), device="cuda")
+    gcs = [torch.full((8,), float("nan"), device="cuda") for _ in chain.stages]
+    if noalloc:
+        chain.train_noalloc(x, w, out, gx, gcs)
+    else:
+        chain.train(x, w, out, gx, gcs)
+    torch.cuda.synchronize()
+    return out, gx, gcs
+
+
+def _pair(frames, rows, cols, seed, h_origin=0, v_origin=0):
+    ts = W.two_stage_filter(frames=frames, rows=rows, cols=cols, taps=8, seed=seed,
+                            h_origin=h_origin, v_origin=v_origin)
+    w = W.loss_weights(ts.v.rep_shape)
+    chain = rsm.Chain([ts.h, ts.v], [dev(ts.c_h), dev(ts.c_v)])
+    x, wd = dev(ts.x), dev(w)
+    got = _step(chain, x, wd, ts.v.rep_shape, noalloc=True)
+    want = _step(chain, x, wd, ts.v.rep_shape, noalloc=False)
+    assert torch.equal(got[0], want[0]), "out differs from rsm_run_chain_train"
+    assert torch.equal(got[1], want[1]), "dL/dx differs from rsm_run_chain_train"
+    assert torch.equal(got[2][0], want[2][0]) and torch.equal(got[2][1], want[2][1]), \
+        "weight gradients differ from rsm_run_chain_train"
+    return ts, w, got
+
+
+def test_noalloc_train_two_calls_match_workspace_entry_point():
+    print("no-alloc training step: 30 x 1080 x 1920, seed 31", flush=True)
+    _pair(30, 1080, 1920, seed=31)
+    print("no-alloc training step: 2 x 80 x 200, origins (-4, -5), seed 32", flush=True)
+    ts, w, (out, gx, gcs) = _pair(2, 80, 200, seed=32, h_origin=-4, v_origin=-5)
+    stages = [ts.h, ts.v]
+    ref = oracle.chain_adjoint(stages, ts.x, w)
+    absd = oracle.chain_adjoint([_abs_problem(s) for s in stages], np.abs(ts.x), np.abs(w))
+    abs_out = oracle.chain_forward([_abs_problem(s) for s in stages], np.abs(ts.x))[-1].out
+    check_close(host(out), ref.forward[-1].out, abs_out, what="no-alloc out")
+    check_close(host(gx), ref.gx, absd.gx, what="no-alloc gx")
+    check_close(host(gcs[0]), ref.gc[0], absd.gc[0], what="no-alloc gc_h")
+    check_close(host(gcs[1]), ref.gc[1], absd.gc[1], what="no-alloc gc_v")
+
+
+def test_noalloc_train_rejects_what_the_workspace_entry_point_rejects():
+    # a single stage is not a two-stage chain: both entry points refuse it
+    # before touching the device
+    ts = W.two_stage_filter(frames=1, rows=40, cols=128, seed=33)
+    w = W.loss_weights(ts.h.rep_shape)
+    chain = rsm.Chain([ts.h], [dev(ts.c_h)])
+    for noalloc in (True, False):
+        with pytest.raises(rsm.RsmError) as e:
+            _step(chain, dev(ts.x), dev(w), ts.h.rep_shape, noalloc=noalloc)
+        assert e.value.name == "RSM_E_UNSUPPORTED"
