@@ -11,13 +11,18 @@ weight gradients).
 
   value      tiled elems/s: pattern elements gathered by every tiler of the
              step (forward 69.98 M + adjoint 69.98 M per step) / step time
-  roofline   the adjoint kernel (the step's largest): algorithmic bytes per
-             launch (read x + dL/dout, write dL/dx) / its average duration,
-             measured with HIP events around each launch in the timed loop
-  cpu_baseline  the CPU oracle on a bounded sample of frames (single thread)
+  roofline   the training-step kernel (the step's only large kernel,
+             fir_chain_train_pair_kernel<8>): algorithmic bytes per launch
+             (read x and the loss weights, write the output and dL/dx) / its
+             average duration, measured with HIP events the library records
+             immediately around the launch, on its stream, in the timed loop
+  cpu_baseline  the CPU oracle (plain C, FP64) on the whole 30-frame step,
+             one process per host core over slices of frames; the
+             single-thread time is reported beside it
 
-Two copies of the input and of the input gradient alternate between steps so
-that the 256 MiB Infinity Cache does not serve repeated reads.
+Four copies of the input and of the input gradient (about 1 GB each set)
+rotate between steps, so the 256 MiB Infinity Cache does not serve repeated
+reads.
 
 Other measurements (matrix product on the matrix cores, batched vs plain
 2-D filters, unfused variants, the small 64x64 task) go under "extra".
@@ -103,14 +108,15 @@ def main():
     ts = W.two_stage_filter(frames=F, rows=H, cols=Wd, taps=T)
     w = W.loss_weights(ts.v.rep_shape)
     stages = [ts.h, ts.v]
+    NCOPY = 4
     xs = [torch.from_numpy(ts.x).to(dev)]
-    xs.append(xs[0].clone())
+    xs += [xs[0].clone() for _ in range(NCOPY - 1)]
     ch = torch.from_numpy(ts.c_h).to(dev)
     cv = torch.from_numpy(ts.c_v).to(dev)
     w2 = (2.0 * torch.from_numpy(w)).to(dev)
     out = torch.empty(ts.v.rep_shape, device=dev)
     gy = torch.empty_like(out)
-    gxs = [torch.empty_like(xs[0]) for _ in range(2)]
+    gxs = [torch.empty_like(xs[0]) for _ in range(NCOPY)]
     gch = torch.empty(T, device=dev)
     gcv = torch.empty(T, device=dev)
     chain = rsm.Chain(stages, [ch, cv])
@@ -131,19 +137,19 @@ def main():
         # immediately around that kernel
         if ev is not None:
             rsm.time_next_kernel(ev[0], ev[1])
-        chain.train(xs[k & 1], wd, out, gxs[k & 1], [gch, gcv])
+        chain.train(xs[k % NCOPY], wd, out, gxs[k % NCOPY], [gch, gcv])
 
     def step_separate(k, ev=None):
         # the same step as three calls: fused forward, torch's 2 w * out,
         # fused adjoint (events around the forward and the adjoint kernels)
-        x = xs[k & 1]
+        x = xs[k % NCOPY]
         if ev is not None:
             rsm.time_next_kernel(ev[0], ev[1])
         chain.forward(x, out)
         torch.mul(w2, out, out=gy)
         if ev is not None:
             rsm.time_next_kernel(ev[2], ev[3])
-        chain.adjoint(x, gy, gxs[k & 1], [gch, gcv])
+        chain.adjoint(x, gy, gxs[k % NCOPY], [gch, gcv])
 
     # A pair of timing events around a kernel costs about 14 us of queue time
     # (the stream drains at each timestamp), so the kernels are timed on every
@@ -184,7 +190,7 @@ def main():
     for k in range(14):
         e = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
         e[0].record()
-        gxs[k & 1].copy_(xs[k & 1])
+        gxs[k % NCOPY].copy_(xs[k % NCOPY])
         e[1].record()
         if k >= 4:
             cev.append(e)
@@ -227,7 +233,11 @@ def main():
                                     "frac": fwd_gbs / HBM_PEAK_GBS},
                   "adjoint_fused": {"kernel": "fir_chain_adjoint_pair_kernel<8>", "avg_us": adj_us,
                                     "bytes": adj_bytes, "gbs": adj_gbs,
-                                    "frac": adj_gbs / HBM_PEAK_GBS}},
+                                    "frac": adj_gbs / HBM_PEAK_GBS,
+                                    "cache_assisted": True,
+                                    "note": "runs right after the forward pass over the same x, "
+                                            "part of which the 256 MiB last-level cache still "
+                                            "holds: not an HBM-only rate"}},
     }
 
     if args.copy_calibration:
@@ -261,6 +271,32 @@ def time_fn(fn, reps=20, warm=3):
     return float(np.median([a.elapsed_time(b) for a, b in ev])) * 1e3
 
 
+def bf16_to_f64(u16):
+    """BF16 bit patterns (uint16) widened exactly to FP64."""
+    import numpy as np
+    return (u16.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def product_errors(got, ref32, refbf, abs32, absbf, rows):
+    """Normwise and elementwise error of sampled rows of a product against
+    FP64 products of the FP32 inputs and (if given) of the BF16-rounded ones."""
+    import numpy as np
+
+    def one(ref, absr):
+        d = got - ref
+        return {"normwise": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+                "max_abs_over_abs_sum": float(np.max(np.abs(d) / absr)),
+                "max_rel_large": float(np.max(np.abs(d)[np.abs(ref) > 1e-3 * np.abs(ref).max()]
+                                              / np.abs(ref)[np.abs(ref) > 1e-3 * np.abs(ref).max()]))}
+
+    out = {"sample": "%d whole rows of C (rows %d..%d evenly spaced), %d outputs"
+                     % (len(rows), rows[0], rows[-1], got.size),
+           "fp32_inputs": one(ref32, abs32)}
+    if refbf is not None:
+        out["bf16_rounded_inputs"] = one(refbf, absbf)
+    return out
+
+
 def extras(args, ts, xs, stages, ch, cv, w2, chain):
     import numpy as np
     import torch
@@ -278,7 +314,7 @@ def extras(args, ts, xs, stages, ch, cv, w2, chain):
 
     def unfused_fwd():
         k = state["k"] = state["k"] + 1
-        chain.forward(xs[k & 1], out, mids=[mid], flags=_abi.NO_FUSE)
+        chain.forward(xs[k % len(xs)], out, mids=[mid], flags=_abi.NO_FUSE)
 
     us = time_fn(unfused_fwd)
     b = xs[0].numel() * 4 + 2 * mid.numel() * 4 + out.numel() * 4
@@ -290,7 +326,7 @@ def extras(args, ts, xs, stages, ch, cv, w2, chain):
 
     def unfused_adj():
         k = state["k"] = state["k"] + 1
-        chain.adjoint(xs[k & 1], gy, gx, [gch, gcv], mids=[mid], flags=_abi.NO_FUSE)
+        chain.adjoint(xs[k % len(xs)], gy, gx, [gch, gcv], mids=[mid], flags=_abi.NO_FUSE)
 
     us = time_fn(unfused_adj)
     b = (out.numel() + 2 * mid.numel() + 2 * xs[0].numel() + mid.numel() * 0) * 4 + mid.numel() * 4
@@ -300,12 +336,12 @@ def extras(args, ts, xs, stages, ch, cv, w2, chain):
     # fused forward alone over four input copies (about 1 GB, so the 256 MiB
     # Infinity Cache serves none of its reads and no adjoint's dirty lines
     # are pending), events around the kernel
-    xr = list(xs) + [xs[0].clone(), xs[0].clone()]
+    xr = list(xs)
     evs = []
     for k in range(24):
         e = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
         rsm.time_next_kernel(*e)
-        chain.forward(xr[k % 4], out)
+        chain.forward(xr[k % len(xr)], out)
         if k >= 4:
             evs.append(e)
     torch.cuda.synchronize()
@@ -315,6 +351,41 @@ def extras(args, ts, xs, stages, ch, cv, w2, chain):
                                       "gbs": b / us / 1e3, "frac": b / us / 1e3 / HBM_PEAK_GBS}
     log("fused forward alone %.1f us %.0f GB/s" % (us, b / us / 1e3))
     del xr
+
+    # the same training step as a user of torch writes it: the chain behind
+    # torch.autograd.Function (rsm.TiledChain), the loss formed by torch, and
+    # loss.backward() running the fused adjoint; wall clock per step, inputs
+    # rotated over the copies
+    wl = w2 * 0.5
+    leaves = [x.detach().clone().requires_grad_(True) for x in xs]
+    chl = ch.detach().clone().requires_grad_(True)
+    cvl = cv.detach().clone().requires_grad_(True)
+
+    def autograd_step(k):
+        xl = leaves[k % len(leaves)]
+        xl.grad = None
+        chl.grad = None
+        cvl.grad = None
+        y = rsm.TiledChain.apply(xl, chl, cvl, stages, True)
+        loss = (wl * y * y).sum()
+        loss.backward()
+
+    for k in range(args.warmup):
+        autograd_step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        autograd_step(k)
+    torch.cuda.synchronize()
+    ag_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    n_tiled = 2 * sum(int(np.prod(st.rep_shape)) * int(np.prod(st.inputs[0].pattern_shape)) for st in stages)
+    ex["training_step_autograd"] = {
+        "route": "rsm.TiledChain.apply (torch.autograd.Function) + torch loss + loss.backward()",
+        "ms_per_step": ag_ms, "value": n_tiled / (ag_ms * 1e-3), "unit": "tiled elems/s",
+        "kernels": "fir_chain_pair_kernel<8> (forward), torch elementwise loss and its gradient, "
+                   "fir_chain_adjoint_pair_kernel<8> + weight-gradient reduction (backward)"}
+    log("autograd route: %.3f ms per step" % ag_ms)
+    del leaves
 
     # adjoint of an overlapping horizontal stage (13 taps every 8 columns,
     # centred origin -6: windows overlap by 5 and wrap at both borders) on the
@@ -332,7 +403,7 @@ def extras(args, ts, xs, stages, ch, cv, w2, chain):
     def overlap_adj(flags):
         def run():
             k = state["k"] = state["k"] + 1
-            rsm.run_adjoint(po, xs[k & 1], gyo, gx, gco, co, flags=flags)
+            rsm.run_adjoint(po, xs[k % len(xs)], gyo, gx, gco, co, flags=flags)
         return run
 
     us_g = time_fn(overlap_adj(0))
@@ -367,6 +438,17 @@ def extras(args, ts, xs, stages, ch, cv, w2, chain):
     tf = 2.0 * M * N * K / us / 1e6
     ex["matmul_bf16_4096"] = {"avg_us": us, "tflops": tf, "frac": tf / BF16_PEAK_TFLOPS,
                               "kernel": rsm.plan(pm, dtypes=(torch.bfloat16,))}
+    # error of the product against FP64 on a sample of whole rows of C
+    rows = np.linspace(0, M - 1, 64).astype(np.int64)
+    ref32 = a[rows].astype(np.float64) @ bm.astype(np.float64)
+    refbf = bf16_to_f64(ab[rows]) @ bf16_to_f64(bb)
+    absbf = np.abs(bf16_to_f64(ab[rows])) @ np.abs(bf16_to_f64(bb))
+    abs32 = np.abs(a[rows].astype(np.float64)) @ np.abs(bm.astype(np.float64))
+    got = cm[torch.from_numpy(rows).to(dev)].double().cpu().numpy()
+    ex["matmul_bf16_4096"]["error_vs_fp64"] = product_errors(got, ref32, refbf, abs32, absbf, rows)
+    log("bf16 product error: %.3e normwise vs FP64 of the FP32 inputs, %.3e vs FP64 of the BF16 inputs"
+        % (ex["matmul_bf16_4096"]["error_vs_fp64"]["fp32_inputs"]["normwise"],
+           ex["matmul_bf16_4096"]["error_vs_fp64"]["bf16_rounded_inputs"]["normwise"]))
     pm.compute = "f32"
     fa = torch.from_numpy(a).to(dev)
     fb = torch.from_numpy(bm).to(dev)
@@ -374,6 +456,8 @@ def extras(args, ts, xs, stages, ch, cv, w2, chain):
     tf = 2.0 * M * N * K / us / 1e6
     ex["matmul_f32_4096"] = {"avg_us": us, "tflops": tf, "frac": tf / FP32_PEAK_TFLOPS,
                              "kernel": rsm.plan(pm)}
+    got = cm[torch.from_numpy(rows).to(dev)].double().cpu().numpy()
+    ex["matmul_f32_4096"]["error_vs_fp64"] = product_errors(got, ref32, None, abs32, None, rows)
     log("matmul bf16 %.1f TF/s, f32 %.1f TF/s" % (ex["matmul_bf16_4096"]["tflops"], tf))
     del da, db, fa, fb, cm
 
@@ -411,7 +495,11 @@ def extras(args, ts, xs, stages, ch, cv, w2, chain):
     us = time_fn(lambda: rsm.run_csr(rp, ci, va, xv, yv), reps=50)
     b = A.nnz * 12 + (A.n + 1) * 4 + A.n * 8 * 2
     ex["spmv_f64_stencil27_51cubed"] = {"avg_us": us, "bytes": b, "gbs": b / us / 1e3,
-                                        "frac": b / us / 1e3 / HBM_PEAK_GBS, "n": A.n, "nnz": A.nnz}
+                                        "frac": b / us / 1e3 / HBM_PEAK_GBS, "n": A.n, "nnz": A.nnz,
+                                        "cache_assisted": True,
+                                        "note": "the 44 MB working set is re-read by 50 back-to-back "
+                                                "products and stays in the 256 MiB last-level cache: "
+                                                "a cache-resident rate, not an HBM one"}
     log("spmv %.1f us %.0f GB/s" % (us, b / us / 1e3))
 
     # the case study's conjugate-gradient loop at its size, FP64, tol 1e-10;
@@ -435,7 +523,9 @@ def extras(args, ts, xs, stages, ch, cv, w2, chain):
     ex["cg_f64_stencil27_51cubed"] = {
         "iterations": info["iterations"], "converged": info["converged"], "ms": ms,
         "us_per_iteration": ms * 1e3 / max(info["iterations"], 1), "gflops": flops / ms / 1e6,
-        "tol": 1e-10, "n": A.n, "nnz": A.nnz,
+        "tol": 1e-10, "n": A.n, "nnz": A.nnz, "cache_assisted": True,
+        "note": "the 53 MB working set of matrix and vectors stays in the 256 MiB last-level cache "
+                "across iterations",
         "paper_1gpu_context": {"gflops": 1.45, "iterations": 116, "seconds": 0.659,
                                "hardware": "Tesla T10, FEM matrix (Table 1)"}}
     log("cg %d iterations %.2f ms (%.1f us/iter) %.1f GFLOP/s" %
@@ -443,30 +533,81 @@ def extras(args, ts, xs, stages, ch, cv, w2, chain):
     return ex
 
 
+def _cpu_slice(frames, seed, q):
+    """Worker of the all-core CPU baseline: the oracle's forward of both
+    stages and their adjoint on `frames` frames (inputs made before timing)."""
+    import rsm_workloads as W
+    import oracle
+    ts = W.two_stage_filter(frames=frames, seed=seed)
+    w = W.loss_weights(ts.v.rep_shape, seed=seed + 1000)
+    t0 = time.perf_counter()
+    oracle.chain_adjoint([ts.h, ts.v], ts.x, w)
+    q.put((t0, time.perf_counter()))
+
+
+def host_cpu():
+    """(threads this process may use, CPU model name)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return n, model
+
+
 def cpu_baseline(args, W):
-    """The oracle (plain C, FP64, one thread) on a bounded sample of frames of
-    the same workload: forward of both stages and their adjoint."""
-    import numpy as np
+    """The oracle (plain C, FP64, unchanged) on the whole 30-frame step --
+    forward of both stages and their adjoint -- once on one thread, and once
+    as one process per host core, each running the single-thread oracle on
+    its slice of the frames (frames are independent repetitions).  The
+    all-core figure is the reported value."""
+    import multiprocessing as mp
 
     import oracle
 
-    def run_frames(n):
-        ts = W.two_stage_filter(frames=n)
-        w = W.loss_weights(ts.v.rep_shape)
-        t0 = time.perf_counter()
-        oracle.chain_adjoint([ts.h, ts.v], ts.x, w)
-        return time.perf_counter() - t0
-
-    log("cpu baseline: oracle on 1 frame")
-    t1 = run_frames(1)
-    n = int(max(1, min(30, args.cpu_seconds / max(t1, 1e-3))))
-    log("cpu baseline: oracle on %d frames" % n)
-    tn = run_frames(n) if n > 1 else t1
     per_frame_tiled = 2 * (1080 * 240 * 8 + 135 * 240 * 8)
-    return {"value": n * per_frame_tiled / tn, "unit": "tiled elems/s", "cores": 1,
+    threads, model = host_cpu()
+    # the box's CPU share for one GPU is 16 threads, whatever the host shows
+    procs = max(1, min(16, threads, 30))
+
+    log("cpu baseline: oracle on 30 frames, one thread")
+    ts = W.two_stage_filter(frames=30)
+    w = W.loss_weights(ts.v.rep_shape)
+    t0 = time.perf_counter()
+    oracle.chain_adjoint([ts.h, ts.v], ts.x, w)
+    t1 = time.perf_counter() - t0
+    del ts, w
+
+    log("cpu baseline: oracle on 30 frames, %d processes" % procs)
+    ctx = mp.get_context("spawn")   # no fork of a process that holds the GPU
+    walls = []
+    for rep in range(3):
+        q = ctx.Queue()
+        share = [30 // procs + (1 if k < 30 % procs else 0) for k in range(procs)]
+        ps = [ctx.Process(target=_cpu_slice, args=(share[k], 100 + k, q)) for k in range(procs)]
+        for p in ps:
+            p.start()
+        spans = [q.get() for _ in ps]
+        for p in ps:
+            p.join()
+        walls.append(max(e for _, e in spans) - min(b for b, _ in spans))
+    tn = sorted(walls)[1]
+    return {"value": 30 * per_frame_tiled / tn, "unit": "tiled elems/s", "cores": procs,
             "kind": "oracle", "seconds": tn,
-            "sample": "%d of 30 frames (1080x1920), forward of both stages + adjoint, FP64 C oracle, "
-                      "single thread; host has %d hardware threads" % (n, os.cpu_count() or 0)}
+            "single_thread": {"value": 30 * per_frame_tiled / t1, "seconds": t1, "cores": 1},
+            "cpu_model": model, "host_threads": threads,
+            "sample": "the whole step: 30 frames of 1080x1920, forward of both stages + adjoint, FP64 C "
+                      "oracle; %d processes of the single-thread oracle over frame slices (%s frames each, "
+                      "same shapes and distributions, per-slice seeds), median wall time of 3 runs from "
+                      "the first slice's start to the last slice's end; the single-thread figure runs "
+                      "the 30 frames in one process" % (procs, "/".join(sorted({str(x) for x in share})))}
 
 
 if __name__ == "__main__":

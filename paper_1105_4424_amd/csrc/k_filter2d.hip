@@ -7,8 +7,10 @@
 // every border).  Each thread then computes an RY x RX block of outputs:
 // every LDS row segment it needs (RX S + K - S floats, 16-byte aligned
 // because RX S = 4) is read once with ds_read_b128 and reused across its RX
-// outputs, so LDS traffic per output falls with RX and RY.  Weights are
-// uniform across the workgroup and live in scalar registers.
+// outputs, so LDS traffic per output falls with RX and RY.  The k x k
+// weights are uniform across the workgroup: they are staged in LDS after the
+// input region and read with broadcast 16-byte LDS reads, one window row at
+// a time.
 //
 // Two launch forms share the tile body:
 //  * filter2d_kernel: one problem, one workgroup per tile (plain launches);
