@@ -215,7 +215,9 @@ class AdjointResult:
 
 
 def adjoint(problem, x: np.ndarray, gy: np.ndarray) -> AdjointResult:
-    """Adjoint of a SUM/WSUM task with a scalar output pattern."""
+    """Adjoint of a SUM task (scalar output pattern) or a WSUM task (any
+    output pattern; weight gradient shaped like the coefficients, i.e.
+    output pattern x input pattern, or the input pattern when scalar)."""
     lib = _load()
     t = problem.inputs[0]
     xw = widen(x).reshape(-1)
@@ -223,8 +225,9 @@ def adjoint(problem, x: np.ndarray, gy: np.ndarray) -> AdjointResult:
     gx = np.zeros(xw.size)
     gxa = np.zeros(xw.size)
     npat = int(np.prod(t.pattern_shape)) if len(t.pattern_shape) else 1
-    gc = np.zeros(npat)
-    gca = np.zeros(npat)
+    nq = int(np.prod(problem.output.pattern_shape)) if len(problem.output.pattern_shape) else 1
+    gc = np.zeros(npat * nq)
+    gca = np.zeros(npat * nq)
     weighted = problem.task == WSUM
     c = widen(problem.coeffs).reshape(-1) if weighted else None
     rs = _i64(problem.rep_shape if len(problem.rep_shape) else [1])
@@ -237,11 +240,12 @@ def adjoint(problem, x: np.ndarray, gy: np.ndarray) -> AdjointResult:
                             _ptr(gc, ctypes.c_double) if weighted else null,
                             _ptr(gca, ctypes.c_double) if weighted else null)
     if rc != 0:
-        raise ValueError("oracle: adjoint needs a scalar output pattern")
+        raise ValueError("oracle: the adjoint of SUM needs a scalar output pattern")
     shp = tuple(t.array_shape)
+    cshape = tuple(t.pattern_shape) if nq == 1 else tuple(problem.output.pattern_shape) + tuple(t.pattern_shape)
     return AdjointResult(gx.reshape(shp), gxa.reshape(shp),
-                         gc.reshape(t.pattern_shape) if weighted else None,
-                         gca.reshape(t.pattern_shape) if weighted else None)
+                         gc.reshape(cshape) if weighted else None,
+                         gca.reshape(cshape) if weighted else None)
 
 
 class ChainResult:

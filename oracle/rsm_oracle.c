@@ -24,6 +24,16 @@
  * weighted-sum task follows from the same definition by transposing the
  * gather: gx[e_in(r,i)] += c[i] gy[e_out(r)], gc[i] += gy[e_out(r)] x[e_in(r,i)].
  *
+ * The weighted sum may also have an output pattern of q > 1 elements (an
+ * elementary task that produces a pattern, as every Array-OL task may: a
+ * polyphase filter, where one repetition reads a window and writes several
+ * outputs, each with its own taps).  Its coefficients are then a q x |s_p|
+ * matrix, row j holding the taps of output element j:
+ *     y(r)[j] = sum_i c[j][i] pat(r)[i]
+ * and its adjoint is gx[e_in(r,i)] += sum_j c[j][i] gy[e_out(r,j)],
+ * gc[j][i] += gy[e_out(r,j)] x[e_in(r,i)].  With q = 1 this is the plain
+ * weighted sum above.
+ *
  * Nothing here is blocked, fused or reordered: every loop is the definition.
  */
 #include <stdint.h>
@@ -118,6 +128,22 @@ static int task_one(int32_t rep_rank, const int64_t* r,
         }
         return 0;
     }
+    if (kind == OR_WSUM && n_out > 1) {
+        /* output pattern of n_out elements: one row of taps per element */
+        if (n_in != 1) return -1;
+        for (int64_t jf = 0; jf < n_out; ++jf) {
+            double acc = 0.0, aabs = 0.0;
+            for (int64_t pf = 0; pf < np; ++pf) {
+                unflatten(pf, in[0].pat_shape, in[0].pat_rank, i);
+                double term = coeffs[jf * np + pf] * x[0][element_offset(&in[0], rep_rank, r, i)];
+                acc += term;
+                aabs += fabs(term);
+            }
+            y[jf] = acc;
+            yabs[jf] = aabs;
+        }
+        return 0;
+    }
     if (n_out != 1) return -1;
     double acc = 0.0, aabs = 0.0;
     if (kind == OR_SUM || kind == OR_WSUM) {
@@ -205,9 +231,11 @@ int oracle_run_sample(int32_t rep_rank, const int64_t* rep_shape,
 
 /*
  * Adjoint of the weighted sum (SUM is the weighted sum with unit weights,
- * coeffs == NULL).  Output pattern is scalar.  gx (array-shaped) and gc
- * (pattern-shaped) are accumulated into (caller zeroes them); *_abs receive
- * the |term| sums for tolerance checks.  gc / gc_abs may be NULL.
+ * coeffs == NULL, and a scalar output pattern).  A weighted sum may have an
+ * output pattern of q elements, coeffs then being q x |s_p| (row j = taps of
+ * output element j).  gx (array-shaped) and gc (q x |s_p|) are accumulated
+ * into (caller zeroes them); *_abs receive the |term| sums for tolerance
+ * checks.  gc / gc_abs may be NULL.
  */
 int oracle_adjoint(int32_t rep_rank, const int64_t* rep_shape,
                    const or_tiler* in, const double* x,
@@ -217,20 +245,24 @@ int oracle_adjoint(int32_t rep_rank, const int64_t* rep_shape,
 {
     int64_t nr = prod(rep_shape, rep_rank);
     int64_t np = prod(in->pat_shape, in->pat_rank);
-    if (prod(out_t->pat_shape, out_t->pat_rank) != 1) return -1;
-    int64_t r[OR_MAXR], i[OR_MAXR], none[OR_MAXR] = {0};
+    int64_t nq = prod(out_t->pat_shape, out_t->pat_rank);
+    if (nq != 1 && !coeffs) return -1;
+    int64_t r[OR_MAXR], i[OR_MAXR], j[OR_MAXR];
     for (int64_t rf = 0; rf < nr; ++rf) {
         unflatten(rf, rep_shape, rep_rank, r);
-        double g = gy[element_offset(out_t, rep_rank, r, none)];
-        for (int64_t pf = 0; pf < np; ++pf) {
-            unflatten(pf, in->pat_shape, in->pat_rank, i);
-            int64_t a = element_offset(in, rep_rank, r, i);
-            double c = coeffs ? coeffs[pf] : 1.0;
-            gx[a] += c * g;
-            gx_abs[a] += fabs(c * g);
-            if (gc) {
-                gc[pf] += g * x[a];
-                gc_abs[pf] += fabs(g * x[a]);
+        for (int64_t jf = 0; jf < nq; ++jf) {
+            unflatten(jf, out_t->pat_shape, out_t->pat_rank, j);
+            double g = gy[element_offset(out_t, rep_rank, r, j)];
+            for (int64_t pf = 0; pf < np; ++pf) {
+                unflatten(pf, in->pat_shape, in->pat_rank, i);
+                int64_t a = element_offset(in, rep_rank, r, i);
+                double c = coeffs ? coeffs[jf * np + pf] : 1.0;
+                gx[a] += c * g;
+                gx_abs[a] += fabs(c * g);
+                if (gc) {
+                    gc[jf * np + pf] += g * x[a];
+                    gc_abs[jf * np + pf] += fabs(g * x[a]);
+                }
             }
         }
     }

@@ -60,7 +60,9 @@ class Problem:
     inputs: List[Tiler]
     output: Tiler
     task: int
-    coeffs: Optional[np.ndarray] = None     # float32, pattern-shaped (WSUM)
+    coeffs: Optional[np.ndarray] = None     # float32 (WSUM): input-pattern shaped, or
+                                            # [output pattern, input pattern] when the
+                                            # output pattern has several elements
     compute: str = "f32"                    # "f32" or "bf16" (DOT only)
     note: str = ""
 
@@ -170,6 +172,65 @@ def two_stage_filter(frames: int = 30, rows: int = 1080, cols: int = 1920,
     hp = Problem(rep_h, [th], identity_output(rep_h), WSUM, c_h)
     vp = Problem(rep_v, [tv], identity_output(rep_v), WSUM, c_v)
     return TwoStage(x, c_h, c_v, hp, vp)
+
+
+# ---------------------------------------------------------------------------
+# Polyphase (multi-output) stages: one repetition reads a window of `taps`
+# elements and writes `phases` consecutive outputs, each with its own taps
+# (a weighted sum whose output pattern has `phases` elements)
+# ---------------------------------------------------------------------------
+
+def phase_output(rep_shape: Sequence[int], axis: int, phases: int) -> Tiler:
+    """Output tiler writing y(r)[j] to B[..., phases * r_axis + j, ...]:
+    origin 0, paving diag with `phases` on `axis`, pattern [phases] along it."""
+    d = len(rep_shape)
+    shape = list(rep_shape)
+    shape[axis] *= phases
+    pav = np.eye(d, dtype=np.int64)
+    pav[axis, axis] = phases
+    fit = np.zeros((d, 1), np.int64)
+    fit[axis, 0] = 1
+    return Tiler(tuple(shape), np.zeros(d), pav, fit, (phases,))
+
+
+def phase_coeffs(rng: np.random.Generator, phases: int, taps: int) -> np.ndarray:
+    """[phases, taps] FP32, each row normalised like normalised_coeffs."""
+    return np.stack([normalised_coeffs(rng, taps) for _ in range(phases)])
+
+
+@dataclass
+class Polyphase:
+    x: np.ndarray
+    c_h: np.ndarray      # [phases_h, taps_h]
+    c_v: np.ndarray      # [phases_v, taps_v]
+    h: Problem
+    v: Problem
+
+
+def polyphase_downscaler(frames: int = 30, rows: int = 1080, cols: int = 1920,
+                         taps_h: int = 13, pave_h: int = 8, phases_h: int = 3, origin_h: int = -2,
+                         taps_v: int = 14, pave_v: int = 9, phases_v: int = 4, origin_v: int = -2,
+                         seed: int = 5) -> Polyphase:
+    """Downscaler built from two polyphase stages (1920x1080 -> 720x480 per
+    frame with the defaults): horizontally every 8 columns a 13-tap window
+    (origin -2, overlapping its neighbours by 5 and wrapping at both borders)
+    gives 3 outputs, then vertically every 9 rows a 14-tap window (origin -2)
+    gives 4 outputs.  x ~ U[0,1) FP32; coefficient rows normalised, from the
+    same seed stream after x."""
+    rng = rng_for(seed)
+    x = rng.random((frames, rows, cols), dtype=np.float32)
+    c_h = phase_coeffs(rng, phases_h, taps_h)
+    c_v = phase_coeffs(rng, phases_v, taps_v)
+    rc = -(-cols // pave_h)
+    rep_h = (frames, rows, rc)
+    th = h_stage(frames, rows, cols, taps_h, pave_h, origin_h)
+    hp = Problem(rep_h, [th], phase_output(rep_h, 2, phases_h), WSUM, c_h)
+    mid_cols = rc * phases_h
+    rr = -(-rows // pave_v)
+    rep_v = (frames, rr, mid_cols)
+    tv = v_stage(frames, rows, mid_cols, taps_v, pave_v, origin_v)
+    vp = Problem(rep_v, [tv], phase_output(rep_v, 1, phases_v), WSUM, c_v)
+    return Polyphase(x, c_h, c_v, hp, vp)
 
 
 def loss_weights(shape: Sequence[int], seed: int = 4) -> np.ndarray:

@@ -33,7 +33,7 @@ MUTATIONS = {
     "dot_same_operand": ("* x[1][element_offset(&in[1], rep_rank, r, i2)];",
                          "* x[0][element_offset(&in[0], rep_rank, r, i)];"),
     "adjoint_sign": ("gx[a] += c * g;", "gx[a] -= c * g;"),
-    "adjoint_weight_grad_uses_weight": ("gc[pf] += g * x[a];", "gc[pf] += c * x[a];"),
+    "adjoint_weight_grad_uses_weight": ("gc[jf * np + pf] += g * x[a];", "gc[jf * np + pf] += c * x[a];"),
     "adjoint_drops_weight": ("gx[a] += c * g;", "gx[a] += g;"),
     "csr_first_column_only": ("double term = vals[k] * x[col_idx[k]];",
                               "double term = vals[k] * x[col_idx[row_ptr[r]]];"),
@@ -57,9 +57,22 @@ MUTATIONS = {
                              "            acc += term;\n"
                              "            aabs = fabs(acc);"),
     "adjoint_gx_bound_scaled": ("gx_abs[a] += fabs(c * g);", "gx_abs[a] += 10.0 * fabs(c * g);"),
-    "adjoint_gc_bound_scaled": ("gc_abs[pf] += fabs(g * x[a]);",
-                                "gc_abs[pf] += 10.0 * fabs(g * x[a]);"),
+    "adjoint_gc_bound_scaled": ("gc_abs[jf * np + pf] += fabs(g * x[a]);",
+                                "gc_abs[jf * np + pf] += 10.0 * fabs(g * x[a]);"),
     "copy_bound_signed": ("yabs[pf] = fabs(y[pf]);", "yabs[pf] = y[pf];"),
+    # slips in the weighted sum with an output pattern of several elements
+    "multi_output_transposed_taps": ("double term = coeffs[jf * np + pf] * x[0]",
+                                     "double term = coeffs[pf * n_out + jf] * x[0]"),
+    "multi_output_first_row_only": ("double term = coeffs[jf * np + pf] * x[0]",
+                                    "double term = coeffs[pf] * x[0]"),
+    "multi_output_bound_drops_weight": ("                acc += term;\n                aabs += fabs(term);\n"
+                                        "            }\n            y[jf] = acc;",
+                                        "                acc += term;\n                aabs += fabs(term / coeffs[jf * np + pf]);\n"
+                                        "            }\n            y[jf] = acc;"),
+    "multi_output_adjoint_transposed_taps": ("double c = coeffs ? coeffs[jf * np + pf] : 1.0;",
+                                             "double c = coeffs ? coeffs[pf * nq + jf] : 1.0;"),
+    "multi_output_adjoint_first_phase_gradient": ("double g = gy[element_offset(out_t, rep_rank, r, j)];",
+                                                  "j[0] = 0; double g = gy[element_offset(out_t, rep_rank, r, j)];"),
 }
 
 PINS = [
@@ -81,6 +94,9 @@ PINS = [
     pins.test_copy_abs_sum_is_magnitude,
     pins.test_adjoint_abs_sums_match_index_table_random_tilers,
     pins.test_adjoint_abs_sums_two_stage_closed_form,
+    pins.test_polyphase_forward_equals_fft_correlation_per_phase,
+    pins.test_polyphase_one_hot_taps_select_samples,
+    pins.test_polyphase_adjoint_equals_fft_and_adjoint_identity,
 ]
 
 

@@ -495,6 +495,159 @@ def test_adjoint_abs_sums_two_stage_closed_form():
     assert np.array_equal(a2.gx_abs, np.repeat(np.repeat(np.abs(g2), 4, 0), 4, 1))
 
 
+# ---------------------------------------------------------------------------
+# Weighted sums with an output pattern of q > 1 elements (polyphase stages):
+# y(r)[j] = sum_i C[j, i] x[e(r, i)].  Along one axis, phase j of every row is
+# the circular cross-correlation of the row with C[j], read at the window
+# starts o + p r; the adjoint places the phase-j gradients at those starts
+# and convolves with C[j].  Both are computed here with FFTs, a mechanism the
+# oracle does not use.
+# ---------------------------------------------------------------------------
+
+def _corr_fft(x, c, axis):
+    """corr[..., m, ...] = sum_i c[i] x[..., (m + i) mod n, ...] along axis."""
+    n = x.shape[axis]
+    cp = np.zeros(n)
+    cp[:len(c)] = c
+    shape = [1] * x.ndim
+    shape[axis] = n
+    fx = np.fft.fft(x, axis=axis)
+    fc = np.conj(np.fft.fft(cp)).reshape(shape)
+    return np.real(np.fft.ifft(fx * fc, axis=axis))
+
+
+def _polyphase_fft(x, C, o, p, reps, axis):
+    """Forward of a polyphase stage along `axis` by FFT correlation."""
+    n = x.shape[axis]
+    starts = (o + p * np.arange(reps)) % n
+    q = C.shape[0]
+    out_shape = list(x.shape)
+    out_shape[axis] = reps * q
+    out = np.zeros(out_shape)
+    for j in range(q):
+        cj = np.take(_corr_fft(x, C[j], axis), starts, axis=axis)
+        sl = [slice(None)] * x.ndim
+        sl[axis] = slice(j, reps * q, q)
+        out[tuple(sl)] = cj
+    return out
+
+
+def _polyphase_adjoint_fft(x, g, C, o, p, axis):
+    """(gx, gc) of a polyphase stage along `axis` by FFT convolution /
+    correlation of the phase gradients placed at the window starts."""
+    n = x.shape[axis]
+    q, T = C.shape
+    reps = g.shape[axis] // q
+    starts = (o + p * np.arange(reps)) % n
+    gx = np.zeros(x.shape)
+    gc = np.zeros((q, T))
+    shape = [1] * x.ndim
+    shape[axis] = n
+    for j in range(q):
+        sl = [slice(None)] * g.ndim
+        sl[axis] = slice(j, reps * q, q)
+        gj = g[tuple(sl)]
+        u = np.zeros(x.shape)
+        usl = [slice(None)] * x.ndim
+        for r in range(reps):      # starts are distinct when p r < n
+            usl[axis] = starts[r]
+            gsl = [slice(None)] * g.ndim
+            gsl[axis] = r
+            u[tuple(usl)] += gj[tuple(gsl)]
+        cp = np.zeros(n)
+        cp[:T] = C[j]
+        fu = np.fft.fft(u, axis=axis)
+        gx += np.real(np.fft.ifft(fu * np.fft.fft(cp).reshape(shape), axis=axis))
+        cr = np.real(np.fft.ifft(np.conj(fu) * np.fft.fft(x, axis=axis), axis=axis))
+        gc[j] = np.take(cr, np.arange(T) % n, axis=axis).sum(axis=tuple(a for a in range(x.ndim) if a != axis))
+    return gx, gc
+
+
+def test_polyphase_forward_equals_fft_correlation_per_phase():
+    pp = W.polyphase_downscaler(frames=2, rows=40, cols=56)
+    x = pp.x.astype(np.float64)
+    ch = pp.c_h.astype(np.float64)
+    cv = pp.c_v.astype(np.float64)
+    fh = oracle.run(pp.h, [pp.x])
+    want_h = _polyphase_fft(x, ch, -2, 8, pp.h.rep_shape[2], axis=2)
+    assert np.allclose(fh.out, want_h, rtol=0, atol=1e-13)
+    assert np.all(fh.hits == 1)
+    want_abs = _polyphase_fft(np.abs(x), np.abs(ch), -2, 8, pp.h.rep_shape[2], axis=2)
+    assert np.allclose(fh.abs_sum, want_abs, rtol=1e-12, atol=0)
+    mid = fh.out.astype(np.float32)
+    fv = oracle.run(pp.v, [mid])
+    want_v = _polyphase_fft(mid.astype(np.float64), cv, -2, 9, pp.v.rep_shape[1], axis=1)
+    assert np.allclose(fv.out, want_v, rtol=0, atol=1e-13)
+    # run_sample gives whole output patterns per repetition
+    y, ya = oracle.run_sample(pp.h, [pp.x], np.array([0, 5, 17]))
+    flat = want_h.reshape(2 * 40, -1)
+    for k, r in enumerate([0, 5, 17]):
+        row, c = divmod(r, pp.h.rep_shape[2])
+        assert np.allclose(y[k], flat[row, 3 * c:3 * c + 3], rtol=0, atol=1e-13)
+
+
+def test_polyphase_one_hot_taps_select_samples():
+    # C[j] = e_{s_j}: phase j of repetition r is x[(o + p r + s_j) mod n]
+    # exactly (np.take with wrapping), for random geometries
+    rng = W.rng_for(5151)
+    for trial in range(30):
+        n = int(rng.integers(5, 40))
+        T = int(rng.integers(1, 9))
+        p_ = int(rng.integers(1, 6))
+        q = int(rng.integers(2, 5))
+        o = int(rng.integers(-12, 12))
+        reps = int(rng.integers(1, 8))
+        sel = rng.integers(0, T, q)
+        C = np.zeros((q, T), np.float32)
+        C[np.arange(q), sel] = 1.0
+        t = W.Tiler((n,), [o], [[p_]], [[1]], (T,))
+        prob = W.Problem((reps,), [t], W.phase_output((reps,), 0, q), W.WSUM, C)
+        x = rng.standard_normal(n).astype(np.float32)
+        got = oracle.run(prob, [x]).out
+        want = np.take(x, (o + p_ * np.arange(reps)[:, None] + sel[None, :]).reshape(-1), mode="wrap")
+        assert np.array_equal(got, want.astype(np.float64)), trial
+
+
+def test_polyphase_adjoint_equals_fft_and_adjoint_identity():
+    pp = W.polyphase_downscaler(frames=2, rows=40, cols=56)
+    rng = W.rng_for(5252)
+    gh = rng.uniform(-1, 1, pp.h.output.array_shape)
+    a = oracle.adjoint(pp.h, pp.x, gh)
+    want_gx, want_gc = _polyphase_adjoint_fft(pp.x.astype(np.float64), gh, pp.c_h.astype(np.float64), -2, 8, axis=2)
+    assert np.allclose(a.gx, want_gx, rtol=0, atol=1e-12)
+    assert a.gc.shape == pp.c_h.shape
+    assert np.allclose(a.gc, want_gc, rtol=0, atol=1e-11)
+    # bounds: the same closed forms on absolute values
+    abs_gx, abs_gc = _polyphase_adjoint_fft(np.abs(pp.x.astype(np.float64)), np.abs(gh),
+                                            np.abs(pp.c_h.astype(np.float64)), -2, 8, axis=2)
+    assert np.allclose(a.gx_abs, abs_gx, rtol=1e-11, atol=1e-13)
+    assert np.allclose(a.gc_abs, abs_gc, rtol=1e-11, atol=0)
+    # vertical stage: <T x, g> = <x, T^t g>, and gc[j, i] = <T_{E_ji} x, g>
+    mid = oracle.run(pp.h, [pp.x]).out.astype(np.float32)
+    gv = rng.uniform(-1, 1, pp.v.output.array_shape)
+    av = oracle.adjoint(pp.v, mid, gv)
+    tx = oracle.run(pp.v, [mid]).out
+    lhs = float(np.sum(tx * gv))
+    assert abs(lhs - float(np.sum(mid.astype(np.float64) * av.gx))) <= 1e-12 * np.sum(np.abs(tx * gv))
+    q, T = pp.c_v.shape
+    for j in range(q):
+        for i in range(T):
+            E = np.zeros((q, T), np.float32)
+            E[j, i] = 1.0
+            pe = W.Problem(pp.v.rep_shape, pp.v.inputs, pp.v.output, W.WSUM, E)
+            want = float(np.sum(oracle.run(pe, [mid]).out * gv))
+            assert abs(av.gc[j, i] - want) <= 1e-12 * (1 + abs(want)), (j, i)
+
+
+def test_polyphase_sum_task_needs_scalar_output():
+    pp = W.polyphase_downscaler(frames=1, rows=18, cols=24)
+    ps = W.Problem(pp.h.rep_shape, pp.h.inputs, pp.h.output, W.SUM)
+    with pytest.raises(ValueError):
+        oracle.run(ps, [pp.x])
+    with pytest.raises(ValueError):
+        oracle.adjoint(ps, pp.x, np.zeros(pp.h.output.array_shape))
+
+
 def test_chain_bound_on_absolutes_equals_einsum():
     # the chain tolerance (both stages run on |x| with |c|) is the closed form
     # of the two einsums on absolute values
