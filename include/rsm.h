@@ -72,7 +72,9 @@ typedef enum { RSM_F32 = 0, RSM_BF16 = 1, RSM_F64 = 2, RSM_I64 = 3 } rsm_dtype;
 typedef enum {
   RSM_TASK_COPY = 0, /* y(r)[j] = pat(r)[j]; |in pattern| == |out pattern|, same dtype */
   RSM_TASK_SUM = 1,  /* y(r) = sum_i pat(r)[i]                                         */
-  RSM_TASK_WSUM = 2, /* y(r) = sum_i c[i] pat(r)[i]; c pattern-shaped                  */
+  RSM_TASK_WSUM = 2, /* y(r)[j] = sum_i c[j][i] pat(r)[i]; c is [|out pattern|][|in
+                        pattern|] (one row of taps per output element; with a scalar
+                        output pattern simply pattern-shaped)                           */
   RSM_TASK_DOT = 3   /* y(r) = sum_i pat_1(r)[i] pat_2(r)[i]; two input tilers         */
 } rsm_task_kind;
 
@@ -112,8 +114,8 @@ typedef struct {
   int32_t compute;     /* RSM_F32: FP32 arithmetic (F32 arrays, or BF16 arrays widened);
                           RSM_BF16: BF16 products with FP32 accumulation (DOT on BF16
                           arrays: the matrix-core path); RSM_F64: FP64 arrays             */
-  const void* coeffs;  /* WSUM: device pointer, pattern-shaped, FP32 (FP64 if compute
-                          is RSM_F64); ignored otherwise                                */
+  const void* coeffs;  /* WSUM: device pointer, [|out pattern|][|in pattern|] row-major,
+                          FP32 (FP64 if compute is RSM_F64); ignored otherwise          */
 } rsm_task;
 
 /* One stage of a chain: stage k reads array k and writes array k+1. */
@@ -193,7 +195,11 @@ rsm_status rsm_indices(const rsm_space* rep, const rsm_tiler* t, int64_t* d_idx,
  * Task/dtype combinations: COPY any dtype (bit-exact, output dtype = input
  * dtype); SUM/WSUM on F32 or BF16 arrays computed in FP32 (F64 in FP64) with
  * an F32 (F64) output; DOT on two F32 arrays (FP32), two BF16 arrays (compute
- * BF16: FP32 accumulation, F32 output) or two F64 arrays.
+ * BF16: FP32 accumulation, F32 output) or two F64 arrays.  SUM and DOT
+ * need a single-element output pattern (RSM_E_SHAPE otherwise); WSUM may
+ * write an output pattern of any size (the elementary task producing a
+ * pattern, as in a polyphase filter: each repetition writes q outputs, each
+ * from its own row of taps).
  */
 rsm_status rsm_run(const rsm_space* rep, const rsm_tiler* in, const void* const* d_in,
                    int32_t n_in, const rsm_tiler* out, void* d_out, const rsm_task* task,
@@ -216,10 +222,15 @@ rsm_status rsm_run_chain(const rsm_stage* stages, int32_t n_stages, const void* 
                          void* const* d_mid, void* d_out, uint32_t flags, void* hip_stream);
 
 /*
- * rsm_run_adjoint -- adjoint of a SUM or WSUM task with a scalar output
- * pattern (the task is linear in its input and in its weights):
- *   gx[e_in(r,i)] = sum over (r,i) hitting it of c[i] * gy[e_out(r)]
- *   gc[i]         = sum_r gy[e_out(r)] * x[e_in(r,i)]
+ * rsm_run_adjoint -- adjoint of a SUM task (scalar output pattern) or of a
+ * WSUM task with any output pattern (the task is linear in its input and in
+ * its weights):
+ *   gx[e_in(r,i)] = sum over (r,i,j) with e_in(r,i) hitting it of c[j][i] * gy[e_out(r,j)]
+ *   gc[j][i]      = sum_r gy[e_out(r,j)] * x[e_in(r,i)]
+ * (j = 0 only for a scalar output pattern; d_gc is shaped like the
+ * coefficients).  A WSUM whose output pattern of q elements lies along the
+ * tap axis of a 1-D window (a polyphase stage: q consecutive outputs per
+ * window) takes a gather for gx and per-repetition partial sums for gc.
  * d_x: the task's input array (needed for gc only; may be NULL if d_gc is
  * NULL).  d_gy: gradient w.r.t. the output array.  d_gx (input-array shaped)
  * and d_gc (pattern-shaped, WSUM only) are FP32 device buffers, each NULL to

@@ -30,7 +30,7 @@ COMMON = [
 ]
 
 SOURCES = ["api.cpp", "batch.cpp", "k_generic.hip", "k_window.hip", "k_gemm.hip", "k_filter2d.hip", "k_sparse.hip",
-           "k_cg.hip", "k_fir_gather.hip", "noalloc.hip"]
+           "k_cg.hip", "k_fir_gather.hip", "k_polyphase.hip", "noalloc.hip"]
 
 
 def _compile(src: str) -> str:

@@ -302,7 +302,10 @@ rsm_status check_task(const rsm_space* rep, const rsm_tiler* in, int32_t n_in, c
       return fail(RSM_E_SHAPE, "COPY: input and output patterns differ in size");
     if (out->dtype != dt) return fail(RSM_E_INVALID, "COPY: output dtype differs from input dtype");
   } else {
-    if (c->n_pat_out != 1) return fail(RSM_E_SHAPE, "reducing task needs a single-element output pattern");
+    // a weighted sum may write an output pattern (one row of taps per output
+    // element); SUM and DOT produce one value per repetition
+    if (c->n_pat_out != 1 && task->kind != RSM_TASK_WSUM)
+      return fail(RSM_E_SHAPE, "SUM and DOT need a single-element output pattern");
     if (dt == RSM_I64) return fail(RSM_E_UNSUPPORTED, "arithmetic on int64 arrays is not supported");
     if (task->kind == RSM_TASK_DOT) {
       if (in[1].dtype != dt) return fail(RSM_E_INVALID, "DOT: the two inputs differ in dtype");
@@ -348,6 +351,12 @@ GTiler to_gtiler(const rsm_tiler& t, int rep_rank) {
     for (int k = 0; k < t.pattern_rank; ++k) g.fit[d][k] = floor_mod(t.fitting[d][k], s);
   }
   return g;
+}
+
+bool is_scalar_pattern(const rsm_tiler& t) {
+  for (int k = 0; k < t.pattern_rank; ++k)
+    if (t.pattern_shape[k] != 1) return false;
+  return true;
 }
 
 bool is_identity_out(const rsm_space& rep, const rsm_tiler& t) {
@@ -451,12 +460,13 @@ bool fir_vec4(const Win3& w, const void* x) {
   return x == nullptr || (reinterpret_cast<uintptr_t>(x) & 15) == 0;
 }
 
-enum class Fam { Empty, Generic, PatternReduce, Fir, Filter2D, Gemm };
+enum class Fam { Empty, Generic, PatternReduce, Fir, Filter2D, Gemm, Poly };
 
 struct Plan {
   Fam fam = Fam::Generic;
   std::string name = "generic";
   Win3 win{};
+  int poly_q = 0;
   bool vec4 = false;
   GemmArgs gemm{};
   Filter2DProblem f2d{};
@@ -512,6 +522,30 @@ bool match_gemm(const rsm_space& rep, const rsm_tiler* in, const rsm_tiler& out,
   return true;
 }
 
+// A weighted sum whose output pattern has q > 1 elements laid along the tap
+// axis of a 1-D window tiler (a polyphase stage): the output array is the
+// repetition shape with the tap axis q times longer, origin 0, paving
+// diagonal (q on the tap axis, 1 elsewhere), pattern [q] with unit fitting
+// on that axis.
+bool match_poly(const rsm_space& rep, const rsm_tiler& in, const rsm_tiler& out, Win3* w, int* q) {
+  if (!canon_win3(rep, in, w) || w->ax < 1 || !outer_axes_inside(*w, w->ax)) return false;
+  const int da = rep.rank;
+  if (out.array_rank != da || out.pattern_rank != 1) return false;
+  const int64_t qv = out.pattern_shape[0];
+  if (qv < 2 || qv > 64) return false;
+  const int d_ax = w->ax - (3 - da);
+  for (int d = 0; d < da; ++d) {
+    if (out.origin[d] != 0) return false;
+    if (out.array_shape[d] != rep.shape[d] * (d == d_ax ? qv : 1)) return false;
+    if (out.fitting[d][0] != (d == d_ax ? 1 : 0)) return false;
+    for (int k = 0; k < da; ++k)
+      if (out.paving[d][k] != (d == k ? (d == d_ax ? qv : 1) : 0)) return false;
+  }
+  if (int64_t(w->rep[0]) * w->rep[1] * w->rep[2] * qv >= (int64_t(1) << 31)) return false;
+  *q = int(qv);
+  return poly_supported(*w, *q);
+}
+
 Plan make_plan(const rsm_space& rep, const rsm_tiler* in, int n_in, const rsm_tiler& out,
                const rsm_task& task, uint32_t flags, const void* const* d_in, int64_t n_rep,
                int64_t n_pat) {
@@ -550,6 +584,14 @@ Plan make_plan(const rsm_space& rep, const rsm_tiler* in, int n_in, const rsm_ti
   // SUM / WSUM on FP32
   if (!f32) return p;
   Win3 w{};
+  int q = 0;
+  if (task.kind == RSM_TASK_WSUM && match_poly(rep, in[0], out, &w, &q)) {
+    p.fam = Fam::Poly;
+    p.win = w;
+    p.poly_q = q;
+    p.name = w.ax == 2 ? "polyphase_cols" : "polyphase_rows";
+    return p;
+  }
   const bool id_out = is_identity_out(rep, out);
   if (task.kind == RSM_TASK_WSUM && id_out && canon_win3(rep, in[0], &w) && w.ax >= 1 &&
       outer_axes_inside(w, w.ax)) {
@@ -566,12 +608,30 @@ Plan make_plan(const rsm_space& rep, const rsm_tiler* in, int n_in, const rsm_ti
     p.name = "filter2d_k" + std::to_string(fp.k) + "_s" + std::to_string(fp.s);
     return p;
   }
-  if (n_pat <= 64) {
+  if (n_pat <= 64 && is_scalar_pattern(out)) {
     p.fam = Fam::PatternReduce;
     p.name = "pattern_reduce";
     return p;
   }
   return p;
+}
+
+// Launch arguments of the polyphase kernels (pointers left to the caller).
+// forward = true: the forward kernels' item layout (row chunks along columns);
+// false: one item per repetition (weight-gradient kernel).
+PolyArgs poly_args(const Win3& w, int q, int64_t n_rep, bool forward) {
+  PolyArgs a{};
+  a.w = w;
+  a.q = q;
+  a.div_rc = make_fastdiv(uint32_t(w.rep[2]));
+  a.div_rr = make_fastdiv(uint32_t(w.rep[1]));
+  a.n_chunks = poly_chunks(w);
+  a.div_chunks = make_fastdiv(uint32_t(a.n_chunks));
+  if (forward && w.ax == 2)
+    a.n_items = uint32_t(int64_t(w.rep[0]) * w.rep[1] * a.n_chunks);
+  else
+    a.n_items = uint32_t(n_rep);
+  return a;
 }
 
 // ---------------------------------------------------------------------------
@@ -603,6 +663,15 @@ rsm_status exec_run(const rsm_space& rep, const rsm_tiler* in, const void* const
       a.c = static_cast<const float*>(task.coeffs);
       e = launch_fir(a, p.vec4, st);
       if (e != hipSuccess) return hip_fail(e, "fir launch");
+      return RSM_OK;
+    }
+    case Fam::Poly: {
+      PolyArgs a = poly_args(p.win, p.poly_q, c.n_rep, true);
+      a.x = static_cast<const float*>(d_in[0]);
+      a.y = static_cast<float*>(d_out);
+      a.c = static_cast<const float*>(task.coeffs);
+      e = launch_poly(a, st);
+      if (e != hipSuccess) return hip_fail(e, "polyphase launch");
       return RSM_OK;
     }
     case Fam::Filter2D: {
@@ -641,6 +710,7 @@ rsm_status exec_run(const rsm_space& rep, const rsm_tiler* in, const void* const
       for (int k = 0; k < kMaxRank; ++k) a.rep_shape[k] = k < rep.rank ? rep.shape[k] : 1;
       a.n_rep = c.n_rep;
       a.n_pat = c.n_pat_in[0];
+      a.n_q = c.n_pat_out;
       for (int t = 0; t < n_in; ++t) {
         a.in[t] = to_gtiler(in[t], rep.rank);
         a.x[t] = d_in[t];
@@ -678,6 +748,8 @@ rsm_status check_adjoint(const rsm_space* rep, const rsm_tiler* in, const rsm_ti
 }
 
 struct AdjPlan {
+  bool poly = false;     // weighted sum with q outputs per repetition along the tap axis
+  int q = 1;
   bool fir = false;
   bool vec4 = false;
   bool exact = false;
@@ -712,6 +784,13 @@ AdjPlan plan_adjoint(const rsm_space& rep, const rsm_tiler& in, const rsm_tiler&
   AdjPlan a;
   if (flags & RSM_FORCE_GENERIC) return a;
   Win3 w{};
+  int q = 0;
+  if (task.kind == RSM_TASK_WSUM && match_poly(rep, in, out, &w, &q) && fir_gather_ok(w)) {
+    a.poly = true;
+    a.q = q;
+    a.w = w;
+    return a;
+  }
   if (task.kind == RSM_TASK_WSUM && is_identity_out(rep, out) && canon_win3(rep, in, &w) &&
       w.ax >= 1 && w.taps <= 16 && outer_axes_inside(w, w.ax)) {
     if (fir_injective(w)) {
@@ -733,8 +812,10 @@ AdjPlan plan_adjoint(const rsm_space& rep, const rsm_tiler& in, const rsm_tiler&
 }
 
 // Workspace bytes the adjoint of one stage needs.
-size_t adjoint_ws_bytes(const AdjPlan& ap, int64_t n_rep, int64_t n_pat, bool want_gc) {
+size_t adjoint_ws_bytes(const AdjPlan& ap, int64_t n_rep, int64_t n_pat, int64_t n_q, bool want_gc) {
   if (!want_gc) return 0;
+  if (ap.poly && poly_gc_supported(ap.w, ap.q))
+    return size_t(poly_gc_grid(uint32_t(n_rep))) * size_t(ap.q) * size_t(ap.w.taps) * sizeof(float);
   if (ap.overlap_cols)
     return size_t(fir_overlap_cols_grid(uint32_t(overlap_items(ap.w)))) * size_t(ap.w.taps) * sizeof(float);
   if (ap.fir) {
@@ -743,7 +824,7 @@ size_t adjoint_ws_bytes(const AdjPlan& ap, int64_t n_rep, int64_t n_pat, bool wa
     return size_t(fir_adjoint_grid(tmp)) * size_t(ap.w.taps) * sizeof(float);
   }
   const int64_t nblk = std::min<int64_t>(std::max<int64_t>((n_rep + 4095) / 4096, 1), 1024);
-  return size_t(nblk) * size_t(n_pat) * sizeof(float);
+  return size_t(nblk) * size_t(n_pat) * size_t(n_q) * sizeof(float);
 }
 
 rsm_status exec_adjoint(const rsm_space& rep, const rsm_tiler& in, const void* d_x,
@@ -758,12 +839,44 @@ rsm_status exec_adjoint(const rsm_space& rep, const rsm_tiler& in, const void* d
     if (!accumulate) {
       if (d_gx && (e = launch_zero(d_gx, prod(in.array_shape, in.array_rank) * 4, st)) != hipSuccess)
         return hip_fail(e, "zero gx");
-      if (d_gc && (e = launch_zero(d_gc, c.n_pat_in[0] * 4, st)) != hipSuccess)
+      if (d_gc && (e = launch_zero(d_gc, c.n_pat_in[0] * c.n_pat_out * 4, st)) != hipSuccess)
         return hip_fail(e, "zero gc");
     }
     return RSM_OK;
   }
   const int64_t n_arr = prod(in.array_shape, in.array_rank);
+  if (ap.poly) {
+    const Win3& w = ap.w;
+    if (d_gx) {
+      PolyGatherArgs g{};
+      g.w = w;
+      g.q = ap.q;
+      g.div_a2 = make_fastdiv(uint32_t(w.A[2]));
+      g.div_a1 = make_fastdiv(uint32_t(w.A[1]));
+      for (int d = 0; d < 3; ++d) g.div_p[d] = make_fastdiv(uint32_t(std::max(w.p[d], 1)));
+      g.o_mod = int32_t(floor_mod(w.o[w.ax], w.A[w.ax]));
+      g.n_arr = uint32_t(n_arr);
+      g.gy = static_cast<const float*>(d_gy);
+      g.gx = static_cast<float*>(d_gx);
+      g.c = static_cast<const float*>(task.coeffs);
+      g.accumulate = accumulate;
+      if ((e = launch_poly_gx_gather(g, st)) != hipSuccess) return hip_fail(e, "polyphase gather adjoint");
+    }
+    if (d_gc && poly_gc_supported(w, ap.q)) {
+      PolyArgs a = poly_args(w, ap.q, c.n_rep, false);
+      a.x = static_cast<const float*>(d_x);
+      a.gy = static_cast<const float*>(d_gy);
+      a.partial = static_cast<float*>(ws);
+      const int nc = ap.q * w.taps;
+      if ((e = launch_poly_gc(a, st)) != hipSuccess) return hip_fail(e, "polyphase weight gradient");
+      if ((e = launch_reduce_partials(a.partial, poly_gc_grid(a.n_items), nc, nc, static_cast<float*>(d_gc),
+                                      accumulate, st)) != hipSuccess)
+        return hip_fail(e, "weight-gradient reduction");
+      return RSM_OK;
+    }
+    if (!d_gc) return RSM_OK;
+    d_gx = nullptr;   // the generic weight-gradient path below, input gradient done
+  }
   if (ap.overlap_cols) {
     const Win3& w = ap.w;
     FirOverlapArgs o{};
@@ -842,6 +955,7 @@ rsm_status exec_adjoint(const rsm_space& rep, const rsm_tiler& in, const void* d
     for (int k = 0; k < kMaxRank; ++k) a.rep_shape[k] = k < rep.rank ? rep.shape[k] : 1;
     a.n_rep = c.n_rep;
     a.n_pat = c.n_pat_in[0];
+    a.n_q = c.n_pat_out;
     a.in = to_gtiler(in, rep.rank);
     a.out = to_gtiler(out, rep.rank);
     a.gy = static_cast<const float*>(d_gy);
@@ -856,6 +970,7 @@ rsm_status exec_adjoint(const rsm_space& rep, const rsm_tiler& in, const void* d
     for (int k = 0; k < kMaxRank; ++k) a.rep_shape[k] = k < rep.rank ? rep.shape[k] : 1;
     a.n_rep = c.n_rep;
     a.n_pat = c.n_pat_in[0];
+    a.n_q = c.n_pat_out;
     a.in = to_gtiler(in, rep.rank);
     a.out = to_gtiler(out, rep.rank);
     a.x = static_cast<const float*>(d_x);
@@ -865,7 +980,7 @@ rsm_status exec_adjoint(const rsm_space& rep, const rsm_tiler& in, const void* d
     a.chunk = (c.n_rep + nblk - 1) / nblk;
     if ((e = launch_generic_coef_grad(a, mr, int(nblk), st)) != hipSuccess)
       return hip_fail(e, "generic weight gradient");
-    if ((e = launch_reduce_rows(a.partial, a.n_pat, nblk, static_cast<float*>(d_gc), accumulate, st)) !=
+    if ((e = launch_reduce_rows(a.partial, a.n_q * a.n_pat, nblk, static_cast<float*>(d_gc), accumulate, st)) !=
         hipSuccess)
       return hip_fail(e, "weight-gradient reduction");
   }
@@ -1026,7 +1141,9 @@ rsm_status rsm_plan(const rsm_space* rep, const rsm_tiler* in, int32_t n_in, con
     if (s) return s;
     if (!name || len <= 0) return fail(RSM_E_INVALID, "name buffer is NULL");
     const AdjPlan ap = plan_adjoint(*rep, *in, *out, *task, flags, nullptr, nullptr);
-    const char* fam = ap.overlap_cols ? "fir_adjoint_overlap_cols"
+    const char* fam = ap.poly           ? (poly_gc_supported(ap.w, ap.q) ? "polyphase_adjoint_gather"
+                                                                         : "polyphase_adjoint_gather_generic_gc")
+                      : ap.overlap_cols ? "fir_adjoint_overlap_cols"
                       : ap.gather ? "fir_adjoint_gather"
                       : ap.fir  ? (ap.vec4 ? "fir_adjoint_vec4" : "fir_adjoint")
                                 : "generic_adjoint";
@@ -1082,6 +1199,17 @@ rsm_status rsm_plan_ports(const rsm_space* rep, const rsm_tiler* in, int32_t n_i
       // uniform across the workgroup
       set(0, RSM_MEM_PRIVATE, int64_t(kThreadsPerWg) * p.win.taps * in_es);
       if (coeffs) set(n_in + 1, RSM_MEM_CONSTANT, int64_t(p.win.taps) * 4);
+      break;
+    case Fam::Poly:
+      if (p.win.ax == 2) {
+        // a chunk's input segment, its outputs and the q x T weights in LDS
+        set(0, RSM_MEM_LOCAL, (int64_t(p.win.p[2]) * 255 + p.win.taps) * in_es);
+        set(n_in, RSM_MEM_LOCAL, int64_t(p.poly_q) * 256 * 4);
+      } else {
+        // each thread holds its window in registers, lanes along columns
+        set(0, RSM_MEM_PRIVATE, int64_t(kThreadsPerWg) * p.win.taps * in_es);
+      }
+      if (coeffs) set(n_in + 1, RSM_MEM_LOCAL, int64_t(p.poly_q) * p.win.taps * 4);
       break;
     case Fam::Filter2D: {
       // the tile's input region (halo included) and the k x k weights in LDS
@@ -1259,7 +1387,7 @@ rsm_status rsm_run_adjoint(const rsm_space* rep, const rsm_tiler* in, const void
   if (c.n_rep > 0 && (!d_gy || (d_gc && !d_x))) return fail(RSM_E_INVALID, "NULL device pointer");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const AdjPlan ap = plan_adjoint(*rep, *in, *out, *task, flags, d_x, d_gx);
-  const size_t wsb = adjoint_ws_bytes(ap, c.n_rep, c.n_pat_in[0], d_gc != nullptr);
+  const size_t wsb = adjoint_ws_bytes(ap, c.n_rep, c.n_pat_in[0], c.n_pat_out, d_gc != nullptr);
   void* ws = nullptr;
   uint32_t* counter = nullptr;
   if (wsb) {
@@ -1349,7 +1477,8 @@ rsm_status rsm_run_chain_adjoint(const rsm_stage* stages, int32_t n_stages, cons
     const void* xk = k == 0 ? d_in : (have_mid ? d_mid[k - 1] : nullptr);
     aps[size_t(k)] = plan_adjoint(sg.rep, sg.in, sg.out, sg.task, flags, xk, nullptr);
     max_part = std::max(max_part, adjoint_ws_bytes(aps[size_t(k)], cs[size_t(k)].n_rep,
-                                                   cs[size_t(k)].n_pat_in[0], d_gc && d_gc[k]));
+                                                   cs[size_t(k)].n_pat_in[0], cs[size_t(k)].n_pat_out,
+                                                   d_gc && d_gc[k]));
     if (k > 0) max_mid = std::max(max_mid, size_t(prod(sg.in.array_shape, sg.in.array_rank)) * 4);
   }
   max_mid = (max_mid + 255) & ~size_t(255);

@@ -185,6 +185,33 @@ RSM_UNROLL_R
   }
 }
 
+// Weighted sum with an output pattern of n_q elements: output element j of
+// repetition r is sum_p c[j n_pat + p] x[e_in(r, p)], written to e_out(r, j).
+template <int R, typename Tin, typename Acc, typename Tout>
+__global__ void __launch_bounds__(kBlock) generic_wsum_multi_kernel(GenericArgs a) {
+  const int64_t stride = int64_t(gridDim.x) * kBlock;
+  const Acc* __restrict__ c = static_cast<const Acc*>(a.coeffs);
+  for (int64_t rf = int64_t(blockIdx.x) * kBlock + threadIdx.x; rf < a.n_rep; rf += stride) {
+    int64_t r[R], c0[R], p0[R], co[R], po[R];
+    unflatten<R>(rf, a.rep_rank, a.rep_shape, r);
+    start_coords<R>(a.out, a.rep_rank, r, co);
+RSM_UNROLL_R
+    for (int k = 0; k < R; ++k) po[k] = 0;
+    for (int64_t j = 0; j < a.n_q; ++j) {
+      start_coords<R>(a.in[0], a.rep_rank, r, c0);
+RSM_UNROLL_R
+      for (int k = 0; k < R; ++k) p0[k] = 0;
+      Acc acc[4] = {Acc(0), Acc(0), Acc(0), Acc(0)};
+      for (int64_t p = 0; p < a.n_pat; ++p) {
+        acc[p & 3] += load_as<Tin, Acc>(a.x[0], linear<R>(a.in[0], c0)) * c[j * a.n_pat + p];
+        if (p + 1 < a.n_pat) step_pattern<R>(a.in[0], p0, c0);
+      }
+      static_cast<Tout*>(a.y)[linear<R>(a.out, co)] = Tout((acc[0] + acc[1]) + (acc[2] + acc[3]));
+      if (j + 1 < a.n_q) step_pattern<R>(a.out, po, co);
+    }
+  }
+}
+
 template <int R, typename E>
 __global__ void __launch_bounds__(kBlock) generic_copy_kernel(GenericArgs a) {
   const int64_t stride = int64_t(gridDim.x) * kBlock;
@@ -221,7 +248,9 @@ hipError_t dispatch_generic(const GenericArgs& a, int in_dtype, int kind, int el
   }
 #define RSM_GEN(TIN, ACC, TOUT)                                                              \
   do {                                                                                       \
-    if (kind == kSum)                                                                        \
+    if (kind == kWsum && a.n_q > 1)                                                          \
+      generic_wsum_multi_kernel<R, TIN, ACC, TOUT><<<grid, kBlock, 0, st>>>(a);               \
+    else if (kind == kSum)                                                                   \
       generic_reduce_kernel<R, TIN, ACC, TOUT, kSum, 1><<<grid, kBlock, 0, st>>>(a);          \
     else if (kind == kWsum)                                                                  \
       generic_reduce_kernel<R, TIN, ACC, TOUT, kWsum, 1><<<grid, kBlock, 0, st>>>(a);         \
@@ -249,31 +278,40 @@ template <int R>
 __global__ void __launch_bounds__(kBlock) generic_adjoint_kernel(GenericAdjArgs a) {
   const int64_t stride = int64_t(gridDim.x) * kBlock;
   for (int64_t rf = int64_t(blockIdx.x) * kBlock + threadIdx.x; rf < a.n_rep; rf += stride) {
-    int64_t r[R], ci[R], co[R], pi[R];
+    int64_t r[R], ci[R], co[R], pi[R], po[R];
     unflatten<R>(rf, a.rep_rank, a.rep_shape, r);
     start_coords<R>(a.out, a.rep_rank, r, co);
-    const float g = a.gy[linear<R>(a.out, co)];
-    start_coords<R>(a.in, a.rep_rank, r, ci);
 RSM_UNROLL_R
-    for (int k = 0; k < R; ++k) pi[k] = 0;
-    for (int64_t p = 0; p < a.n_pat; ++p) {
-      const float c = a.c ? a.c[p] : 1.0f;
-      atomicAdd(a.gx + linear<R>(a.in, ci), c * g);
-      if (p + 1 < a.n_pat) step_pattern<R>(a.in, pi, ci);
+    for (int k = 0; k < R; ++k) po[k] = 0;
+    // output element j of the repetition sends c[j n_pat + p] gy to input element p
+    for (int64_t j = 0; j < a.n_q; ++j) {
+      const float g = a.gy[linear<R>(a.out, co)];
+      start_coords<R>(a.in, a.rep_rank, r, ci);
+RSM_UNROLL_R
+      for (int k = 0; k < R; ++k) pi[k] = 0;
+      for (int64_t p = 0; p < a.n_pat; ++p) {
+        const float c = a.c ? a.c[j * a.n_pat + p] : 1.0f;
+        atomicAdd(a.gx + linear<R>(a.in, ci), c * g);
+        if (p + 1 < a.n_pat) step_pattern<R>(a.in, pi, ci);
+      }
+      if (j + 1 < a.n_q) step_pattern<R>(a.out, po, co);
     }
   }
 }
 
-// partial[p][block] = sum over this block's repetitions of gy[r] * x[e(r, p)]
+// partial[k][block] = sum over this block's repetitions of
+// gy[e_out(r, j)] * x[e_in(r, p)], for weight k = j n_pat + p
 template <int R>
 __global__ void __launch_bounds__(kBlock) generic_coef_grad_kernel(GenericCoefGradArgs a) {
   __shared__ float red[kBlock];
   const int64_t r_begin = int64_t(blockIdx.x) * a.chunk;
   int64_t r_end = r_begin + a.chunk;
   if (r_end > a.n_rep) r_end = a.n_rep;
-  for (int64_t p = blockIdx.y; p < a.n_pat; p += gridDim.y) {
-    int64_t pidx[R];
+  for (int64_t kc = blockIdx.y; kc < a.n_q * a.n_pat; kc += gridDim.y) {
+    const int64_t jq = kc / a.n_pat, p = kc - jq * a.n_pat;
+    int64_t pidx[R], qidx[R];
     unflatten<R>(p, a.in.pat_rank, a.in.pat_shape, pidx);
+    unflatten<R>(jq, a.out.pat_rank, a.out.pat_shape, qidx);
     float acc = 0.0f;
     for (int64_t rf = r_begin + threadIdx.x; rf < r_end; rf += kBlock) {
       int64_t r[R], ci[R], co[R];
@@ -290,6 +328,16 @@ RSM_UNROLL_R
         }
       }
       start_coords<R>(a.out, a.rep_rank, r, co);
+RSM_UNROLL_R
+      for (int d = 0; d < R; ++d) {
+        if (d < a.out.arr_rank) {
+          int64_t v = co[d];
+RSM_UNROLL_R
+          for (int k = 0; k < R; ++k)
+            if (k < a.out.pat_rank) v = (v + (a.out.fit[d][k] * qidx[k]) % a.out.shape[d]) % a.out.shape[d];
+          co[d] = v;
+        }
+      }
       acc += a.gy[linear<R>(a.out, co)] * a.x[linear<R>(a.in, ci)];
     }
     red[threadIdx.x] = acc;
@@ -298,7 +346,7 @@ RSM_UNROLL_R
       if (int(threadIdx.x) < s) red[threadIdx.x] += red[threadIdx.x + s];
       __syncthreads();
     }
-    if (threadIdx.x == 0) a.partial[p * int64_t(gridDim.x) + blockIdx.x] = red[0];
+    if (threadIdx.x == 0) a.partial[kc * int64_t(gridDim.x) + blockIdx.x] = red[0];
     __syncthreads();
   }
 }
@@ -401,7 +449,8 @@ hipError_t launch_generic_adjoint(const GenericAdjArgs& a, int max_rank, hipStre
 
 hipError_t launch_generic_coef_grad(const GenericCoefGradArgs& a, int max_rank, int n_blocks,
                                     hipStream_t st) {
-  dim3 grid(n_blocks, unsigned(a.n_pat < 65535 ? a.n_pat : 65535));
+  const int64_t n_coef = a.n_q * a.n_pat;
+  dim3 grid(n_blocks, unsigned(n_coef < 65535 ? n_coef : 65535));
   if (max_rank <= 4)
     generic_coef_grad_kernel<4><<<grid, kBlock, 0, st>>>(a);
   else

@@ -39,6 +39,7 @@ struct GenericArgs {
   int64_t rep_shape[kMaxRank];
   int64_t n_rep;   // |s_r|
   int64_t n_pat;   // |s_p| (flat pattern length walked by every tiler)
+  int64_t n_q;     // output pattern elements (WSUM: coeffs are [n_q][n_pat])
   GTiler in[2];
   GTiler out;
   const void* x[2];
@@ -184,6 +185,39 @@ struct FirChainAdjArgs {
   float* y;
 };
 
+// Weighted sum whose output pattern has q > 1 elements along the tap axis
+// (polyphase stage): y[.., q r + j, ..] = sum_i c[j T + i] x[.., (o + p r + i) mod A, ..]
+// along axis w.ax (1 or 2) of the [B, R, C] view; the output array is the
+// repetition shape with the tap axis multiplied by q.  Outer axes do not wrap.
+struct PolyArgs {
+  Win3 w;
+  int32_t q;           // outputs per repetition
+  int32_t n_chunks;    // columns kernel: items of 256 repetitions per row
+  FastDiv div_chunks;  // divide by n_chunks
+  FastDiv div_rc;      // divide by rep[2]
+  FastDiv div_rr;      // divide by rep[1]
+  uint32_t n_items;    // columns kernel: rep[0] rep[1] n_chunks; otherwise rep[0] rep[1] rep[2]
+  const float* x;
+  float* y;            // forward output
+  const float* c;      // [q][T]
+  const float* gy;     // weight gradient: output gradient
+  float* partial;      // weight gradient: [grid][q T]
+};
+
+// Input gradient of a polyphase stage as a gather (one thread per element).
+struct PolyGatherArgs {
+  Win3 w;
+  int32_t q;
+  FastDiv div_a2, div_a1;
+  FastDiv div_p[3];    // divide by max(p[d], 1)
+  int32_t o_mod;       // o[ax] mod A[ax]
+  uint32_t n_arr;
+  const float* gy;
+  float* gx;           // every element written
+  const float* c;
+  int32_t accumulate;
+};
+
 // Small-pattern reduction: a group of G lanes (G = 2^k >= |pattern|, G <= 64)
 // per repetition, one lane per pattern element, butterfly reduction.
 struct PatternReduceArgs {
@@ -205,6 +239,7 @@ struct GenericAdjArgs {
   int64_t rep_shape[kMaxRank];
   int64_t n_rep;
   int64_t n_pat;
+  int64_t n_q;         // output pattern elements (c is [n_q][n_pat])
   GTiler in;
   GTiler out;
   const float* x;
@@ -217,7 +252,8 @@ struct GenericCoefGradArgs {
   int32_t rep_rank;
   int64_t rep_shape[kMaxRank];
   int64_t n_rep;
-  int64_t n_pat;
+  int64_t n_pat;       // input pattern elements
+  int64_t n_q;         // output pattern elements; partial rows are [n_q n_pat][gridDim.x]
   GTiler in;
   GTiler out;
   const float* x;
@@ -330,6 +366,13 @@ hipError_t launch_generic_coef_grad(const GenericCoefGradArgs& a, int max_rank, 
 hipError_t launch_reduce_rows(const float* partial, int64_t n_rows, int64_t n_cols,
                               float* out, int accumulate, hipStream_t st);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
+bool poly_supported(const Win3& w, int q);
+bool poly_gc_supported(const Win3& w, int q);
+int poly_chunks(const Win3& w);
+hipError_t launch_poly(const PolyArgs& a, hipStream_t st);
+hipError_t launch_poly_gx_gather(const PolyGatherArgs& a, hipStream_t st);
+int poly_gc_grid(uint32_t n_rep);
+hipError_t launch_poly_gc(const PolyArgs& a, hipStream_t st);
 int64_t gemm_lds_bytes_per_operand(const GemmArgs& g, int compute);   // LDS per workgroup, one operand
 int gemm_tile_side(const GemmArgs& g, int compute);                   // output tile side (128 or 256)
 hipError_t launch_gemm(const GemmArgs& a, int compute, hipStream_t st);

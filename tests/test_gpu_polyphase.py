@@ -1,0 +1,180 @@
+"""GPU parity of weighted sums whose output pattern has several elements
+(polyphase stages: one repetition reads a window and writes q outputs, each
+with its own taps) against the FP64 oracle.
+
+* forward and adjoint of single stages, taps along columns and along rows,
+  on the polyphase kernels and on the generic kernels (FORCE_GENERIC), with
+  windows that overlap and wrap at the borders and rows longer than one
+  256-repetition chunk;
+* the downscaler built from two such stages (1920x1080 -> 720x480 per frame)
+  at its full size of 30 frames: every output of both stages against the
+  oracle, the stage adjoints against the oracle's, and the chain through the
+  autograd wrappers.
+
+Tolerance: 1e-5 of each value's |term| sum (the oracle's), as for every FP32
+task.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import rsm_workloads as W
+from paper_1105_4424_amd import _abi, rsm
+
+from .helpers import check_close, dev, host, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _stage(A, taps, pave, q, origin, axis, seed):
+    """One polyphase stage on a [F, H, W] array with taps along `axis`."""
+    F, H, Wd = A
+    rng = W.rng_for(seed)
+    if axis == 2:
+        t = W.h_stage(F, H, Wd, taps, pave, origin)
+        rep = (F, H, -(-Wd // pave))
+    else:
+        t = W.v_stage(F, H, Wd, taps, pave, origin)
+        rep = (F, -(-H // pave), Wd)
+    c = W.phase_coeffs(rng, q, taps)
+    x = rng.standard_normal(A).astype(np.float32)
+    return W.Problem(rep, [t], W.phase_output(rep, axis, q), W.WSUM, c), x
+
+
+def _forward_check(p, x, flags=0, what=""):
+    ref = oracle.run(p, [x])
+    out = torch.full(p.output.array_shape, float("nan"), device="cuda")
+    rsm.run(p, [dev(x)], out, coeffs=dev(p.coeffs), flags=flags)
+    check_close(host(out), ref.out, ref.abs_sum, what=what + " forward")
+    return out
+
+
+def _adjoint_check(p, x, gy, flags=0, what=""):
+    a = oracle.adjoint(p, x, gy)
+    gx = torch.full(p.inputs[0].array_shape, float("nan"), device="cuda")
+    gc = torch.full(p.coeffs.shape, float("nan"), device="cuda")
+    rsm.run_adjoint(p, dev(x), dev(gy), gx, gc, dev(p.coeffs), flags=flags)
+    check_close(host(gx), a.gx, a.gx_abs, what=what + " gx")
+    check_close(host(gc), a.gc, a.gc_abs, what=what + " gc")
+    # accumulate adds onto the previous contents
+    gx2, gc2 = gx.clone(), gc.clone()
+    rsm.run_adjoint(p, dev(x), dev(gy), gx2, gc2, dev(p.coeffs), flags=flags | _abi.ACCUMULATE)
+    check_close(host(gx2), 2 * a.gx, 2 * a.gx_abs, what=what + " gx accumulate")
+    check_close(host(gc2), 2 * a.gc, 2 * a.gc_abs, what=what + " gc accumulate")
+
+
+CASES = [
+    # (array, taps, pave, q, origin, axis)
+    ((2, 24, 200), 13, 8, 3, -2, 2),     # overlapping windows wrapping at both ends
+    ((1, 5, 2100), 13, 8, 3, -6, 2),     # 263 repetitions per row: two chunks
+    ((2, 7, 61), 5, 3, 2, 4, 2),         # ragged: 21 windows of step 3 over 61 columns
+    ((1, 3, 40), 16, 4, 4, -7, 2),       # windows four steps long
+    ((1, 4, 33), 32, 16, 8, 0, 2),       # the largest pattern and step the kernels take
+    ((2, 72, 40), 14, 9, 4, -2, 1),      # taps along rows
+    ((1, 50, 17), 7, 2, 3, -3, 1),
+    ((1, 9, 8), 20, 3, 2, -11, 1),       # windows longer than the axis: several lifts
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[str(k) for k in range(len(CASES))])
+@pytest.mark.parametrize("generic", [False, True], ids=["polyphase", "generic"])
+def test_polyphase_stage_forward_and_adjoint(case, generic):
+    A, taps, pave, q, origin, axis = case
+    p, x = _stage(A, taps, pave, q, origin, axis, seed=600 + taps + pave)
+    flags = _abi.FORCE_GENERIC if generic else 0
+    fam = rsm.plan(p, flags=flags)
+    assert fam == ("generic" if generic else ("polyphase_cols" if axis == 2 else "polyphase_rows")), fam
+    say("polyphase", A, taps, pave, q, origin, axis, fam)
+    _forward_check(p, x, flags, what=str(case))
+    gy = W.rng_for(700 + taps).uniform(-1, 1, p.output.array_shape).astype(np.float32)
+    _adjoint_check(p, x, gy, flags, what=str(case))
+
+
+def test_polyphase_kernel_plan_names():
+    p, _ = _stage((1, 8, 64), 13, 8, 3, -2, 2, seed=1)
+    assert rsm.plan(p, flags=_abi.PLAN_ADJOINT) == "polyphase_adjoint_gather"
+    p5, _ = _stage((1, 8, 64), 20, 8, 3, -2, 2, seed=1)   # 20 taps: weight gradient on the generic kernel
+    assert rsm.plan(p5, flags=_abi.PLAN_ADJOINT) == "polyphase_adjoint_gather_generic_gc"
+    ports = rsm.plan_ports(p)
+    assert [sp for sp, _ in ports] == ["local", "local", "local"]
+
+
+def test_polyphase_sum_task_rejected():
+    p, x = _stage((1, 8, 64), 13, 8, 3, -2, 2, seed=2)
+    ps = W.Problem(p.rep_shape, p.inputs, p.output, W.SUM)
+    with pytest.raises(rsm.RsmError) as e:
+        rsm.run(ps, [dev(x)], torch.empty(p.output.array_shape, device="cuda"))
+    assert e.value.name == "RSM_E_SHAPE"
+
+
+def _abs_problem(p):
+    return W.Problem(p.rep_shape, p.inputs, p.output, p.task, np.abs(p.coeffs))
+
+
+def test_polyphase_downscaler_full_size():
+    say("polyphase downscaler 30 x 1080 x 1920")
+    pp = W.polyphase_downscaler()
+    x = dev(pp.x)
+    ch, cv = dev(pp.c_h), dev(pp.c_v)
+    mid = torch.full(pp.h.output.array_shape, float("nan"), device="cuda")
+    out = torch.full(pp.v.output.array_shape, float("nan"), device="cuda")
+    rsm.run(pp.h, [x], mid, coeffs=ch)
+    rsm.run(pp.v, [mid], out, coeffs=cv)
+    ref_h = oracle.run(pp.h, [pp.x])
+    check_close(host(mid), ref_h.out, ref_h.abs_sum, what="full H")
+    mid_h = host(mid)
+    ref_v = oracle.run(pp.v, [mid_h])
+    check_close(host(out), ref_v.out, ref_v.abs_sum, what="full V (on the GPU's H output)")
+    # the chain call (stage by stage through the library's workspace) gives the same bits
+    out2 = torch.full(pp.v.output.array_shape, float("nan"), device="cuda")
+    rsm.run_chain([pp.h, pp.v], x, out2, [ch, cv])
+    assert torch.equal(out2, out)
+    # adjoints of both stages at full size
+    rng = W.rng_for(808)
+    gv = rng.uniform(-1, 1, pp.v.output.array_shape).astype(np.float32)
+    say("polyphase adjoint V")
+    _adjoint_full(pp.v, mid_h, gv, "full V")
+    gh = rng.uniform(-1, 1, pp.h.output.array_shape).astype(np.float32)
+    say("polyphase adjoint H")
+    _adjoint_full(pp.h, pp.x, gh, "full H")
+
+
+def _adjoint_full(p, x, gy, what):
+    a = oracle.adjoint(p, x, gy)
+    gx = torch.full(p.inputs[0].array_shape, float("nan"), device="cuda")
+    gc = torch.full(p.coeffs.shape, float("nan"), device="cuda")
+    rsm.run_adjoint(p, dev(x), dev(gy), gx, gc, dev(p.coeffs))
+    check_close(host(gx), a.gx, a.gx_abs, what=what + " gx")
+    check_close(host(gc), a.gc, a.gc_abs, what=what + " gc")
+
+
+def test_polyphase_chain_autograd_matches_oracle():
+    # loss sum(w * out^2) of the two-stage polyphase downscaler on 2 frames,
+    # through rsm.TiledChain (the library runs the stages one by one and
+    # recomputes the intermediate for the backward pass)
+    pp = W.polyphase_downscaler(frames=2, rows=108, cols=192)
+    w = W.loss_weights(pp.v.output.array_shape, seed=9)
+    x = dev(pp.x).requires_grad_(True)
+    ch = dev(pp.c_h).requires_grad_(True)
+    cv = dev(pp.c_v).requires_grad_(True)
+    out = rsm.TiledChain.apply(x, ch, cv, [pp.h, pp.v], True)
+    loss = (dev(w) * out * out).sum()
+    loss.backward()
+    stages = [pp.h, pp.v]
+    ref = oracle.chain_adjoint(stages, pp.x, w)
+    absd = oracle.chain_adjoint([_abs_problem(s) for s in stages], np.abs(pp.x), np.abs(w))
+    abs_out = oracle.chain_forward([_abs_problem(s) for s in stages], np.abs(pp.x))[-1].out
+    check_close(host(out), ref.forward[-1].out, abs_out, what="chain out")
+    check_close(host(x.grad), ref.gx, absd.gx, what="chain gx")
+    check_close(host(ch.grad), ref.gc[0], absd.gc[0], what="chain gc_h")
+    check_close(host(cv.grad), ref.gc[1], absd.gc[1], what="chain gc_v")
+    # a single stage through rsm.TiledTask
+    xs = dev(pp.x).requires_grad_(True)
+    cs = dev(pp.c_h).requires_grad_(True)
+    y = rsm.TiledTask.apply(xs, cs, pp.h)
+    g = W.rng_for(10).uniform(-1, 1, pp.h.output.array_shape).astype(np.float32)
+    (y * dev(g)).sum().backward()
+    a = oracle.adjoint(pp.h, pp.x, g)
+    check_close(host(xs.grad), a.gx, a.gx_abs, what="task gx")
+    check_close(host(cs.grad), a.gc, a.gc_abs, what="task gc")
