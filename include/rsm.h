@@ -268,16 +268,22 @@ rsm_status rsm_run_chain_adjoint(const rsm_stage* stages, int32_t n_stages, cons
  * rsm_run_chain_train -- one training step of a two-stage chain under the
  * loss L = sum over output elements o of w[o] * y[o]^2 (y the chain's output):
  * the forward (Sec. 3 and 6.1 repetitive tasks chained, as rsm_run_chain),
- * dL/dy = 2 w y, and the adjoint of both stages (as rsm_run_chain_adjoint),
- * fused into one pass over the input: d_in is read once, dL/dy is formed in
- * registers and never stored.  d_w: loss weights, FP32, shaped like the
- * output; d_out: receives y; d_gx (nullable): dL/dx, input-shaped;
- * d_gc (HOST array of 2 DEVICE pointers, nullable, entries nullable): the
- * stages' weight gradients.  RSM_ACCUMULATE adds into d_gx and d_gc.
- * Supported: the pair the fused chain kernels handle with 8 taps per stage,
- * weighted sums, injective tilers and 16-byte aligned input rows (the
- * two-stage 8-tap filter); anything else returns RSM_E_UNSUPPORTED.  Weight
- * gradients are reduced in a fixed order (deterministic).
+ * dL/dy = 2 (w y), and the adjoint of both stages (as rsm_run_chain_adjoint).
+ * d_w: loss weights, FP32, shaped like the output array; d_out: receives y;
+ * d_gx (nullable): dL/dx, input-shaped; d_gc (HOST array of 2 DEVICE
+ * pointers, nullable, entries nullable): the stages' weight gradients.
+ * RSM_ACCUMULATE adds into d_gx and d_gc.  Stages: FP32 SUM or WSUM tasks
+ * (single-stage adjoints as rsm_run_adjoint).  A pair of weighted sums along
+ * columns then rows whose windows do not overlap (at most 16 taps each, any
+ * alignment and origin) runs fused in one pass over the input: d_in is read
+ * once and dL/dy is formed in registers, never stored (8 taps per stage on
+ * 16-byte aligned rows take a lane-pair kernel).  Every other chain
+ * (overlapping windows, multi-element output patterns, other tilers; or any
+ * chain with RSM_NO_FUSE / RSM_FORCE_GENERIC) runs stage by stage: the
+ * forward into a workspace intermediate and d_out, dL/dy into the
+ * workspace, then the adjoint of each stage in reverse.  Chains of other
+ * than two stages return RSM_E_UNSUPPORTED.  Weight gradients are reduced in
+ * a fixed order (deterministic).
  */
 rsm_status rsm_run_chain_train(const rsm_stage* stages, int32_t n_stages, const void* d_in, const void* d_w,
                                void* d_out, void* d_gx, void* const* d_gc, uint32_t flags, void* hip_stream);
@@ -285,13 +291,14 @@ rsm_status rsm_run_chain_train(const rsm_stage* stages, int32_t n_stages, const 
 /*
  * rsm_run_chain_train_noalloc -- rsm_run_chain_train for callers that cannot
  * allocate device memory: code being captured into a graph, tight serving
- * loops, harnesses that forbid hipMalloc.  Same arguments, supported chains,
- * results (the same kernels: the same bits) and errors as
- * rsm_run_chain_train, but the weight-gradient partial rows live in a fixed
- * 256 KiB array of device memory inside the library instead of the stream's
- * workspace, so the call never allocates (no hipMalloc, hipFree or
- * allocating library routine); a step whose partial rows would not fit
- * returns RSM_E_UNSUPPORTED.  Every device holds its own copy of the array
+ * loops, harnesses that forbid hipMalloc.  Same arguments, results (the
+ * same kernels: the same bits) and errors as rsm_run_chain_train for the
+ * chains it runs fused in one pass; chains that rsm_run_chain_train runs
+ * stage by stage need workspace and return RSM_E_UNSUPPORTED here.  The
+ * weight-gradient partial rows live in a fixed 256 KiB array of device
+ * memory inside the library instead of the stream's workspace, so the call
+ * never allocates (no hipMalloc, hipFree or allocating library routine); a
+ * step whose partial rows would not fit returns RSM_E_UNSUPPORTED.  Every device holds its own copy of the array
  * until the process ends, and every call on a device shares that copy (it
  * keeps the last call's contents; nothing in it needs to start at zero):
  * calls that may overlap on one device -- on different streams, or from

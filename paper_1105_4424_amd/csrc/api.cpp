@@ -1316,6 +1316,99 @@ rsm_status chain_forward_mids(const rsm_stage* stages, int n, const void* d_in, 
   return RSM_OK;
 }
 
+// Workspace of the stage-by-stage chain adjoint: two intermediate-gradient
+// buffers (alternating between stages) and the weight-gradient partial rows.
+struct StagedLayout {
+  size_t max_mid = 0, max_part = 0;
+  std::vector<AdjPlan> aps;
+  size_t bytes() const { return 2 * max_mid + max_part; }
+};
+
+StagedLayout staged_layout(const rsm_stage* stages, int n, const void* d_in, const void* const* d_mid,
+                           void* const* d_gc, uint32_t flags, const std::vector<Checked>& cs) {
+  StagedLayout l;
+  l.aps.resize(size_t(n));
+  for (int k = 0; k < n; ++k) {
+    const rsm_stage& sg = stages[k];
+    // a recomputed intermediate lives in the workspace, 256-byte aligned:
+    // planned as aligned (no pointer)
+    const void* xk = k == 0 ? d_in : (d_mid ? d_mid[k - 1] : nullptr);
+    l.aps[size_t(k)] = plan_adjoint(sg.rep, sg.in, sg.out, sg.task, flags, xk, nullptr);
+    l.max_part = std::max(l.max_part, adjoint_ws_bytes(l.aps[size_t(k)], cs[size_t(k)].n_rep,
+                                                       cs[size_t(k)].n_pat_in[0], cs[size_t(k)].n_pat_out,
+                                                       d_gc && d_gc[k]));
+    if (k > 0) l.max_mid = std::max(l.max_mid, size_t(prod(sg.in.array_shape, sg.in.array_rank)) * 4);
+  }
+  l.max_mid = (l.max_mid + 255) & ~size_t(255);
+  l.max_part = (l.max_part + 255) & ~size_t(255);
+  return l;
+}
+
+// The chain's adjoint stage by stage, in reverse, from the forward
+// intermediates fwd_mid; ws holds the layout's buffers.
+rsm_status staged_adjoint(const rsm_stage* stages, int n, const void* d_in, const std::vector<void*>& fwd_mid,
+                          const void* d_gy, void* d_gx, void* const* d_gc, uint32_t flags,
+                          const std::vector<Checked>& cs, const StagedLayout& lay, char* ws, uint32_t* counter,
+                          hipStream_t st) {
+  const int accumulate = (flags & RSM_ACCUMULATE) ? 1 : 0;
+  char* gbuf[2] = {ws, ws + lay.max_mid};
+  void* part = ws + 2 * lay.max_mid;
+  const void* g = d_gy;
+  rsm_status s = RSM_OK;
+  for (int k = n - 1; k >= 0; --k) {
+    const rsm_stage& sg = stages[k];
+    const void* xk = k == 0 ? d_in : fwd_mid[size_t(k - 1)];
+    void* gxk = k == 0 ? d_gx : gbuf[k & 1];
+    void* gck = d_gc ? d_gc[k] : nullptr;
+    // intermediate gradients are overwritten; the caller's buffers follow the flags
+    uint32_t fk = flags & (RSM_FORCE_GENERIC | RSM_REDUCE_IN_KERNEL);
+    if (accumulate) fk |= RSM_ACCUMULATE;
+    if (k > 0 && accumulate) {
+      // accumulate applies to the caller's gc, not to the intermediate gradient
+      if (gck) {
+        s = exec_adjoint(sg.rep, sg.in, xk, sg.out, g, sg.task, nullptr, gck, fk, cs[size_t(k)], part,
+                         counter, st);
+        if (s) return s;
+      }
+      s = exec_adjoint(sg.rep, sg.in, xk, sg.out, g, sg.task, gxk, nullptr, fk & ~RSM_ACCUMULATE,
+                       cs[size_t(k)], part, counter, st);
+    } else {
+      s = exec_adjoint(sg.rep, sg.in, xk, sg.out, g, sg.task, gxk, gck, fk, cs[size_t(k)], part,
+                       counter, st);
+    }
+    if (s) return s;
+    g = gxk;
+    if (!g && k > 0) return fail(RSM_E_INVALID, "internal: missing intermediate gradient");
+  }
+  return RSM_OK;
+}
+
+// Training step of any two-stage chain of SUM / WSUM stages, stage by
+// stage: the forward into the workspace intermediate and d_out, dL/dy =
+// 2 (w y) into the workspace, then the staged adjoint.  Workspace layout:
+// [adjoint buffers | forward intermediate | dL/dy].
+rsm_status train_staged(const rsm_stage* stages, const void* d_in, const void* d_w, void* d_out, void* d_gx,
+                        void* const* d_gc, uint32_t flags, const std::vector<Checked>& cs, hipStream_t st) {
+  std::vector<size_t> mid_offs;
+  const size_t mid_bytes = (chain_mid_bytes(stages, 2, &mid_offs) + 255) & ~size_t(255);
+  const int64_t n_out = prod(stages[1].out.array_shape, stages[1].out.array_rank);
+  const StagedLayout lay = staged_layout(stages, 2, d_in, nullptr, d_gc, flags, cs);
+  rsm_status s = RSM_OK;
+  uint32_t* counter = nullptr;
+  char* ws = static_cast<char*>(workspace(lay.bytes() + mid_bytes + size_t(n_out) * 4 + 256, st, &s, &counter));
+  if (s) return s;
+  std::vector<void*> fwd_mid(1, ws + lay.bytes() + mid_offs[0]);
+  float* g = reinterpret_cast<float*>(ws + lay.bytes() + mid_bytes);
+  if ((s = chain_forward_mids(stages, 2, d_in, fwd_mid.data(), cs, flags, st)) != RSM_OK) return s;
+  const void* src = fwd_mid[0];
+  if ((s = exec_run(stages[1].rep, &stages[1].in, &src, 1, stages[1].out, d_out, stages[1].task,
+                    flags & RSM_FORCE_GENERIC, cs[1], st)) != RSM_OK)
+    return s;
+  hipError_t e = launch_loss_grad(static_cast<const float*>(d_out), static_cast<const float*>(d_w), g, n_out, st);
+  if (e != hipSuccess) return hip_fail(e, "loss gradient");
+  return staged_adjoint(stages, 2, d_in, fwd_mid, g, d_gx, d_gc, flags, cs, lay, ws, counter, st);
+}
+
 }  // namespace
 }  // namespace rsm
 
@@ -1468,57 +1561,15 @@ rsm_status rsm_run_chain_adjoint(const rsm_stage* stages, int32_t n_stages, cons
   std::vector<void*> fwd_mid(size_t(n_stages > 1 ? n_stages - 1 : 0), nullptr);
   if (have_mid)
     for (int k = 0; k + 1 < n_stages; ++k) fwd_mid[size_t(k)] = const_cast<void*>(d_mid[k]);
-  size_t max_mid = 0, max_part = 0;
-  std::vector<AdjPlan> aps(static_cast<size_t>(n_stages));
-  for (int k = 0; k < n_stages; ++k) {
-    const rsm_stage& sg = stages[k];
-    // a recomputed intermediate lives in the workspace, 256-byte aligned:
-    // planned as aligned (no pointer)
-    const void* xk = k == 0 ? d_in : (have_mid ? d_mid[k - 1] : nullptr);
-    aps[size_t(k)] = plan_adjoint(sg.rep, sg.in, sg.out, sg.task, flags, xk, nullptr);
-    max_part = std::max(max_part, adjoint_ws_bytes(aps[size_t(k)], cs[size_t(k)].n_rep,
-                                                   cs[size_t(k)].n_pat_in[0], cs[size_t(k)].n_pat_out,
-                                                   d_gc && d_gc[k]));
-    if (k > 0) max_mid = std::max(max_mid, size_t(prod(sg.in.array_shape, sg.in.array_rank)) * 4);
-  }
-  max_mid = (max_mid + 255) & ~size_t(255);
-  max_part = (max_part + 255) & ~size_t(255);
+  const StagedLayout lay = staged_layout(stages, n_stages, d_in, have_mid ? d_mid : nullptr, d_gc, flags, cs);
   uint32_t* counter = nullptr;
-  char* ws = static_cast<char*>(workspace(2 * max_mid + max_part + fwd_bytes + 256, st, &s, &counter));
+  char* ws = static_cast<char*>(workspace(lay.bytes() + fwd_bytes + 256, st, &s, &counter));
   if (s) return s;
-  char* gbuf[2] = {ws, ws + max_mid};
-  void* part = ws + 2 * max_mid;
   if (!have_mid) {
-    for (int k = 0; k + 1 < n_stages; ++k) fwd_mid[size_t(k)] = ws + 2 * max_mid + max_part + mid_offs[size_t(k)];
+    for (int k = 0; k + 1 < n_stages; ++k) fwd_mid[size_t(k)] = ws + lay.bytes() + mid_offs[size_t(k)];
     if ((s = chain_forward_mids(stages, n_stages, d_in, fwd_mid.data(), cs, flags, st)) != RSM_OK) return s;
   }
-  const void* g = d_gy;
-  for (int k = n_stages - 1; k >= 0; --k) {
-    const rsm_stage& sg = stages[k];
-    const void* xk = k == 0 ? d_in : fwd_mid[size_t(k - 1)];
-    void* gxk = k == 0 ? d_gx : gbuf[k & 1];
-    void* gck = d_gc ? d_gc[k] : nullptr;
-    // intermediate gradients are overwritten; the caller's buffers follow the flags
-    uint32_t fk = flags & (RSM_FORCE_GENERIC | RSM_REDUCE_IN_KERNEL);
-    if (accumulate) fk |= RSM_ACCUMULATE;
-    if (k > 0 && accumulate) {
-      // accumulate applies to the caller's gc, not to the intermediate gradient
-      if (gck) {
-        s = exec_adjoint(sg.rep, sg.in, xk, sg.out, g, sg.task, nullptr, gck, fk, cs[size_t(k)], part,
-                         counter, st);
-        if (s) return s;
-      }
-      s = exec_adjoint(sg.rep, sg.in, xk, sg.out, g, sg.task, gxk, nullptr, fk & ~RSM_ACCUMULATE,
-                       cs[size_t(k)], part, counter, st);
-    } else {
-      s = exec_adjoint(sg.rep, sg.in, xk, sg.out, g, sg.task, gxk, gck, fk, cs[size_t(k)], part,
-                       counter, st);
-    }
-    if (s) return s;
-    g = gxk;
-    if (!g && k > 0) return fail(RSM_E_INVALID, "internal: missing intermediate gradient");
-  }
-  return RSM_OK;
+  return staged_adjoint(stages, n_stages, d_in, fwd_mid, d_gy, d_gx, d_gc, flags, cs, lay, ws, counter, st);
   RSM_GUARD_END
 }
 
@@ -1549,13 +1600,23 @@ rsm_status chain_train_step(const rsm_stage* stages, int32_t n_stages, const voi
   if (!d_in || !d_w || !d_out) return fail(RSM_E_INVALID, "NULL device pointer");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const int accumulate = (flags & RSM_ACCUMULATE) ? 1 : 0;
+  if (n_stages != 2) return fail(RSM_E_UNSUPPORTED, "the training step takes a chain of two stages");
   Win3 h{}, v{};
   bool vec4 = false;
-  if (n_stages != 2 || !chain_fusable(stages, n_stages, d_in, &h, &v, &vec4) || !fir_injective(h) ||
-      !fir_injective(v) || h.taps != 8 || v.taps != 8 || !vec4 || !fir_vec4(h, d_gx) ||
-      stages[0].task.kind != RSM_TASK_WSUM || stages[1].task.kind != RSM_TASK_WSUM)
-    return fail(RSM_E_UNSUPPORTED,
-                "fused training step needs a fusable pair of 8-tap weighted sums with 16-byte rows");
+  const bool fusable = !(flags & (RSM_NO_FUSE | RSM_FORCE_GENERIC)) &&
+                       chain_fusable(stages, n_stages, d_in, &h, &v, &vec4) && fir_injective(h) &&
+                       fir_injective(v) && h.taps <= 16 && v.taps <= 16;
+  const bool pair8 = fusable && h.taps == 8 && v.taps == 8 && vec4 && fir_vec4(h, d_gx);
+  if (!fusable) {
+    // any other pair of stages: forward stage by stage, dL/dy = 2 w y, then
+    // the stage-by-stage adjoint, through the library's workspace
+    if (fixed_partial)
+      return fail(RSM_E_UNSUPPORTED,
+                  "without allocation the training step takes only chains it runs in one pass (two "
+                  "weighted sums along columns then rows, windows that do not overlap, at most 16 taps "
+                  "each); this chain runs stage by stage through the library's workspace");
+    return train_staged(stages, d_in, d_w, d_out, d_gx, d_gc, flags, cs, st);
+  }
   if (cs[1].n_rep == 0) return RSM_OK;
   hipError_t e;
   if (d_gx && !accumulate && !(fir_exact_cover(h) && fir_exact_cover(v))) {
@@ -1577,7 +1638,9 @@ rsm_status chain_train_step(const rsm_stage* stages, int32_t n_stages, const voi
   a.y = static_cast<float*>(d_out);
   float* gch = d_gc ? static_cast<float*>(d_gc[0]) : nullptr;
   float* gcv = d_gc ? static_cast<float*>(d_gc[1]) : nullptr;
-  const int grid = fir_chain_adjoint_grid(a, true);
+  // 8-tap lane-pair kernel: partial rows of 8 + 8 (the horizontal taps split
+  // over the two lanes); other pairs: one thread per output, rows of t0 + t1
+  const int grid = pair8 ? fir_chain_adjoint_grid(a, true) : fir_chain_train_generic_grid(a);
   const int nc = h.taps + v.taps;
   if (gch || gcv) {
     const size_t need = size_t(grid) * nc * sizeof(float);
@@ -1593,7 +1656,9 @@ rsm_status chain_train_step(const rsm_stage* stages, int32_t n_stages, const voi
       if (s) return s;
     }
   }
-  if ((e = probed(probe, st, [&] { return launch_fir_chain_train(a, st); })) != hipSuccess)
+  if ((e = probed(probe, st, [&] {
+         return pair8 ? launch_fir_chain_train(a, st) : launch_fir_chain_train_generic(a, st);
+       })) != hipSuccess)
     return hip_fail(e, "fused training step");
   if ((gch || gcv) && (e = reduce_chain_partials(a.partial, grid, h.taps, gch, v.taps, gcv, nc, accumulate,
                                                  st)) != hipSuccess)

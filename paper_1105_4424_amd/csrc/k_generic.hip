@@ -407,6 +407,12 @@ __global__ void __launch_bounds__(kBlock) reduce_pair_kernel(const float* src, i
   }
 }
 
+__global__ void __launch_bounds__(kBlock) loss_grad_kernel(const float* __restrict__ y, const float* __restrict__ w,
+                                                          float* __restrict__ g, int64_t n) {
+  const int64_t stride = int64_t(gridDim.x) * kBlock;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) g[i] = 2.0f * (w[i] * y[i]);
+}
+
 __global__ void __launch_bounds__(kBlock) zero_kernel(uint32_t* p, int64_t n_words) {
   const int64_t stride = int64_t(gridDim.x) * kBlock;
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n_words; i += stride) p[i] = 0u;
@@ -483,6 +489,12 @@ hipError_t launch_reduce_partials(const float* partial, int n_blocks, int n_coef
   if (n_coef <= 0) return hipSuccess;
   reduce_strided_kernel<<<unsigned(n_coef), kBlock, 0, st>>>(partial, n_blocks, 1, row_stride, out,
                                                              accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_grad(const float* y, const float* w, float* g, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  loss_grad_kernel<<<grid_for(n, kBlock, 16384), kBlock, 0, st>>>(y, w, g, n);
   return hipGetLastError();
 }
 

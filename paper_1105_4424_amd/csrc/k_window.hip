@@ -1161,6 +1161,96 @@ __global__ void __launch_bounds__(kBlock) fir_chain_train_pair_kernel(FirChainAd
   }
 }
 
+// ---------------------------------------------------------------------------
+// training step of a fused injective pair with any tap counts (up to 16 per
+// stage) and any window alignment: one thread per output.  The forward sums
+// are formed as in fir_chain_kernel (taps in order, then the stage-2 sum),
+// dL/dy = 2 wl y, and the adjoint follows fir_chain_adjoint_kernel; x is read
+// twice per output, the second time from the cache the first read filled.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) fir_chain_train_kernel(FirChainAdjArgs a) {
+  const Win3& h = a.h;
+  const Win3& v = a.v;
+  const int t0 = h.taps, t1 = v.taps;
+  float ch[kMaxTaps], cv[kMaxTaps], gp[2 * kMaxTaps];
+#pragma unroll
+  for (int k = 0; k < kMaxTaps; ++k) {
+    ch[k] = k < t0 ? a.ch[k] : 0.0f;
+    cv[k] = k < t1 ? a.cv[k] : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < 2 * kMaxTaps; ++k) gp[k] = 0.0f;
+  const uint32_t stride = gridDim.x * kBlock;
+  for (uint32_t o = blockIdx.x * kBlock + threadIdx.x; o < a.n_out; o += stride) {
+    const OutPos q = decode(o, v, a.div_rc, a.div_rr);
+    const int mb = v.o[0] + v.p[0] * q.b;
+    const int mc = v.o[2] + v.p[2] * q.c;
+    const int xb = h.o[0] + h.p[0] * mb;
+    const int xstart = h.o[2] + h.p[2] * mc;
+    const bool inside = xstart >= 0 && xstart + t0 <= h.A[2];
+    const int col0 = inside ? xstart : wrap_mod(xstart, h.A[2]);
+    const int mr0 = wrap_mod(int64_t(v.o[1]) + int64_t(v.p[1]) * q.r, v.A[1]);
+    // forward
+    float mid[kMaxTaps];
+    float y = 0.0f;
+    int mr = mr0;
+#pragma unroll
+    for (int j = 0; j < kMaxTaps; ++j) {
+      mid[j] = 0.0f;
+      if (j >= t1) break;
+      const int row_base = (xb * h.A[1] + h.o[1] + h.p[1] * mr) * h.A[2];
+      float m = 0.0f;
+      int e = col0;
+#pragma unroll
+      for (int k = 0; k < kMaxTaps; ++k) {
+        if (k >= t0) break;
+        m = fmaf(ch[k], a.x[row_base + e], m);
+        if (++e == h.A[2]) e = 0;
+      }
+      mid[j] = m;
+      y = fmaf(cv[j], m, y);
+      if (++mr == v.A[1]) mr = 0;
+    }
+    a.y[o] = y;
+    const float g = 2.0f * (a.wl[o] * y);
+    // adjoint
+    mr = mr0;
+#pragma unroll
+    for (int j = 0; j < kMaxTaps; ++j) {
+      if (j >= t1) break;
+      const int row_base = (xb * h.A[1] + h.o[1] + h.p[1] * mr) * h.A[2];
+      const float gm = cv[j] * g;
+      gp[kMaxTaps + j] = fmaf(g, mid[j], gp[kMaxTaps + j]);
+      int e = col0;
+#pragma unroll
+      for (int k = 0; k < kMaxTaps; ++k) {
+        if (k >= t0) break;
+        gp[k] = fmaf(gm, a.x[row_base + e], gp[k]);
+        if (a.gx) {
+          float* d = a.gx + row_base + e;
+          const float gv = ch[k] * gm;
+          *d = a.accumulate ? *d + gv : gv;
+        }
+        if (++e == h.A[2]) e = 0;
+      }
+      if (++mr == v.A[1]) mr = 0;
+    }
+  }
+  if (a.partial) {
+    // [ch grads (t0) | cv grads (t1)] contiguously
+    float packed[2 * kMaxTaps];
+#pragma unroll
+    for (int k = 0; k < 2 * kMaxTaps; ++k) packed[k] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kMaxTaps; ++k)
+      if (k < t0) packed[k] = gp[k];
+#pragma unroll
+    for (int k = 0; k < kMaxTaps; ++k)
+      if (k < t1) packed[t0 + k] = gp[kMaxTaps + k];
+    block_reduce_store<2 * kMaxTaps>(packed, t0 + t1, a.partial + int64_t(blockIdx.x) * (t0 + t1), false);
+  }
+}
+
 int stream_grid(uint32_t work, int waves_per_cu = 8) {
   // enough resident blocks to cover the chip several times, grid-stride beyond
   const int cap = 256 * waves_per_cu;
@@ -1265,6 +1355,13 @@ hipError_t launch_fir_chain_adjoint(const FirChainAdjArgs& a, bool vec4, hipStre
 
 hipError_t launch_fir_chain_train(const FirChainAdjArgs& a, hipStream_t st) {
   fir_chain_train_pair_kernel<8><<<fir_chain_adjoint_grid(a, true), kBlock, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+int fir_chain_train_generic_grid(const FirChainAdjArgs& a) { return stream_grid(a.n_out, 8); }
+
+hipError_t launch_fir_chain_train_generic(const FirChainAdjArgs& a, hipStream_t st) {
+  fir_chain_train_kernel<<<fir_chain_train_generic_grid(a), kBlock, 0, st>>>(a);
   return hipGetLastError();
 }
 

@@ -384,6 +384,12 @@ int csr_group_size(int64_t n_rows, int64_t nnz);
 // forward + loss gradient + adjoint of a fused 8-tap pair (vec4 layout only);
 // same grid and partial rows as launch_fir_chain_adjoint
 hipError_t launch_fir_chain_train(const FirChainAdjArgs& a, hipStream_t st);
+// Training step of an injective pair with any tap counts (<= 16 per stage):
+// one thread per output; partial rows [grid][h.taps + v.taps].
+int fir_chain_train_generic_grid(const FirChainAdjArgs& a);
+hipError_t launch_fir_chain_train_generic(const FirChainAdjArgs& a, hipStream_t st);
+// dL/dy = 2 (w y) of the loss sum(w y^2), elementwise over n values
+hipError_t launch_loss_grad(const float* y, const float* w, float* g, int64_t n, hipStream_t st);
 
 // The training step behind rsm_run_chain_train.  With fixed_partial set, the
 // weight-gradient partial rows go to that device buffer of fixed_bytes

@@ -82,3 +82,31 @@ def test_noalloc_train_rejects_what_the_workspace_entry_point_rejects():
         with pytest.raises(rsm.RsmError) as e:
             _step(chain, dev(ts.x), dev(w), ts.h.rep_shape, noalloc=noalloc)
         assert e.value.name == "RSM_E_UNSUPPORTED"
+
+
+def test_noalloc_train_other_single_pass_pairs_and_staged_chains():
+    # 5 taps per stage: the one-thread-per-output fused kernel, whose partial
+    # rows are t0 + t1 wide; the same bits as the workspace entry point
+    ts = W.two_stage_filter(frames=2, rows=40, cols=120, taps=5, seed=34)
+    w = W.loss_weights(ts.v.rep_shape)
+    chain = rsm.Chain([ts.h, ts.v], [dev(ts.c_h), dev(ts.c_v)])
+    x, wd = dev(ts.x), dev(w)
+
+    def step(noalloc):
+        out = torch.full(ts.v.rep_shape, float("nan"), device="cuda")
+        gx = torch.full(tuple(x.shape), float("nan"), device="cuda")
+        gcs = [torch.full((5,), float("nan"), device="cuda") for _ in range(2)]
+        (chain.train_noalloc if noalloc else chain.train)(x, wd, out, gx, gcs)
+        torch.cuda.synchronize()
+        return out, gx, gcs
+
+    a, b = step(True), step(False)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    assert torch.equal(a[2][0], b[2][0]) and torch.equal(a[2][1], b[2][1])
+    # overlapping windows run stage by stage through the workspace: refused
+    to = W.two_stage_filter(frames=1, rows=72, cols=200, taps=13, seed=35, h_origin=-6, pave=8)
+    wo = W.loss_weights(to.v.rep_shape)
+    co = rsm.Chain([to.h, to.v], [dev(to.c_h), dev(to.c_v)])
+    with pytest.raises(rsm.RsmError) as e:
+        co.train_noalloc(dev(to.x), dev(wo), torch.empty(to.v.rep_shape, device="cuda"), None, None)
+    assert e.value.name == "RSM_E_UNSUPPORTED"
