@@ -417,6 +417,96 @@ def extras(args, ts, xs, stages, ch, cv, w2, chain):
         % (us_g, b / us_g / 1e3, us_a))
     del gyo
 
+    # the horizontal stage alone under every port placement the planner
+    # honours (the paper's MemoryMapping: one address space per port, in
+    # order input, output, weights): taps in registers with uniform weights
+    # (the default), the window staged in LDS, one pattern element per lane,
+    # everything read in place
+    hmid = torch.empty(ts.h.rep_shape, device=dev)
+    b_hs = (xs[0].numel() + hmid.numel()) * 4
+    ex["placements_horizontal_stage_30x1080x1920"] = {}
+    for spaces in (None, ["local", "any", "any"], ["any", "any", "private"], ["global", "any", "any"]):
+        name, ports = rsm.plan_placed(ts.h, spaces)
+
+        def run_h(spaces=spaces):
+            k = state["k"] = state["k"] + 1
+            rsm.run_placed(ts.h, [xs[k % len(xs)]], hmid, spaces, coeffs=ch)
+
+        us = time_fn(run_h, reps=10 if name in ("generic", "pattern_reduce") else 20)
+        ex["placements_horizontal_stage_30x1080x1920"][name] = {
+            "request": spaces, "ports": ports, "avg_us": us, "bytes": b_hs, "gbs": b_hs / us / 1e3,
+            "frac": b_hs / us / 1e3 / HBM_PEAK_GBS}
+        log("placement %s (%s): %.1f us %.0f GB/s" % (name, [sp for sp, _ in ports], us, b_hs / us / 1e3))
+    del hmid
+
+    # polyphase downscaler (weighted sums writing several outputs per
+    # repetition): 30 frames of 1920x1080 -> 720x480; horizontally 3 outputs
+    # per 13-tap window every 8 columns, vertically 4 outputs per 14-tap
+    # window every 9 rows.  Algorithmic bytes: each stage's input read once
+    # and output written once; each adjoint reads x and dL/dy once and
+    # writes dL/dx once.
+    log("polyphase downscaler 30 x 1080 x 1920 -> 30 x 480 x 720")
+    pp = W.polyphase_downscaler()
+    pch = torch.from_numpy(pp.c_h).to(dev)
+    pcv = torch.from_numpy(pp.c_v).to(dev)
+    pmid = torch.empty(pp.h.output.array_shape, device=dev)
+    pout = torch.empty(pp.v.output.array_shape, device=dev)
+    del pp.x
+
+    def poly_h():
+        k = state["k"] = state["k"] + 1
+        rsm.run(pp.h, [xs[k % len(xs)]], pmid, coeffs=pch)
+
+    us_h = time_fn(poly_h)
+    us_v = time_fn(lambda: rsm.run(pp.v, [pmid], pout, coeffs=pcv))
+    pgy = torch.rand(pp.h.output.array_shape, device=dev)
+    pgc = torch.empty(pp.c_h.shape, device=dev)
+
+    def poly_h_adj():
+        k = state["k"] = state["k"] + 1
+        rsm.run_adjoint(pp.h, xs[k % len(xs)], pgy, gx, pgc, pch)
+
+    us_ha = time_fn(poly_h_adj)
+    b_h = (xs[0].numel() + pmid.numel()) * 4
+    b_v = (pmid.numel() + pout.numel()) * 4
+    b_ha = (2 * xs[0].numel() + pmid.numel()) * 4
+    ex["polyphase_downscaler_30x1080x1920"] = {
+        "horizontal": {"kernel": rsm.plan(pp.h), "avg_us": us_h, "bytes": b_h, "gbs": b_h / us_h / 1e3,
+                       "frac": b_h / us_h / 1e3 / HBM_PEAK_GBS},
+        "vertical": {"kernel": rsm.plan(pp.v), "avg_us": us_v, "bytes": b_v, "gbs": b_v / us_v / 1e3,
+                     "frac": b_v / us_v / 1e3 / HBM_PEAK_GBS,
+                     "note": "its 93 MB input was just written by the horizontal stage and is partly "
+                             "cache-resident"},
+        "horizontal_adjoint": {"kernels": rsm.plan(pp.h, flags=_abi.PLAN_ADJOINT), "avg_us": us_ha,
+                               "bytes": b_ha, "gbs": b_ha / us_ha / 1e3,
+                               "frac": b_ha / us_ha / 1e3 / HBM_PEAK_GBS}}
+    log("polyphase: H %.1f us (%.0f GB/s), V %.1f us, H adjoint %.1f us (%.0f GB/s)"
+        % (us_h, b_h / us_h / 1e3, us_v, us_ha, b_ha / us_ha / 1e3))
+    del pmid, pout, pgy
+
+    # training step of the overlapping pair (13 taps every 8 columns, then
+    # every 8 rows, centred): it runs stage by stage through the workspace
+    to = W.two_stage_filter(frames=F, rows=H, cols=Wd, taps=13, pave=8, h_origin=-6, v_origin=-6)
+    del to.x
+    tw = torch.rand(to.v.rep_shape, device=dev)
+    tout = torch.empty(to.v.rep_shape, device=dev)
+    tch = torch.from_numpy(to.c_h).to(dev)
+    tcv = torch.from_numpy(to.c_v).to(dev)
+    tg = [torch.empty(13, device=dev), torch.empty(13, device=dev)]
+    tchain = rsm.Chain([to.h, to.v], [tch, tcv])
+
+    def train_overlap():
+        k = state["k"] = state["k"] + 1
+        tchain.train(xs[k % len(xs)], tw, tout, gx, tg)
+
+    us_t = time_fn(train_overlap, reps=10)
+    ex["training_step_overlapping_13tap_step8"] = {
+        "route": "stage by stage (windows overlap: not fusable in one pass)", "avg_us": us_t,
+        "fused_minimum_bytes": 2 * xs[0].numel() * 4 + 2 * tout.numel() * 4,
+        "gbs_on_fused_minimum": (2 * xs[0].numel() * 4 + 2 * tout.numel() * 4) / us_t / 1e3}
+    log("overlapping-pair training step %.1f us" % us_t)
+    del tw, tout
+
     # small plain task: 64x64 -> 16x16 sums
     x0, p0 = W.small_sum()
     xd = torch.from_numpy(x0).to(dev)

@@ -181,6 +181,46 @@ rsm_status rsm_plan_ports(const rsm_space* rep, const rsm_tiler* in, int32_t n_i
                           rsm_port_placement* ports, int32_t max_ports, int32_t* n_ports);
 
 /*
+ * Placement as a decision.  The paper's MemoryMapping model gives every
+ * flowPort a DataAllocate whose spaceAddress is one of the OpenCL address
+ * spaces global, constant, local, private (Sec. 5), and the port's
+ * direction decides what is read-only (Sec. 6).  `spaces` is such a request
+ * for one task: a HOST array of n_spaces entries, one rsm_mem_space per port
+ * in port order (inputs 0 .. n_in - 1, the output, then the coefficients of
+ * a WSUM task), RSM_MEM_ANY where the caller leaves the choice open; NULL =
+ * no request at all.  The planner takes, among the kernel families that can
+ * run the task, the first in its order of preference whose placement meets
+ * every requested space.  For example the taps of a 1-D weighted sum may be
+ * kept in registers with the weights in scalar registers (input private,
+ * weights constant), or the window staged in LDS with the weights in LDS
+ * (input, output and weights local), or everything read in place (global);
+ * a k x k window keeps its tile in LDS, or, for at most 64 pattern elements,
+ * one element per lane in registers; a matrix product stages both operands
+ * in LDS and accumulates in registers.
+ * Errors: RSM_E_INVALID for a malformed request (wrong count, unknown space,
+ * the output port in constant memory: it is written); RSM_E_UNSUPPORTED when
+ * no family of this build meets the request (e.g. an input array in
+ * constant memory, or 81 elements of a 9 x 9 window in registers).
+ *
+ * rsm_plan_placed -- host only: the family that honours the request (name,
+ * nullable, of at most len bytes) and its placement of every port (ports,
+ * nullable, as rsm_plan_ports; *n_ports = port count).
+ * rsm_run_placed -- rsm_run with the request: runs the family
+ * rsm_plan_placed names.  With spaces NULL both behave as rsm_plan /
+ * rsm_plan_ports and rsm_run.
+ */
+#define RSM_MEM_ANY (-1)
+
+rsm_status rsm_plan_placed(const rsm_space* rep, const rsm_tiler* in, int32_t n_in,
+                           const rsm_tiler* out, const rsm_task* task, uint32_t flags,
+                           const int32_t* spaces, int32_t n_spaces, char* name, int32_t len,
+                           rsm_port_placement* ports, int32_t max_ports, int32_t* n_ports);
+
+rsm_status rsm_run_placed(const rsm_space* rep, const rsm_tiler* in, const void* const* d_in,
+                          int32_t n_in, const rsm_tiler* out, void* d_out, const rsm_task* task,
+                          const int32_t* spaces, int32_t n_spaces, uint32_t flags, void* hip_stream);
+
+/*
  * rsm_indices -- the index table of one tiler (the index step of the
  * definition above): d_idx[r * |s_p| + i] = linear offset of e(r, i) in the
  * tiler's array, int64, r and i flat row-major.  d_idx is a device buffer of

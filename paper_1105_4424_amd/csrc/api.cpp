@@ -463,6 +463,7 @@ bool fir_vec4(const Win3& w, const void* x) {
 enum class Fam { Empty, Generic, PatternReduce, Fir, Filter2D, Gemm, Poly };
 
 struct Plan {
+  bool ok = true;   // false: no family meets the requested placement
   Fam fam = Fam::Generic;
   std::string name = "generic";
   Win3 win{};
@@ -546,74 +547,177 @@ bool match_poly(const rsm_space& rep, const rsm_tiler& in, const rsm_tiler& out,
   return poly_supported(*w, *q);
 }
 
+// Where a planned family keeps each port's data while a workgroup computes
+// (the address spaces of the paper's MemoryMapping, Sec. 5-6: global =
+// device memory read or written in place, constant = uniform across the
+// workgroup in scalar registers, local = LDS, private = VGPR/AGPR), and how
+// many bytes of it one workgroup holds there.  Ports: inputs, the output,
+// then the coefficients of a weighted sum.
+struct Placement {
+  int count = 0;
+  int space[4] = {RSM_MEM_GLOBAL, RSM_MEM_GLOBAL, RSM_MEM_GLOBAL, RSM_MEM_GLOBAL};
+  int64_t bytes[4] = {0, 0, 0, 0};
+};
+
+Placement placement_of(const Plan& p, const rsm_tiler* in, int n_in, const rsm_task& task) {
+  constexpr int kThreadsPerWg = 256;
+  Placement pl;
+  const bool coeffs = task.kind == RSM_TASK_WSUM;
+  pl.count = n_in + 1 + (coeffs ? 1 : 0);
+  const int out = n_in, cf = n_in + 1;
+  auto set = [&](int k, int space, int64_t bytes) {
+    pl.space[k] = space;
+    pl.bytes[k] = bytes;
+  };
+  const int64_t in_es = elem_size(in[0].dtype);
+  switch (p.fam) {
+    case Fam::Empty:
+    case Fam::Generic:
+      break;   // every element read and written in place, weights read per term
+    case Fam::PatternReduce:
+      // one pattern element per lane, reduced across the lane group
+      set(0, RSM_MEM_PRIVATE, kThreadsPerWg * in_es);
+      if (coeffs) set(cf, RSM_MEM_PRIVATE, kThreadsPerWg * 4);
+      break;
+    case Fam::Fir:
+      // each thread holds the taps of its window; the taps' weights are
+      // uniform across the workgroup
+      set(0, RSM_MEM_PRIVATE, int64_t(kThreadsPerWg) * p.win.taps * in_es);
+      if (coeffs) set(cf, RSM_MEM_CONSTANT, int64_t(p.win.taps) * 4);
+      break;
+    case Fam::Poly:
+      if (p.win.ax == 2) {
+        // a chunk's input segment, its outputs and the q x T weights in LDS
+        set(0, RSM_MEM_LOCAL, (int64_t(p.win.p[2]) * 255 + p.win.taps) * in_es);
+        set(out, RSM_MEM_LOCAL, int64_t(p.poly_q) * 256 * 4);
+      } else {
+        // each thread holds its window in registers, lanes along columns
+        set(0, RSM_MEM_PRIVATE, int64_t(kThreadsPerWg) * p.win.taps * in_es);
+      }
+      if (coeffs) set(cf, RSM_MEM_LOCAL, int64_t(p.poly_q) * p.win.taps * 4);
+      break;
+    case Fam::Filter2D: {
+      // the tile's input region (halo included) and the k x k weights in LDS
+      const int64_t lds = int64_t(filter2d_lds_bytes(p.f2d.k, p.f2d.s, 1));
+      const int64_t wbytes = int64_t(12) * p.f2d.k * 4;
+      set(0, RSM_MEM_LOCAL, lds - wbytes);
+      if (coeffs) set(cf, RSM_MEM_LOCAL, wbytes);
+      break;
+    }
+    case Fam::Gemm: {
+      // double-buffered k-tiles of both operands in LDS; the output tile in
+      // accumulator registers for the whole k loop
+      const int compute = in[0].dtype == RSM_BF16 ? RSM_BF16 : RSM_F32;
+      const int64_t lds = gemm_lds_bytes_per_operand(p.gemm, compute);
+      const int64_t side = gemm_tile_side(p.gemm, compute);
+      set(0, RSM_MEM_LOCAL, lds);
+      if (n_in > 1) set(1, RSM_MEM_LOCAL, lds);
+      set(out, RSM_MEM_PRIVATE, side * side * 4);
+      break;
+    }
+  }
+  return pl;
+}
+
+// A requested space per port (RSM_MEM_ANY: no request) met by a placement.
+bool meets(const Placement& pl, const int32_t* req) {
+  if (!req) return true;
+  for (int k = 0; k < pl.count; ++k)
+    if (req[k] != RSM_MEM_ANY && req[k] != pl.space[k]) return false;
+  return true;
+}
+
+// The kernel family for a task: the first candidate, in order of preference,
+// whose port placement meets the request `req` (one space per port, or NULL
+// for none).  plan.ok is false when no candidate meets it.
 Plan make_plan(const rsm_space& rep, const rsm_tiler* in, int n_in, const rsm_tiler& out,
                const rsm_task& task, uint32_t flags, const void* const* d_in, int64_t n_rep,
-               int64_t n_pat) {
-  Plan p;
-  p.max_rank = max_rank_of(rep, in, n_in, out);
+               int64_t n_pat, const int32_t* req = nullptr) {
+  std::vector<Plan> cands;
+  Plan base;
+  base.max_rank = max_rank_of(rep, in, n_in, out);
   if (n_rep == 0) {
-    p.fam = Fam::Empty;
-    p.name = "empty";
-    return p;
+    base.fam = Fam::Empty;
+    base.name = "empty";
+    return base;   // nothing runs: any placement is met
   }
-  if (flags & RSM_FORCE_GENERIC) return p;
+  const Plan generic = base;   // fam Generic, name "generic"
   const bool f32 = in[0].dtype == RSM_F32 && task.compute == RSM_F32;
-  if (task.kind == RSM_TASK_DOT) {
-    GemmArgs g{};
-    const bool bf = in[0].dtype == RSM_BF16 && (task.compute == RSM_BF16 || task.compute == RSM_F32);
-    if ((bf || f32) && match_gemm(rep, in, out, &g)) {
-      const int compute = bf ? RSM_BF16 : RSM_F32;
-      // operands read in place (k-contiguous) must start on a 16-byte boundary
-      bool aligned = true;
-      if (d_in) {
-        if (g.a_sk == 1 && (reinterpret_cast<uintptr_t>(d_in[0]) & 15)) aligned = false;
-        if (g.b_sk == 1 && (reinterpret_cast<uintptr_t>(d_in[1]) & 15)) aligned = false;
+  if (!(flags & RSM_FORCE_GENERIC)) {
+    if (task.kind == RSM_TASK_DOT) {
+      GemmArgs g{};
+      const bool bf = in[0].dtype == RSM_BF16 && (task.compute == RSM_BF16 || task.compute == RSM_F32);
+      if ((bf || f32) && match_gemm(rep, in, out, &g)) {
+        const int compute = bf ? RSM_BF16 : RSM_F32;
+        // operands read in place (k-contiguous) must start on a 16-byte boundary
+        bool aligned = true;
+        if (d_in) {
+          if (g.a_sk == 1 && (reinterpret_cast<uintptr_t>(d_in[0]) & 15)) aligned = false;
+          if (g.b_sk == 1 && (reinterpret_cast<uintptr_t>(d_in[1]) & 15)) aligned = false;
+        }
+        if (aligned && gemm_supported(g, compute)) {
+          Plan p = base;
+          p.fam = Fam::Gemm;
+          p.gemm = g;
+          p.gemm.a = d_in ? d_in[0] : nullptr;
+          p.gemm.b = d_in ? d_in[1] : nullptr;
+          p.name = gemm_variant_name(g, compute);
+          cands.push_back(p);
+        }
       }
-      if (aligned && gemm_supported(g, compute)) {
-        p.fam = Fam::Gemm;
-        p.gemm = g;
-        p.gemm.a = d_in ? d_in[0] : nullptr;
-        p.gemm.b = d_in ? d_in[1] : nullptr;
-        p.name = gemm_variant_name(g, compute);
-        return p;
+    } else if (task.kind != RSM_TASK_COPY && f32) {
+      // SUM / WSUM on FP32
+      Win3 w{};
+      int q = 0;
+      if (task.kind == RSM_TASK_WSUM && match_poly(rep, in[0], out, &w, &q)) {
+        Plan p = base;
+        p.fam = Fam::Poly;
+        p.win = w;
+        p.poly_q = q;
+        p.name = w.ax == 2 ? "polyphase_cols" : "polyphase_rows";
+        cands.push_back(p);
+      }
+      if (task.kind == RSM_TASK_WSUM && is_identity_out(rep, out) && canon_win3(rep, in[0], &w) && w.ax >= 1 &&
+          outer_axes_inside(w, w.ax)) {
+        Plan p = base;
+        p.fam = Fam::Fir;
+        p.win = w;
+        p.vec4 = fir_vec4(w, d_in ? d_in[0] : nullptr);
+        p.name = w.ax == 2 ? (p.vec4 ? "fir_cols_vec4" : "fir_cols") : "fir_rows";
+        cands.push_back(p);
+        // the same taps with the window staged in LDS (columns) or the
+        // weights in LDS (rows): the polyphase kernels with one output
+        if (poly_supported(w, 1)) {
+          Plan l = base;
+          l.fam = Fam::Poly;
+          l.win = w;
+          l.poly_q = 1;
+          l.name = w.ax == 2 ? "fir_cols_lds" : "fir_rows_lds_weights";
+          cands.push_back(l);
+        }
+      }
+      Filter2DProblem fp{};
+      if (plan_filter2d(rep, in[0], out, task, &fp)) {
+        Plan p = base;
+        p.fam = Fam::Filter2D;
+        p.f2d = fp;
+        p.name = "filter2d_k" + std::to_string(fp.k) + "_s" + std::to_string(fp.s);
+        cands.push_back(p);
+      }
+      if (n_pat <= 64 && is_scalar_pattern(out)) {
+        Plan p = base;
+        p.fam = Fam::PatternReduce;
+        p.name = "pattern_reduce";
+        cands.push_back(p);
       }
     }
-    return p;
   }
-  if (task.kind == RSM_TASK_COPY) return p;
-  // SUM / WSUM on FP32
-  if (!f32) return p;
-  Win3 w{};
-  int q = 0;
-  if (task.kind == RSM_TASK_WSUM && match_poly(rep, in[0], out, &w, &q)) {
-    p.fam = Fam::Poly;
-    p.win = w;
-    p.poly_q = q;
-    p.name = w.ax == 2 ? "polyphase_cols" : "polyphase_rows";
-    return p;
-  }
-  const bool id_out = is_identity_out(rep, out);
-  if (task.kind == RSM_TASK_WSUM && id_out && canon_win3(rep, in[0], &w) && w.ax >= 1 &&
-      outer_axes_inside(w, w.ax)) {
-    p.fam = Fam::Fir;
-    p.win = w;
-    p.vec4 = fir_vec4(w, d_in ? d_in[0] : nullptr);
-    p.name = w.ax == 2 ? (p.vec4 ? "fir_cols_vec4" : "fir_cols") : "fir_rows";
-    return p;
-  }
-  Filter2DProblem fp{};
-  if (plan_filter2d(rep, in[0], out, task, &fp)) {
-    p.fam = Fam::Filter2D;
-    p.f2d = fp;
-    p.name = "filter2d_k" + std::to_string(fp.k) + "_s" + std::to_string(fp.s);
-    return p;
-  }
-  if (n_pat <= 64 && is_scalar_pattern(out)) {
-    p.fam = Fam::PatternReduce;
-    p.name = "pattern_reduce";
-    return p;
-  }
-  return p;
+  cands.push_back(generic);
+  for (const Plan& c : cands)
+    if (meets(placement_of(c, in, n_in, task), req)) return c;
+  Plan none = generic;
+  none.ok = false;
+  return none;
 }
 
 // Launch arguments of the polyphase kernels (pointers left to the caller).
@@ -639,8 +743,9 @@ PolyArgs poly_args(const Win3& w, int q, int64_t n_rep, bool forward) {
 // ---------------------------------------------------------------------------
 rsm_status exec_run(const rsm_space& rep, const rsm_tiler* in, const void* const* d_in, int n_in,
                     const rsm_tiler& out, void* d_out, const rsm_task& task, uint32_t flags,
-                    const Checked& c, hipStream_t st) {
-  Plan p = make_plan(rep, in, n_in, out, task, flags, d_in, c.n_rep, c.n_pat_in[0]);
+                    const Checked& c, hipStream_t st, const int32_t* req = nullptr) {
+  Plan p = make_plan(rep, in, n_in, out, task, flags, d_in, c.n_rep, c.n_pat_in[0], req);
+  if (!p.ok) return fail(RSM_E_UNSUPPORTED, "no kernel of this build keeps the ports where requested");
   hipError_t e = hipSuccess;
   switch (p.fam) {
     case Fam::Empty:
@@ -724,6 +829,25 @@ rsm_status exec_run(const rsm_space& rep, const rsm_tiler* in, const void* const
     }
   }
   return fail(RSM_E_UNSUPPORTED, "no kernel family");
+}
+
+// A placement request: one rsm_mem_space (or RSM_MEM_ANY) per port, in port
+// order (inputs, output, coefficients); NULL = no request.  An output port is
+// written, so it cannot sit in constant memory, which is read-only while a
+// kernel runs (port direction, Sec. 6).
+rsm_status check_spaces(const int32_t* spaces, int32_t n_spaces, int count, int n_in) {
+  if (!spaces) return RSM_OK;
+  if (n_spaces != count)
+    return fail(RSM_E_INVALID, "placement request needs one space per port (" + std::to_string(count) + "), got " +
+                                   std::to_string(n_spaces));
+  for (int k = 0; k < count; ++k) {
+    if (spaces[k] < RSM_MEM_ANY || spaces[k] > RSM_MEM_PRIVATE)
+      return fail(RSM_E_INVALID, "unknown memory space " + std::to_string(spaces[k]) + " for port " +
+                                     std::to_string(k));
+    if (k == n_in && spaces[k] == RSM_MEM_CONSTANT)
+      return fail(RSM_E_INVALID, "the output port is written: it cannot be placed in constant memory");
+  }
+  return RSM_OK;
 }
 
 bool ptrs_ok(const void* const* d, int n) {
@@ -1162,77 +1286,52 @@ rsm_status rsm_plan(const rsm_space* rep, const rsm_tiler* in, int32_t n_in, con
 rsm_status rsm_plan_ports(const rsm_space* rep, const rsm_tiler* in, int32_t n_in, const rsm_tiler* out,
                           const rsm_task* task, uint32_t flags, rsm_port_placement* ports, int32_t max_ports,
                           int32_t* n_ports) {
+  return rsm_plan_placed(rep, in, n_in, out, task, flags, nullptr, 0, nullptr, 0, ports, max_ports, n_ports);
+}
+
+rsm_status rsm_plan_placed(const rsm_space* rep, const rsm_tiler* in, int32_t n_in, const rsm_tiler* out,
+                           const rsm_task* task, uint32_t flags, const int32_t* spaces, int32_t n_spaces,
+                           char* name, int32_t len, rsm_port_placement* ports, int32_t max_ports,
+                           int32_t* n_ports) {
   RSM_GUARD_BEGIN
   Checked c;
   rsm_status s = check_task(rep, in, n_in, out, task, flags & ~RSM_CHECK_SINGLE_ASSIGN, &c);
   if (s) return s;
-  if (!n_ports) return fail(RSM_E_INVALID, "n_ports is NULL");
-  const bool coeffs = task->kind == RSM_TASK_WSUM;
-  const int count = n_in + 1 + (coeffs ? 1 : 0);
-  *n_ports = count;
-  if (!ports || max_ports < count) return fail(RSM_E_INVALID, "ports array too short");
-  const Plan p = make_plan(*rep, in, n_in, *out, *task, flags, nullptr, c.n_rep, c.n_pat_in[0]);
-  constexpr int kThreadsPerWg = 256;
-  std::vector<rsm_port_placement> v(static_cast<size_t>(count));
-  for (int k = 0; k < count; ++k) {
-    v[size_t(k)] = rsm_port_placement{};
-    v[size_t(k)].port = k;
-    v[size_t(k)].is_output = k == n_in ? 1 : 0;
-    v[size_t(k)].space = RSM_MEM_GLOBAL;
-  }
-  auto set = [&](int k, int space, int64_t bytes) {
-    v[size_t(k)].space = space;
-    v[size_t(k)].bytes_per_workgroup = bytes;
-  };
-  const int64_t in_es = elem_size(in[0].dtype);
-  switch (p.fam) {
-    case Fam::Empty:
-    case Fam::Generic:
-      break;   // every element read and written in place
-    case Fam::PatternReduce:
-      // one pattern element per lane, reduced across the lane group
-      set(0, RSM_MEM_PRIVATE, kThreadsPerWg * in_es);
-      if (coeffs) set(n_in + 1, RSM_MEM_PRIVATE, kThreadsPerWg * 4);
-      break;
-    case Fam::Fir:
-      // each thread holds the taps of its window; the taps' weights are
-      // uniform across the workgroup
-      set(0, RSM_MEM_PRIVATE, int64_t(kThreadsPerWg) * p.win.taps * in_es);
-      if (coeffs) set(n_in + 1, RSM_MEM_CONSTANT, int64_t(p.win.taps) * 4);
-      break;
-    case Fam::Poly:
-      if (p.win.ax == 2) {
-        // a chunk's input segment, its outputs and the q x T weights in LDS
-        set(0, RSM_MEM_LOCAL, (int64_t(p.win.p[2]) * 255 + p.win.taps) * in_es);
-        set(n_in, RSM_MEM_LOCAL, int64_t(p.poly_q) * 256 * 4);
-      } else {
-        // each thread holds its window in registers, lanes along columns
-        set(0, RSM_MEM_PRIVATE, int64_t(kThreadsPerWg) * p.win.taps * in_es);
-      }
-      if (coeffs) set(n_in + 1, RSM_MEM_LOCAL, int64_t(p.poly_q) * p.win.taps * 4);
-      break;
-    case Fam::Filter2D: {
-      // the tile's input region (halo included) and the k x k weights in LDS
-      const int64_t lds = int64_t(filter2d_lds_bytes(p.f2d.k, p.f2d.s, 1));
-      const int64_t wbytes = int64_t(12) * p.f2d.k * 4;
-      set(0, RSM_MEM_LOCAL, lds - wbytes);
-      if (coeffs) set(n_in + 1, RSM_MEM_LOCAL, wbytes);
-      break;
+  const int count = n_in + 1 + (task->kind == RSM_TASK_WSUM ? 1 : 0);
+  if ((s = check_spaces(spaces, n_spaces, count, n_in)) != RSM_OK) return s;
+  const Plan p = make_plan(*rep, in, n_in, *out, *task, flags, nullptr, c.n_rep, c.n_pat_in[0], spaces);
+  if (!p.ok) return fail(RSM_E_UNSUPPORTED, "no kernel of this build keeps the ports where requested");
+  if (name && len > 0) std::snprintf(name, size_t(len), "%s", p.name.c_str());
+  if (n_ports) *n_ports = count;
+  if (ports) {
+    if (max_ports < count) return fail(RSM_E_INVALID, "ports array too short");
+    const Placement pl = placement_of(p, in, n_in, *task);
+    for (int k = 0; k < count; ++k) {
+      ports[k] = rsm_port_placement{};
+      ports[k].port = k;
+      ports[k].is_output = k == n_in ? 1 : 0;
+      ports[k].space = pl.space[k];
+      ports[k].bytes_per_workgroup = pl.bytes[k];
     }
-    case Fam::Gemm: {
-      // double-buffered k-tiles of both operands in LDS; the output tile in
-      // accumulator registers for the whole k loop
-      const int compute = in[0].dtype == RSM_BF16 ? RSM_BF16 : RSM_F32;
-      const int64_t lds = gemm_lds_bytes_per_operand(p.gemm, compute);
-      const int64_t side = gemm_tile_side(p.gemm, compute);
-      set(0, RSM_MEM_LOCAL, lds);
-      if (n_in > 1) set(1, RSM_MEM_LOCAL, lds);
-      set(n_in, RSM_MEM_PRIVATE, side * side * 4);
-      break;
-    }
+  } else if (!name && !n_ports) {
+    return fail(RSM_E_INVALID, "nothing to return: name, ports and n_ports are all NULL");
   }
-  for (int k = 0; k < count; ++k) ports[k] = v[size_t(k)];
   return RSM_OK;
+  RSM_GUARD_END
+}
+
+rsm_status rsm_run_placed(const rsm_space* rep, const rsm_tiler* in, const void* const* d_in, int32_t n_in,
+                          const rsm_tiler* out, void* d_out, const rsm_task* task, const int32_t* spaces,
+                          int32_t n_spaces, uint32_t flags, void* hip_stream) {
+  RSM_GUARD_BEGIN
+  Checked c;
+  rsm_status s = check_task(rep, in, n_in, out, task, flags, &c);
+  if (s) return s;
+  const int count = n_in + 1 + (task->kind == RSM_TASK_WSUM ? 1 : 0);
+  if ((s = check_spaces(spaces, n_spaces, count, n_in)) != RSM_OK) return s;
+  if (c.n_rep > 0 && (!ptrs_ok(d_in, n_in) || !d_out)) return fail(RSM_E_INVALID, "NULL device pointer");
+  return exec_run(*rep, in, d_in, n_in, *out, d_out, *task, flags, c, static_cast<hipStream_t>(hip_stream),
+                  spaces);
   RSM_GUARD_END
 }
 

@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(kBlock) poly_gc_kernel(PolyArgs a) {
 
 bool poly_supported(const Win3& w, int q) {
   if (w.ax == 2 && (w.p[2] < 1 || w.p[2] > kMaxP)) return false;
-  return w.taps >= 1 && w.taps <= kMaxT && q >= 2 && q <= kMaxQ;
+  return w.taps >= 1 && w.taps <= kMaxT && q >= 1 && q <= kMaxQ;
 }
 
 bool poly_gc_supported(const Win3& w, int q) { return w.taps <= 16 && q <= 4; }

@@ -150,6 +150,54 @@ def plan_ports(problem, dtypes: Sequence[torch.dtype] = (torch.float32,), flags:
     return [(_abi.MEM_SPACES[ports[k].space], int(ports[k].bytes_per_workgroup)) for k in range(n.value)]
 
 
+def _spaces(spaces):
+    """Placement request: a sequence of space names ("global", "constant",
+    "local", "private", "any") or None, one per port (inputs, output,
+    coefficients)."""
+    if spaces is None:
+        return None, 0
+    arr = (ctypes.c_int32 * len(spaces))(*[_abi.MEM_CODES[s] for s in spaces])
+    return arr, len(spaces)
+
+
+def plan_placed(problem, spaces, dtypes: Sequence[torch.dtype] = (torch.float32,), flags: int = 0):
+    """(family name, [(space, bytes per workgroup) per port]) of the kernel
+    family that keeps the ports where `spaces` asks (host only); raises
+    RsmError (RSM_E_UNSUPPORTED) when no family does."""
+    lib = _abi.load()
+    codes = [_DTYPES[d] for d in dtypes]
+    tin = (_abi.Tiler * len(problem.inputs))(*[_tiler(t, codes[min(i, len(codes) - 1)])
+                                               for i, t in enumerate(problem.inputs)])
+    c0 = codes[0]
+    out_code = c0 if problem.task == _abi.TASK_COPY else (_abi.F64 if c0 == _abi.F64 else _abi.F32)
+    comp = _abi.F64 if c0 == _abi.F64 else _COMPUTE.get(getattr(problem, "compute", "f32"))
+    task = _abi.Task(problem.task, comp, ctypes.c_void_p(1).value)
+    sp, ns = _spaces(spaces)
+    buf = ctypes.create_string_buffer(64)
+    ports = (_abi.PortPlacement * 8)()
+    n = ctypes.c_int32(0)
+    _check(lib.rsm_plan_placed(ctypes.byref(_space(problem.rep_shape)), tin, len(problem.inputs),
+                               ctypes.byref(_tiler(problem.output, out_code)), ctypes.byref(task), flags,
+                               sp, ns, buf, 64, ports, 8, ctypes.byref(n)))
+    return buf.value.decode(), [(_abi.MEM_SPACES[ports[k].space], int(ports[k].bytes_per_workgroup))
+                                for k in range(n.value)]
+
+
+def run_placed(problem, inputs: List[torch.Tensor], out: torch.Tensor, spaces, coeffs: torch.Tensor = None,
+               flags: int = 0, stream=None) -> torch.Tensor:
+    """run() by the kernel family that keeps the ports where `spaces` asks."""
+    lib = _abi.load()
+    n = len(inputs)
+    tin = (_abi.Tiler * n)(*[_tiler(t, _dcode(x)) for t, x in zip(problem.inputs, inputs)])
+    ptrs = (ctypes.c_void_p * n)(*[_ptr(x).value for x in inputs])
+    task = _task(problem.task, _compute_for(problem, inputs[0]), coeffs)
+    sp, ns = _spaces(spaces)
+    _check(lib.rsm_run_placed(ctypes.byref(_space(problem.rep_shape)), tin, ptrs, n,
+                              ctypes.byref(_tiler(problem.output, _dcode(out))), _ptr(out),
+                              ctypes.byref(task), sp, ns, flags, _stream(stream)))
+    return out
+
+
 def plan(problem, dtypes: Sequence[torch.dtype] = (torch.float32,), flags: int = 0,
          compute: str = None) -> str:
     """Kernel family the planner picks (host only)."""

@@ -231,3 +231,66 @@ def test_cg_solve_host_checks():
     # an empty system is solved with no work
     assert name(call(n=0, nnz=0)) == "RSM_OK"
     assert info.iterations == 0 and info.converged == 1 and info.breakdown == 0
+
+
+def test_placement_request_routes_the_kernel_family():
+    # a request names the memory space of each port (inputs, output,
+    # coefficients); the planner takes the first family that meets it
+    import torch
+    ts = W.two_stage_filter(frames=2, rows=16, cols=32)
+    P = rsm.plan_placed
+    assert P(ts.h, None) == ("fir_cols_vec4", rsm.plan_ports(ts.h))
+    # the window staged in LDS (input, output and weights local)
+    name, ports = P(ts.h, ["local", "any", "any"])
+    assert name == "fir_cols_lds" and [s for s, _ in ports] == ["local", "local", "local"]
+    assert ports[0][1] == (8 * 255 + 8) * 4 and ports[2][1] == 8 * 4
+    assert P(ts.h, ["any", "any", "local"])[0] == "fir_cols_lds"
+    assert P(ts.h, ["any", "local", "any"])[0] == "fir_cols_lds"
+    # taps in registers, weights uniform (the default family)
+    assert P(ts.h, ["private", "global", "constant"])[0] == "fir_cols_vec4"
+    # weights per lane: one pattern element per lane
+    assert P(ts.h, ["any", "any", "private"])[0] == "pattern_reduce"
+    # everything in place
+    assert P(ts.h, ["global", "any", "any"]) == ("generic", [("global", 0)] * 3)
+    # rows: weights in LDS, taps in registers; no family stages row taps in LDS
+    assert P(ts.v, ["any", "any", "local"])[0] == "fir_rows_lds_weights"
+    with pytest.raises(rsm.RsmError) as e:
+        P(ts.v, ["local", "any", "any"])
+    assert e.value.name == "RSM_E_UNSUPPORTED"
+    # an input array is not uniform across a workgroup: never constant
+    with pytest.raises(rsm.RsmError) as e:
+        P(ts.h, ["constant", "any", "any"])
+    assert e.value.name == "RSM_E_UNSUPPORTED"
+    # the output port is written: constant memory contradicts its direction
+    with pytest.raises(rsm.RsmError) as e:
+        P(ts.h, ["any", "constant", "any"])
+    assert e.value.name == "RSM_E_INVALID"
+    # one space per port
+    with pytest.raises(rsm.RsmError) as e:
+        P(ts.h, ["any", "any"])
+    assert e.value.name == "RSM_E_INVALID"
+    # k x k windows: LDS tile by default, one element per lane up to 64
+    # elements, in place on the generic kernel; never weights in constant
+    f5 = W.filter2d_problem(70, 90, 5, 1)
+    assert P(f5, None)[0] == "filter2d_k5_s1"
+    assert P(f5, ["private", "any", "any"])[0] == "pattern_reduce"
+    assert P(f5, ["global", "any", "any"])[0] == "generic"
+    with pytest.raises(rsm.RsmError) as e:
+        P(f5, ["any", "any", "constant"])
+    assert e.value.name == "RSM_E_UNSUPPORTED"
+    f9 = W.filter2d_problem(70, 90, 9, 1)
+    with pytest.raises(rsm.RsmError) as e:
+        P(f9, ["private", "any", "any"])    # 81 elements: more than a lane group holds
+    assert e.value.name == "RSM_E_UNSUPPORTED"
+    # matrix product: operands in LDS, accumulators in registers, or in place
+    mm = W.matmul_tilers(256, 256, 256)
+    assert P(mm, ["local", "local", "private"])[0] == "gemm_mfma_f32_nn"
+    assert P(mm, ["global", "any", "any"])[0] == "generic"
+    with pytest.raises(rsm.RsmError) as e:
+        P(mm, ["any", "any", "local"])
+    assert e.value.name == "RSM_E_UNSUPPORTED"
+    # polyphase stage: the columns kernel stages everything in LDS
+    pp = W.polyphase_downscaler(frames=1, rows=18, cols=48)
+    assert P(pp.h, ["local", "local", "local"])[0] == "polyphase_cols"
+    assert P(pp.h, ["global", "any", "any"])[0] == "generic"
+    assert P(pp.v, ["private", "global", "local"])[0] == "polyphase_rows"
