@@ -938,6 +938,15 @@ AdjPlan plan_adjoint(const rsm_space& rep, const rsm_tiler& in, const rsm_tiler&
 // Workspace bytes the adjoint of one stage needs.
 size_t adjoint_ws_bytes(const AdjPlan& ap, int64_t n_rep, int64_t n_pat, int64_t n_q, bool want_gc) {
   if (!want_gc) return 0;
+  if (ap.poly && poly_adj_cols_supported(ap.w, ap.q)) {
+    const Win3& w = ap.w;
+    const int64_t chunks = std::max<int64_t>(
+        std::max<int64_t>((int64_t(w.A[2]) + 256 * int64_t(w.p[2]) - 1) / (256 * int64_t(w.p[2])),
+                          (int64_t(w.rep[2]) + 255) / 256),
+        1);
+    return size_t(poly_adj_cols_grid(uint32_t(int64_t(w.rep[0]) * w.rep[1] * chunks))) * size_t(ap.q) *
+           size_t(w.taps) * sizeof(float);
+  }
   if (ap.poly && poly_gc_supported(ap.w, ap.q))
     return size_t(poly_gc_grid(uint32_t(n_rep))) * size_t(ap.q) * size_t(ap.w.taps) * sizeof(float);
   if (ap.overlap_cols)
@@ -969,6 +978,39 @@ rsm_status exec_adjoint(const rsm_space& rep, const rsm_tiler& in, const void* d
     return RSM_OK;
   }
   const int64_t n_arr = prod(in.array_shape, in.array_rank);
+  if (ap.poly && poly_adj_cols_supported(ap.w, ap.q)) {
+    // both gradients in one pass over row chunks; the kernel visits the rows
+    // the repetitions read, so rows no repetition reads are cleared first
+    const Win3& w = ap.w;
+    const bool all_rows = w.rep[0] == w.A[0] && w.rep[1] == w.A[1] && w.o[0] == 0 && w.o[1] == 0 &&
+                          (w.A[0] == 1 || w.p[0] == 1) && (w.A[1] == 1 || w.p[1] == 1);
+    if (d_gx && !accumulate && !all_rows && (e = launch_zero(d_gx, n_arr * 4, st)) != hipSuccess)
+      return hip_fail(e, "zero gx");
+    PolyAdjArgs o{};
+    o.w = w;
+    o.q = ap.q;
+    o.n_chunks = int32_t(std::max<int64_t>(
+        std::max<int64_t>((int64_t(w.A[2]) + 256 * int64_t(w.p[2]) - 1) / (256 * int64_t(w.p[2])),
+                          (int64_t(w.rep[2]) + 255) / 256),
+        1));
+    o.o_mod = int32_t(floor_mod(w.o[2], w.A[2]));
+    o.div_chunks = make_fastdiv(uint32_t(o.n_chunks));
+    o.div_rr = make_fastdiv(uint32_t(w.rep[1]));
+    o.div_p = make_fastdiv(uint32_t(w.p[2]));
+    o.n_items = uint32_t(int64_t(w.rep[0]) * w.rep[1] * o.n_chunks);
+    o.x = static_cast<const float*>(d_x);
+    o.gy = static_cast<const float*>(d_gy);
+    o.gx = static_cast<float*>(d_gx);
+    o.c = static_cast<const float*>(task.coeffs);
+    o.partial = d_gc ? static_cast<float*>(ws) : nullptr;
+    o.accumulate = accumulate;
+    if ((e = launch_poly_adj_cols(o, st)) != hipSuccess) return hip_fail(e, "polyphase adjoint");
+    const int nc = ap.q * w.taps;
+    if (d_gc && (e = launch_reduce_partials(o.partial, poly_adj_cols_grid(o.n_items), nc, nc,
+                                            static_cast<float*>(d_gc), accumulate, st)) != hipSuccess)
+      return hip_fail(e, "weight-gradient reduction");
+    return RSM_OK;
+  }
   if (ap.poly) {
     const Win3& w = ap.w;
     if (d_gx) {
@@ -1265,8 +1307,9 @@ rsm_status rsm_plan(const rsm_space* rep, const rsm_tiler* in, int32_t n_in, con
     if (s) return s;
     if (!name || len <= 0) return fail(RSM_E_INVALID, "name buffer is NULL");
     const AdjPlan ap = plan_adjoint(*rep, *in, *out, *task, flags, nullptr, nullptr);
-    const char* fam = ap.poly           ? (poly_gc_supported(ap.w, ap.q) ? "polyphase_adjoint_gather"
-                                                                         : "polyphase_adjoint_gather_generic_gc")
+    const char* fam = ap.poly           ? (poly_adj_cols_supported(ap.w, ap.q) ? "polyphase_adjoint_cols"
+                                           : poly_gc_supported(ap.w, ap.q)     ? "polyphase_adjoint_gather"
+                                                                               : "polyphase_adjoint_gather_generic_gc")
                       : ap.overlap_cols ? "fir_adjoint_overlap_cols"
                       : ap.gather ? "fir_adjoint_gather"
                       : ap.fir  ? (ap.vec4 ? "fir_adjoint_vec4" : "fir_adjoint")

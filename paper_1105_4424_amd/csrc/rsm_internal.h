@@ -204,6 +204,26 @@ struct PolyArgs {
   float* partial;      // weight gradient: [grid][q T]
 };
 
+// Both gradients of a polyphase stage along columns in one pass (T <= 16,
+// q <= 4, p <= 16): items (row, chunk of 256 repetitions), ownership of the
+// columns whose first lift falls in the chunk.
+struct PolyAdjArgs {
+  Win3 w;
+  int32_t q;
+  int32_t n_chunks;    // max(ceil(A[2] / (256 p)), ceil(rep[2] / 256))
+  int32_t o_mod;       // o[2] mod A[2]
+  FastDiv div_chunks;  // divide by n_chunks
+  FastDiv div_rr;      // divide by rep[1]
+  FastDiv div_p;       // divide by p[2]
+  uint32_t n_items;    // rep[0] rep[1] n_chunks
+  const float* x;      // needed when partial is set
+  const float* gy;
+  float* gx;           // nullable; every element written
+  const float* c;
+  float* partial;      // [grid][q T] weight-gradient partials, nullable
+  int32_t accumulate;
+};
+
 // Input gradient of a polyphase stage as a gather (one thread per element).
 struct PolyGatherArgs {
   Win3 w;
@@ -373,6 +393,9 @@ hipError_t launch_poly(const PolyArgs& a, hipStream_t st);
 hipError_t launch_poly_gx_gather(const PolyGatherArgs& a, hipStream_t st);
 int poly_gc_grid(uint32_t n_rep);
 hipError_t launch_poly_gc(const PolyArgs& a, hipStream_t st);
+bool poly_adj_cols_supported(const Win3& w, int q);
+int poly_adj_cols_grid(uint32_t n_items);
+hipError_t launch_poly_adj_cols(const PolyAdjArgs& a, hipStream_t st);
 int64_t gemm_lds_bytes_per_operand(const GemmArgs& g, int compute);   // LDS per workgroup, one operand
 int gemm_tile_side(const GemmArgs& g, int compute);                   // output tile side (128 or 256)
 hipError_t launch_gemm(const GemmArgs& a, int compute, hipStream_t st);

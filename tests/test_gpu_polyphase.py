@@ -74,6 +74,8 @@ CASES = [
     ((2, 72, 40), 14, 9, 4, -2, 1),      # taps along rows
     ((1, 50, 17), 7, 2, 3, -3, 1),
     ((1, 9, 8), 20, 3, 2, -11, 1),       # windows longer than the axis: several lifts
+    ((1, 6, 48), 13, 4, 3, -5, 2),       # step 4: the phase form of the column adjoint
+    ((1, 3, 36), 13, 3, 2, -1, 2),       # step 3 (not a power of two): the per-slot form
 ]
 
 
@@ -92,9 +94,13 @@ def test_polyphase_stage_forward_and_adjoint(case, generic):
 
 
 def test_polyphase_kernel_plan_names():
+    # along columns both gradients come from one pass over row chunks
     p, _ = _stage((1, 8, 64), 13, 8, 3, -2, 2, seed=1)
-    assert rsm.plan(p, flags=_abi.PLAN_ADJOINT) == "polyphase_adjoint_gather"
-    p5, _ = _stage((1, 8, 64), 20, 8, 3, -2, 2, seed=1)   # 20 taps: weight gradient on the generic kernel
+    assert rsm.plan(p, flags=_abi.PLAN_ADJOINT) == "polyphase_adjoint_cols"
+    # along rows: a gather for dL/dx, per-repetition partials for the weights
+    pr, _ = _stage((1, 64, 8), 13, 8, 3, -2, 1, seed=1)
+    assert rsm.plan(pr, flags=_abi.PLAN_ADJOINT) == "polyphase_adjoint_gather"
+    p5, _ = _stage((1, 64, 8), 20, 8, 3, -2, 1, seed=1)   # 20 taps: weight gradient on the generic kernel
     assert rsm.plan(p5, flags=_abi.PLAN_ADJOINT) == "polyphase_adjoint_gather_generic_gc"
     ports = rsm.plan_ports(p)
     assert [sp for sp, _ in ports] == ["local", "local", "local"]
@@ -178,3 +184,17 @@ def test_polyphase_chain_autograd_matches_oracle():
     a = oracle.adjoint(pp.h, pp.x, g)
     check_close(host(xs.grad), a.gx, a.gx_abs, what="task gx")
     check_close(host(cs.grad), a.gc, a.gc_abs, what="task gc")
+
+
+def test_polyphase_column_adjoint_rows_not_read_are_zero():
+    # the column tiler reads every other row of a [1, 10, 64] array: dL/dx of
+    # the rows no window reads must come out zero
+    x = W.rng_for(909).standard_normal((1, 10, 64)).astype(np.float32)
+    t = W.Tiler((1, 10, 64), [0, 1, -3], np.diag([1, 2, 8]), [[0], [0], [1]], (13,))
+    rep = (1, 5, 8)
+    c = W.phase_coeffs(W.rng_for(910), 3, 13)
+    p = W.Problem(rep, [t], W.phase_output(rep, 2, 3), W.WSUM, c)
+    assert rsm.plan(p, flags=_abi.PLAN_ADJOINT) == "polyphase_adjoint_cols"
+    gy = W.rng_for(911).uniform(-1, 1, p.output.array_shape).astype(np.float32)
+    _forward_check(p, x, 0, what="strided rows")
+    _adjoint_check(p, x, gy, 0, what="strided rows")
