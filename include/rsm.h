@@ -477,7 +477,9 @@ rsm_status rsm_batch_tile(rsm_batch b, int32_t k, int32_t* tile_rows, int32_t* t
  */
 rsm_status rsm_time_next_kernel(void* hip_event_start, void* hip_event_stop);
 
-const char* rsm_status_string(rsm_status s);
+/* Name of a status code; any value is accepted (unknown ones give
+ * "RSM_E_UNKNOWN"), so the argument is a plain int32_t. */
+const char* rsm_status_string(int32_t status);
 const char* rsm_last_error(void); /* thread-local detail of the last failing call */
 int32_t rsm_abi_version(void);
 

@@ -1272,8 +1272,8 @@ rsm_status rsm_time_next_kernel(void* hip_event_start, void* hip_event_stop) {
 
 int32_t rsm_abi_version(void) { return RSM_ABI_VERSION; }
 
-const char* rsm_status_string(rsm_status s) {
-  switch (s) {
+const char* rsm_status_string(int32_t status) {
+  switch (status) {
     case RSM_OK: return "RSM_OK";
     case RSM_E_INVALID: return "RSM_E_INVALID";
     case RSM_E_RANK: return "RSM_E_RANK";
