@@ -271,6 +271,21 @@ def time_fn(fn, reps=20, warm=3):
     return float(np.median([a.elapsed_time(b) for a, b in ev])) * 1e3
 
 
+def wall_us(fn, calls=400, warm=20):
+    """Wall time per call of back-to-back calls on the host thread (the
+    stream drains once at the end)."""
+    import time
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / calls * 1e6
+
+
 def bf16_to_f64(u16):
     """BF16 bit patterns (uint16) widened exactly to FP64."""
     import numpy as np
@@ -511,7 +526,15 @@ def extras(args, ts, xs, stages, ch, cv, w2, chain):
     x0, p0 = W.small_sum()
     xd = torch.from_numpy(x0).to(dev)
     o0 = torch.empty((16, 16), device=dev)
-    ex["small_sum_64x64"] = {"avg_us": time_fn(lambda: rsm.run(p0, [xd], o0)), "kernel": rsm.plan(p0)}
+    pr0 = rsm.Prepared(p0)
+    ex["small_sum_64x64"] = {
+        "avg_us": time_fn(lambda: rsm.run(p0, [xd], o0)), "kernel": rsm.plan(p0),
+        "call_us": wall_us(lambda: rsm.run(p0, [xd], o0)),
+        "prepared_call_us": wall_us(lambda: pr0.run([xd], o0)),
+        "note": "avg_us: HIP events around one rsm.run call (host marshalling, the plan kept for "
+                "these descriptors, launch, kernel); call_us / prepared_call_us: wall time per call "
+                "of 400 back-to-back calls through rsm.run and through rsm.Prepared.run"}
+    pr0.close()
 
     # matrix product on the matrix cores
     M = N = K = 4096

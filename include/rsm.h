@@ -246,6 +246,47 @@ rsm_status rsm_run(const rsm_space* rep, const rsm_tiler* in, const void* const*
                    uint32_t flags, void* hip_stream);
 
 /*
+ * Validation and planning (the host side of a call: checking the descriptors
+ * against Sec. 6.1's shaped repetition space and the tiler definition above,
+ * then choosing a kernel family and its launch shape) cost microseconds per
+ * call, which a small task feels.  Two ways avoid repeating them:
+ *
+ *  - rsm_run keeps, per host thread, the last 32 descriptors it validated
+ *    successfully together with their plans; a call whose descriptors
+ *    (every entry below the ranks, the task's kind and compute type, whether
+ *    weights are given, the flags, and whether each input starts on a
+ *    16-byte boundary) equal a kept one is launched directly.
+ *    rsm_plan_cache_hits() counts such calls on the calling thread.
+ *
+ *  - rsm_prepare validates and plans one task once and returns an opaque
+ *    handle that the library owns until rsm_prepared_destroy (NULL is
+ *    ignored).  rsm_run_prepared then takes only the arrays: d_in a HOST
+ *    array of n_in DEVICE pointers, d_out, and for a WSUM task the DEVICE
+ *    weights d_coeffs (NULL: RSM_E_INVALID; ignored for other tasks; the
+ *    task's own coeffs field is ignored by rsm_prepare).  The arrays must
+ *    have the shapes and dtypes the descriptors state, as for rsm_run.  The
+ *    plan assumes inputs starting on 16-byte boundaries; a call with other
+ *    addresses plans again for them (same results, host cost of rsm_run).
+ *    flags: RSM_CHECK_SINGLE_ASSIGN (checked once, at rsm_prepare) and
+ *    RSM_FORCE_GENERIC; any other flag is RSM_E_INVALID.  A handle is read
+ *    only after creation: calls on different streams or threads may share it.
+ *    rsm_prepared_name writes the planned family (at most len bytes).
+ */
+typedef struct rsm_prepared_s* rsm_prepared;
+
+uint64_t rsm_plan_cache_hits(void);
+
+rsm_status rsm_prepare(const rsm_space* rep, const rsm_tiler* in, int32_t n_in, const rsm_tiler* out,
+                       const rsm_task* task, uint32_t flags, rsm_prepared* handle);
+
+rsm_status rsm_prepared_name(const struct rsm_prepared_s* handle, char* name, int32_t len);
+
+rsm_status rsm_run_prepared(const struct rsm_prepared_s* handle, const void* const* d_in, void* d_out,
+                            const void* d_coeffs, void* hip_stream);
+
+void rsm_prepared_destroy(rsm_prepared handle);
+
+/*
  * rsm_run_chain -- n_stages single-input tasks where stage k's output array
  * is stage k+1's input array (stage k's out tiler and stage k+1's in tiler
  * describe the same array).  d_mid is a HOST array of n_stages-1 DEVICE

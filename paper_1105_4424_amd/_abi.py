@@ -90,6 +90,7 @@ EXPORTS = [
     "rsm_batch_tile", "rsm_batch_destroy", "rsm_status_string", "rsm_last_error",
     "rsm_abi_version", "rsm_run_csr", "rsm_cg_solve", "rsm_time_next_kernel", "rsm_run_chain_train",
     "rsm_plan_ports", "rsm_run_chain_train_noalloc", "rsm_plan_placed", "rsm_run_placed",
+    "rsm_plan_cache_hits", "rsm_prepare", "rsm_prepared_name", "rsm_run_prepared", "rsm_prepared_destroy",
 ]
 
 _lib = None
@@ -115,6 +116,13 @@ def load(path: str = LIB_PATH):
     lib.rsm_plan_placed.argtypes = [P(Space), P(Tiler), i32, P(Tiler), P(Task), u32, P(i32), i32,
                                     ctypes.c_char_p, i32, P(PortPlacement), i32, P(i32)]
     lib.rsm_run_placed.argtypes = [P(Space), P(Tiler), P(vp), i32, P(Tiler), vp, P(Task), P(i32), i32, u32, vp]
+    lib.rsm_prepare.argtypes = [P(Space), P(Tiler), i32, P(Tiler), P(Task), u32, P(vp)]
+    lib.rsm_prepared_name.argtypes = [vp, ctypes.c_char_p, i32]
+    lib.rsm_run_prepared.argtypes = [vp, P(vp), vp, vp, vp]
+    lib.rsm_prepared_destroy.argtypes = [vp]
+    lib.rsm_prepared_destroy.restype = None
+    lib.rsm_plan_cache_hits.argtypes = []
+    lib.rsm_plan_cache_hits.restype = ctypes.c_uint64
     lib.rsm_indices.argtypes = [P(Space), P(Tiler), vp, vp]
     lib.rsm_run.argtypes = [P(Space), P(Tiler), P(vp), i32, P(Tiler), vp, P(Task), u32, vp]
     lib.rsm_run_chain.argtypes = [P(Stage), i32, vp, P(vp), vp, u32, vp]
@@ -135,7 +143,7 @@ def load(path: str = LIB_PATH):
     for name in ("rsm_validate", "rsm_plan", "rsm_plan_ports", "rsm_indices", "rsm_run", "rsm_run_chain",
                  "rsm_run_adjoint", "rsm_run_chain_adjoint", "rsm_batch_create", "rsm_batch_run",
                  "rsm_run_csr", "rsm_cg_solve", "rsm_run_chain_train", "rsm_run_chain_train_noalloc",
-                 "rsm_plan_placed", "rsm_run_placed",
+                 "rsm_plan_placed", "rsm_run_placed", "rsm_prepare", "rsm_prepared_name", "rsm_run_prepared",
                  "rsm_batch_run_plain", "rsm_batch_query", "rsm_batch_tile", "rsm_batch_destroy"):
         getattr(lib, name).restype = st
     lib.rsm_time_next_kernel.argtypes = [vp, vp]

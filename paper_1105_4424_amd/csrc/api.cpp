@@ -658,9 +658,7 @@ Plan make_plan(const rsm_space& rep, const rsm_tiler* in, int n_in, const rsm_ti
         if (aligned && gemm_supported(g, compute)) {
           Plan p = base;
           p.fam = Fam::Gemm;
-          p.gemm = g;
-          p.gemm.a = d_in ? d_in[0] : nullptr;
-          p.gemm.b = d_in ? d_in[1] : nullptr;
+          p.gemm = g;   // operand pointers are set per call (a plan holds none)
           p.name = gemm_variant_name(g, compute);
           cands.push_back(p);
         }
@@ -684,16 +682,28 @@ Plan make_plan(const rsm_space& rep, const rsm_tiler* in, int n_in, const rsm_ti
         p.win = w;
         p.vec4 = fir_vec4(w, d_in ? d_in[0] : nullptr);
         p.name = w.ax == 2 ? (p.vec4 ? "fir_cols_vec4" : "fir_cols") : "fir_rows";
-        cands.push_back(p);
         // the same taps with the window staged in LDS (columns) or the
         // weights in LDS (rows): the polyphase kernels with one output
-        if (poly_supported(w, 1)) {
-          Plan l = base;
+        Plan l = base;
+        const bool lds = poly_supported(w, 1);
+        if (lds) {
           l.fam = Fam::Poly;
           l.win = w;
           l.poly_q = 1;
           l.name = w.ax == 2 ? "fir_cols_lds" : "fir_rows_lds_weights";
+        }
+        // Along columns, windows that overlap or leave gaps (taps != step)
+        // make each lane's taps a strided read that neighbouring lanes
+        // repeat or skip; row segments staged in LDS read every line once
+        // (30 x 1080 x 1920: 13 taps every 8, 116 -> 73 us; 6 every 8,
+        // 102 -> 47 us).  Exact covers stay in registers (8 every 8 off the
+        // 16-byte grid: 43 us against 64 us staged).
+        if (lds && w.ax == 2 && !p.vec4 && w.taps != w.p[2]) {
           cands.push_back(l);
+          cands.push_back(p);
+        } else {
+          cands.push_back(p);
+          if (lds) cands.push_back(l);
         }
       }
       Filter2DProblem fp{};
@@ -741,16 +751,19 @@ PolyArgs poly_args(const Win3& w, int q, int64_t n_rep, bool forward) {
 // ---------------------------------------------------------------------------
 // execution of one planned task
 // ---------------------------------------------------------------------------
-rsm_status exec_run(const rsm_space& rep, const rsm_tiler* in, const void* const* d_in, int n_in,
-                    const rsm_tiler& out, void* d_out, const rsm_task& task, uint32_t flags,
-                    const Checked& c, hipStream_t st, const int32_t* req = nullptr) {
-  Plan p = make_plan(rep, in, n_in, out, task, flags, d_in, c.n_rep, c.n_pat_in[0], req);
-  if (!p.ok) return fail(RSM_E_UNSUPPORTED, "no kernel of this build keeps the ports where requested");
+// Runs a task by a plan made for these descriptors (make_plan; the launch
+// arguments that depend on the arrays' addresses are filled in here).
+rsm_status exec_planned(Plan p, const rsm_space& rep, const rsm_tiler* in, const void* const* d_in, int n_in,
+                        const rsm_tiler& out, void* d_out, const rsm_task& task, const Checked& c,
+                        hipStream_t st) {
   hipError_t e = hipSuccess;
   switch (p.fam) {
     case Fam::Empty:
       return RSM_OK;
     case Fam::Gemm: {
+      // the plan is made once per descriptor: the operands are this call's
+      p.gemm.a = d_in[0];
+      p.gemm.b = d_in[1];
       p.gemm.c = static_cast<float*>(d_out);
       const int compute = in[0].dtype == RSM_BF16 ? RSM_BF16 : RSM_F32;
       e = launch_gemm(p.gemm, compute, st);
@@ -803,7 +816,9 @@ rsm_status exec_run(const rsm_space& rep, const rsm_tiler* in, const void* const
       a.x = static_cast<const float*>(d_in[0]);
       a.y = static_cast<float*>(d_out);
       a.c = task.kind == RSM_TASK_WSUM ? static_cast<const float*>(task.coeffs) : nullptr;
-      e = launch_pattern_reduce(a, p.max_rank, st);
+      PatternReduceSmallArgs sa;
+      e = pattern_reduce_small_args(a, &sa) ? launch_pattern_reduce_small(sa, st)
+                                            : launch_pattern_reduce(a, p.max_rank, st);
       if (e != hipSuccess) return hip_fail(e, "pattern_reduce launch");
       return RSM_OK;
     }
@@ -829,6 +844,95 @@ rsm_status exec_run(const rsm_space& rep, const rsm_tiler* in, const void* const
     }
   }
   return fail(RSM_E_UNSUPPORTED, "no kernel family");
+}
+
+rsm_status exec_run(const rsm_space& rep, const rsm_tiler* in, const void* const* d_in, int n_in,
+                    const rsm_tiler& out, void* d_out, const rsm_task& task, uint32_t flags,
+                    const Checked& c, hipStream_t st, const int32_t* req = nullptr) {
+  const Plan p = make_plan(rep, in, n_in, out, task, flags, d_in, c.n_rep, c.n_pat_in[0], req);
+  if (!p.ok) return fail(RSM_E_UNSUPPORTED, "no kernel of this build keeps the ports where requested");
+  return exec_planned(p, rep, in, d_in, n_in, out, d_out, task, c, st);
+}
+
+// ---------------------------------------------------------------------------
+// plans cached by descriptor
+// ---------------------------------------------------------------------------
+// Validation and planning read only the entries of the descriptors below
+// their ranks, the task's kind and compute type, whether weights are given,
+// the flags, and (for the families that read in place with 16-byte loads)
+// whether each input starts on a 16-byte boundary.  The key lists exactly
+// those; equal keys give the same validation result and the same plan.
+bool descriptor_key(const rsm_space* rep, const rsm_tiler* in, int n_in, const rsm_tiler* out,
+                    const rsm_task* task, uint32_t flags, const void* const* d_in,
+                    std::vector<int64_t>* key) {
+  if (!rep || !in || !out || !task || n_in < 1 || n_in > 2) return false;
+  if (rep->rank < 0 || rep->rank > RSM_MAX_RANK) return false;
+  key->clear();
+  key->push_back(rep->rank);
+  for (int k = 0; k < rep->rank; ++k) key->push_back(rep->shape[k]);
+  key->push_back(n_in);
+  for (int t = 0; t <= n_in; ++t) {
+    const rsm_tiler& x = t < n_in ? in[t] : *out;
+    if (x.array_rank < 0 || x.array_rank > RSM_MAX_RANK || x.pattern_rank < 0 || x.pattern_rank > RSM_MAX_RANK)
+      return false;
+    key->push_back(x.array_rank);
+    key->push_back(x.pattern_rank);
+    key->push_back(x.dtype);
+    for (int k = 0; k < x.pattern_rank; ++k) key->push_back(x.pattern_shape[k]);
+    for (int d = 0; d < x.array_rank; ++d) {
+      key->push_back(x.array_shape[d]);
+      key->push_back(x.origin[d]);
+      for (int k = 0; k < rep->rank; ++k) key->push_back(x.paving[d][k]);
+      for (int k = 0; k < x.pattern_rank; ++k) key->push_back(x.fitting[d][k]);
+    }
+  }
+  int64_t align = 0;
+  for (int t = 0; t < n_in; ++t)
+    if (d_in && (reinterpret_cast<uintptr_t>(d_in[t]) & 15)) align |= int64_t(1) << t;
+  key->push_back(task->kind);
+  key->push_back(task->compute);
+  key->push_back(task->coeffs != nullptr);
+  key->push_back(flags);
+  key->push_back(align);
+  return true;
+}
+
+uint64_t key_hash(const std::vector<int64_t>& key) {
+  uint64_t h = 1469598103934665603ull;   // FNV-1a over the 64-bit words
+  for (int64_t v : key) {
+    h ^= uint64_t(v);
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+struct CachedPlan {
+  uint64_t hash = 0;
+  std::vector<int64_t> key;
+  Checked c;
+  Plan plan;
+};
+
+constexpr int kPlanCache = 32;
+thread_local CachedPlan g_plan_cache[kPlanCache];
+thread_local int g_plan_cache_next = 0;
+thread_local int g_plan_cache_used = 0;
+thread_local uint64_t g_plan_cache_hits = 0;
+
+const CachedPlan* plan_cache_find(const std::vector<int64_t>& key, uint64_t h) {
+  for (int k = 0; k < g_plan_cache_used; ++k)
+    if (g_plan_cache[k].hash == h && g_plan_cache[k].key == key) return &g_plan_cache[k];
+  return nullptr;
+}
+
+void plan_cache_put(const std::vector<int64_t>& key, uint64_t h, const Checked& c, const Plan& p) {
+  CachedPlan& e = g_plan_cache[g_plan_cache_next];
+  g_plan_cache_next = (g_plan_cache_next + 1) % kPlanCache;
+  if (g_plan_cache_used < kPlanCache) ++g_plan_cache_used;
+  e.hash = h;
+  e.key = key;
+  e.c = c;
+  e.plan = p;
 }
 
 // A placement request: one rsm_mem_space (or RSM_MEM_ANY) per port, in port
@@ -1401,15 +1505,111 @@ rsm_status rsm_run(const rsm_space* rep, const rsm_tiler* in, const void* const*
                    const rsm_tiler* out, void* d_out, const rsm_task* task, uint32_t flags,
                    void* hip_stream) {
   RSM_GUARD_BEGIN
+  const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  // a descriptor seen before on this thread skips validation and planning
+  thread_local std::vector<int64_t> key;
+  const bool keyed = descriptor_key(rep, in, n_in, out, task, flags, d_in, &key);
+  const uint64_t h = keyed ? key_hash(key) : 0;
+  if (keyed) {
+    if (const CachedPlan* e = plan_cache_find(key, h)) {
+      ++g_plan_cache_hits;
+      if (e->c.n_rep == 0) return RSM_OK;
+      if (!ptrs_ok(d_in, n_in) || !d_out) return fail(RSM_E_INVALID, "NULL device pointer");
+      return exec_planned(e->plan, *rep, in, d_in, n_in, *out, d_out, *task, e->c, st);
+    }
+  }
   Checked c;
   rsm_status s = check_task(rep, in, n_in, out, task, flags, &c);
   if (s) return s;
-  if (c.n_rep == 0) return RSM_OK;
+  if (c.n_rep == 0) {
+    if (keyed) plan_cache_put(key, h, c, Plan{});
+    return RSM_OK;
+  }
   if (!ptrs_ok(d_in, n_in) || !d_out) return fail(RSM_E_INVALID, "NULL device pointer");
-  return exec_run(*rep, in, d_in, n_in, *out, d_out, *task, flags, c,
-                  static_cast<hipStream_t>(hip_stream));
+  const Plan p = make_plan(*rep, in, n_in, *out, *task, flags, d_in, c.n_rep, c.n_pat_in[0]);
+  if (keyed) plan_cache_put(key, h, c, p);
+  return exec_planned(p, *rep, in, d_in, n_in, *out, d_out, *task, c, st);
   RSM_GUARD_END
 }
+
+uint64_t rsm_plan_cache_hits(void) { return g_plan_cache_hits; }
+
+}  // extern "C"
+
+// A task validated and planned once.  The plan assumes inputs that start on
+// 16-byte boundaries; a call with other addresses plans again for them.
+struct rsm_prepared_s {
+  rsm_space rep;
+  rsm_tiler in[2];
+  int32_t n_in;
+  rsm_tiler out;
+  rsm_task task;
+  uint32_t flags;
+  rsm::Checked c;
+  rsm::Plan plan;
+};
+
+extern "C" {
+
+rsm_status rsm_prepare(const rsm_space* rep, const rsm_tiler* in, int32_t n_in, const rsm_tiler* out,
+                       const rsm_task* task, uint32_t flags, rsm_prepared* handle) {
+  RSM_GUARD_BEGIN
+  if (!handle) return fail(RSM_E_INVALID, "handle pointer is NULL");
+  *handle = nullptr;
+  if (!task) return fail(RSM_E_INVALID, "task is NULL");
+  if (flags & ~uint32_t(RSM_CHECK_SINGLE_ASSIGN | RSM_FORCE_GENERIC))
+    return fail(RSM_E_INVALID, "rsm_prepare takes RSM_CHECK_SINGLE_ASSIGN and RSM_FORCE_GENERIC only");
+  // the weights are given per call: validate as if they were
+  rsm_task tk = *task;
+  tk.coeffs = tk.kind == RSM_TASK_WSUM ? static_cast<const void*>(task) : nullptr;
+  Checked c;
+  rsm_status s = check_task(rep, in, n_in, out, &tk, flags, &c);
+  if (s) return s;
+  rsm_prepared_s* p = new (std::nothrow) rsm_prepared_s();
+  if (!p) return fail(RSM_E_NOMEM, "prepared task");
+  p->rep = *rep;
+  for (int t = 0; t < n_in; ++t) p->in[t] = in[t];
+  p->n_in = n_in;
+  p->out = *out;
+  p->task = *task;
+  p->task.coeffs = nullptr;
+  p->flags = flags & RSM_FORCE_GENERIC;
+  p->c = c;
+  p->plan = make_plan(*rep, in, n_in, *out, tk, flags, nullptr, c.n_rep, c.n_pat_in[0]);
+  *handle = p;
+  return RSM_OK;
+  RSM_GUARD_END
+}
+
+rsm_status rsm_prepared_name(const rsm_prepared_s* handle, char* name, int32_t len) {
+  RSM_GUARD_BEGIN
+  if (!handle) return fail(RSM_E_INVALID, "handle is NULL");
+  if (!name || len <= 0) return fail(RSM_E_INVALID, "name buffer is NULL");
+  std::snprintf(name, size_t(len), "%s", handle->plan.name.c_str());
+  return RSM_OK;
+  RSM_GUARD_END
+}
+
+rsm_status rsm_run_prepared(const rsm_prepared_s* h, const void* const* d_in, void* d_out,
+                            const void* d_coeffs, void* hip_stream) {
+  RSM_GUARD_BEGIN
+  if (!h) return fail(RSM_E_INVALID, "handle is NULL");
+  if (h->c.n_rep == 0) return RSM_OK;
+  if (!ptrs_ok(d_in, h->n_in) || !d_out) return fail(RSM_E_INVALID, "NULL device pointer");
+  rsm_task tk = h->task;
+  if (tk.kind == RSM_TASK_WSUM) {
+    if (!d_coeffs) return fail(RSM_E_INVALID, "WSUM needs coefficients");
+    tk.coeffs = d_coeffs;
+  }
+  const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  bool aligned = true;
+  for (int t = 0; t < h->n_in; ++t) aligned = aligned && !(reinterpret_cast<uintptr_t>(d_in[t]) & 15);
+  if (aligned) return exec_planned(h->plan, h->rep, h->in, d_in, h->n_in, h->out, d_out, tk, h->c, st);
+  return exec_run(h->rep, h->in, d_in, h->n_in, h->out, d_out, tk, h->flags, h->c, st);
+  RSM_GUARD_END
+}
+
+void rsm_prepared_destroy(rsm_prepared_s* handle) { delete handle; }
 
 namespace rsm {
 namespace {

@@ -423,6 +423,94 @@ __global__ void zero_bytes_kernel(uint8_t* p, int64_t n) {
   if (i < n) p[i] = 0;
 }
 
+// pattern_reduce in 32-bit arithmetic (conditions in PatternReduceSmallArgs):
+// one lane per pattern element, groups of 2^group_log2 lanes per repetition
+// summed by a butterfly of shuffles, as pattern_reduce_kernel (k_window.hip)
+// does in 64-bit arithmetic; the index walk uses multiply-high divisions.
+__device__ __forceinline__ uint32_t fmod32(uint32_t n, const FastDiv& f) { return n - fdiv(n, f) * f.d; }
+
+__global__ void __launch_bounds__(kBlock) pattern_reduce_small_kernel(PatternReduceSmallArgs a) {
+  const int G = 1 << a.group_log2;
+  const int lane = threadIdx.x & (G - 1);
+  const uint32_t groups_total = (gridDim.x * kBlock) >> a.group_log2;
+  const uint32_t group0 = (blockIdx.x * kBlock + threadIdx.x) >> a.group_log2;
+
+  // this lane's pattern element and its offset (F i) mod s per dimension
+  uint32_t off[4] = {0, 0, 0, 0};
+  {
+    uint32_t i[4] = {0, 0, 0, 0};
+    uint32_t f = uint32_t(lane);
+#pragma unroll
+    for (int k = 3; k >= 0; --k)
+      if (k < a.pat_rank) {
+        i[k] = f % a.pat_s[k];
+        f /= a.pat_s[k];
+      }
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+      if (d < a.in_rank) {
+        uint64_t v = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (k < a.pat_rank) v += uint64_t(a.in_f[d][k]) * i[k];
+        off[d] = uint32_t(v % a.in_s[d]);
+      }
+  }
+  const bool active = lane < a.n_pat;
+  const float coef = (active && a.c) ? a.c[lane] : 1.0f;
+
+  for (uint32_t rf = group0; rf < a.n_rep; rf += groups_total) {
+    uint32_t r[4] = {0, 0, 0, 0};
+    {
+      uint32_t f = rf;
+#pragma unroll
+      for (int k = 3; k >= 0; --k)
+        if (k < a.rep_rank) {
+          const uint32_t q = fdiv(f, a.rep_div[k]);
+          r[k] = f - q * a.rep_div[k].d;
+          f = q;
+        }
+    }
+    float v = 0.0f;
+    if (active) {
+      uint32_t lin = 0;
+#pragma unroll
+      for (int d = 0; d < 4; ++d)
+        if (d < a.in_rank) {
+          const uint32_t s = a.in_s[d];
+          uint32_t c = a.in_o[d] + off[d];
+          if (c >= s) c -= s;
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (k < a.rep_rank) {
+              c += fmod32(a.in_p[d][k] * r[k], a.in_div[d]);
+              if (c >= s) c -= s;
+            }
+          lin = lin * s + c;
+        }
+      v = a.x[lin] * coef;
+    }
+    for (int m = G >> 1; m > 0; m >>= 1) v += __shfl_xor(v, m);
+    if (lane == 0) {
+      uint32_t lin = 0;
+#pragma unroll
+      for (int d = 0; d < 4; ++d)
+        if (d < a.out_rank) {
+          const uint32_t s = a.out_s[d];
+          uint32_t c = a.out_o[d];
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (k < a.rep_rank) {
+              c += fmod32(a.out_p[d][k] * r[k], a.out_div[d]);
+              if (c >= s) c -= s;
+            }
+          lin = lin * s + c;
+        }
+      a.y[lin] = v;
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_indices(const GTiler& t, int rep_rank, const int64_t* rep_shape, int64_t n_rep,
@@ -509,6 +597,61 @@ hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st) {
   } else {
     zero_bytes_kernel<<<unsigned((bytes + 255) / 256), 256, 0, st>>>(static_cast<uint8_t*>(p), bytes);
   }
+  return hipGetLastError();
+}
+
+bool pattern_reduce_small_args(const PatternReduceArgs& a, PatternReduceSmallArgs* s) {
+  const int64_t kMax31 = (int64_t(1) << 31) - 1;
+  if (a.rep_rank > 4 || a.in.arr_rank > 4 || a.in.pat_rank > 4 || a.out.arr_rank > 4) return false;
+  if (a.n_rep > kMax31 || a.n_pat > 64) return false;
+  // the launch covers n_rep << group_log2 lanes; keep the counters in 32 bits
+  if ((a.n_rep << a.group_log2) > kMax31) return false;
+  int64_t n_in = 1, n_out = 1;
+  for (int d = 0; d < a.in.arr_rank; ++d) n_in *= a.in.shape[d];
+  for (int d = 0; d < a.out.arr_rank; ++d) n_out *= a.out.shape[d];
+  if (n_in > kMax31 || n_out > kMax31) return false;
+  *s = PatternReduceSmallArgs{};
+  s->n_rep = uint32_t(a.n_rep);
+  s->rep_rank = a.rep_rank;
+  s->group_log2 = a.group_log2;
+  s->n_pat = int32_t(a.n_pat);
+  for (int k = 0; k < 4; ++k) s->rep_div[k] = make_fastdiv(uint32_t(k < a.rep_rank ? a.rep_shape[k] : 1));
+  s->in_rank = a.in.arr_rank;
+  s->pat_rank = a.in.pat_rank;
+  s->out_rank = a.out.arr_rank;
+  const uint64_t kMax32 = uint64_t(1) << 32;
+  for (int d = 0; d < 4; ++d) {
+    const bool di = d < a.in.arr_rank, dout = d < a.out.arr_rank;
+    s->in_s[d] = uint32_t(di ? a.in.shape[d] : 1);
+    s->in_o[d] = uint32_t(di ? a.in.origin[d] : 0);
+    s->in_div[d] = make_fastdiv(s->in_s[d]);
+    s->out_s[d] = uint32_t(dout ? a.out.shape[d] : 1);
+    s->out_o[d] = uint32_t(dout ? a.out.origin[d] : 0);
+    s->out_div[d] = make_fastdiv(s->out_s[d]);
+    s->pat_s[d] = uint32_t(d < a.in.pat_rank ? a.in.pat_shape[d] : 1);
+    for (int k = 0; k < 4; ++k) {
+      s->in_p[d][k] = uint32_t(di && k < a.rep_rank ? a.in.pav[d][k] : 0);
+      s->in_f[d][k] = uint32_t(di && k < a.in.pat_rank ? a.in.fit[d][k] : 0);
+      s->out_p[d][k] = uint32_t(dout && k < a.rep_rank ? a.out.pav[d][k] : 0);
+      // reduced steps times repetition indices must stay below 2^32
+      if (k < a.rep_rank) {
+        const uint64_t rk = uint64_t(a.rep_shape[k]);
+        if (uint64_t(s->in_p[d][k]) * rk >= kMax32 || uint64_t(s->out_p[d][k]) * rk >= kMax32) return false;
+      }
+    }
+  }
+  s->x = a.x;
+  s->y = a.y;
+  s->c = a.c;
+  return true;
+}
+
+hipError_t launch_pattern_reduce_small(const PatternReduceSmallArgs& a, hipStream_t st) {
+  const int64_t lanes = int64_t(a.n_rep) << a.group_log2;
+  int64_t grid = (lanes + kBlock - 1) / kBlock;
+  if (grid < 1) grid = 1;
+  if (grid > 16384) grid = 16384;
+  pattern_reduce_small_kernel<<<unsigned(grid), kBlock, 0, st>>>(a);
   return hipGetLastError();
 }
 

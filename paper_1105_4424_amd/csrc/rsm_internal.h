@@ -253,6 +253,26 @@ struct PatternReduceArgs {
   const float* c;      // nullable (SUM)
 };
 
+// pattern_reduce in 32-bit arithmetic for ranks <= 4: every array below 2^31
+// elements and every product P[d][k] r_k (reduced P) below 2^32, so the
+// walk reduces each product with a multiply-high division.  The arguments
+// are a fifth of PatternReduceArgs, which shortens the launch of a small task.
+struct PatternReduceSmallArgs {
+  uint32_t n_rep;
+  int32_t rep_rank;
+  int32_t group_log2;
+  int32_t n_pat;
+  FastDiv rep_div[4];      // by rep_shape[k]
+  int32_t in_rank, pat_rank, out_rank, pad0;
+  uint32_t in_s[4], in_o[4], in_p[4][4], in_f[4][4], pat_s[4];
+  FastDiv in_div[4];
+  uint32_t out_s[4], out_o[4], out_p[4][4];
+  FastDiv out_div[4];
+  const float* x;
+  float* y;
+  const float* c;      // nullable (SUM)
+};
+
 // Generic adjoint: gx by atomic scatter-add, weight gradient by partials.
 struct GenericAdjArgs {
   int32_t rep_rank;
@@ -367,6 +387,10 @@ hipError_t launch_indices(const GTiler& t, int rep_rank, const int64_t* rep_shap
 hipError_t launch_generic(const GenericArgs& a, int max_rank, int in_dtype, int out_dtype,
                           int kind, int elem_bytes, hipStream_t st);
 hipError_t launch_pattern_reduce(const PatternReduceArgs& a, int max_rank, hipStream_t st);
+// The 32-bit form of the same kernel when the task fits it (false: use
+// launch_pattern_reduce).
+bool pattern_reduce_small_args(const PatternReduceArgs& a, PatternReduceSmallArgs* s);
+hipError_t launch_pattern_reduce_small(const PatternReduceSmallArgs& a, hipStream_t st);
 hipError_t launch_fir(const FirArgs& a, bool vec4, hipStream_t st);
 hipError_t launch_fir_chain(const FirChainArgs& a, bool vec4, hipStream_t st);
 hipError_t launch_fir_adjoint(const FirAdjArgs& a, bool vec4, int* grid_out, hipStream_t st);

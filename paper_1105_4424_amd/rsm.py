@@ -242,6 +242,67 @@ def run(problem, inputs: List[torch.Tensor], out: torch.Tensor, coeffs: torch.Te
     return out
 
 
+def plan_cache_hits() -> int:
+    """rsm_run calls on this thread launched from a kept plan (no validation
+    or planning on the host)."""
+    return int(_abi.load().rsm_plan_cache_hits())
+
+
+class Prepared:
+    """One task validated and planned once (rsm_prepare); run() passes only
+    the arrays' addresses and the stream.  `dtypes` are the input arrays'
+    dtypes (the output's follows from the task)."""
+
+    def __init__(self, problem, dtypes: Sequence[torch.dtype] = (torch.float32,), flags: int = 0,
+                 compute: str = None):
+        lib = _abi.load()
+        n = len(problem.inputs)
+        self.in_dtypes = [dtypes[min(k, len(dtypes) - 1)] for k in range(n)]
+        codes = [_DTYPES[d] for d in self.in_dtypes]
+        tin = (_abi.Tiler * n)(*[_tiler(t, c) for t, c in zip(problem.inputs, codes)])
+        c0 = codes[0]
+        out_code = c0 if problem.task == _abi.TASK_COPY else (_abi.F64 if c0 == _abi.F64 else _abi.F32)
+        self.out_dtype = {v: k for k, v in _DTYPES.items()}[out_code]
+        comp = _COMPUTE[compute] if compute else (_abi.F64 if c0 == _abi.F64 else
+                                                  _COMPUTE.get(getattr(problem, "compute", "f32")))
+        task = _abi.Task(problem.task, comp, None)
+        h = ctypes.c_void_p()
+        _check(lib.rsm_prepare(ctypes.byref(_space(problem.rep_shape)), tin, n,
+                               ctypes.byref(_tiler(problem.output, out_code)), ctypes.byref(task), flags,
+                               ctypes.byref(h)))
+        self._lib, self._h, self.n_in = lib, h, n
+        self._ptrs = (ctypes.c_void_p * n)()
+        buf = ctypes.create_string_buffer(64)
+        _check(lib.rsm_prepared_name(h, buf, 64))
+        self.name = buf.value.decode()
+
+    def run(self, inputs: List[torch.Tensor], out: torch.Tensor, coeffs: torch.Tensor = None,
+            stream=None) -> torch.Tensor:
+        if self._h is None:
+            raise RuntimeError("prepared task is closed")
+        if len(inputs) != self.n_in:
+            raise ValueError("expected %d input arrays" % self.n_in)
+        for k, x in enumerate(inputs):
+            if x.dtype != self.in_dtypes[k]:
+                raise TypeError("input %d is %s, prepared for %s" % (k, x.dtype, self.in_dtypes[k]))
+            self._ptrs[k] = _ptr(x).value
+        if out.dtype != self.out_dtype:
+            raise TypeError("output is %s, prepared for %s" % (out.dtype, self.out_dtype))
+        _check(self._lib.rsm_run_prepared(self._h, self._ptrs, _ptr(out), _ptr(coeffs), _stream(stream)))
+        return out
+
+    def close(self):
+        if self._h is not None:
+            self._lib.rsm_prepared_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def _stages(stages, coeffs, x_dtype=torch.float32):
     n = len(stages)
     arr = (_abi.Stage * n)()

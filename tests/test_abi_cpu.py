@@ -115,7 +115,12 @@ def test_planner_routes_workloads_to_their_kernels():
     assert rsm.plan(ts.v) == "fir_rows"
     assert rsm.plan(ts.h, flags=_abi.FORCE_GENERIC) == "generic"
     tw = W.two_stage_filter(frames=1, rows=8, cols=40, taps=13, pave=8, h_origin=-6)
-    assert rsm.plan(tw.h) == "fir_cols"
+    assert rsm.plan(tw.h) == "fir_cols_lds"      # overlapping windows: row segments in LDS
+    tg = W.two_stage_filter(frames=1, rows=8, cols=40, taps=6, pave=8, h_origin=2)
+    assert rsm.plan(tg.h) == "fir_cols_lds"      # gaps between windows
+    te = W.two_stage_filter(frames=1, rows=8, cols=40, taps=8, pave=8, h_origin=-3)
+    assert rsm.plan(te.h) == "fir_cols"          # exact cover off the 16-byte grid: registers
+    assert rsm.plan_placed(tw.h, ["private", "any", "any"])[0] == "fir_cols"
     import torch
     mm = W.matmul_tilers(256, 256, 256)
     mm.compute = "bf16"
@@ -294,3 +299,84 @@ def test_placement_request_routes_the_kernel_family():
     assert P(pp.h, ["local", "local", "local"])[0] == "polyphase_cols"
     assert P(pp.h, ["global", "any", "any"])[0] == "generic"
     assert P(pp.v, ["private", "global", "local"])[0] == "polyphase_rows"
+
+
+def _raw(problem, dtype=_abi.F32):
+    """ctypes descriptors of a problem with FP32 arrays."""
+    n = len(problem.inputs)
+    tin = (_abi.Tiler * n)(*[rsm._tiler(t, dtype) for t in problem.inputs])
+    return rsm._space(problem.rep_shape), tin, n, rsm._tiler(problem.output, _abi.F32)
+
+
+def test_prepared_task_plans_once_on_the_host():
+    lib = _abi.load()
+    ts = W.two_stage_filter(frames=2, rows=16, cols=32)
+    for prob, fam in ((ts.h, "fir_cols_vec4"), (ts.v, "fir_rows"), (W.small_sum()[1], "pattern_reduce")):
+        assert rsm.Prepared(prob).name == fam == rsm.plan(prob)
+    assert rsm.Prepared(ts.h, flags=_abi.FORCE_GENERIC).name == "generic"
+    # weights are given per call: a WSUM task prepares without them
+    rep, tin, n, out = _raw(ts.h)
+    h = ctypes.c_void_p()
+    task = _abi.Task(_abi.TASK_WSUM, _abi.F32, None)
+    assert lib.rsm_prepare(ctypes.byref(rep), tin, n, ctypes.byref(out), ctypes.byref(task), 0,
+                           ctypes.byref(h)) == _abi.OK and h.value
+    # ... and refuses a call without them, before any launch
+    ptrs = (ctypes.c_void_p * 1)(16)
+    assert lib.rsm_run_prepared(h, ptrs, ctypes.c_void_p(16), None, None) == _abi.E_INVALID
+    assert b"coefficients" in lib.rsm_last_error()
+    lib.rsm_prepared_destroy(h)
+    lib.rsm_prepared_destroy(None)
+    # flags other than the single-assignment check and the generic kernel
+    for f in (_abi.ACCUMULATE, _abi.NO_FUSE, _abi.PLAN_ADJOINT, 0x1000):
+        h = ctypes.c_void_p(7)
+        assert lib.rsm_prepare(ctypes.byref(rep), tin, n, ctypes.byref(out), ctypes.byref(task), f,
+                               ctypes.byref(h)) == _abi.E_INVALID
+        assert not h.value
+    # invalid descriptors fail as rsm_run does, with no handle
+    bad = W.Problem((4,), [W.Tiler((0,), [0], [[1]], [[1]], (2,))], W.identity_output((4,)), W.SUM)
+    _expect("RSM_E_SHAPE", lambda: rsm.Prepared(bad))
+    t = W.Tiler((6,), [0], [[1]], np.zeros((1, 0)), ())
+    collide = W.Problem((6,), [t], W.Tiler((3,), [0], [[1]], np.zeros((1, 0)), ()), W.COPY)
+    rsm.Prepared(collide)
+    _expect("RSM_E_OVERLAP", lambda: rsm.Prepared(collide, flags=_abi.CHECK_SINGLE_ASSIGN))
+    assert lib.rsm_run_prepared(None, ptrs, ctypes.c_void_p(16), None, None) == _abi.E_INVALID
+
+
+def test_run_keeps_plans_by_descriptor():
+    # an empty repetition space runs nothing, so rsm_run returns on the host
+    # and the cache can be watched without a GPU
+    lib = _abi.load()
+    t = W.Tiler((8,), [0], [[1]], [[1]], (2,))
+    p = W.Problem((0,), [t], W.Tiler((1,), [0], [[1]], np.zeros((1, 0)), ()), W.SUM)
+    rep, tin, n, out = _raw(p)
+    task = _abi.Task(_abi.TASK_SUM, _abi.F32, None)
+    ptrs = (ctypes.c_void_p * 1)(None)
+
+    def call(rep=rep, tin=tin, out=out, flags=0):
+        return lib.rsm_run(ctypes.byref(rep), tin, ptrs, n, ctypes.byref(out), None, ctypes.byref(task), flags,
+                           None)
+
+    h0 = lib.rsm_plan_cache_hits()
+    assert call() == _abi.OK
+    assert call() == _abi.OK and call() == _abi.OK
+    assert lib.rsm_plan_cache_hits() == h0 + 2
+    # another origin, other flags: new entries, not hits
+    tin2 = (_abi.Tiler * 1)(rsm._tiler(W.Tiler((8,), [1], [[1]], [[1]], (2,)), _abi.F32))
+    assert call(tin=tin2) == _abi.OK and call(flags=_abi.CHECK_SINGLE_ASSIGN) == _abi.OK
+    assert lib.rsm_plan_cache_hits() == h0 + 2
+    # entries beyond the pattern rank are not part of the descriptor
+    tin3 = (_abi.Tiler * 1)(rsm._tiler(t, _abi.F32))
+    tin3[0].fitting[0][5] = 99
+    assert call(tin=tin3) == _abi.OK
+    assert lib.rsm_plan_cache_hits() == h0 + 3
+    # a failing descriptor is never kept: it fails every time
+    tin4 = (_abi.Tiler * 1)(rsm._tiler(t, _abi.F32))
+    tin4[0].array_shape[0] = 0
+    assert call(tin=tin4) == _abi.E_SHAPE and call(tin=tin4) == _abi.E_SHAPE
+    assert lib.rsm_plan_cache_hits() == h0 + 3
+    # the cache holds 32 descriptors: after 40 others the first is planned again
+    for k in range(40):
+        assert call(tin=(_abi.Tiler * 1)(rsm._tiler(W.Tiler((8,), [k + 2], [[1]], [[1]], (2,)), _abi.F32))) == 0
+    h1 = lib.rsm_plan_cache_hits()
+    assert call() == _abi.OK and lib.rsm_plan_cache_hits() == h1
+    assert call() == _abi.OK and lib.rsm_plan_cache_hits() == h1 + 1

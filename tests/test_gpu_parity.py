@@ -313,3 +313,22 @@ def test_pattern_reduce_ragged_and_wrapping():
     rsm.run(p2, [dev(x2)], out2)
     r2 = oracle.run(p2, [x2])
     check_close(host(out2), r2.out, r2.abs_sum, what="pattern_reduce transposed out")
+
+
+def test_pattern_reduce_rank5_walk():
+    # five repetition dimensions: past the 32-bit form's rank 4, so the
+    # kernel walks the tilers in 64-bit arithmetic; wrapping origins
+    rng = W.rng_for(88)
+    F = np.zeros((5, 2), dtype=np.int64)
+    F[3, 0] = 1
+    F[4, 1] = 1
+    t = W.Tiler((6, 5, 4, 3, 8), [1, -2, 0, 1, -3], np.diag([1, 1, 1, 1, 2]), F, (2, 4))
+    rep = (6, 5, 4, 3, 4)
+    c = rng.uniform(-1, 1, (2, 4)).astype(np.float32)
+    p = W.Problem(rep, [t], W.identity_output(rep), W.WSUM, c)
+    assert rsm.plan(p) == "pattern_reduce"
+    x = W.random_array(rng, t.array_shape)
+    out = torch.full(rep, float("nan"), device="cuda")
+    rsm.run(p, [dev(x)], out, coeffs=dev(c))
+    r = oracle.run(p, [x])
+    check_close(host(out), r.out, r.abs_sum, what="pattern_reduce rank 5")
