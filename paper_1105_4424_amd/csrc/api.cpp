@@ -1310,6 +1310,8 @@ bool plan_filter2d(const rsm_space& rep, const rsm_tiler& in, const rsm_tiler& o
   if (w.taps != w.taps2 || w.p[1] != w.p[2] || !filter2d_supported(w.taps, w.p[1])) return false;
   // identity along frames
   if (w.o[0] != 0 || w.rep[0] != w.A[0] || (w.A[0] > 1 && w.p[0] != 1)) return false;
+  // each frame is addressed as one buffer of 32-bit byte offsets
+  if (int64_t(w.A[1]) * w.A[2] * 4 >= (int64_t(1) << 31)) return false;
   *fp = Filter2DProblem{};
   fp->H = w.A[1];
   fp->W = w.A[2];

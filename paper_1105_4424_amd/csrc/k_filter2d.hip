@@ -29,6 +29,8 @@ namespace rsm {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr uint32_t kRawBuffer = 0x00020000;   // buffer resource word 3: 32-bit data, raw access
+constexpr uint32_t kOutOfRange = 0x80000000u;  // a byte offset past every buffer here (< 2 GiB)
 
 __host__ __device__ constexpr int rx_of(int S) { return 4 / S; }
 __host__ __device__ constexpr int seg_of(int K, int S) { return (rx_of(S) - 1) * S + K; }
@@ -48,15 +50,13 @@ __host__ __device__ constexpr int lds_floats(int K, int S, int RY) {
   return lds_rows(K, S, RY) * lds_pitch(K, S) + kWPitch * K;
 }
 
-// The problem's arrays live in device global memory.  Their pointers come
-// out of a descriptor read from memory, so without these casts the compiler
-// addresses them as generic ("flat") memory, whose accesses count against
-// the LDS wait counter too: every LDS read of a tile would then also wait
-// for the tile's outstanding global loads and stores.
-typedef __attribute__((address_space(1))) float gfloat;
+// The weights live in device global memory.  Their pointer comes out of a
+// descriptor read from memory, so without this cast the compiler addresses
+// them as generic ("flat") memory, whose accesses count against the LDS wait
+// counter too: LDS reads would then also wait for that load.  (The input
+// and output arrays are read and written through buffer resources.)
 typedef __attribute__((address_space(1))) const float gcfloat;
 __device__ __forceinline__ gcfloat* global_in(const float* p) { return (gcfloat*)(p); }
-__device__ __forceinline__ gfloat* global_out(float* p) { return (gfloat*)(p); }
 
 __device__ __forceinline__ int mod_pos(int v, int n) {
   // v >= 0 here; reduce into [0, n)
@@ -80,7 +80,6 @@ __device__ __forceinline__ void compute_tile(const Filter2DProblem& p, int64_t l
   constexpr int SEG4 = seg4_of(K, S);
   int frame, ty, tx;
   tile_pos(p, local, &frame, &ty, &tx);
-  gfloat* __restrict__ y = global_out(p.y) + int64_t(frame) * p.RH * p.RW;
   const float* lw = lds + LR * LP;
   const int t = threadIdx.x;
   const int tr = t >> 4, tc = t & 15;
@@ -114,15 +113,20 @@ __device__ __forceinline__ void compute_tile(const Filter2DProblem& p, int64_t l
         for (int dx = 0; dx < K; ++dx) acc[i][j] = fmaf(w[dx], seg[j * S + dx], acc[i][j]);
     }
   }
+  // the frame's outputs as a raw buffer: an output past the array's edge
+  // gets an offset past the buffer's end, and the hardware drops that store
+  // (no branch per output)
+  const __amdgpu_buffer_rsrc_t ry = __builtin_amdgcn_make_buffer_rsrc(
+      p.y + int64_t(frame) * p.RH * p.RW, short(0), p.RH * p.RW * 4, int(kRawBuffer));
   const int oy0 = ty * TH + tr * RY, ox0 = tx * TW + tc * RX;
 #pragma unroll
   for (int i = 0; i < RY; ++i) {
     const int oy = oy0 + i;
-    if (oy >= p.RH) break;
 #pragma unroll
     for (int j = 0; j < RX; ++j) {
       const int ox = ox0 + j;
-      if (ox < p.RW) y[int64_t(oy) * p.RW + ox] = acc[i][j];
+      const uint32_t off = (oy < p.RH && ox < p.RW) ? uint32_t(oy * p.RW + ox) * 4u : kOutOfRange;
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, acc[i][j]), ry, off, 0, 0);
     }
   }
 }
@@ -136,13 +140,11 @@ __device__ __forceinline__ void filter_tile(const Filter2DProblem p, int64_t loc
 
   int frame, ty, tx;
   tile_pos(p, local, &frame, &ty, &tx);
-  gcfloat* __restrict__ x = global_in(p.x) + int64_t(frame) * p.H * p.W;
 
   // ---- stage the tile's input region, wrapping modulo the array shape ----
-  // Thread (rq, lane) stages rows rq, rq + 4, ... at columns lane and
-  // lane + 64: successive elements are a constant stride apart, so addresses
-  // are plain adds.  Rows go out in chunks of CR, all loads of a chunk issued
-  // before any is consumed.
+  // Wave rq stages rows rq, rq + 4, ... with lane l at columns l and l + 64.
+  // Rows go out in chunks of CR, all loads of a chunk issued before any is
+  // consumed.
   constexpr int NR = (LR + 3) / 4;          // rows per row group
   constexpr int NC = (LC + 63) / 64;        // column passes (1 or 2)
   constexpr int CR = NR < 8 ? NR : 8;       // rows per chunk
@@ -150,9 +152,19 @@ __device__ __forceinline__ void filter_tile(const Filter2DProblem p, int64_t loc
   const int iy0 = p.oh + ty * TH * S;   // >= 0 (origin stored reduced)
   const int ix0 = p.ow + tx * TW * S;
   const int t = threadIdx.x;
-  const int lane = t & 63, rq = t >> 6;
+  const int lane = t & 63;
+  // the wave's row group: the same on every lane, so the row walk below
+  // (row indices, wrapping, row base addresses, the row bound) runs on the
+  // scalar unit and each load takes a scalar base plus a 32-bit lane offset
+  const int rq = __builtin_amdgcn_readfirstlane(t >> 6);
   const bool interior = iy0 + LR <= p.H && ix0 + LC <= p.W;
   float* ldst = lds + rq * LP + lane;
+  // lanes past the region's last column load its last element instead (same
+  // cache lines) and store nothing
+  const bool col0 = LC >= 64 || lane < LC;
+  const bool col1 = NC > 1 && lane + 64 < LC;
+  const int l0 = col0 ? lane : LC - 1;
+  const int l1 = col1 ? lane + 64 : LC - 1;
   // weights: thread t < K*K fetches one with the tile's input (the compiler
   // cannot prove the weights unaliased by the output, so reading them from
   // memory inside the window loop would cost a global round trip per row)
@@ -162,51 +174,45 @@ __device__ __forceinline__ void filter_tile(const Filter2DProblem p, int64_t loc
   // them it outranks the waves of other workgroups on the CU that are
   // computing (the batch runs about 7 % faster)
   __builtin_amdgcn_s_setprio(2);
+  // The frame is read as a raw buffer (frames under 2 GiB, a planner
+  // condition): a load takes the row's byte offset in a scalar register and
+  // the lane's in a 32-bit vector register, with no 64-bit address arithmetic.
+  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(p.x + int64_t(frame) * p.H * p.W), short(0), p.H * p.W * 4, int(kRawBuffer));
+  uint32_t c0, c1;
+  int rowi;   // array row of the wave's next region row (border tiles)
   if (interior) {
-    gcfloat* src = x + int64_t(iy0 + rq) * p.W + ix0 + lane;
-    const int64_t step = 4 * int64_t(p.W);
+    c0 = uint32_t(ix0 + l0) * 4u;
+    c1 = uint32_t(ix0 + l1) * 4u;
+    rowi = iy0 + rq;
+  } else {
+    c0 = uint32_t(mod_pos(ix0 + l0, p.W)) * 4u;
+    c1 = uint32_t(mod_pos(ix0 + l1, p.W)) * 4u;
+    rowi = mod_pos(iy0 + rq, p.H);
+  }
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) {
-      float v[CR][NC];
+  for (int ch = 0; ch < NCH; ++ch) {
+    float v[CR][NC];
 #pragma unroll
-      for (int i = 0; i < CR; ++i) {
-        const int r = rq + 4 * (ch * CR + i);
-#pragma unroll
-        for (int u = 0; u < NC; ++u)
-          v[i][u] = (r < LR && lane + 64 * u < LC) ? src[64 * u] : 0.0f;
-        src += step;
-      }
-      if (ch == 0) __syncthreads();  // the previous tile's readers are done with LDS
-#pragma unroll
-      for (int i = 0; i < CR; ++i) {
-        const int r = rq + 4 * (ch * CR + i);
-#pragma unroll
-        for (int u = 0; u < NC; ++u)
-          if (r < LR && lane + 64 * u < LC) ldst[4 * (ch * CR + i) * LP + 64 * u] = v[i][u];
+    for (int i = 0; i < CR; ++i) {
+      const int r = rq + 4 * (ch * CR + i);
+      if (r < LR) {
+        const int rowb = rowi * p.W * 4;
+        v[i][0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, c0, rowb, 0));
+        if (NC > 1) v[i][NC - 1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, c1, rowb, 0));
+        // next row of this wave: 4 further, wrapped (border tiles only)
+        rowi += 4;
+        if (!interior)
+          while (rowi >= p.H) rowi -= p.H;
       }
     }
-  } else {
-    int gcol[NC];
+    if (ch == 0) __syncthreads();  // the previous tile's readers are done with LDS
 #pragma unroll
-    for (int u = 0; u < NC; ++u) gcol[u] = mod_pos(ix0 + lane + 64 * u, p.W);
-#pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) {
-      float v[CR][NC];
-#pragma unroll
-      for (int i = 0; i < CR; ++i) {
-        const int r = rq + 4 * (ch * CR + i);
-        gcfloat* row = x + int64_t(mod_pos(iy0 + r, p.H)) * p.W;
-#pragma unroll
-        for (int u = 0; u < NC; ++u)
-          v[i][u] = (r < LR && lane + 64 * u < LC) ? row[gcol[u]] : 0.0f;
-      }
-      if (ch == 0) __syncthreads();  // the previous tile's readers are done with LDS
-#pragma unroll
-      for (int i = 0; i < CR; ++i) {
-        const int r = rq + 4 * (ch * CR + i);
-#pragma unroll
-        for (int u = 0; u < NC; ++u)
-          if (r < LR && lane + 64 * u < LC) ldst[4 * (ch * CR + i) * LP + 64 * u] = v[i][u];
+    for (int i = 0; i < CR; ++i) {
+      const int r = rq + 4 * (ch * CR + i);
+      if (r < LR) {
+        if (col0) ldst[4 * (ch * CR + i) * LP] = v[i][0];
+        if (NC > 1 && col1) ldst[4 * (ch * CR + i) * LP + 64] = v[i][NC - 1];
       }
     }
   }
