@@ -1054,7 +1054,8 @@ size_t adjoint_ws_bytes(const AdjPlan& ap, int64_t n_rep, int64_t n_pat, int64_t
   if (ap.poly && poly_gc_supported(ap.w, ap.q))
     return size_t(poly_gc_grid(uint32_t(n_rep))) * size_t(ap.q) * size_t(ap.w.taps) * sizeof(float);
   if (ap.overlap_cols)
-    return size_t(fir_overlap_cols_grid(uint32_t(overlap_items(ap.w)))) * size_t(ap.w.taps) * sizeof(float);
+    return size_t(fir_overlap_cols_grid(uint32_t(overlap_items(ap.w)), ap.w.p[2])) * size_t(ap.w.taps) *
+           sizeof(float);
   if (ap.fir) {
     FirAdjArgs tmp{};
     tmp.n_rep = uint32_t(n_rep);
@@ -1169,7 +1170,7 @@ rsm_status exec_adjoint(const rsm_space& rep, const rsm_tiler& in, const void* d
     o.accumulate = accumulate;
     if ((e = launch_fir_adjoint_overlap_cols(o, st)) != hipSuccess) return hip_fail(e, "fir overlap adjoint");
     if (d_gc &&
-        (e = launch_reduce_partials(o.partial, fir_overlap_cols_grid(o.n_items), w.taps, w.taps,
+        (e = launch_reduce_partials(o.partial, fir_overlap_cols_grid(o.n_items, w.p[2]), w.taps, w.taps,
                                     static_cast<float*>(d_gc), accumulate, st)) != hipSuccess)
       return hip_fail(e, "weight-gradient reduction");
     return RSM_OK;

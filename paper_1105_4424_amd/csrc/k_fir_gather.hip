@@ -16,6 +16,11 @@
 // of p_d below p_d rep_d.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <mutex>
+#include <utility>
+#include <vector>
+
 #include "rsm_internal.h"
 
 namespace rsm {
@@ -135,9 +140,13 @@ __device__ __forceinline__ void overlap_fetch_gy(const FirOverlapArgs& a, int ch
 
 // KS: taps per lift K as a compile-time constant (1..4), or 0 for any K.
 // GC: the weight gradient is wanted (a.partial set).
-template <bool ACC, int KS, bool GC>
+// KP: positions per lane per item, 8 when the step p is at most 8 (else 16):
+// a form sized for 16 keeps 16 x values and 16 guarded loads per item where
+// 8 are used (13 taps every 8 columns on 30 x 1080 x 1920: 128 -> 113 us,
+// with the first-lift taps of a fixed tap count held in registers).
+template <bool ACC, int KS, bool GC, int KP>
 // at most 80 registers: six waves per SIMD instead of five (127-132 us
-// against 132-136 us for 13 taps every 8 columns on 30 x 1080 x 1920)
+// against 132-136 us for the same workload, when every form held 16)
 __global__ void __launch_bounds__(kBlock, 6) fir_adjoint_overlap_cols_kernel(FirOverlapArgs a) {
   const Win3& w = a.w;
   const int A2 = w.A[2], R = w.rep[2], p = w.p[2], T = w.taps;
@@ -155,6 +164,13 @@ __global__ void __launch_bounds__(kBlock, 6) fir_adjoint_overlap_cols_kernel(Fir
   const int t = int(threadIdx.x);
   if (t < 2 * kMaxTaps) cs[t] = t < T ? a.c[t] : 0.0f;
   const int jph = t % p;                     // this lane's position phase
+  __syncthreads();
+  // every position of this lane has phase jph: its first-lift taps are
+  // jph + k p, the same for all of them, so a fixed tap count keeps them in
+  // registers (the form for any tap count reads them from LDS)
+  float cl[KS ? KS : 1];
+#pragma unroll
+  for (int k = 0; k < (KS ? KS : 1); ++k) cl[k] = cs[jph + k * p];
   const int per = kBlock / T;                // further-lift pairs: repetitions per pass
   const int li = t % T, lr = t / T;
   float gcl[KM];                             // first-lift slots: tap jph + k p
@@ -172,7 +188,7 @@ __global__ void __launch_bounds__(kBlock, 6) fir_adjoint_overlap_cols_kernel(Fir
     const int r0 = chunk * kRC, rs = r0 - (K - 1);
     // this item's x values at the lane's positions, all loads issued before
     // any is used (positions past the chunk, or rows nothing reads, read zero)
-    float xr[kPos];
+    float xr[KP];
     // a wave issuing an item's loads outranks the computing waves of the
     // other workgroups on its CU (125 against 132-138 us)
     __builtin_amdgcn_s_setprio(2);
@@ -181,7 +197,7 @@ __global__ void __launch_bounds__(kBlock, 6) fir_adjoint_overlap_cols_kernel(Fir
           const_cast<float*>(a.x) + int64_t(row) * A2, short(0), read ? A2 * 4 : 0, int(kBufferWord3));
       const int v_end = min((chunk + 1) * W, A2);
 #pragma unroll
-      for (int m = 0; m < kPos; ++m) {
+      for (int m = 0; m < KP; ++m) {
         const int v = chunk * W + t + m * step;
         int e = a.o_mod + v;
         if (e >= A2) e -= A2;
@@ -206,7 +222,7 @@ __global__ void __launch_bounds__(kBlock, 6) fir_adjoint_overlap_cols_kernel(Fir
     const int v0 = cur_chunk * W + t;
     const int q0 = int(fdiv(uint32_t(v0), a.div_p));
 #pragma unroll
-    for (int m = 0; m < kPos; ++m) {
+    for (int m = 0; m < KP; ++m) {
       const int v = v0 + m * step;
       if (!(t < step && v < v_end && (gxrow || (GC && read)))) continue;
       const int q = q0 + m * qstep;
@@ -221,7 +237,7 @@ __global__ void __launch_bounds__(kBlock, 6) fir_adjoint_overlap_cols_kernel(Fir
         for (int k = 0; k < KM; ++k) {
           if (!KS && k >= K) break;
           const float g = gys[q - k - rs];
-          acc = fmaf(cs[jph + k * p], g, acc);
+          acc = fmaf(KS ? cl[KS ? k : 0] : cs[jph + k * p], g, acc);
           if (GC) gcl[k] = fmaf(xv, g, gcl[k]);
         }
         if (gxrow) {
@@ -284,51 +300,68 @@ __global__ void __launch_bounds__(kBlock, 6) fir_adjoint_overlap_cols_kernel(Fir
 
 }  // namespace
 
-// One resident wave of workgroups (occupancy x compute units), at most one
-// per item.  The weight-gradient workspace holds one partial row per
-// workgroup, so the planner sizes it with this same function.
 namespace {
-template <bool GC>
-void launch_overlap(const FirOverlapArgs& a, int grid, int K, hipStream_t st) {
-  if (a.accumulate) {
-    fir_adjoint_overlap_cols_kernel<true, 0, GC><<<grid, kBlock, 0, st>>>(a);
-    return;
-  }
+typedef void (*OverlapKernel)(FirOverlapArgs);
+
+template <bool GC, int KP>
+OverlapKernel overlap_kernel_kp(int K, bool acc) {
+  if (acc) return fir_adjoint_overlap_cols_kernel<true, 0, GC, KP>;
   switch (K) {
-    case 1: fir_adjoint_overlap_cols_kernel<false, 1, GC><<<grid, kBlock, 0, st>>>(a); break;
-    case 2: fir_adjoint_overlap_cols_kernel<false, 2, GC><<<grid, kBlock, 0, st>>>(a); break;
-    case 3: fir_adjoint_overlap_cols_kernel<false, 3, GC><<<grid, kBlock, 0, st>>>(a); break;
-    case 4: fir_adjoint_overlap_cols_kernel<false, 4, GC><<<grid, kBlock, 0, st>>>(a); break;
-    default: fir_adjoint_overlap_cols_kernel<false, 0, GC><<<grid, kBlock, 0, st>>>(a); break;
+    case 1: return fir_adjoint_overlap_cols_kernel<false, 1, GC, KP>;
+    case 2: return fir_adjoint_overlap_cols_kernel<false, 2, GC, KP>;
+    case 3: return fir_adjoint_overlap_cols_kernel<false, 3, GC, KP>;
+    case 4: return fir_adjoint_overlap_cols_kernel<false, 4, GC, KP>;
+    default: return fir_adjoint_overlap_cols_kernel<false, 0, GC, KP>;
   }
+}
+
+// The kernel form for step p (positions per lane ceil(256 / floor(256 / p)):
+// at most 8 for p <= 8), K taps per lift, accumulation, weight gradient.
+OverlapKernel overlap_kernel(int p, int K, bool acc, bool gc) {
+  if (p <= 8) return gc ? overlap_kernel_kp<true, 8>(K, acc) : overlap_kernel_kp<false, 8>(K, acc);
+  return gc ? overlap_kernel_kp<true, kPos>(K, acc) : overlap_kernel_kp<false, kPos>(K, acc);
+}
+
+// Resident workgroups of a kernel form on the device (cached per form).
+int overlap_resident(OverlapKernel k) {
+  static std::mutex mu;
+  static std::vector<std::pair<OverlapKernel, int>> known;
+  std::lock_guard<std::mutex> lock(mu);
+  for (const auto& e : known)
+    if (e.first == k) return e.second;
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k), kBlock, 0) !=
+          hipSuccess ||
+      per_cu < 1) {
+    (void)hipGetLastError();   // a failed query must not surface as a launch error
+    per_cu = 4;
+  }
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+    (void)hipGetLastError();
+    cus = 256;
+  }
+  known.emplace_back(k, per_cu * cus);
+  return per_cu * cus;
 }
 }  // namespace
 
-int fir_overlap_cols_grid(uint32_t n_items) {
-  static const int resident = [] {
-    int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fir_adjoint_overlap_cols_kernel<false, 0, true>, kBlock, 0) !=
-            hipSuccess || per_cu < 1) {
-      (void)hipGetLastError();   // a failed query must not surface as a launch error
-      per_cu = 4;
-    }
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
-      (void)hipGetLastError();
-      cus = 256;
-    }
-    return per_cu * cus;
-  }();
+// One resident wave of workgroups of the form for any tap count (the one
+// holding the most registers), at most one per item, whatever form runs:
+// for 13 taps every 8 columns on 30 x 1080 x 1920 that is 6 workgroups per
+// CU, and measured with 3 .. 8 per CU: 140, 119, 115, 114, 142, 131 us.  The
+// weight-gradient workspace holds one partial row per workgroup, so the
+// planner sizes it with this same function.
+int fir_overlap_cols_grid(uint32_t n_items, int p) {
+  const int resident = overlap_resident(overlap_kernel(p, 0, false, true));
   return int(n_items < uint32_t(resident) ? (n_items ? n_items : 1) : uint32_t(resident));
 }
 
 hipError_t launch_fir_adjoint_overlap_cols(const FirOverlapArgs& a, hipStream_t st) {
-  const int grid = fir_overlap_cols_grid(a.n_items);
-  const int K = (a.w.taps + a.w.p[2] - 1) / a.w.p[2];
-  if (a.partial)
-    launch_overlap<true>(a, grid, K, st);
-  else
-    launch_overlap<false>(a, grid, K, st);
+  const int p = a.w.p[2], K = (a.w.taps + p - 1) / p;
+  const bool gc = a.partial != nullptr;
+  const int grid = fir_overlap_cols_grid(a.n_items, p);
+  hipLaunchKernelGGL(overlap_kernel(p, K, a.accumulate != 0, gc), dim3(grid), dim3(kBlock), 0, st, a);
   return hipGetLastError();
 }
 

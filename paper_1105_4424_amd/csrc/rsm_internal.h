@@ -396,7 +396,7 @@ hipError_t launch_fir_chain(const FirChainArgs& a, bool vec4, hipStream_t st);
 hipError_t launch_fir_adjoint(const FirAdjArgs& a, bool vec4, int* grid_out, hipStream_t st);
 hipError_t launch_fir_gx_gather(const FirGatherArgs& a, hipStream_t st);
 hipError_t launch_fir_adjoint_overlap_cols(const FirOverlapArgs& a, hipStream_t st);
-int fir_overlap_cols_grid(uint32_t n_items);
+int fir_overlap_cols_grid(uint32_t n_items, int p);
 int fir_adjoint_grid(const FirAdjArgs& a);
 hipError_t launch_fir_chain_adjoint(const FirChainAdjArgs& a, bool vec4, hipStream_t st);
 int fir_chain_adjoint_grid(const FirChainAdjArgs& a, bool vec4);
