@@ -16,7 +16,9 @@
 //    q outputs of one repetition from its window in LDS.
 //  * poly_rows_kernel: taps along rows.  One thread per repetition, lanes
 //    along the contiguous column axis, so every load and store of a
-//    wavefront is one contiguous 256-byte run.
+//    wavefront is one contiguous 256-byte run; poly_rows_vec_kernel gives a
+//    thread four adjacent repetitions (16-byte loads and stores) where the
+//    columns allow it.
 //  * poly_gx_gather_kernel: input gradient as a gather, one thread per input
 //    element: the (repetition, tap) pairs that reach the element are found
 //    by lifting its index to the unwrapped window positions, and each pair
@@ -257,6 +259,90 @@ __global__ void __launch_bounds__(kBlock) poly_rows_kernel(PolyArgs a) {
           }
         }
         dst[int64_t(j) * w.rep[2]] = acc;
+      }
+    }
+  }
+}
+
+
+// The same with V adjacent repetitions along the column axis per thread
+// (column step 1, rows of a multiple of V repetitions starting on a 4V-byte
+// boundary, the launcher checks): every load and store moves 4V bytes and
+// each coefficient read serves V windows.
+template <int V>
+struct VecF;
+template <>
+struct VecF<2> {
+  typedef float2 T;
+};
+template <>
+struct VecF<4> {
+  typedef float4 T;
+};
+
+template <int KT, int QT, int V>
+__global__ void __launch_bounds__(kBlock) poly_rows_vec_kernel(PolyArgs a) {
+  typedef typename VecF<V>::T vec;
+  __shared__ __align__(16) float cs[kMaxQ * kMaxT];
+  const Win3& w = a.w;
+  const int T = w.taps, q = a.q;
+  {
+    const int t = int(threadIdx.x);
+    const int j = t / kMaxT, i = t - j * kMaxT;   // rows padded with zeros to kMaxT
+    cs[t] = (j < q && i < T) ? a.c[j * T + i] : 0.0f;
+  }
+  __syncthreads();
+  const uint32_t nv = a.n_items / V;
+  const uint32_t stride = gridDim.x * kBlock;
+  for (uint32_t ov = blockIdx.x * kBlock + threadIdx.x; ov < nv; ov += stride) {
+    const uint32_t o = V * ov;
+    const uint32_t rowi = fdiv(o, a.div_rc);
+    const int c = int(o - rowi * uint32_t(w.rep[2]));   // a multiple of V
+    const uint32_t b = fdiv(rowi, a.div_rr);
+    const int r = int(rowi - b * uint32_t(w.rep[1]));
+    const int xb = w.o[0] + w.p[0] * int(b);
+    const float* __restrict__ plane = a.x + int64_t(xb) * w.A[1] * w.A[2] + w.o[2] + c;
+    const int64_t start = int64_t(w.o[1]) + int64_t(w.p[1]) * r;
+    float win[KT][V];
+    int xr = start >= 0 && start < w.A[1] ? int(start) : wrap_mod(start, w.A[1]);
+#pragma unroll
+    for (int i = 0; i < KT; ++i) {
+      if (i < T) {
+        const vec v = *reinterpret_cast<const vec*>(plane + int64_t(xr) * w.A[2]);
+        const float* f = reinterpret_cast<const float*>(&v);
+#pragma unroll
+        for (int e = 0; e < V; ++e) win[i][e] = f[e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e) win[i][e] = 0.0f;
+      }
+      if (++xr == w.A[1]) xr = 0;
+    }
+    float* __restrict__ dst = a.y + (int64_t(b) * w.rep[1] * q + int64_t(q) * r) * w.rep[2] + c;
+#pragma unroll
+    for (int j = 0; j < QT; ++j) {
+      if (j < q) {
+        float acc[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc[e] = 0.0f;
+#pragma unroll
+        for (int u = 0; u < KT / 4; ++u) {
+          if (4 * u < T) {
+            const float4 c4 = *reinterpret_cast<const float4*>(cs + j * kMaxT + 4 * u);
+            const float cc[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+              if (4 * u + k < T) {
+#pragma unroll
+                for (int e = 0; e < V; ++e) acc[e] = fmaf(cc[k], win[4 * u + k][e], acc[e]);
+              }
+          }
+        }
+        vec out;
+        float* of = reinterpret_cast<float*>(&out);
+#pragma unroll
+        for (int e = 0; e < V; ++e) of[e] = acc[e];
+        *reinterpret_cast<vec*>(dst + int64_t(j) * w.rep[2]) = out;
       }
     }
   }
@@ -799,6 +885,24 @@ hipError_t launch_poly(const PolyArgs& a, hipStream_t st) {
     const int qt = a.q == 1 ? 1 : a.q <= 4 ? 4 : 8;
     launch_cols(a, T <= 8 ? 8 : T <= 16 ? 16 : 32, small_step ? 9 : 17, qt, grid, st);
   } else {
+    // four repetitions per thread where the columns allow 16-byte accesses
+    // (30 x 1080 x 720 -> 480 rows, 14 taps every 9 rows, 4 outputs: 43.9 ->
+    // 31.3 us; two per thread with 8-byte accesses 33.4 us)
+    const uintptr_t xy = reinterpret_cast<uintptr_t>(a.x) | reinterpret_cast<uintptr_t>(a.y);
+    if (a.w.p[2] == 1 && a.w.o[2] >= 0 && a.w.o[2] + a.w.rep[2] <= a.w.A[2] && T <= 16 && a.w.rep[2] % 4 == 0 &&
+        a.w.A[2] % 4 == 0 && a.w.o[2] % 4 == 0 && !(xy & 15)) {
+      const uint32_t need = (a.n_items / 4 + kBlock - 1) / kBlock;
+      const int grid = int(need < 256u * 16u ? (need ? need : 1) : 256u * 16u);
+      if (T <= 8 && a.q <= 4)
+        poly_rows_vec_kernel<8, 4, 4><<<grid, kBlock, 0, st>>>(a);
+      else if (T <= 8)
+        poly_rows_vec_kernel<8, 8, 4><<<grid, kBlock, 0, st>>>(a);
+      else if (a.q <= 4)
+        poly_rows_vec_kernel<16, 4, 4><<<grid, kBlock, 0, st>>>(a);
+      else
+        poly_rows_vec_kernel<16, 8, 4><<<grid, kBlock, 0, st>>>(a);
+      return hipGetLastError();
+    }
     const uint32_t need = (a.n_items + kBlock - 1) / kBlock;
     const int grid = int(need < 256u * 16u ? (need ? need : 1) : 256u * 16u);
     if (T <= 8)
