@@ -294,7 +294,13 @@ __global__ void __launch_bounds__(kBlock) poly_rows_vec_kernel(PolyArgs a) {
   __syncthreads();
   const uint32_t nv = a.n_items / V;
   const uint32_t stride = gridDim.x * kBlock;
-  for (uint32_t ov = blockIdx.x * kBlock + threadIdx.x; ov < nv; ov += stride) {
+  // workgroups are dealt to the 8 XCDs round-robin; give each XCD a
+  // contiguous band of the launch (the grid is a multiple of 8), so that the
+  // windows one step further down a column, taken one output row of threads
+  // later, usually run on the same XCD and find their shared rows in its L2
+  const uint32_t band = gridDim.x / 8;
+  const uint32_t lb = (blockIdx.x % 8) * band + blockIdx.x / 8;
+  for (uint32_t ov = lb * kBlock + threadIdx.x; ov < nv; ov += stride) {
     const uint32_t o = V * ov;
     const uint32_t rowi = fdiv(o, a.div_rc);
     const int c = int(o - rowi * uint32_t(w.rep[2]));   // a multiple of V
@@ -892,7 +898,7 @@ hipError_t launch_poly(const PolyArgs& a, hipStream_t st) {
     if (a.w.p[2] == 1 && a.w.o[2] >= 0 && a.w.o[2] + a.w.rep[2] <= a.w.A[2] && T <= 16 && a.w.rep[2] % 4 == 0 &&
         a.w.A[2] % 4 == 0 && a.w.o[2] % 4 == 0 && !(xy & 15)) {
       const uint32_t need = (a.n_items / 4 + kBlock - 1) / kBlock;
-      const int grid = int(need < 256u * 16u ? (need ? need : 1) : 256u * 16u);
+      const int grid = int(((need < 256u * 16u ? need : 256u * 16u) + 7) / 8 * 8);   // a multiple of 8
       if (T <= 8 && a.q <= 4)
         poly_rows_vec_kernel<8, 4, 4><<<grid, kBlock, 0, st>>>(a);
       else if (T <= 8)
