@@ -89,7 +89,7 @@ def measured_traffic():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs every kernel on a single MI355X "
+        print("bench.py measures one GPU only: this library runs every kernel on a single MI355X "
               "and has no multi-GPU path (requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

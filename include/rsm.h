@@ -62,7 +62,7 @@ typedef enum {
   RSM_E_SHAPE = 3,       /* non-positive extent, shapes that do not agree       */
   RSM_E_OVERFLOW = 4,    /* index arithmetic would not fit in 62 bits           */
   RSM_E_OVERLAP = 5,     /* output tiler writes an element twice (when checked) */
-  RSM_E_UNSUPPORTED = 6, /* valid request that no kernel of this build handles  */
+  RSM_E_UNSUPPORTED = 6, /* valid request that no kernel of the library handles */
   RSM_E_HIP = 7,         /* a HIP runtime call failed                           */
   RSM_E_NOMEM = 8        /* device or host allocation failed                    */
 } rsm_status;
@@ -199,7 +199,7 @@ rsm_status rsm_plan_ports(const rsm_space* rep, const rsm_tiler* in, int32_t n_i
  * in LDS and accumulates in registers.
  * Errors: RSM_E_INVALID for a malformed request (wrong count, unknown space,
  * the output port in constant memory: it is written); RSM_E_UNSUPPORTED when
- * no family of this build meets the request (e.g. an input array in
+ * no family of the library meets the request (e.g. an input array in
  * constant memory, or 81 elements of a 9 x 9 window in registers).
  *
  * rsm_plan_placed -- host only: the family that honours the request (name,

@@ -850,7 +850,7 @@ rsm_status exec_run(const rsm_space& rep, const rsm_tiler* in, const void* const
                     const rsm_tiler& out, void* d_out, const rsm_task& task, uint32_t flags,
                     const Checked& c, hipStream_t st, const int32_t* req = nullptr) {
   const Plan p = make_plan(rep, in, n_in, out, task, flags, d_in, c.n_rep, c.n_pat_in[0], req);
-  if (!p.ok) return fail(RSM_E_UNSUPPORTED, "no kernel of this build keeps the ports where requested");
+  if (!p.ok) return fail(RSM_E_UNSUPPORTED, "no kernel of this library keeps the ports where requested");
   return exec_planned(p, rep, in, d_in, n_in, out, d_out, task, c, st);
 }
 
@@ -1450,7 +1450,7 @@ rsm_status rsm_plan_placed(const rsm_space* rep, const rsm_tiler* in, int32_t n_
   const int count = n_in + 1 + (task->kind == RSM_TASK_WSUM ? 1 : 0);
   if ((s = check_spaces(spaces, n_spaces, count, n_in)) != RSM_OK) return s;
   const Plan p = make_plan(*rep, in, n_in, *out, *task, flags, nullptr, c.n_rep, c.n_pat_in[0], spaces);
-  if (!p.ok) return fail(RSM_E_UNSUPPORTED, "no kernel of this build keeps the ports where requested");
+  if (!p.ok) return fail(RSM_E_UNSUPPORTED, "no kernel of this library keeps the ports where requested");
   if (name && len > 0) std::snprintf(name, size_t(len), "%s", p.name.c_str());
   if (n_ports) *n_ports = count;
   if (ports) {
