@@ -194,8 +194,9 @@ rsm_status rsm_plan_ports(const rsm_space* rep, const rsm_tiler* in, int32_t n_i
  * kept in registers with the weights in scalar registers (input private,
  * weights constant), or the window staged in LDS with the weights in LDS
  * (input, output and weights local), or everything read in place (global);
- * a k x k window keeps its tile in LDS, or, for at most 64 pattern elements,
- * one element per lane in registers; a matrix product stages both operands
+ * a k x k window keeps its tile in LDS with its weights in constant memory,
+ * or, for at most 64 pattern elements, one element per lane in registers
+ * (weights in registers too); a matrix product stages both operands
  * in LDS and accumulates in registers.
  * Errors: RSM_E_INVALID for a malformed request (wrong count, unknown space,
  * the output port in constant memory: it is written); RSM_E_UNSUPPORTED when

@@ -597,11 +597,10 @@ Placement placement_of(const Plan& p, const rsm_tiler* in, int n_in, const rsm_t
       if (coeffs) set(cf, RSM_MEM_LOCAL, int64_t(p.poly_q) * p.win.taps * 4);
       break;
     case Fam::Filter2D: {
-      // the tile's input region (halo included) and the k x k weights in LDS
-      const int64_t lds = int64_t(filter2d_lds_bytes(p.f2d.k, p.f2d.s, 1));
-      const int64_t wbytes = int64_t(12) * p.f2d.k * 4;
-      set(0, RSM_MEM_LOCAL, lds - wbytes);
-      if (coeffs) set(cf, RSM_MEM_LOCAL, wbytes);
+      // the tile's input region (halo included) in LDS; the k x k weights,
+      // uniform and read-only, through the scalar unit
+      set(0, RSM_MEM_LOCAL, int64_t(filter2d_lds_bytes(p.f2d.k, p.f2d.s, 1)));
+      if (coeffs) set(cf, RSM_MEM_CONSTANT, int64_t(p.f2d.k) * p.f2d.k * 4);
       break;
     }
     case Fam::Gemm: {

@@ -8,9 +8,9 @@
 // every LDS row segment it needs (RX S + K - S floats, 16-byte aligned
 // because RX S = 4) is read once with ds_read_b128 and reused across its RX
 // outputs, so LDS traffic per output falls with RX and RY.  The k x k
-// weights are uniform across the workgroup: they are staged in LDS after the
-// input region and read with broadcast 16-byte LDS reads, one window row at
-// a time.
+// weights are uniform across the workgroup and read-only: they are read as
+// constant memory through the scalar unit, one window row per trip, and the
+// FMAs take them from scalar registers.
 //
 // Two launch forms share the tile body:
 //  * filter2d_kernel: one problem, one workgroup per tile (plain launches);
@@ -42,21 +42,9 @@ __host__ __device__ constexpr int lds_pitch(int K, int S) {
   return 60 + 4 * seg4_of(K, S) + 4;
 }
 __host__ __device__ constexpr int lds_cols(int K, int S) { return (16 * rx_of(S) - 1) * S + K; }
-// The k x k weights follow the input region in LDS, one window row per 12
-// floats (three 16-byte broadcast reads per row); the region's size is a
-// multiple of 4 floats, so they start 16-byte aligned.
-constexpr int kWPitch = 12;
-__host__ __device__ constexpr int lds_floats(int K, int S, int RY) {
-  return lds_rows(K, S, RY) * lds_pitch(K, S) + kWPitch * K;
-}
+constexpr int kWPitch = 12;   // weights of one window row held per trip (K <= 9 of them)
+__host__ __device__ constexpr int lds_floats(int K, int S, int RY) { return lds_rows(K, S, RY) * lds_pitch(K, S); }
 
-// The weights live in device global memory.  Their pointer comes out of a
-// descriptor read from memory, so without this cast the compiler addresses
-// them as generic ("flat") memory, whose accesses count against the LDS wait
-// counter too: LDS reads would then also wait for that load.  (The input
-// and output arrays are read and written through buffer resources.)
-typedef __attribute__((address_space(1))) const float gcfloat;
-__device__ __forceinline__ gcfloat* global_in(const float* p) { return (gcfloat*)(p); }
 
 __device__ __forceinline__ int mod_pos(int v, int n) {
   // v >= 0 here; reduce into [0, n)
@@ -80,7 +68,11 @@ __device__ __forceinline__ void compute_tile(const Filter2DProblem& p, int64_t l
   constexpr int SEG4 = seg4_of(K, S);
   int frame, ty, tx;
   tile_pos(p, local, &frame, &ty, &tx);
-  const float* lw = lds + LR * LP;
+  // the k x k weights are the same for every thread of the tile and are not
+  // written by the kernel: read as constant memory, they come through the
+  // scalar unit into scalar registers, one window row per trip, and every
+  // FMA takes its weight from there (no LDS reads for them)
+  const __attribute__((address_space(4))) float* wc = (const __attribute__((address_space(4))) float*)(p.c);
   const int t = threadIdx.x;
   const int tr = t >> 4, tc = t & 15;
   float acc[RY][RX];
@@ -94,10 +86,7 @@ __device__ __forceinline__ void compute_tile(const Filter2DProblem& p, int64_t l
   for (int dy = 0; dy < K; ++dy) {
     float w[kWPitch];
 #pragma unroll
-    for (int v = 0; v < (K + 3) / 4; ++v) {
-      const float4 q = *reinterpret_cast<const float4*>(lw + dy * kWPitch + 4 * v);
-      w[4 * v + 0] = q.x; w[4 * v + 1] = q.y; w[4 * v + 2] = q.z; w[4 * v + 3] = q.w;
-    }
+    for (int v = 0; v < K; ++v) w[v] = wc[dy * K + v];
 #pragma unroll
     for (int i = 0; i < RY; ++i) {
       const float* row = lds + ((tr * RY + i) * S + dy) * LP + tc * RX * S;
@@ -165,11 +154,6 @@ __device__ __forceinline__ void filter_tile(const Filter2DProblem p, int64_t loc
   const bool col1 = NC > 1 && lane + 64 < LC;
   const int l0 = col0 ? lane : LC - 1;
   const int l1 = col1 ? lane + 64 : LC - 1;
-  // weights: thread t < K*K fetches one with the tile's input (the compiler
-  // cannot prove the weights unaliased by the output, so reading them from
-  // memory inside the window loop would cost a global round trip per row)
-  float* lw = lds + LR * LP;
-  const float wt = t < K * K ? global_in(p.c)[t] : 0.0f;
   // the staging loads are the tile's latency chain: while a wave issues
   // them it outranks the waves of other workgroups on the CU that are
   // computing (the batch runs about 7 % faster)
@@ -217,7 +201,6 @@ __device__ __forceinline__ void filter_tile(const Filter2DProblem p, int64_t loc
     }
   }
   __builtin_amdgcn_s_setprio(0);
-  if (t < K * K) lw[(t / K) * kWPitch + t % K] = wt;  // after the staging barrier
   __syncthreads();
 
   compute_tile<K, S, RY>(p, local, lds);

@@ -173,11 +173,11 @@ def test_port_placement_follows_the_planned_kernel():
     assert rsm.plan_ports(ts.h) == [("private", 256 * 8 * 4), ("global", 0), ("constant", 32)]
     # forced onto the generic kernel: every port read and written in place
     assert rsm.plan_ports(ts.h, flags=_abi.FORCE_GENERIC) == [("global", 0)] * 3
-    # k x k windows: input region and weights staged in LDS
+    # k x k windows: input region staged in LDS, weights read as constants
     f = W.filter2d_problem(200, 300, 9, 1)
     ports = rsm.plan_ports(f)
-    assert [sp for sp, _ in ports] == ["local", "global", "local"]
-    assert ports[2][1] == 12 * 9 * 4
+    assert [sp for sp, _ in ports] == ["local", "global", "constant"]
+    assert ports[2][1] == 9 * 9 * 4
     # region rows x padded pitch of the tile class a single run uses:
     # (32 - 1) + 9 rows, pitch 60 + 4 * 3 + 4 floats
     assert ports[0][1] == (31 + 9) * 76 * 4
@@ -274,14 +274,16 @@ def test_placement_request_routes_the_kernel_family():
     with pytest.raises(rsm.RsmError) as e:
         P(ts.h, ["any", "any"])
     assert e.value.name == "RSM_E_INVALID"
-    # k x k windows: LDS tile by default, one element per lane up to 64
-    # elements, in place on the generic kernel; never weights in constant
+    # k x k windows: LDS tile by default (weights read as constants), one
+    # element per lane up to 64 elements, in place on the generic kernel;
+    # never weights in LDS
     f5 = W.filter2d_problem(70, 90, 5, 1)
     assert P(f5, None)[0] == "filter2d_k5_s1"
+    assert P(f5, ["local", "global", "constant"])[0] == "filter2d_k5_s1"
     assert P(f5, ["private", "any", "any"])[0] == "pattern_reduce"
     assert P(f5, ["global", "any", "any"])[0] == "generic"
     with pytest.raises(rsm.RsmError) as e:
-        P(f5, ["any", "any", "constant"])
+        P(f5, ["any", "any", "local"])
     assert e.value.name == "RSM_E_UNSUPPORTED"
     f9 = W.filter2d_problem(70, 90, 9, 1)
     with pytest.raises(rsm.RsmError) as e:
