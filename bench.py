@@ -5,9 +5,10 @@ Workload (the one the headline metric is quoted on): the two-stage
 downscaler-style filter on 30 frames of 1080x1920 FP32 -- an 8-tap
 horizontal weighted sum with paving 8, then an 8-tap vertical one -- run
 forward and through its adjoint (loss sum(w * out^2)), inputs resident in
-HBM.  One step = fused forward (input -> output, intermediate kept on chip)
-+ dL/dout = 2 w out + fused adjoint (input gradient and both stages'
-weight gradients).
+HBM.  One step = one training-step call: the fused forward (input ->
+output, intermediate kept on chip), dL/dout = 2 w out and the fused adjoint
+(input gradient and both stages' weight gradients) in one kernel, then one
+small launch that reduces the weight-gradient partial rows.
 
   value      tiled elems/s: pattern elements gathered by every tiler of the
              step (forward 69.98 M + adjoint 69.98 M per step) / step time
@@ -24,8 +25,12 @@ Four copies of the input and of the input gradient (about 1 GB each set)
 rotate between steps, so the 256 MiB Infinity Cache does not serve repeated
 reads.
 
-Other measurements (matrix product on the matrix cores, batched vs plain
-2-D filters, unfused variants, the small 64x64 task) go under "extra".
+Other measurements go under "extra": the same step as separate calls and
+through torch.autograd, unfused variants, the overlapping-window adjoint
+and training step, the horizontal stage under each placement request, the
+polyphase downscaler, the small 64x64 task (per call, planned and
+prepared), the 4096^3 matrix products (with their error against FP64),
+batched vs plain 2-D filters, the sparse product and the CG solve.
 """
 import argparse
 import json
