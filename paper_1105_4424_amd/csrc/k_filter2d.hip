@@ -6,11 +6,12 @@
 // once, with the modular wrap applied while loading (centred origins wrap on
 // every border).  Each thread then computes an RY x RX block of outputs:
 // every LDS row segment it needs (RX S + K - S floats, 16-byte aligned
-// because RX S = 4) is read once with ds_read_b128 and reused across its RX
-// outputs, so LDS traffic per output falls with RX and RY.  The k x k
+// because RX S = 4) is read once with ds_read_b128 and used by each of its
+// RX outputs and each of its RY output rows that the segment's row meets,
+// so LDS traffic per output falls with RX and RY.  The k x k
 // weights are uniform across the workgroup and read-only: they are read as
-// constant memory through the scalar unit, one window row per trip, and the
-// FMAs take them from scalar registers.
+// constant memory through the scalar unit, one window row at a time, and
+// the FMAs take them from scalar registers.
 //
 // Two launch forms share the tile body:
 //  * filter2d_kernel: one problem, one workgroup per tile (plain launches);
@@ -70,7 +71,7 @@ __device__ __forceinline__ void compute_tile(const Filter2DProblem& p, int64_t l
   tile_pos(p, local, &frame, &ty, &tx);
   // the k x k weights are the same for every thread of the tile and are not
   // written by the kernel: read as constant memory, they come through the
-  // scalar unit into scalar registers, one window row per trip, and every
+  // scalar unit into scalar registers, one window row at a time, and every
   // FMA takes its weight from there (no LDS reads for them)
   const __attribute__((address_space(4))) float* wc = (const __attribute__((address_space(4))) float*)(p.c);
   const int t = threadIdx.x;
@@ -80,26 +81,38 @@ __device__ __forceinline__ void compute_tile(const Filter2DProblem& p, int64_t l
   for (int i = 0; i < RY; ++i)
 #pragma unroll
     for (int j = 0; j < RX; ++j) acc[i][j] = 0.0f;
-  // one window row per trip: keeps live registers to one row segment per
-  // output row (full unrolling hoists K x RY segments and spills)
+  // one LDS row per trip, read once: with stride S the thread's RY output
+  // rows use the (RY - 1) S + K region rows from tr RY S on, and region row
+  // r meets output row i through window row dy = r - i S when 0 <= dy < K
+  // (a test uniform over the wave).  A row segment read once serves every
+  // output row whose windows cover it (RY K segment reads become
+  // (RY - 1) S + K), and each output still adds its window rows in
+  // ascending order, so the sums do not change.  The loop is not unrolled:
+  // one segment and the accumulators are live, not K x RY segments.
+  constexpr int NRW = (RY - 1) * S + K;
+  static_assert(15 * RY * S + NRW <= LR, "the last thread's rows lie inside the staged region");
+  const float* base = lds + tr * RY * S * LP + tc * RX * S;
 #pragma unroll 1
-  for (int dy = 0; dy < K; ++dy) {
-    float w[kWPitch];
+  for (int r = 0; r < NRW; ++r) {
+    const float* row = base + r * LP;
+    float seg[4 * SEG4];
 #pragma unroll
-    for (int v = 0; v < K; ++v) w[v] = wc[dy * K + v];
+    for (int v = 0; v < SEG4; ++v) {
+      const float4 q = *reinterpret_cast<const float4*>(row + 4 * v);
+      seg[4 * v + 0] = q.x; seg[4 * v + 1] = q.y; seg[4 * v + 2] = q.z; seg[4 * v + 3] = q.w;
+    }
 #pragma unroll
     for (int i = 0; i < RY; ++i) {
-      const float* row = lds + ((tr * RY + i) * S + dy) * LP + tc * RX * S;
-      float seg[4 * SEG4];
+      const int dy = r - i * S;
+      if (dy >= 0 && dy < K) {
+        float w[kWPitch];
 #pragma unroll
-      for (int v = 0; v < SEG4; ++v) {
-        const float4 q = *reinterpret_cast<const float4*>(row + 4 * v);
-        seg[4 * v + 0] = q.x; seg[4 * v + 1] = q.y; seg[4 * v + 2] = q.z; seg[4 * v + 3] = q.w;
+        for (int v = 0; v < K; ++v) w[v] = wc[dy * K + v];
+#pragma unroll
+        for (int j = 0; j < RX; ++j)
+#pragma unroll
+          for (int dx = 0; dx < K; ++dx) acc[i][j] = fmaf(w[dx], seg[j * S + dx], acc[i][j]);
       }
-#pragma unroll
-      for (int j = 0; j < RX; ++j)
-#pragma unroll
-        for (int dx = 0; dx < K; ++dx) acc[i][j] = fmaf(w[dx], seg[j * S + dx], acc[i][j]);
     }
   }
   // the frame's outputs as a raw buffer: an output past the array's edge
