@@ -468,6 +468,7 @@ struct Plan {
   std::string name = "generic";
   Win3 win{};
   int poly_q = 0;
+  bool poly_vec = false;   // columns: window read as 16-byte vectors into registers
   bool vec4 = false;
   GemmArgs gemm{};
   Filter2DProblem f2d{};
@@ -586,6 +587,13 @@ Placement placement_of(const Plan& p, const rsm_tiler* in, int n_in, const rsm_t
       if (coeffs) set(cf, RSM_MEM_CONSTANT, int64_t(p.win.taps) * 4);
       break;
     case Fam::Poly:
+      if (p.poly_vec) {
+        // each thread holds its window (16 floats) and the shifted weights
+        // of its q outputs in registers; outputs stored in place
+        set(0, RSM_MEM_PRIVATE, int64_t(kThreadsPerWg) * 16 * in_es);
+        if (coeffs) set(cf, RSM_MEM_PRIVATE, int64_t(kThreadsPerWg) * 16 * p.poly_q * 4);
+        break;
+      }
       if (p.win.ax == 2) {
         // a chunk's input segment, its outputs and the q x T weights in LDS
         set(0, RSM_MEM_LOCAL, (int64_t(p.win.p[2]) * 255 + p.win.taps) * in_es);
@@ -672,6 +680,15 @@ Plan make_plan(const rsm_space& rep, const rsm_tiler* in, int n_in, const rsm_ti
         p.win = w;
         p.poly_q = q;
         p.name = w.ax == 2 ? "polyphase_cols" : "polyphase_rows";
+        // along columns, windows on a common 16-byte phase read straight
+        // into registers (13 taps every 8, 3 outputs, 30 x 1080 x 1920:
+        // 102-105 us staged in LDS, 72-73 us in registers)
+        if (w.ax == 2 && poly_cols_vec_ok(w, q, d_in ? d_in[0] : nullptr)) {
+          Plan v = p;
+          v.poly_vec = true;
+          v.name = "polyphase_cols_vec";
+          cands.push_back(v);
+        }
         cands.push_back(p);
       }
       if (task.kind == RSM_TASK_WSUM && is_identity_out(rep, out) && canon_win3(rep, in[0], &w) && w.ax >= 1 &&
@@ -698,6 +715,14 @@ Plan make_plan(const rsm_space& rep, const rsm_tiler* in, int n_in, const rsm_ti
         // 102 -> 47 us).  Exact covers stay in registers (8 every 8 off the
         // 16-byte grid: 43 us against 64 us staged).
         if (lds && w.ax == 2 && !p.vec4 && w.taps != w.p[2]) {
+          // windows on a common 16-byte phase: read straight into registers
+          // as 16-byte vectors (13 taps every 8: 74 us staged, 55 us)
+          if (poly_cols_vec_ok(w, 1, d_in ? d_in[0] : nullptr)) {
+            Plan v = l;
+            v.poly_vec = true;
+            v.name = "fir_cols_window_vec";
+            cands.push_back(v);
+          }
           cands.push_back(l);
           cands.push_back(p);
         } else {
@@ -787,7 +812,7 @@ rsm_status exec_planned(Plan p, const rsm_space& rep, const rsm_tiler* in, const
       a.x = static_cast<const float*>(d_in[0]);
       a.y = static_cast<float*>(d_out);
       a.c = static_cast<const float*>(task.coeffs);
-      e = launch_poly(a, st);
+      e = p.poly_vec ? launch_poly_cols_vec(a, st) : launch_poly(a, st);
       if (e != hipSuccess) return hip_fail(e, "polyphase launch");
       return RSM_OK;
     }

@@ -14,6 +14,9 @@
 //    LDS from registers that were loaded, coalesced, while it computed the
 //    previous items (two items in flight); each thread forms and stores the
 //    q outputs of one repetition from its window in LDS.
+//  * poly_cols_vec_kernel: taps along columns, one thread per repetition,
+//    its window read as four 16-byte vectors (p and A[2] multiples of four,
+//    o mod 4 + T <= 16, q <= 4).
 //  * poly_rows_kernel: taps along rows.  One thread per repetition, lanes
 //    along the contiguous column axis, so every load and store of a
 //    wavefront is one contiguous 256-byte run; poly_rows_vec_kernel gives a
@@ -29,6 +32,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "rsm_internal.h"
 
@@ -204,6 +208,75 @@ __global__ void __launch_bounds__(kBlock) poly_cols_kernel(PolyArgs a) {
     col_step<KT, PF, QT>(a, col_item(a, item), v1, item + 2 * g, xs, cs, ws);
     item += g;
     if (item >= a.n_items) break;
+  }
+}
+
+// One thread per repetition with the window in registers, read as 16-byte
+// vectors straight from memory.  With p and A[2] multiples of four, every
+// window start o + p r lies the same distance off = o mod 4 past a 16-byte
+// boundary, so taps 0 .. T-1 are floats off .. off+T-1 of the four aligned
+// vectors at o + p r - off (off + T <= 16).  The weights, shifted by off and
+// zero outside the taps, are uniform and read-only: they are read as
+// constants into scalar registers once per thread.  Floats of the 16 outside
+// the window are zeroed before the products (they may hold non-finite
+// values that the window does not contain), so each output adds its taps in
+// ascending order to zero, like the staged kernel.  Neighbouring windows
+// share half of their vectors; the second read comes from the L1 cache.
+// Windows that cross the row's border read each float with the wrap.
+template <int QT>
+__global__ void __launch_bounds__(kBlock) poly_cols_vec_kernel(PolyArgs a) {
+  const Win3& w = a.w;
+  const int T = w.taps, p = w.p[2], A2 = w.A[2], R = w.rep[2];
+  const int off = ((w.o[2] % 4) + 4) % 4;
+  // the shifted weights in vector registers (16 q of them: in scalar
+  // registers they spill for q >= 3); lane0 is zero on every lane but not
+  // known to be uniform, so the loads are vector loads
+  const int lane0 = int(__builtin_amdgcn_mbcnt_lo(0u, 0u));
+  float cv[QT][16];
+#pragma unroll
+  for (int j = 0; j < QT; ++j)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int k = i - off;
+      const int kc = k < 0 ? 0 : (k >= T ? T - 1 : k);   // an address inside the weights
+      const float v = a.c[j * T + kc + lane0];
+      cv[j][i] = (k >= 0 && k < T) ? v : 0.0f;
+    }
+  const uint32_t stride = gridDim.x * kBlock;
+  for (uint32_t it = blockIdx.x * kBlock + threadIdx.x; it < a.n_items; it += stride) {
+    const uint32_t row = fdiv(it, a.div_rc);
+    const int c = int(it - row * uint32_t(R));
+    const uint32_t b = fdiv(row, a.div_rr);
+    const int r1 = int(row - b * uint32_t(w.rep[1]));
+    const float* xrow = a.x + (int64_t(w.o[0] + w.p[0] * int(b)) * w.A[1] + (w.o[1] + w.p[1] * r1)) * A2;
+    const int base = w.o[2] + p * c - off;   // a multiple of 4
+    float win[16];
+    if (base >= 0 && base + 16 <= A2) {
+      const float4* src = reinterpret_cast<const float4*>(xrow + base);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float4 f = src[u];
+        win[4 * u + 0] = f.x; win[4 * u + 1] = f.y; win[4 * u + 2] = f.z; win[4 * u + 3] = f.w;
+      }
+    } else {
+      int col = wrap_mod(base, A2);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        win[i] = xrow[col];
+        if (++col == A2) col = 0;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (i < off || i >= off + T) win[i] = 0.0f;
+    float* dst = a.y + (int64_t(row) * R + c) * QT;
+#pragma unroll
+    for (int j = 0; j < QT; ++j) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc = fmaf(cv[j][i], win[i], acc);
+      dst[j] = acc;
+    }
   }
 }
 
@@ -917,6 +990,30 @@ hipError_t launch_poly(const PolyArgs& a, hipStream_t st) {
       poly_rows_kernel<16><<<grid, kBlock, 0, st>>>(a);
     else
       poly_rows_kernel<32><<<grid, kBlock, 0, st>>>(a);
+  }
+  return hipGetLastError();
+}
+
+bool poly_cols_vec_ok(const Win3& w, int q, const void* x) {
+  if (w.ax != 2 || q < 1 || q > 4 || w.p[2] % 4 || w.A[2] % 4) return false;
+  if (((w.o[2] % 4) + 4) % 4 + w.taps > 16) return false;
+  if (int64_t(w.rep[0]) * w.rep[1] * w.rep[2] >= (int64_t(1) << 31)) return false;   // item index + stride in 32 bits
+  // window starts in 32-bit arithmetic
+  if (std::abs(int64_t(w.o[2])) + int64_t(w.p[2]) * w.rep[2] + 16 >= (int64_t(1) << 31)) return false;
+  return x == nullptr || (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+}
+
+hipError_t launch_poly_cols_vec(const PolyArgs& args, hipStream_t st) {
+  PolyArgs a = args;
+  a.n_items = uint32_t(int64_t(a.w.rep[0]) * a.w.rep[1] * a.w.rep[2]);
+  if (a.n_items == 0) return hipSuccess;
+  const uint32_t need = (a.n_items + kBlock - 1) / kBlock;
+  const int grid = int(need < 256u * 32u ? need : 256u * 32u);
+  switch (a.q) {
+    case 1: poly_cols_vec_kernel<1><<<grid, kBlock, 0, st>>>(a); break;
+    case 2: poly_cols_vec_kernel<2><<<grid, kBlock, 0, st>>>(a); break;
+    case 3: poly_cols_vec_kernel<3><<<grid, kBlock, 0, st>>>(a); break;
+    default: poly_cols_vec_kernel<4><<<grid, kBlock, 0, st>>>(a); break;
   }
   return hipGetLastError();
 }

@@ -414,6 +414,10 @@ bool poly_supported(const Win3& w, int q);
 bool poly_gc_supported(const Win3& w, int q);
 int poly_chunks(const Win3& w);
 hipError_t launch_poly(const PolyArgs& a, hipStream_t st);
+// Columns form with the window read as 16-byte vectors (one thread per
+// repetition); x may be null when planning without an array.
+bool poly_cols_vec_ok(const Win3& w, int q, const void* x);
+hipError_t launch_poly_cols_vec(const PolyArgs& a, hipStream_t st);
 hipError_t launch_poly_gx_gather(const PolyGatherArgs& a, hipStream_t st);
 int poly_gc_grid(uint32_t n_rep);
 hipError_t launch_poly_gc(const PolyArgs& a, hipStream_t st);

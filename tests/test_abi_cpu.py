@@ -114,13 +114,21 @@ def test_planner_routes_workloads_to_their_kernels():
     assert rsm.plan(ts.h) == "fir_cols_vec4"
     assert rsm.plan(ts.v) == "fir_rows"
     assert rsm.plan(ts.h, flags=_abi.FORCE_GENERIC) == "generic"
+    # overlapping windows on a common 16-byte phase: 16-byte vectors into
+    # registers; on request, or off that phase, row segments staged in LDS
     tw = W.two_stage_filter(frames=1, rows=8, cols=40, taps=13, pave=8, h_origin=-6)
-    assert rsm.plan(tw.h) == "fir_cols_lds"      # overlapping windows: row segments in LDS
+    assert rsm.plan(tw.h) == "fir_cols_window_vec"
+    assert rsm.plan_placed(tw.h, ["local", "any", "any"])[0] == "fir_cols_lds"
     tg = W.two_stage_filter(frames=1, rows=8, cols=40, taps=6, pave=8, h_origin=2)
-    assert rsm.plan(tg.h) == "fir_cols_lds"      # gaps between windows
+    assert rsm.plan(tg.h) == "fir_cols_window_vec"   # gaps between windows
+    t3 = W.two_stage_filter(frames=1, rows=8, cols=39, taps=13, pave=8, h_origin=-6)
+    assert rsm.plan(t3.h) == "fir_cols_lds"          # rows of 39 floats: no common phase
+    t7 = W.two_stage_filter(frames=1, rows=8, cols=40, taps=15, pave=8, h_origin=-6)
+    assert rsm.plan(t7.h) == "fir_cols_lds"          # phase 2 + 15 taps: more than four vectors
     te = W.two_stage_filter(frames=1, rows=8, cols=40, taps=8, pave=8, h_origin=-3)
     assert rsm.plan(te.h) == "fir_cols"          # exact cover off the 16-byte grid: registers
-    assert rsm.plan_placed(tw.h, ["private", "any", "any"])[0] == "fir_cols"
+    assert rsm.plan_placed(tw.h, ["private", "any", "constant"])[0] == "fir_cols"
+    assert rsm.plan_placed(tw.h, ["private", "any", "private"])[0] == "fir_cols_window_vec"
     import torch
     mm = W.matmul_tilers(256, 256, 256)
     mm.compute = "bf16"
@@ -296,9 +304,15 @@ def test_placement_request_routes_the_kernel_family():
     with pytest.raises(rsm.RsmError) as e:
         P(mm, ["any", "any", "local"])
     assert e.value.name == "RSM_E_UNSUPPORTED"
-    # polyphase stage: the columns kernel stages everything in LDS
+    # polyphase stage: windows and weights in registers by default; the
+    # staged columns kernel keeps everything in LDS
     pp = W.polyphase_downscaler(frames=1, rows=18, cols=48)
+    name, ports = P(pp.h, None)
+    assert name == "polyphase_cols_vec"
+    assert [s for s, _ in ports] == ["private", "global", "private"]
+    assert ports[0][1] == 256 * 16 * 4 and ports[2][1] == 256 * 16 * 3 * 4
     assert P(pp.h, ["local", "local", "local"])[0] == "polyphase_cols"
+    assert P(pp.h, ["any", "local", "any"])[0] == "polyphase_cols"
     assert P(pp.h, ["global", "any", "any"])[0] == "generic"
     assert P(pp.v, ["private", "global", "local"])[0] == "polyphase_rows"
 

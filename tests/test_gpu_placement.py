@@ -48,6 +48,33 @@ def test_column_taps_every_placement(spaces, family):
     _run(ts.h, [ts.x], list(spaces), ts.c_h, family)
 
 
+# 13 taps every 8 columns (origin -6: windows overlap by 5 and wrap at both
+# borders), 2 frames of 64 x 200
+@pytest.mark.parametrize("spaces,family", [
+    ((A, A, A), "fir_cols_window_vec"),
+    (("private", "global", "private"), "fir_cols_window_vec"),
+    (("private", A, "constant"), "fir_cols"),
+    (("local", A, A), "fir_cols_lds"),
+    (("global", A, A), "generic"),
+])
+def test_overlapping_column_taps_every_placement(spaces, family):
+    ts = W.two_stage_filter(frames=2, rows=64, cols=200, taps=13, pave=8, seed=74, h_origin=-6)
+    say("placement", spaces)
+    _run(ts.h, [ts.x], list(spaces), ts.c_h, family)
+
+
+# polyphase stage (13 taps every 8 columns, 3 outputs per window)
+@pytest.mark.parametrize("spaces,family", [
+    ((A, A, A), "polyphase_cols_vec"),
+    ((A, "local", A), "polyphase_cols"),
+    (("global", A, A), "generic"),
+])
+def test_polyphase_columns_every_placement(spaces, family):
+    pp = W.polyphase_downscaler(frames=1, rows=24, cols=200)
+    say("placement", spaces)
+    _run(pp.h, [pp.x], list(spaces), pp.c_h, family)
+
+
 @pytest.mark.parametrize("spaces,family", [
     ((A, A, A), "fir_rows"),
     ((A, A, "local"), "fir_rows_lds_weights"),

@@ -79,6 +79,13 @@ CASES = [
 ]
 
 
+def _vec_form(A, taps, pave, q, origin, axis):
+    """Whether the columns form that reads windows as 16-byte vectors applies:
+    steps and rows in whole vectors, the window inside four vectors from its
+    phase, at most four outputs per repetition."""
+    return axis == 2 and pave % 4 == 0 and A[2] % 4 == 0 and origin % 4 + taps <= 16 and q <= 4
+
+
 @pytest.mark.parametrize("case", CASES, ids=[str(k) for k in range(len(CASES))])
 @pytest.mark.parametrize("generic", [False, True], ids=["polyphase", "generic"])
 def test_polyphase_stage_forward_and_adjoint(case, generic):
@@ -86,11 +93,64 @@ def test_polyphase_stage_forward_and_adjoint(case, generic):
     p, x = _stage(A, taps, pave, q, origin, axis, seed=600 + taps + pave)
     flags = _abi.FORCE_GENERIC if generic else 0
     fam = rsm.plan(p, flags=flags)
-    assert fam == ("generic" if generic else ("polyphase_cols" if axis == 2 else "polyphase_rows")), fam
+    if generic:
+        want = "generic"
+    elif axis == 1:
+        want = "polyphase_rows"
+    else:
+        want = "polyphase_cols_vec" if _vec_form(*case) else "polyphase_cols"
+    assert fam == want, fam
     say("polyphase", A, taps, pave, q, origin, axis, fam)
     _forward_check(p, x, flags, what=str(case))
     gy = W.rng_for(700 + taps).uniform(-1, 1, p.output.array_shape).astype(np.float32)
     _adjoint_check(p, x, gy, flags, what=str(case))
+
+
+@pytest.mark.parametrize("case", [c for c in CASES if c[5] == 2], ids=lambda c: str(c))
+def test_polyphase_columns_staged_form(case):
+    # the LDS-staged columns kernel, requested by placement where the
+    # vector form would be the default
+    p, x = _stage(*case, seed=600 + case[1] + case[2])
+    ref = oracle.run(p, [x])
+    out = torch.full(p.output.array_shape, float("nan"), device="cuda")
+    assert rsm.plan_placed(p, ["local", "any", "any"])[0] == "polyphase_cols"
+    rsm.run_placed(p, [dev(x)], out, ["local", "any", "any"], coeffs=dev(p.coeffs))
+    check_close(host(out), ref.out, ref.abs_sum, what=str(case) + " staged")
+
+
+def test_vector_form_ignores_values_outside_the_windows():
+    # 6 taps every 8 columns leave gaps of 2; infinities and NaNs there are
+    # read by the vector form (inside its four vectors) but must not reach
+    # any output
+    A = (2, 9, 96)
+    p, x = _stage(A, 6, 8, 3, 1, 2, seed=640)
+    assert rsm.plan(p) == "polyphase_cols_vec"
+    cols = np.arange(A[2])
+    in_gap = ((cols - 1) % 8) >= 6
+    x = x.copy()
+    x[:, 0::2, in_gap] = np.inf
+    x[:, 1::2, in_gap] = np.nan
+    ref = oracle.run(p, [x])
+    assert np.isfinite(ref.out).all()
+    out = torch.full(p.output.array_shape, float("nan"), device="cuda")
+    rsm.run(p, [dev(x)], out, coeffs=dev(p.coeffs))
+    check_close(host(out), ref.out, ref.abs_sum, what="gaps holding inf/nan")
+
+
+def test_input_off_a_16_byte_boundary():
+    # the same stage on an input 4 bytes past a 16-byte boundary (the plan
+    # kept for these descriptors and that alignment, which the vector form
+    # does not meet)
+    p, x = _stage((1, 6, 200), 13, 8, 3, -2, 2, seed=641)
+    buf = torch.empty(x.size + 4, device="cuda")
+    xd = buf[1:1 + x.size].view(x.shape)
+    xd.copy_(dev(x))
+    assert xd.data_ptr() % 16 == 4
+    ref = oracle.run(p, [x])
+    out = torch.full(p.output.array_shape, float("nan"), device="cuda")
+    rsm.run(p, [xd], out, coeffs=dev(p.coeffs))
+    check_close(host(out), ref.out, ref.abs_sum, what="misaligned input")
+    assert rsm.plan(p) == "polyphase_cols_vec"   # an aligned array keeps the vector form
 
 
 def test_polyphase_kernel_plan_names():
@@ -102,8 +162,9 @@ def test_polyphase_kernel_plan_names():
     assert rsm.plan(pr, flags=_abi.PLAN_ADJOINT) == "polyphase_adjoint_gather"
     p5, _ = _stage((1, 64, 8), 20, 8, 3, -2, 1, seed=1)   # 20 taps: weight gradient on the generic kernel
     assert rsm.plan(p5, flags=_abi.PLAN_ADJOINT) == "polyphase_adjoint_gather_generic_gc"
-    ports = rsm.plan_ports(p)
-    assert [sp for sp, _ in ports] == ["local", "local", "local"]
+    # forward along columns: window and weights in registers
+    assert rsm.plan(p) == "polyphase_cols_vec"
+    assert [sp for sp, _ in rsm.plan_ports(p)] == ["private", "global", "private"]
 
 
 def test_polyphase_sum_task_rejected():

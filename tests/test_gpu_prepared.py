@@ -28,7 +28,7 @@ def _cases():
         ("fir_cols_vec4", ts.h, [ts.x], ts.c_h),
         ("fir_rows", ts.v, [mid], ts.c_v),
         ("filter2d_k5_s2", k5, [x5], k5.coeffs),
-        ("polyphase_cols", pp.h, [pp.x], pp.c_h),
+        ("polyphase_cols_vec", pp.h, [pp.x], pp.c_h),
     ]
 
 
