@@ -167,6 +167,63 @@ def test_polyphase_kernel_plan_names():
     assert [sp for sp, _ in rsm.plan_ports(p)] == ["private", "global", "private"]
 
 
+# column adjoints on steps 4, 8 and 16, one to four outputs, one to three
+# windows per column, gaps between windows, and rows that windows wrap
+# around more than once (more repetitions than the row holds steps)
+COL_ADJ_CASES = [
+    # (array, taps, pave, q, origin, repetitions along the row or None)
+    ((2, 5, 64), 13, 8, 1, -6, None),
+    ((1, 4, 96), 6, 8, 2, 1, None),
+    ((1, 3, 64), 16, 16, 4, 0, None),
+    ((1, 3, 48), 9, 4, 4, -1, None),
+    ((1, 2, 32), 13, 8, 3, -3, 6),
+]
+
+
+def _col_adj_stage(A, taps, pave, q, origin, reps, seed):
+    F, H, Wd = A
+    t = W.h_stage(F, H, Wd, taps, pave, origin)
+    rep = (F, H, reps if reps else -(-Wd // pave))
+    c = W.phase_coeffs(W.rng_for(seed), q, taps)
+    x = W.rng_for(seed + 1).standard_normal(A).astype(np.float32)
+    return W.Problem(rep, [t], W.phase_output(rep, 2, q), W.WSUM, c), x
+
+
+@pytest.mark.parametrize("case", COL_ADJ_CASES, ids=[str(k) for k in range(len(COL_ADJ_CASES))])
+def test_column_adjoint_phases_gaps_and_laps(case):
+    p, x = _col_adj_stage(*case, seed=660 + case[1])
+    fam = rsm.plan(p, flags=_abi.PLAN_ADJOINT)
+    say("column adjoint", case, fam)
+    assert fam != "generic_adjoint", fam
+    gy = W.rng_for(670 + case[1]).uniform(-1, 1, p.output.array_shape).astype(np.float32)
+    _adjoint_check(p, x, gy, what=str(case))
+    # one gradient at a time
+    a = oracle.adjoint(p, x, gy)
+    gx = torch.full(p.inputs[0].array_shape, float("nan"), device="cuda")
+    rsm.run_adjoint(p, dev(x), dev(gy), gx, None, dev(p.coeffs))
+    check_close(host(gx), a.gx, a.gx_abs, what=str(case) + " gx only")
+    gc = torch.full(p.coeffs.shape, float("nan"), device="cuda")
+    rsm.run_adjoint(p, dev(x), dev(gy), None, gc, dev(p.coeffs))
+    check_close(host(gc), a.gc, a.gc_abs, what=str(case) + " gc only")
+
+
+def test_column_adjoint_keeps_other_windows_out():
+    # infinities in dL/dy of one window must reach only the input columns
+    # of that window
+    p, x = _col_adj_stage((1, 4, 96), 6, 8, 2, 1, None, seed=680)
+    gy = W.rng_for(681).uniform(-1, 1, p.output.array_shape).astype(np.float32)
+    gy[0, 1, 2 * 5:2 * 5 + 2] = np.inf      # window 5 of row 1: columns 41 .. 46
+    a = oracle.adjoint(p, x, gy)
+    gx = torch.full(p.inputs[0].array_shape, float("nan"), device="cuda")
+    rsm.run_adjoint(p, dev(x), dev(gy), gx, None, dev(p.coeffs))
+    got, want = host(gx), a.gx
+    assert np.array_equal(np.isinf(got), np.isinf(want)) and np.array_equal(np.isnan(got), np.isnan(want))
+    fin = np.isfinite(want)
+    assert fin.sum() > 0.9 * fin.size
+    check_close(np.where(fin, got, 0), np.where(fin, want, 0), np.where(fin, a.gx_abs, 0),
+                what="finite columns")
+
+
 def test_polyphase_sum_task_rejected():
     p, x = _stage((1, 8, 64), 13, 8, 3, -2, 2, seed=2)
     ps = W.Problem(p.rep_shape, p.inputs, p.output, W.SUM)
