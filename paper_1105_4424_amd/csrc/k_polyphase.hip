@@ -627,10 +627,8 @@ __global__ void __launch_bounds__(kBlock) poly_adj_cols_kernel(PolyAdjArgs a) {
     const int rs = c0 - (K - 1);                   // first staged repetition
     const int ng = min(kChunk + K - 1, R - rs);    // staged repetitions
     __syncthreads();   // the previous item's readers of xs and gys are done
-    for (int e = t; e < q * ng; e += kBlock) {
-      const int r = rs + e / q;
-      gys[e] = r >= 0 ? gyrow[int64_t(rs) * q + e] : 0.0f;
-    }
+    const int e_lo = rs < 0 ? -rs * q : 0;        // repetition rs + e / q >= 0
+    for (int e = t; e < q * ng; e += kBlock) gys[e] = e >= e_lo ? gyrow[int64_t(rs) * q + e] : 0.0f;
     const int L = n > 0 ? p * (n - 1) + T : 0;
     if (a.partial && L > 0) {
       const float* xrow = a.x + xoff;
@@ -744,11 +742,13 @@ template <int XF, int GF>
 __device__ __forceinline__ void adj_fetch(const PolyAdjArgs& a, const AdjItem& it, float (&xv)[XF], float (&gv)[GF]) {
   const int t = int(threadIdx.x);
   const int A2 = a.w.A[2], q = a.q;
+  // staged value e belongs to repetition rs + e / q, which exists from
+  // e >= -rs q on (rs < 0 only in a row's first chunk): no division
+  const int e_lo = it.rs < 0 ? -it.rs * q : 0, e_hi = q * it.ng;
 #pragma unroll
   for (int m = 0; m < GF; ++m) {
     const int e = t + kBlock * m;
-    const int r = it.rs + e / q;
-    gv[m] = (e < q * it.ng && r >= 0) ? it.gyrow[int64_t(it.rs) * q + e] : 0.0f;
+    gv[m] = (e < e_hi && e >= e_lo) ? it.gyrow[int64_t(it.rs) * q + e] : 0.0f;
   }
   if (!a.partial) return;
   const float* xrow = a.x + it.xoff;
