@@ -76,6 +76,8 @@ CASES = [
     ((1, 9, 8), 20, 3, 2, -11, 1),       # windows longer than the axis: several lifts
     ((1, 6, 48), 13, 4, 3, -5, 2),       # step 4: the phase form of the column adjoint
     ((1, 3, 36), 13, 3, 2, -1, 2),       # step 3 (not a power of two): the per-slot form
+    ((1, 5, 64), 12, 4, 4, 0, 2),        # four outputs per window in registers
+    ((2, 4, 12), 5, 4, 2, -3, 2),        # rows shorter than four vectors: every window wraps
 ]
 
 
