@@ -1072,7 +1072,7 @@ size_t adjoint_ws_bytes(const AdjPlan& ap, int64_t n_rep, int64_t n_pat, int64_t
         std::max<int64_t>((int64_t(w.A[2]) + 256 * int64_t(w.p[2]) - 1) / (256 * int64_t(w.p[2])),
                           (int64_t(w.rep[2]) + 255) / 256),
         1);
-    return size_t(poly_adj_cols_grid(uint32_t(int64_t(w.rep[0]) * w.rep[1] * chunks))) * size_t(ap.q) *
+    return size_t(poly_adj_cols_grid(w, ap.q, uint32_t(int64_t(w.rep[0]) * w.rep[1] * chunks))) * size_t(ap.q) *
            size_t(w.taps) * sizeof(float);
   }
   if (ap.poly && poly_gc_supported(ap.w, ap.q))
@@ -1135,7 +1135,7 @@ rsm_status exec_adjoint(const rsm_space& rep, const rsm_tiler& in, const void* d
     o.accumulate = accumulate;
     if ((e = launch_poly_adj_cols(o, st)) != hipSuccess) return hip_fail(e, "polyphase adjoint");
     const int nc = ap.q * w.taps;
-    if (d_gc && (e = launch_reduce_partials(o.partial, poly_adj_cols_grid(o.n_items), nc, nc,
+    if (d_gc && (e = launch_reduce_partials(o.partial, poly_adj_cols_grid(w, ap.q, o.n_items), nc, nc,
                                             static_cast<float*>(d_gc), accumulate, st)) != hipSuccess)
       return hip_fail(e, "weight-gradient reduction");
     return RSM_OK;

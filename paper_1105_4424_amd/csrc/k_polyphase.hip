@@ -33,6 +33,9 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <mutex>
+#include <utility>
+#include <vector>
 
 #include "rsm_internal.h"
 
@@ -1033,54 +1036,54 @@ bool poly_adj_cols_supported(const Win3& w, int q) {
          int64_t(w.p[2]) * (w.rep[2] - 1) + w.taps < (int64_t(1) << 30);
 }
 
-namespace {
-int poly_adj_resident() {
-  static const int resident = [] {
-    int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, poly_adj_cols_kernel, kBlock, 0) != hipSuccess ||
-        per_cu < 1) {
-      (void)hipGetLastError();
-      per_cu = 4;
-    }
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
-      (void)hipGetLastError();
-      cus = 256;
-    }
-    return per_cu * cus;
-  }();
-  return resident;
-}
-}  // namespace
-
-int poly_adj_cols_grid(uint32_t n_items) {
-  return int(n_items < uint32_t(poly_adj_resident()) ? (n_items ? n_items : 1) : uint32_t(poly_adj_resident()));
-}
-
 bool poly_adj_phase_ok(const Win3& w, int q) {
   const int p = w.p[2];
   return (p & (p - 1)) == 0 && (kBlock % p) == 0 && (w.A[2] % p) == 0 && (w.taps + p - 1) / p <= 4 && q <= 4;
 }
 
-hipError_t launch_poly_adj_cols(const PolyAdjArgs& a, hipStream_t st) {
-  const int grid = poly_adj_cols_grid(a.n_items);
-  if (poly_adj_phase_ok(a.w, a.q)) {
-    // GF = 5 registers hold q (256 + K - 1) <= 4 x 259 staged values; XF = p
-    const int K = (a.w.taps + a.w.p[2] - 1) / a.w.p[2];
-    if (a.w.p[2] <= 8) {
-      if (K <= 2)
-        poly_adj_phase_kernel<2, 4, 8, 5><<<grid, kBlock, 0, st>>>(a);
-      else
-        poly_adj_phase_kernel<4, 4, 8, 5><<<grid, kBlock, 0, st>>>(a);
-    } else {
-      if (K <= 2)
-        poly_adj_phase_kernel<2, 4, 16, 5><<<grid, kBlock, 0, st>>>(a);
-      else
-        poly_adj_phase_kernel<4, 4, 16, 5><<<grid, kBlock, 0, st>>>(a);
-    }
-  } else {
-    poly_adj_cols_kernel<<<grid, kBlock, 0, st>>>(a);
+namespace {
+using PolyAdjKernel = void (*)(PolyAdjArgs);
+
+// The columns adjoint for this stage: the phase form (GF = 5 registers hold
+// q (256 + K - 1) <= 4 x 259 staged values; XF = p) or the general one.
+PolyAdjKernel poly_adj_kernel_for(const Win3& w, int q) {
+  if (!poly_adj_phase_ok(w, q)) return poly_adj_cols_kernel;
+  const int K = (w.taps + w.p[2] - 1) / w.p[2];
+  if (w.p[2] <= 8) return K <= 2 ? poly_adj_phase_kernel<2, 4, 8, 5> : poly_adj_phase_kernel<4, 4, 8, 5>;
+  return K <= 2 ? poly_adj_phase_kernel<2, 4, 16, 5> : poly_adj_phase_kernel<4, 4, 16, 5>;
+}
+
+// Workgroups of a kernel resident on the whole device, from its own
+// occupancy (cached per kernel).
+int poly_adj_resident(PolyAdjKernel k) {
+  static std::mutex mu;
+  static std::vector<std::pair<PolyAdjKernel, int>> known;
+  std::lock_guard<std::mutex> lock(mu);
+  for (const auto& e : known)
+    if (e.first == k) return e.second;
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlock, 0) != hipSuccess || per_cu < 1) {
+    (void)hipGetLastError();   // a failed query must not surface as a launch error
+    per_cu = 4;
   }
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+    (void)hipGetLastError();
+    cus = 256;
+  }
+  known.emplace_back(k, per_cu * cus);
+  return per_cu * cus;
+}
+}  // namespace
+
+int poly_adj_cols_grid(const Win3& w, int q, uint32_t n_items) {
+  const uint32_t res = uint32_t(poly_adj_resident(poly_adj_kernel_for(w, q)));
+  return int(n_items < res ? (n_items ? n_items : 1) : res);
+}
+
+hipError_t launch_poly_adj_cols(const PolyAdjArgs& a, hipStream_t st) {
+  const int grid = poly_adj_cols_grid(a.w, a.q, a.n_items);
+  hipLaunchKernelGGL(poly_adj_kernel_for(a.w, a.q), dim3(grid), dim3(kBlock), 0, st, a);
   return hipGetLastError();
 }
 

@@ -422,7 +422,7 @@ hipError_t launch_poly_gx_gather(const PolyGatherArgs& a, hipStream_t st);
 int poly_gc_grid(uint32_t n_rep);
 hipError_t launch_poly_gc(const PolyArgs& a, hipStream_t st);
 bool poly_adj_cols_supported(const Win3& w, int q);
-int poly_adj_cols_grid(uint32_t n_items);
+int poly_adj_cols_grid(const Win3& w, int q, uint32_t n_items);   // workgroups = partial rows
 hipError_t launch_poly_adj_cols(const PolyAdjArgs& a, hipStream_t st);
 int64_t gemm_lds_bytes_per_operand(const GemmArgs& g, int compute);   // LDS per workgroup, one operand
 int gemm_tile_side(const GemmArgs& g, int compute);                   // output tile side (128 or 256)
