@@ -194,6 +194,10 @@ rsm_status rsm_plan_ports(const rsm_space* rep, const rsm_tiler* in, int32_t n_i
  * kept in registers with the weights in scalar registers (input private,
  * weights constant), or the window staged in LDS with the weights in LDS
  * (input, output and weights local), or everything read in place (global);
+ * overlapping column windows on a common 16-byte phase, and polyphase
+ * stages along columns, may also read each window straight into registers
+ * with the weights in registers (input private, output global, weights
+ * private);
  * a k x k window keeps its tile in LDS with its weights in constant memory,
  * or, for at most 64 pattern elements, one element per lane in registers
  * (weights in registers too); a matrix product stages both operands
