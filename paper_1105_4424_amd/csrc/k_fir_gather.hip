@@ -27,6 +27,7 @@ namespace rsm {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kMaxTapsGather = 16;   // taps of a 1-D window on the tap paths
 
 __device__ __forceinline__ int wrap_mod(int v, int n) {
   const int q = v % n;
@@ -43,11 +44,18 @@ __device__ __forceinline__ int outer_rep(int a_d, int o, int p, int rep, const F
   return (q * p == v && q < rep) ? q : -1;
 }
 
-template <int AX>
+// KM >= ceil(T / p): the taps of one lift that can meet an element.  Its
+// pairs r = r0 - k, i = i0 + k p (k < KM) are tested and their dL/dy loads
+// issued together, then added in the order of ascending tap (the order of
+// a walk down from r0); the weights are read from LDS.
+template <int AX, int KM>
 __global__ void __launch_bounds__(kBlock) fir_gx_gather_kernel(FirGatherArgs a) {
   const Win3& w = a.w;
   const int n_ax = w.A[AX], R = w.rep[AX], p = w.p[AX], T = w.taps;
   const int span = p * (R - 1) + T;   // unwrapped positions covered, v in [0, span)
+  __shared__ float cs[kMaxTapsGather];
+  if (threadIdx.x < kMaxTapsGather) cs[threadIdx.x] = int(threadIdx.x) < T ? a.c[threadIdx.x] : 0.0f;
+  __syncthreads();
   const uint32_t stride = gridDim.x * kBlock;
   for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < a.n_arr; e += stride) {
     const uint32_t row = fdiv(e, a.div_a2);
@@ -72,12 +80,87 @@ __global__ void __launch_bounds__(kBlock) fir_gx_gather_kernel(FirGatherArgs a) 
       int v = at - a.o_mod;   // first lift: v = (a - o) mod A
       if (v < 0) v += n_ax;
       for (; v < span; v += n_ax) {
-        int r = int(fdiv(uint32_t(v), a.div_p[AX]));
-        if (r > R - 1) r = R - 1;
-        for (int i = v - p * r; r >= 0 && i < T; --r, i += p) acc = fmaf(a.c[i], a.gy[g0 + r * gs], acc);
+        const int r0 = int(fdiv(uint32_t(v), a.div_p[AX]));
+        const int i0 = v - p * r0;   // in [0, p)
+        float g[KM];
+        bool ok[KM];
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+          const int r = r0 - k, i = i0 + k * p;
+          ok[k] = r >= 0 && r <= R - 1 && i < T;
+          g[k] = ok[k] ? a.gy[g0 + r * gs] : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+          const int i = i0 + k * p;
+          if (ok[k]) acc = fmaf(cs[i < kMaxTapsGather ? i : 0], g[k], acc);
+        }
       }
     }
     a.gx[e] = a.accumulate ? a.gx[e] + acc : acc;
+  }
+}
+
+// Taps along rows with the column axis taken whole (p[2] = 1, o[2] = 0,
+// rep[2] = A[2], A[2] a multiple of 4, dL/dy and dL/dx 16-byte aligned):
+// one thread per four adjacent columns of a row, which meet the same
+// windows, so the index work is done once and dL/dy and dL/dx move as
+// 16-byte vectors.  Each column adds its pairs in the order of the
+// one-column kernel above.
+template <int KM>
+__global__ void __launch_bounds__(kBlock) fir_gx_gather_rows_vec_kernel(FirGatherArgs a) {
+  const Win3& w = a.w;
+  const int n_ax = w.A[1], R = w.rep[1], p = w.p[1], T = w.taps;
+  const int span = p * (R - 1) + T;   // unwrapped positions covered, v in [0, span)
+  __shared__ float cs[kMaxTapsGather];
+  if (threadIdx.x < kMaxTapsGather) cs[threadIdx.x] = int(threadIdx.x) < T ? a.c[threadIdx.x] : 0.0f;
+  __syncthreads();
+  const uint32_t n4 = a.n_arr / 4;
+  const uint32_t stride = gridDim.x * kBlock;
+  for (uint32_t q4 = blockIdx.x * kBlock + threadIdx.x; q4 < n4; q4 += stride) {
+    const uint32_t e = 4 * q4;
+    const uint32_t row = fdiv(e, a.div_a2);
+    const int ac = int(e - row * uint32_t(w.A[2]));
+    const uint32_t b = fdiv(row, a.div_a1);
+    const int ar = int(row - b * uint32_t(w.A[1]));
+    const int rb = outer_rep(int(b), w.o[0], w.p[0], w.rep[0], a.div_p[0]);
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (rb >= 0) {
+      const int64_t g0 = int64_t(rb) * w.rep[1] * w.rep[2] + ac;
+      const int gs = w.rep[2];
+      int v = ar - a.o_mod;   // first lift: v = (a - o) mod A
+      if (v < 0) v += n_ax;
+      for (; v < span; v += n_ax) {
+        const int r0 = int(fdiv(uint32_t(v), a.div_p[1]));
+        const int i0 = v - p * r0;   // in [0, p)
+        float4 g[KM];
+        bool ok[KM];
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+          const int r = r0 - k, i = i0 + k * p;
+          ok[k] = r >= 0 && r <= R - 1 && i < T;
+          g[k] = ok[k] ? *reinterpret_cast<const float4*>(a.gy + g0 + int64_t(r) * gs)
+                       : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+          if (!ok[k]) continue;
+          const int i = i0 + k * p;
+          const float c = cs[i < kMaxTapsGather ? i : 0];
+          acc[0] = fmaf(c, g[k].x, acc[0]);
+          acc[1] = fmaf(c, g[k].y, acc[1]);
+          acc[2] = fmaf(c, g[k].z, acc[2]);
+          acc[3] = fmaf(c, g[k].w, acc[3]);
+        }
+      }
+    }
+    float4* dst = reinterpret_cast<float4*>(a.gx + e);
+    float4 out = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    if (a.accumulate) {
+      const float4 old = *dst;
+      out.x += old.x; out.y += old.y; out.z += old.z; out.w += old.w;
+    }
+    *dst = out;
   }
 }
 
@@ -368,10 +451,28 @@ hipError_t launch_fir_adjoint_overlap_cols(const FirOverlapArgs& a, hipStream_t 
 hipError_t launch_fir_gx_gather(const FirGatherArgs& a, hipStream_t st) {
   const uint32_t need = (a.n_arr + kBlock - 1) / kBlock;
   const int grid = int(need < 256u * 16u ? (need ? need : 1) : 256u * 16u);
-  if (a.w.ax == 2)
-    fir_gx_gather_kernel<2><<<grid, kBlock, 0, st>>>(a);
-  else
-    fir_gx_gather_kernel<1><<<grid, kBlock, 0, st>>>(a);
+  const int p = a.w.p[a.w.ax];
+  const int K = p >= 1 ? (a.w.taps + p - 1) / p : a.w.taps;   // taps of one lift
+  const uintptr_t al = reinterpret_cast<uintptr_t>(a.gy) | reinterpret_cast<uintptr_t>(a.gx);
+  if (a.w.ax == 1 && a.w.p[2] == 1 && a.w.o[2] == 0 && a.w.rep[2] == a.w.A[2] && a.w.A[2] % 4 == 0 &&
+      (al & 15) == 0 && K <= 4) {
+    const uint32_t need4 = (a.n_arr / 4 + kBlock - 1) / kBlock;
+    const int grid4 = int(need4 < 256u * 16u ? (need4 ? need4 : 1) : 256u * 16u);
+    if (K <= 2)
+      fir_gx_gather_rows_vec_kernel<2><<<grid4, kBlock, 0, st>>>(a);
+    else
+      fir_gx_gather_rows_vec_kernel<4><<<grid4, kBlock, 0, st>>>(a);
+    return hipGetLastError();
+  }
+  if (a.w.ax == 2) {
+    if (K <= 2) fir_gx_gather_kernel<2, 2><<<grid, kBlock, 0, st>>>(a);
+    else if (K <= 4) fir_gx_gather_kernel<2, 4><<<grid, kBlock, 0, st>>>(a);
+    else fir_gx_gather_kernel<2, kMaxTapsGather><<<grid, kBlock, 0, st>>>(a);
+  } else {
+    if (K <= 2) fir_gx_gather_kernel<1, 2><<<grid, kBlock, 0, st>>>(a);
+    else if (K <= 4) fir_gx_gather_kernel<1, 4><<<grid, kBlock, 0, st>>>(a);
+    else fir_gx_gather_kernel<1, kMaxTapsGather><<<grid, kBlock, 0, st>>>(a);
+  }
   return hipGetLastError();
 }
 

@@ -134,6 +134,24 @@ def test_overlap_cols_chunks_and_laps(A, R, pave, taps, origin):
     _adjoint_check(p, x, gy, 0, "overlap cols %s R=%d p=%d T=%d o=%d" % (A, R, pave, taps, origin))
 
 
+# taps along rows with whole rows of columns: the input gradient four
+# columns per thread (16-byte dL/dy and dL/dx); frames the tiler skips (every
+# other one), windows wrapping at both ends, one to four windows per element
+@pytest.mark.parametrize("A,R,pave,taps,origin", [((4, 40, 64), 5, 8, 13, -6),
+                                                   ((3, 24, 16), 6, 4, 16, -3),
+                                                   ((2, 9, 12), 9, 1, 3, -1)])
+def test_gather_adjoint_rows_four_columns(A, R, pave, taps, origin):
+    rng = W.rng_for(97 + taps)
+    rep = ((A[0] + 1) // 2, R, A[2])
+    t = W.Tiler(A, [0, origin, 0], np.diag([2, pave, 1]), [[0], [1], [0]], (taps,))
+    c = rng.uniform(-1, 1, taps).astype(np.float32)
+    p = W.Problem(rep, [t], W.identity_output(rep), W.WSUM, c)
+    assert rsm.plan(p, flags=_abi.PLAN_ADJOINT) == "fir_adjoint_gather"
+    x = W.random_array(rng, A)
+    gy = rng.uniform(-1, 1, rep).astype(np.float32)
+    _adjoint_check(p, x, gy, 0, "rows, whole columns %s R=%d p=%d T=%d o=%d" % (A, R, pave, taps, origin))
+
+
 @pytest.mark.parametrize("stage", ["h", "v"])
 def test_gather_adjoint_overlapping_full_frames(stage):
     # 13 taps every 8 columns (rows), centred origin -6: windows overlap by 5
