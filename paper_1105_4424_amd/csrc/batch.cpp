@@ -33,7 +33,7 @@
 
 namespace {
 
-constexpr const char* kKernelRevision = "filter2d-r10";
+constexpr const char* kKernelRevision = "filter2d-r11";
 constexpr double kHbmBytesPerS = 8.0e12;
 constexpr double kFp32FmaPerS = 39.3e12;   // unpacked FP32 FMA issue rate of the chip
 

@@ -121,14 +121,32 @@ __device__ __forceinline__ void compute_tile(const Filter2DProblem& p, int64_t l
   const __amdgpu_buffer_rsrc_t ry = __builtin_amdgcn_make_buffer_rsrc(
       p.y + int64_t(frame) * p.RH * p.RW, short(0), p.RH * p.RW * 4, int(kRawBuffer));
   const int oy0 = ty * TH + tr * RY, ox0 = tx * TW + tc * RX;
+  // a thread's RX outputs of a row go out as one store when all lie inside
+  // the row (buffer stores need 4-byte alignment only); a group cut by the
+  // row's end stores its outputs one by one
+  const bool full = ox0 + RX <= p.RW;
 #pragma unroll
   for (int i = 0; i < RY; ++i) {
     const int oy = oy0 + i;
+    if (RX == 4) {
+      typedef __attribute__((ext_vector_type(4))) unsigned int u4;
+      const u4 v = {__builtin_bit_cast(uint32_t, acc[i][0]), __builtin_bit_cast(uint32_t, acc[i][1]),
+                    __builtin_bit_cast(uint32_t, acc[i][2]), __builtin_bit_cast(uint32_t, acc[i][3])};
+      const uint32_t off = (oy < p.RH && full) ? uint32_t(oy * p.RW + ox0) * 4u : kOutOfRange;
+      __builtin_amdgcn_raw_buffer_store_b128(v, ry, off, 0, 0);
+    } else if (RX == 2) {
+      typedef __attribute__((ext_vector_type(2))) unsigned int u2;
+      const u2 v = {__builtin_bit_cast(uint32_t, acc[i][0]), __builtin_bit_cast(uint32_t, acc[i][RX - 1])};
+      const uint32_t off = (oy < p.RH && full) ? uint32_t(oy * p.RW + ox0) * 4u : kOutOfRange;
+      __builtin_amdgcn_raw_buffer_store_b64(v, ry, off, 0, 0);
+    }
+    if (RX == 1 || !full) {
 #pragma unroll
-    for (int j = 0; j < RX; ++j) {
-      const int ox = ox0 + j;
-      const uint32_t off = (oy < p.RH && ox < p.RW) ? uint32_t(oy * p.RW + ox) * 4u : kOutOfRange;
-      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, acc[i][j]), ry, off, 0, 0);
+      for (int j = 0; j < RX; ++j) {
+        const int ox = ox0 + j;
+        const uint32_t off = (oy < p.RH && ox < p.RW) ? uint32_t(oy * p.RW + ox) * 4u : kOutOfRange;
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, acc[i][j]), ry, off, 0, 0);
+      }
     }
   }
 }
